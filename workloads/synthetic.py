@@ -1,0 +1,106 @@
+"""Parameter sets and seeded draws for the parquet hot path.
+
+Workloads (all synthetic; the paper's DMFT / CT-INT inputs are not available):
+
+* ``c1``  momentum-independent parquet approximation: Nk = 1, Weiss field from a
+  semicircular density of states (half-bandwidth D = 2), U = 1, beta = 5,
+  half filling, fermionic box Nv = 32 (31 bosonic), mixing 0.5, tol 1e-8.
+* ``c2``  4x4 square lattice, t = 1, t' = 0, U = 2, beta = 4, half filling,
+  Nv = 16 (BSE dimension 256, 240 transfer blocks).
+* ``c3``  8x8 square lattice, t = 1, t' = -0.2, U = 2, beta = 5, filling 0.9,
+  Nv = 16 (BSE dimension 1024, 960 transfer blocks), kernel level 2.
+* ``tiny*`` small boxes used by the unit and parity tests.
+
+Random draws use ``numpy.random.Generator(PCG64(seed))`` so that every consumer
+(the oracle, the HIP path, the tests) sees bit-identical inputs.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class ModelParams:
+    """Physical and numerical parameters of one parquet instance."""
+
+    Lx: int
+    Ly: int
+    Nv: int                 # fermionic box size (even); bosonic box has Nv - 1
+    U: float
+    beta: float
+    t: float = 1.0
+    tp: float = 0.0         # next-nearest-neighbour hopping t'
+    filling: float = 1.0    # total density n (both spins)
+    D: float = 2.0          # semicircle half-bandwidth (local mode, Nk = 1)
+    f_ext: int = 2          # extension factor of the regulation box
+    kernel_level: int = 2   # 0: truncation, 1: K1 only, 2: K1 + K2
+    edge_rule: int = 0      # 0: far edge per channel and sign of m; 1: lowest edge always
+    mu_mode: int = 0        # 0: mu_tilde fixed to mu_fixed; 1: bisection on the filling
+    mu_fixed: float = 0.0
+    alpha: float = 0.5      # linear mixing of Sigma and Phi
+    tol: float = 1e-8
+
+    @property
+    def Nk(self) -> int:
+        return self.Lx * self.Ly
+
+    @property
+    def local(self) -> bool:
+        return self.Nk == 1
+
+    def replace(self, **kw) -> "ModelParams":
+        return dataclasses.replace(self, **kw)
+
+
+CONFIGS: Dict[str, ModelParams] = {
+    "c1": ModelParams(Lx=1, Ly=1, Nv=32, U=1.0, beta=5.0, D=2.0, filling=1.0,
+                      mu_mode=0, tol=1e-8),
+    "c2": ModelParams(Lx=4, Ly=4, Nv=16, U=2.0, beta=4.0, t=1.0, tp=0.0,
+                      filling=1.0, mu_mode=0, tol=1e-6),
+    "c3": ModelParams(Lx=8, Ly=8, Nv=16, U=2.0, beta=5.0, t=1.0, tp=-0.2,
+                      filling=0.9, mu_mode=1, tol=1e-6),
+    # small boxes for tests
+    "tiny_local": ModelParams(Lx=1, Ly=1, Nv=8, U=1.0, beta=5.0, D=2.0),
+    "tiny_2x2": ModelParams(Lx=2, Ly=2, Nv=4, U=1.5, beta=3.0, tp=-0.1,
+                            filling=0.95, mu_mode=1),
+    "tiny_2x2_hf": ModelParams(Lx=2, Ly=2, Nv=8, U=2.0, beta=4.0),
+    "small_4x4": ModelParams(Lx=4, Ly=4, Nv=4, U=2.0, beta=3.0, tp=-0.2,
+                             filling=0.9, mu_mode=1),
+    "small_2x4": ModelParams(Lx=2, Ly=4, Nv=6, U=1.5, beta=4.0, tp=0.1,
+                             filling=1.05, mu_mode=1),
+}
+
+
+def config(name: str, **overrides) -> ModelParams:
+    p = CONFIGS[name]
+    return p.replace(**overrides) if overrides else p
+
+
+def rand_complex(shape, seed: int, scale: float = 1.0) -> np.ndarray:
+    """Complex normal draws with Re, Im ~ N(0, scale^2 / 2) each (E|z|^2 = scale^2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = scale / np.sqrt(2.0)
+    re = rng.standard_normal(shape)
+    im = rng.standard_normal(shape)
+    return (re * s + 1j * (im * s)).astype(np.complex128)
+
+
+def bse_microbench_gamma(n: int, blocks, base_seed: int = 1510) -> np.ndarray:
+    """Seeded i.i.d. complex N(0, 1/n) blocks, block b drawn from PCG64(base_seed + b)."""
+    out = np.empty((len(blocks), n, n), dtype=np.complex128)
+    for i, b in enumerate(blocks):
+        out[i] = rand_complex((n, n), base_seed + int(b), scale=1.0 / np.sqrt(n))
+    return out
+
+
+def random_phi(nq: int, n: int, seed: int, scale: float = 0.1) -> np.ndarray:
+    """Four seeded random reducible-vertex arrays, layout [channel][q][k][k']."""
+    return rand_complex((4, nq, n, n), seed, scale)
+
+
+def random_sigma(nfreq: int, nk: int, seed: int, scale: float = 0.2) -> np.ndarray:
+    """Seeded random self-energy on [frequency][momentum]."""
+    return rand_complex((nfreq, nk), seed, scale)
