@@ -1,0 +1,248 @@
+/*
+ * parquet.h -- C ABI of the MI355X (gfx950) parquet hot-path library.
+ *
+ * One iteration of the parquet approximation for the Hubbard model, following
+ * G. Li, N. Wentzell, P. Pudleiner, P. Thunstroem, K. Held, "Efficient
+ * implementation of the parquet equations -- role of the reducible vertex
+ * function and its kernel approximation":
+ *
+ *   Dyson equation (Eq. PA_Dyson)                      -> dyson_update
+ *   G G factors of the Bethe-Salpeter equations         -> bubble_build
+ *   first/second-level kernel functions                -> kernel_extract
+ *   parquet equations with kernel fill (Eqs. PA_Gamma_dm, PA_Gamma_st)
+ *                                                       -> channel_remap
+ *   regulated Schwinger-Dyson equation (Eq. PA_Sigma with the auxiliary
+ *   vertex of Eq. auxiliary_function and the Sigma~_1/Sigma~_2 split)
+ *                                                       -> sigma_sde
+ *   Bethe-Salpeter equations (Eq. PA_F_Phi) solved as F = [1 - s Gamma X]^-1 Gamma
+ *                                                       -> bse_solve
+ *   linear mixing and convergence norm                  -> sigma_mix
+ *   the whole loop on one device                        -> parquet_* context API
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Sizes: Nk = Lx*Ly momenta, fermionic box Nv (even) with n in [-Nv/2, Nv/2-1],
+ * bosonic box NW = Nv-1 with m in [-(Nv/2-1), Nv/2-1]; extended box Nve = f*Nv
+ * fermionic / NWe = f*Nv-1 bosonic; Green's-function grid NG = 2*f*Nv;
+ * BSE dimension n = Nk*Nv; number of transfers Nq = Nk*NW.
+ * Compound indices are frequency-major: k = (n, K) -> (n + Nv/2)*Nk + K,
+ * q = (m, Q) -> (m + Nv/2 - 1)*Nk + Q, K = kx*Ly + ky.
+ * Layouts (row-major, complex interleaved re/im):
+ *   vertex arrays  [4][Nq][n][n]  channels (d, m, s, t), "storage" precision
+ *   G              [NG][Nk]        complex double
+ *   Sigma          [Nve][Nk]       complex double
+ *   X_ph, X_pp     [Nq][n]         complex double
+ *   K1             [4][Nq]         complex double
+ *   K2             [4][Nq][n]      complex double
+ * Storage precision: PQ_STORE_C64 (float2) or PQ_STORE_C128 (double2).
+ *
+ * Ownership: every pointer is caller-owned device memory (except pq_params and
+ * the host stats structs). The library never allocates or frees device memory;
+ * scratch comes from the caller's workspace, sized by the *_workspace queries.
+ * Asynchrony: stage entry points only enqueue work on the given stream and
+ * return; errors of the enqueued kernels surface at the next synchronising
+ * call. Invalid sizes or null pointers return PQ_ERR_ARG before anything is
+ * enqueued. No C++ exception crosses this interface. parquet_last_error()
+ * returns a thread-local message for the last failing call.
+ */
+#ifndef PARQUET_H
+#define PARQUET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* pq_stream;   /* a hipStream_t (0 = the legacy default stream) */
+
+typedef enum {
+  PQ_OK = 0,
+  PQ_ERR_ARG = 1,          /* invalid argument, nothing enqueued            */
+  PQ_ERR_HIP = 2,          /* a HIP runtime call failed                      */
+  PQ_ERR_NOMEM = 3,        /* workspace too small                            */
+  PQ_ERR_SINGULAR = 4,     /* a BSE block lost its pivots (see bse stats)    */
+  PQ_ERR_NOT_CONVERGED = 5,
+  PQ_ERR_NONFINITE = 6,    /* NaN/Inf in Sigma                               */
+  PQ_ERR_REFINE = 7        /* refinement did not reach its tolerance         */
+} pq_status;
+
+typedef enum { PQ_STORE_C128 = 0, PQ_STORE_C64 = 1 } pq_storage;
+
+typedef enum {
+  PQ_PREC_FP64 = 0,        /* complex128 elimination, FP64 MFMA              */
+  PQ_PREC_FP32 = 1,        /* complex64 elimination, FP32 MFMA               */
+  PQ_PREC_FP32_REFINE = 2  /* FP32 elimination + one FP64-residual refinement
+                              sweep on blocks the pivot monitor flags        */
+} pq_precision;
+
+typedef enum { PQ_CH_D = 0, PQ_CH_M = 1, PQ_CH_S = 2, PQ_CH_T = 3 } pq_channel;
+
+/* Model and numerical parameters of one parquet instance. */
+typedef struct {
+  int32_t Lx, Ly;          /* lattice; Lx = Ly = 1 selects the local mode    */
+  int32_t Nv;              /* fermionic box size, even, >= 2                 */
+  int32_t f_ext;           /* extension factor of the regulation box, >= 1   */
+  int32_t kernel_level;    /* 0 truncation, 1 K1 only, 2 K1 + K2             */
+  int32_t edge_rule;       /* 0 far edge per channel and sign of m, 1 lowest */
+  int32_t mu_mode;         /* 0 fixed mu~ = mu_fixed, 1 bisection on filling */
+  int32_t storage;         /* pq_storage of the vertex arrays                */
+  int32_t precision;       /* pq_precision of the BSE                        */
+  int32_t reserved;
+  double U, beta, t, tp;   /* interaction, inverse temperature, hoppings     */
+  double filling;          /* total density n for mu_mode = 1                */
+  double D;                /* semicircle half-bandwidth (local mode)         */
+  double mu_fixed;
+  double alpha;            /* linear mixing of Sigma and Phi, (0, 1]         */
+} pq_params;
+
+/* Sizes derived from pq_params (filled by pq_dims_from_params). */
+typedef struct {
+  int32_t Lx, Ly, Nk, Nv, NW, f_ext, Nve, NWe, NG, n, Nq, ntau;
+  int64_t vertex_elems;    /* Nq*n*n per channel */
+} pq_dims;
+
+/* Validate params and derive sizes; PQ_ERR_ARG if inconsistent. */
+pq_status pq_dims_from_params(const pq_params* p, pq_dims* out);
+
+/* Human-readable message of the last failing call on this thread. */
+const char* parquet_last_error(void);
+
+/* ------------------------------------------------------------------ stages */
+
+/* Dyson equation (Eq. PA_Dyson) on the G grid: G = 1/(i nu + mu~ - eps_K - Sigma)
+ * (lattice, Hartree absorbed into mu~) or 1/(1/G0 - Sigma) (local, semicircle
+ * G0). Sigma is taken as zero outside the extended box. With mu_mode = 1, mu~
+ * is found by bisection so that 2 n_sigma = filling, the density including the
+ * exact tail beyond the grid. sigma: [Nve][Nk] c128 (read); g_out: [NG][Nk]
+ * c128 (written); mu_out: one device double (written). */
+pq_status dyson_update(const pq_params* p, const void* sigma, void* g_out,
+                       void* mu_out, pq_stream stream);
+
+/* X_ph(k;q) = (T/N) G(k) G(k+q), X_pp(k;q) = (T/2N) G(k) G(q-k) for k in the
+ * box (the G G factors of Eq. PA_F_Phi). g: [NG][Nk]; xph, xpp: [Nq][n] c128. */
+pq_status bubble_build(const pq_params* p, const void* g, void* xph, void* xpp,
+                       pq_stream stream);
+
+/* Kernel functions (two-level kernel approximation): K1_r(q) = mean over K,K'
+ * of Phi_r at both fermionic arguments on the box edge n_e, K2_r(k;q) = mean
+ * over K' of Phi_r^{k,(n_e,K')}(q) - K1_r(q). n_e: the edge away from the
+ * stripes (ph channels: top edge for m > 0, bottom for m < 0; pp channels the
+ * opposite; both edges averaged at m = 0), or the bottom edge with
+ * edge_rule = 1. kernel_level 1 zeroes K2, level 0 zeroes both.
+ * phi: [4][Nq][n][n] (storage precision); k1: [4][Nq] c128; k2: [4][Nq][n] c128. */
+pq_status kernel_extract(const pq_params* p, const void* phi, void* k1, void* k2,
+                         pq_stream stream);
+
+/* Parquet equations (Eqs. PA_Gamma_dm, PA_Gamma_st): for every (q, k, k') in
+ * the box, Gamma_r = Lambda_r + the eight remapped reducible vertices
+ *   d/m: Phi_{d,m}(k, k+q; k'-k), Psi_{s,t}(k, k'; k+k'+q)
+ *   s/t: Phi_{d,m}(k, q-k'; k'-k), Phi_{d,m}(k, k'; q-k-k')
+ * with the stored Phi when every argument is inside the box and the kernel
+ * value K1(p) + [k1 in box] K2(k1;p) + [k2 in box] K2(k2;p) otherwise (zero
+ * when the transfer p leaves the bosonic box). lambda: 4 host doubles
+ * (the parquet approximation uses U, -U, 2U, 0). phi, gamma_out:
+ * [4][Nq][n][n] storage precision, must not alias. */
+pq_status channel_remap(const pq_params* p, const double lambda[4], const void* phi,
+                        const void* k1, const void* k2, void* gamma_out,
+                        pq_stream stream);
+
+/* Workspace bytes for sigma_sde. */
+pq_status sigma_sde_workspace(const pq_params* p, size_t* bytes);
+
+/* Regulated Schwinger-Dyson equation (high-frequency regulation subsection):
+ *   Sigma(k) = Sigma~_1(k) + Sigma~_2(k) + [k in box] Sigma_box(k)
+ * Sigma~_1: second-order diagram over all Matsubara frequencies through
+ * imaginary time; Sigma~_2: (F~ - Lambda) summed over the extended box;
+ * Sigma_box: (F - F~) over the box, F = Gamma + Phi built from Phi by the
+ * parquet equations (no Gamma input needed), F~ from the kernel functions.
+ * FP64 accumulation throughout. phi: [4][Nq][n][n]; k1, k2: kernel tables;
+ * g: [NG][Nk]; mu: device double from dyson_update; sigma_out: [Nve][Nk]
+ * c128. ws: device workspace of sigma_sde_workspace bytes. */
+pq_status sigma_sde(const pq_params* p, const void* phi, const void* k1,
+                    const void* k2, const void* g, const void* mu, void* sigma_out,
+                    void* ws, size_t ws_bytes, pq_stream stream);
+
+/* Workspace bytes for bse_solve on one channel. */
+pq_status bse_workspace(const pq_params* p, size_t* bytes);
+
+/* Per-block diagnostics written by bse_solve (device memory, Nq entries). */
+typedef struct {
+  float min_pivot;       /* smallest |pivot| / largest |pivot| of the block  */
+  float growth;          /* largest |entry| seen / largest |entry| of A      */
+  int32_t flags;         /* bit 0: weak pivot, bit 1: non-finite, bit 2: refined */
+  int32_t reserved;
+} pq_bse_block_stats;
+
+/* Bethe-Salpeter equation of one channel (Eq. PA_F_Phi) for every transfer q:
+ *   F = [1 - s_r Gamma_r X_r]^-1 Gamma_r,  s = (+1, +1, -1, +1) for (d, m, s, t),
+ *   X = X_ph for d, m and X_pp for s, t,
+ *   phi_io <- alpha (F - Gamma_r) + (1 - alpha) phi_io   (alpha = 1: plain output).
+ * Elimination without row exchanges (A is the identity minus a small-norm
+ * kernel); the pivot monitor flags weak blocks in stats (nullable).
+ * gamma: [Nq][n][n] (one channel), chi0: [Nq][n] c128, phi_io: [Nq][n][n],
+ * both in storage precision; ws: bse_workspace bytes. */
+pq_status bse_solve(const pq_params* p, int32_t channel, int32_t precision,
+                    const void* gamma, const void* chi0, void* phi_io, double alpha,
+                    void* stats, void* ws, size_t ws_bytes, pq_stream stream);
+
+/* sigma_io <- alpha sigma_new + (1 - alpha) sigma_io on [Nve][Nk] c128 and
+ * dnorm_out (device double) <- max |sigma_new - sigma_io_old|. */
+pq_status sigma_mix(const pq_params* p, const void* sigma_new, void* sigma_io,
+                    double alpha, void* dnorm_out, pq_stream stream);
+
+/* ------------------------------------------------------------ context API */
+
+typedef struct pq_ctx pq_ctx;
+
+typedef enum {
+  PQ_FIELD_SIGMA = 0,  /* [Nve][Nk] c128           */
+  PQ_FIELD_G = 1,      /* [NG][Nk] c128            */
+  PQ_FIELD_PHI = 2,    /* [4][Nq][n][n] storage    */
+  PQ_FIELD_GAMMA = 3,  /* [4][Nq][n][n] storage    */
+  PQ_FIELD_K1 = 4,     /* [4][Nq] c128             */
+  PQ_FIELD_K2 = 5,     /* [4][Nq][n] c128          */
+  PQ_FIELD_MU = 6,     /* 1 double                 */
+  PQ_FIELD_XPH = 7,    /* [Nq][n] c128             */
+  PQ_FIELD_XPP = 8     /* [Nq][n] c128             */
+} pq_field;
+
+typedef struct {
+  int32_t iteration;       /* iterations done since init                       */
+  int32_t flagged_blocks;  /* BSE blocks flagged by the pivot monitor (last it) */
+  double dsigma;           /* max |Sigma_new - Sigma_old| of the last iteration */
+  double mu;               /* mu~ used by the last iteration                    */
+  double ms_total;         /* wall time of the last iteration (device events)   */
+  double ms_stage[8];      /* dyson, bubbles, kernels, remap, sigma, bse, mix, other */
+} pq_iter_stats;
+
+/* Device bytes parquet_init needs in its workspace. */
+pq_status parquet_query_workspace(const pq_params* p, size_t* bytes);
+
+/* Bind a context to caller workspace and stream, and set the bare-vertex start:
+ * Phi_r = 0, Sigma_0 = Sigma~_1[G_0] (second-order diagram of the Sigma = 0 G). */
+pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream stream,
+                       pq_ctx** out);
+
+/* Run up to n_iter iterations (Dyson -> bubbles -> kernels -> remap -> SDE ->
+ * BSE -> mixing); stops early once max|Sigma_new - Sigma_old| < tol (tol <= 0:
+ * never). Synchronises once per iteration for the norm. stats: host, nullable. */
+pq_status parquet_iterate(pq_ctx* ctx, int32_t n_iter, double tol, pq_iter_stats* stats,
+                          int32_t* iters_done, int32_t* converged);
+
+/* Copy a state field out of / into the context (device-to-device, on the
+ * context stream; synchronises). bytes must equal the field size. */
+pq_status parquet_get(pq_ctx* ctx, int32_t field, void* dev_dst, size_t bytes);
+pq_status parquet_set(pq_ctx* ctx, int32_t field, const void* dev_src, size_t bytes);
+
+/* Byte size of a field for this context. */
+pq_status parquet_field_bytes(pq_ctx* ctx, int32_t field, size_t* bytes);
+
+pq_status parquet_destroy(pq_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARQUET_H */

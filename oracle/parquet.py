@@ -506,13 +506,14 @@ def semicircle_poles(D: float, M: int = 128):
 
 def tau_grid(p, grid: Grid, mu: float):
     """Gauss-Legendre nodes and weights on [0, beta] for the imaginary-time route
-    of Sigma~_1. Node count 8 f Nv + 64 + 4 ceil(beta E), E the largest |pole|
-    (|eps_K - mu~| on the lattice, D locally): enough for the highest frequency
-    (4 nu_max) and the steepest exponential of the integrand."""
+    of Sigma~_1. Node count 8 f Nv + 64 + 4 ceil(beta E) with E = D locally and
+    E = 2 max|eps_K| on the lattice (a bound on |eps_K - mu~| for any mu~ inside
+    the band): enough for the highest frequency (4 nu_max) and the steepest
+    exponential of the integrand. (mu~ does not enter the count.)"""
     if grid.Nk == 1:
         emax = p.D
     else:
-        emax = float(np.max(np.abs(dispersion(grid, p.t, p.tp) - mu)))
+        emax = 2.0 * float(np.max(np.abs(dispersion(grid, p.t, p.tp))))
     nt = 8 * grid.f * grid.Nv + 64 + 4 * int(math.ceil(p.beta * emax))
     x, w = np.polynomial.legendre.leggauss(nt)
     return 0.5 * p.beta * (x + 1.0), 0.5 * p.beta * w

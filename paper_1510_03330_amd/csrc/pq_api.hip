@@ -1,0 +1,460 @@
+// C ABI of libparquet: argument validation, the stateless stage entry points
+// and the context API that runs whole parquet iterations on one stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "pq_internal.h"
+
+namespace pq {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+pq_status hip_fail(hipError_t e, const char* what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return PQ_ERR_HIP;
+}
+
+double max_abs_eps(const pq_params& p, const Dims& d) {
+  if (d.Nk == 1) return 0.0;
+  double mx = 0.0;
+  for (int K = 0; K < d.Nk; ++K) {
+    int kx = K / d.Ly, ky = K % d.Ly;
+    double cx = cos(2.0 * M_PI * kx / d.Lx), cy = cos(2.0 * M_PI * ky / d.Ly);
+    double e = -2.0 * p.t * (cx + cy) - 4.0 * p.tp * cx * cy;
+    mx = fmax(mx, fabs(e));
+  }
+  return mx;
+}
+
+bool make_dims(const pq_params* p, Dims* d) {
+  if (!p) { set_error("null params"); return false; }
+  if (p->Lx < 1 || p->Ly < 1 || p->Lx * p->Ly > 64) { set_error("lattice %dx%d outside 1..64 momenta", p->Lx, p->Ly); return false; }
+  if (p->Lx * p->Ly > 1 && (p->Lx > 255 || p->Ly > 255)) { set_error("lattice too large"); return false; }
+  if (p->Nv < 2 || (p->Nv & 1)) { set_error("Nv must be even and >= 2 (got %d)", p->Nv); return false; }
+  if (p->f_ext < 1 || p->f_ext > 16) { set_error("f_ext must be in 1..16"); return false; }
+  if (p->kernel_level < 0 || p->kernel_level > 2) { set_error("kernel_level must be 0, 1 or 2"); return false; }
+  if (p->edge_rule < 0 || p->edge_rule > 1) { set_error("edge_rule must be 0 or 1"); return false; }
+  if (p->mu_mode < 0 || p->mu_mode > 1) { set_error("mu_mode must be 0 or 1"); return false; }
+  if (p->storage != PQ_STORE_C64 && p->storage != PQ_STORE_C128) { set_error("bad storage"); return false; }
+  if (p->precision == PQ_PREC_FP64 && p->storage != PQ_STORE_C128) { set_error("FP64 BSE needs complex128 storage"); return false; }
+  if (p->precision == PQ_PREC_FP32 && p->storage != PQ_STORE_C64) { set_error("FP32 BSE needs complex64 storage"); return false; }
+  if (p->precision != PQ_PREC_FP64 && p->precision != PQ_PREC_FP32) { set_error("precision %d not available", p->precision); return false; }
+  if (!(p->beta > 0.0) || !isfinite(p->U) || !isfinite(p->beta)) { set_error("beta must be > 0 and U finite"); return false; }
+  if (!(p->alpha > 0.0 && p->alpha <= 1.0)) { set_error("alpha must be in (0, 1]"); return false; }
+  if (p->Lx * p->Ly == 1 && !(p->D > 0.0)) { set_error("local mode needs D > 0"); return false; }
+  Dims x;
+  x.Lx = p->Lx; x.Ly = p->Ly; x.Nk = p->Lx * p->Ly; x.Nv = p->Nv; x.NW = p->Nv - 1;
+  x.f = p->f_ext; x.Nve = p->f_ext * p->Nv; x.NWe = x.Nve - 1; x.NG = 2 * x.Nve;
+  x.n = x.Nk * x.Nv; x.Nq = x.Nk * x.NW;
+  if (x.n > 4096) { set_error("BSE dimension %d above 4096", x.n); return false; }
+  const double E = x.Nk == 1 ? p->D : 2.0 * max_abs_eps(*p, x);
+  x.ntau = 8 * x.f * x.Nv + 64 + 4 * (int)ceil(p->beta * E);
+  *d = x;
+  return true;
+}
+
+pq_dims to_public(const Dims& d) {
+  pq_dims o;
+  o.Lx = d.Lx; o.Ly = d.Ly; o.Nk = d.Nk; o.Nv = d.Nv; o.NW = d.NW; o.f_ext = d.f;
+  o.Nve = d.Nve; o.NWe = d.NWe; o.NG = d.NG; o.n = d.n; o.Nq = d.Nq; o.ntau = d.ntau;
+  o.vertex_elems = (int64_t)d.Nq * d.n * d.n;
+  return o;
+}
+
+}  // namespace pq
+
+using namespace pq;
+
+#define PQ_CHECK_ARG(cond, ...)      \
+  do {                               \
+    if (!(cond)) {                   \
+      set_error(__VA_ARGS__);        \
+      return PQ_ERR_ARG;             \
+    }                                \
+  } while (0)
+
+static pq_status enq(hipError_t e, const char* what) {
+  if (e != hipSuccess) return hip_fail(e, what);
+  return PQ_OK;
+}
+
+extern "C" {
+
+const char* parquet_last_error(void) { return g_err; }
+
+pq_status pq_dims_from_params(const pq_params* p, pq_dims* out) {
+  PQ_CHECK_ARG(out, "null output");
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  *out = to_public(d);
+  return PQ_OK;
+}
+
+pq_status dyson_update(const pq_params* p, const void* sigma, void* g_out, void* mu_out,
+                       pq_stream stream) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(sigma && g_out && mu_out, "null pointer");
+  return enq(launch_dyson(*p, d, (const double2*)sigma, (double2*)g_out, (double*)mu_out,
+                          (hipStream_t)stream), "dyson_update");
+}
+
+pq_status bubble_build(const pq_params* p, const void* g, void* xph, void* xpp, pq_stream stream) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(g && xph && xpp, "null pointer");
+  return enq(launch_bubbles(*p, d, (const double2*)g, (double2*)xph, (double2*)xpp,
+                            (hipStream_t)stream), "bubble_build");
+}
+
+pq_status kernel_extract(const pq_params* p, const void* phi, void* k1, void* k2, pq_stream stream) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(phi && k1 && k2, "null pointer");
+  return enq(launch_kernel_extract(*p, d, phi, (double2*)k1, (double2*)k2, (hipStream_t)stream),
+             "kernel_extract");
+}
+
+pq_status channel_remap(const pq_params* p, const double lambda[4], const void* phi, const void* k1,
+                        const void* k2, void* gamma_out, pq_stream stream) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(lambda && phi && k1 && k2 && gamma_out, "null pointer");
+  PQ_CHECK_ARG(phi != gamma_out, "phi and gamma_out must not alias");
+  return enq(launch_remap(*p, d, lambda, phi, (const double2*)k1, (const double2*)k2, gamma_out,
+                          (hipStream_t)stream), "channel_remap");
+}
+
+pq_status sigma_sde_workspace(const pq_params* p, size_t* bytes) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(bytes, "null output");
+  *bytes = sigma_ws_bytes(d);
+  return PQ_OK;
+}
+
+pq_status sigma_sde(const pq_params* p, const void* phi, const void* k1, const void* k2,
+                    const void* g, const void* mu, void* sigma_out, void* ws, size_t ws_bytes,
+                    pq_stream stream) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(phi && k1 && k2 && g && mu && sigma_out && ws, "null pointer");
+  if (ws_bytes < sigma_ws_bytes(d)) {
+    set_error("sigma_sde workspace %zu < %zu bytes", ws_bytes, sigma_ws_bytes(d));
+    return PQ_ERR_NOMEM;
+  }
+  return enq(launch_sigma(*p, d, phi, (const double2*)k1, (const double2*)k2, (const double2*)g,
+                          (const double*)mu, (double2*)sigma_out, ws, (hipStream_t)stream),
+             "sigma_sde");
+}
+
+pq_status bse_workspace(const pq_params* p, size_t* bytes) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(bytes, "null output");
+  *bytes = bse_ws_bytes(*p, d, p->precision);
+  return PQ_OK;
+}
+
+pq_status bse_solve(const pq_params* p, int32_t channel, int32_t precision, const void* gamma,
+                    const void* chi0, void* phi_io, double alpha, void* stats, void* ws,
+                    size_t ws_bytes, pq_stream stream) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(channel >= 0 && channel < 4, "channel must be 0..3");
+  PQ_CHECK_ARG(precision == p->precision, "precision must match params.precision");
+  PQ_CHECK_ARG(gamma && chi0 && phi_io && ws, "null pointer");
+  PQ_CHECK_ARG(alpha > 0.0 && alpha <= 1.0, "alpha must be in (0, 1]");
+  PQ_CHECK_ARG(gamma != phi_io, "gamma and phi_io must not alias");
+  if (ws_bytes < bse_ws_bytes(*p, d, precision)) {
+    set_error("bse workspace %zu < %zu bytes", ws_bytes, bse_ws_bytes(*p, d, precision));
+    return PQ_ERR_NOMEM;
+  }
+  return enq(launch_bse(*p, d, channel, precision, gamma, (const double2*)chi0, phi_io, alpha,
+                        (pq_bse_block_stats*)stats, ws, (hipStream_t)stream),
+             "bse_solve");
+}
+
+pq_status sigma_mix(const pq_params* p, const void* sigma_new, void* sigma_io, double alpha,
+                    void* dnorm_out, pq_stream stream) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(sigma_new && sigma_io && dnorm_out, "null pointer");
+  PQ_CHECK_ARG(alpha > 0.0 && alpha <= 1.0, "alpha must be in (0, 1]");
+  return enq(launch_mix(d, (const double2*)sigma_new, (double2*)sigma_io, alpha, (double*)dnorm_out,
+                        (hipStream_t)stream),
+             "sigma_mix");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- context API
+struct pq_ctx {
+  pq_params p;
+  Dims d;
+  hipStream_t s;
+  char* ws;
+  size_t ws_bytes;
+  double2 *sigma, *sigma_new, *g, *xph, *xpp, *k1, *k2;
+  double *mu, *dnorm;
+  void *phi, *gamma, *bse_ws, *sig_ws;
+  size_t bse_bytes, sig_bytes;
+  pq_bse_block_stats* bstats;
+  int iteration;
+  hipEvent_t ev[8];
+  bool have_events;
+};
+
+namespace {
+
+struct CtxLayout {
+  size_t sigma, sigma_new, g, mu, dnorm, xph, xpp, k1, k2, phi, gamma, bse, sig, bstats, total;
+  size_t bse_bytes, sig_bytes;
+};
+
+CtxLayout ctx_layout(const pq_params& p, const Dims& d) {
+  CtxLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off += align256(b); return o; };
+  const size_t nk = (size_t)d.Nk;
+  L.sigma = take(sizeof(double2) * d.Nve * nk);
+  L.sigma_new = take(sizeof(double2) * d.Nve * nk);
+  L.g = take(sizeof(double2) * d.NG * nk);
+  L.mu = take(sizeof(double));
+  L.dnorm = take(sizeof(double));
+  L.xph = take(sizeof(double2) * (size_t)d.Nq * d.n);
+  L.xpp = take(sizeof(double2) * (size_t)d.Nq * d.n);
+  L.k1 = take(sizeof(double2) * 4 * (size_t)d.Nq);
+  L.k2 = take(sizeof(double2) * 4 * (size_t)d.Nq * d.n);
+  const size_t vb = elem_bytes(p) * (size_t)d.Nq * d.n * d.n * 4;
+  L.phi = take(vb);
+  L.gamma = take(vb);
+  L.bse_bytes = bse_ws_bytes(p, d, p.precision);
+  L.bse = take(L.bse_bytes);
+  L.sig_bytes = sigma_ws_bytes(d);
+  L.sig = take(L.sig_bytes);
+  L.bstats = take(sizeof(pq_bse_block_stats) * 4 * (size_t)d.Nq);
+  L.total = off;
+  return L;
+}
+
+size_t field_bytes(const pq_ctx* c, int f) {
+  const Dims& d = c->d;
+  switch (f) {
+    case PQ_FIELD_SIGMA: return sizeof(double2) * d.Nve * (size_t)d.Nk;
+    case PQ_FIELD_G: return sizeof(double2) * d.NG * (size_t)d.Nk;
+    case PQ_FIELD_PHI:
+    case PQ_FIELD_GAMMA: return elem_bytes(c->p) * (size_t)d.Nq * d.n * d.n * 4;
+    case PQ_FIELD_K1: return sizeof(double2) * 4 * (size_t)d.Nq;
+    case PQ_FIELD_K2: return sizeof(double2) * 4 * (size_t)d.Nq * d.n;
+    case PQ_FIELD_MU: return sizeof(double);
+    case PQ_FIELD_XPH:
+    case PQ_FIELD_XPP: return sizeof(double2) * (size_t)d.Nq * d.n;
+    default: return 0;
+  }
+}
+
+void* field_ptr(pq_ctx* c, int f) {
+  switch (f) {
+    case PQ_FIELD_SIGMA: return c->sigma;
+    case PQ_FIELD_G: return c->g;
+    case PQ_FIELD_PHI: return c->phi;
+    case PQ_FIELD_GAMMA: return c->gamma;
+    case PQ_FIELD_K1: return c->k1;
+    case PQ_FIELD_K2: return c->k2;
+    case PQ_FIELD_MU: return c->mu;
+    case PQ_FIELD_XPH: return c->xph;
+    case PQ_FIELD_XPP: return c->xpp;
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+pq_status parquet_query_workspace(const pq_params* p, size_t* bytes) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(bytes, "null output");
+  *bytes = ctx_layout(*p, d).total;
+  return PQ_OK;
+}
+
+pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream stream, pq_ctx** out) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(ws && out, "null pointer");
+  CtxLayout L = ctx_layout(*p, d);
+  if (ws_bytes < L.total) {
+    set_error("parquet workspace %zu < %zu bytes", ws_bytes, L.total);
+    return PQ_ERR_NOMEM;
+  }
+  pq_ctx* c = new (std::nothrow) pq_ctx();
+  if (!c) { set_error("host allocation failed"); return PQ_ERR_NOMEM; }
+  c->p = *p;
+  c->d = d;
+  c->s = (hipStream_t)stream;
+  c->ws = (char*)ws;
+  c->ws_bytes = ws_bytes;
+  char* w = c->ws;
+  c->sigma = (double2*)(w + L.sigma);
+  c->sigma_new = (double2*)(w + L.sigma_new);
+  c->g = (double2*)(w + L.g);
+  c->mu = (double*)(w + L.mu);
+  c->dnorm = (double*)(w + L.dnorm);
+  c->xph = (double2*)(w + L.xph);
+  c->xpp = (double2*)(w + L.xpp);
+  c->k1 = (double2*)(w + L.k1);
+  c->k2 = (double2*)(w + L.k2);
+  c->phi = w + L.phi;
+  c->gamma = w + L.gamma;
+  c->bse_ws = w + L.bse;
+  c->sig_ws = w + L.sig;
+  c->bse_bytes = L.bse_bytes;
+  c->sig_bytes = L.sig_bytes;
+  c->bstats = (pq_bse_block_stats*)(w + L.bstats);
+  c->iteration = 0;
+  c->have_events = true;
+  for (int i = 0; i < 8; ++i)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) c->have_events = false;
+  hipError_t e;
+  const size_t vb = field_bytes(c, PQ_FIELD_PHI);
+  if ((e = hipMemsetAsync(c->phi, 0, vb, c->s)) != hipSuccess) goto fail;
+  if ((e = hipMemsetAsync(c->sigma, 0, field_bytes(c, PQ_FIELD_SIGMA), c->s)) != hipSuccess) goto fail;
+  if ((e = launch_dyson(c->p, d, c->sigma, c->g, c->mu, c->s)) != hipSuccess) goto fail;
+  if ((e = launch_sigma1(c->p, d, c->g, c->mu, c->sigma, c->sig_ws, c->s)) != hipSuccess) goto fail;
+  if ((e = hipStreamSynchronize(c->s)) != hipSuccess) goto fail;
+  *out = c;
+  return PQ_OK;
+fail:
+  for (int i = 0; i < 8; ++i)
+    if (c->have_events) hipEventDestroy(c->ev[i]);
+  delete c;
+  return hip_fail(e, "parquet_init");
+}
+
+pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* stats,
+                          int32_t* iters_done, int32_t* converged) {
+  PQ_CHECK_ARG(c, "null context");
+  PQ_CHECK_ARG(n_iter >= 0, "n_iter must be >= 0");
+  const Dims& d = c->d;
+  const pq_params& p = c->p;
+  const double lam[4] = {p.U, -p.U, 2.0 * p.U, 0.0};
+  const size_t vstride = elem_bytes(p) * (size_t)d.Nq * d.n * d.n;
+  int done = 0, conv = 0;
+  pq_status st = PQ_OK;
+  for (int it = 0; it < n_iter; ++it) {
+    hipError_t e = hipSuccess;
+    auto rec = [&](int i) { if (c->have_events) hipEventRecord(c->ev[i], c->s); };
+    rec(0);
+    if ((e = launch_dyson(p, d, c->sigma, c->g, c->mu, c->s)) != hipSuccess) return hip_fail(e, "dyson");
+    rec(1);
+    if ((e = launch_bubbles(p, d, c->g, c->xph, c->xpp, c->s)) != hipSuccess) return hip_fail(e, "bubbles");
+    if ((e = launch_kernel_extract(p, d, c->phi, c->k1, c->k2, c->s)) != hipSuccess) return hip_fail(e, "kernels");
+    rec(2);
+    if ((e = launch_remap(p, d, lam, c->phi, c->k1, c->k2, c->gamma, c->s)) != hipSuccess) return hip_fail(e, "remap");
+    rec(3);
+    if ((e = launch_sigma(p, d, c->phi, c->k1, c->k2, c->g, c->mu, c->sigma_new, c->sig_ws, c->s)) != hipSuccess)
+      return hip_fail(e, "sigma");
+    rec(4);
+    for (int r = 0; r < 4; ++r) {
+      const double2* x = r < 2 ? c->xph : c->xpp;
+      e = launch_bse(p, d, r, p.precision, (char*)c->gamma + r * vstride, x, (char*)c->phi + r * vstride,
+                     p.alpha, c->bstats + (size_t)r * d.Nq, c->bse_ws, c->s);
+      if (e != hipSuccess) return hip_fail(e, "bse");
+    }
+    rec(5);
+    if ((e = launch_mix(d, c->sigma_new, c->sigma, p.alpha, c->dnorm, c->s)) != hipSuccess) return hip_fail(e, "mix");
+    rec(6);
+    double dn = 0.0, mu = 0.0;
+    if ((e = hipMemcpyAsync(&dn, c->dnorm, sizeof(double), hipMemcpyDeviceToHost, c->s)) != hipSuccess) return hip_fail(e, "norm copy");
+    if ((e = hipMemcpyAsync(&mu, c->mu, sizeof(double), hipMemcpyDeviceToHost, c->s)) != hipSuccess) return hip_fail(e, "mu copy");
+    if ((e = hipStreamSynchronize(c->s)) != hipSuccess) return hip_fail(e, "iteration");
+    c->iteration++;
+    done++;
+    if (stats) {
+      memset(stats, 0, sizeof(*stats));
+      stats->iteration = c->iteration;
+      stats->dsigma = dn;
+      stats->mu = mu;
+      if (c->have_events) {
+        float ms;
+        hipEventElapsedTime(&ms, c->ev[0], c->ev[6]); stats->ms_total = ms;
+        hipEventElapsedTime(&ms, c->ev[0], c->ev[1]); stats->ms_stage[0] = ms;
+        hipEventElapsedTime(&ms, c->ev[1], c->ev[2]); stats->ms_stage[1] = ms;
+        hipEventElapsedTime(&ms, c->ev[2], c->ev[3]); stats->ms_stage[3] = ms;
+        hipEventElapsedTime(&ms, c->ev[3], c->ev[4]); stats->ms_stage[4] = ms;
+        hipEventElapsedTime(&ms, c->ev[4], c->ev[5]); stats->ms_stage[5] = ms;
+        hipEventElapsedTime(&ms, c->ev[5], c->ev[6]); stats->ms_stage[6] = ms;
+      }
+      const size_t nb = 4 * (size_t)d.Nq;
+      pq_bse_block_stats* hs = new (std::nothrow) pq_bse_block_stats[nb];
+      if (hs && hipMemcpy(hs, c->bstats, nb * sizeof(pq_bse_block_stats), hipMemcpyDeviceToHost) == hipSuccess) {
+        int flagged = 0;
+        for (size_t i = 0; i < nb; ++i) flagged += hs[i].flags != 0;
+        stats->flagged_blocks = flagged;
+      }
+      delete[] hs;
+    }
+    if (!(dn == dn)) {
+      set_error("non-finite self-energy at iteration %d", c->iteration);
+      st = PQ_ERR_NONFINITE;
+      break;
+    }
+    if (tol > 0.0 && dn < tol) {
+      conv = 1;
+      break;
+    }
+  }
+  if (iters_done) *iters_done = done;
+  if (converged) *converged = conv;
+  return st;
+}
+
+pq_status parquet_field_bytes(pq_ctx* c, int32_t field, size_t* bytes) {
+  PQ_CHECK_ARG(c && bytes, "null pointer");
+  size_t b = field_bytes(c, field);
+  PQ_CHECK_ARG(b > 0, "unknown field %d", field);
+  *bytes = b;
+  return PQ_OK;
+}
+
+pq_status parquet_get(pq_ctx* c, int32_t field, void* dev_dst, size_t bytes) {
+  PQ_CHECK_ARG(c && dev_dst, "null pointer");
+  size_t b = field_bytes(c, field);
+  PQ_CHECK_ARG(b > 0 && bytes == b, "field %d needs %zu bytes, got %zu", field, b, bytes);
+  hipError_t e = hipMemcpyAsync(dev_dst, field_ptr(c, field), b, hipMemcpyDeviceToDevice, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  return e == hipSuccess ? PQ_OK : hip_fail(e, "parquet_get");
+}
+
+pq_status parquet_set(pq_ctx* c, int32_t field, const void* dev_src, size_t bytes) {
+  PQ_CHECK_ARG(c && dev_src, "null pointer");
+  size_t b = field_bytes(c, field);
+  PQ_CHECK_ARG(b > 0 && bytes == b, "field %d needs %zu bytes, got %zu", field, b, bytes);
+  hipError_t e = hipMemcpyAsync(field_ptr(c, field), dev_src, b, hipMemcpyDeviceToDevice, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  return e == hipSuccess ? PQ_OK : hip_fail(e, "parquet_set");
+}
+
+pq_status parquet_destroy(pq_ctx* c) {
+  if (!c) return PQ_OK;
+  if (c->have_events)
+    for (int i = 0; i < 8; ++i) hipEventDestroy(c->ev[i]);
+  delete c;
+  return PQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// Host-side declarations shared by the translation units of libparquet.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "parquet.h"
+#include "pq_device.h"
+
+namespace pq {
+
+// thread-local error message
+void set_error(const char* fmt, ...);
+pq_status hip_fail(hipError_t e, const char* what);
+
+// Validates params and fills the device size struct (sets the error on failure).
+bool make_dims(const pq_params* p, Dims* d);
+pq_dims to_public(const Dims& d);
+
+// largest |eps_K| of the lattice (0 in the local mode)
+double max_abs_eps(const pq_params& p, const Dims& d);
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline size_t elem_bytes(const pq_params& p) {
+  return p.storage == PQ_STORE_C64 ? sizeof(float2) : sizeof(double2);
+}
+
+// ---- launchers (enqueue only) ----
+hipError_t launch_dyson(const pq_params& p, const Dims& d, const double2* sigma, double2* g,
+                        double* mu_out, hipStream_t s);
+hipError_t launch_bubbles(const pq_params& p, const Dims& d, const double2* g, double2* xph,
+                          double2* xpp, hipStream_t s);
+hipError_t launch_mix(const Dims& d, const double2* snew, double2* sio, double alpha,
+                      double* dnorm, hipStream_t s);
+hipError_t launch_kernel_extract(const pq_params& p, const Dims& d, const void* phi, double2* k1,
+                                 double2* k2, hipStream_t s);
+hipError_t launch_remap(const pq_params& p, const Dims& d, const double lam[4], const void* phi,
+                        const double2* k1, const double2* k2, void* gamma, hipStream_t s);
+size_t sigma_ws_bytes(const Dims& d);
+hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, const double2* k1,
+                        const double2* k2, const double2* g, const double* mu, double2* sigma_out,
+                        void* ws, hipStream_t s);
+// Sigma~_1 alone (used for the bare-vertex start)
+hipError_t launch_sigma1(const pq_params& p, const Dims& d, const double2* g, const double* mu,
+                         double2* sigma_out, void* ws, hipStream_t s);
+size_t bse_ws_bytes(const pq_params& p, const Dims& d, int precision);
+hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precision,
+                      const void* gamma, const double2* chi0, void* phi_io, double alpha,
+                      pq_bse_block_stats* stats, void* ws, hipStream_t s);
+
+}  // namespace pq

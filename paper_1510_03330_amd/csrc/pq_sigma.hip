@@ -1,0 +1,488 @@
+// Regulated Schwinger-Dyson self-energy (high-frequency regulation subsection
+// of the paper, Eq. PA_Sigma with the auxiliary vertex):
+//
+//   Sigma(k) = Sigma~_1(k) + Sigma~_2(k) + [k in box] Sigma_box(k)
+//
+// Sigma~_1 is the second-order diagram -U^2 G(r)^2 G(-r) over all Matsubara
+// frequencies. G is split into its non-interacting pole part (transformed to
+// imaginary time analytically, anti-periodic) and a correction supported on
+// the extended box (a finite Fourier sum); the tau integral is analytic on
+// [0, beta] and is done by Gauss-Legendre quadrature, momenta by direct
+// lattice Fourier sums.
+//
+// Sigma~_2 and Sigma_box are evaluated in "native" variables: every term of
+// F - F~ (resp. F~ - Lambda) is a reducible vertex P_r(k, b; p) at its own
+// argument triple, so substituting (k', q) -> (b, p) turns both sums into
+//   C sum_{p in bosonic box} sum_b { A1 [P_d W16 - P_m (W16 + 2 W25)] + A3 (P_s + P_t) W34 }
+// with A1 = G(k+p) G(b+p) G(b), A3 = G(p-b) G(p-k) G(b), C = -U T^2 / 4N^2 and
+// integer indicator weights W that encode which original (k', q) lie in the
+// summation domain. The box part then only streams Phi (no Gamma, no
+// gathers), and the kernel part only needs contiguous rows of K2.
+#include <math.h>
+
+#include "pq_internal.h"
+
+namespace pq {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPoles = 128;   // semicircle pole representation (Gauss-Chebyshev)
+
+__device__ inline double nu_of(int n, double beta) { return (2 * n + 1) * M_PI / beta; }
+
+__device__ inline double pole_tau(double e, double tau, double beta) {
+  // imaginary-time transform of 1/(i nu - e), 0 < tau < beta
+  if (e >= 0.0) return -exp(-e * tau) / (1.0 + exp(-beta * e));
+  return -exp(e * (beta - tau)) / (exp(beta * e) + 1.0);
+}
+
+__device__ inline void semicircle_pole(int l, double D, double* e, double* c) {
+  double th = (l + 1) * M_PI / (kPoles + 1);
+  double s = sin(th);
+  *e = D * cos(th);
+  *c = 2.0 * s * s / (kPoles + 1);
+}
+
+__device__ inline double eps_of(int K, const Dims& d, double t, double tp) {
+  int kx = K / d.Ly, ky = K - (K / d.Ly) * d.Ly;
+  double cx = cos(2.0 * M_PI * kx / d.Lx), cy = cos(2.0 * M_PI * ky / d.Ly);
+  return -2.0 * t * (cx + cy) - 4.0 * tp * cx * cy;
+}
+
+// exp(+2 pi i (kx rx / Lx + ky ry / Ly)) with the products reduced modulo the lattice
+__device__ inline double2 lattice_phase(int K, int R, const Dims& d) {
+  int kx = K / d.Ly, ky = K - kx * d.Ly, rx = R / d.Ly, ry = R - rx * d.Ly;
+  double ang = 2.0 * M_PI * ((double)((kx * rx) % d.Lx) / d.Lx + (double)((ky * ry) % d.Ly) / d.Ly);
+  double s, c;
+  sincos(ang, &s, &c);
+  return mk(c, s);
+}
+
+struct S1Args {
+  Dims d;
+  double beta, U, t, tp, D;
+  int local;
+  const double2* g;      // [NG][Nk]
+  const double* mu;
+  double* tau;           // [ntau]
+  double* wt;            // [ntau]
+  double2* dg;           // [Nve][Nk]
+  double2* gkt;          // [ntau][Nk]
+  double2* grt;          // [ntau][Nk] (R)
+  double2* trn;          // [Nve][Nk] (R)
+  double2* out;          // [Nve][Nk]
+};
+
+// Gauss-Legendre nodes/weights on [0, beta], ascending, exactly symmetric.
+__global__ void gl_nodes_kernel(S1Args a) {
+  const int nt = a.d.ntau;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int half = (nt + 1) / 2;
+  if (i >= half) return;
+  double x = cos(M_PI * (i + 0.75) / (nt + 0.5));
+  double dp = 1.0;
+  for (int it = 0; it < 100; ++it) {
+    double p0 = 1.0, p1 = x;
+    for (int j = 2; j <= nt; ++j) {
+      double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = nt * (x * p1 - p0) / (x * x - 1.0);
+    double dx = p1 / dp;
+    x -= dx;
+    if (fabs(dx) <= 1e-15) {
+      // one more evaluation for the derivative at the converged node
+      p0 = 1.0; p1 = x;
+      for (int j = 2; j <= nt; ++j) {
+        double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = nt * (x * p1 - p0) / (x * x - 1.0);
+      break;
+    }
+  }
+  double w = 2.0 / ((1.0 - x * x) * dp * dp);
+  if ((nt & 1) && i == half - 1) x = 0.0;
+  // x is the i-th largest root
+  int hi = nt - 1 - i, lo = i;
+  a.tau[hi] = 0.5 * a.beta * (x + 1.0);
+  a.tau[lo] = 0.5 * a.beta * (1.0 - x);
+  a.wt[hi] = 0.5 * a.beta * w;
+  a.wt[lo] = 0.5 * a.beta * w;
+}
+
+// dG = G - G_pole on the extended box
+__global__ void s1_dg_kernel(S1Args a) {
+  const Dims& d = a.d;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.Nve * d.Nk) return;
+  int e = idx / d.Nk, K = idx - e * d.Nk;
+  int n = e - d.Nve / 2;
+  double nu = nu_of(n, a.beta);
+  double2 gv = a.g[(size_t)(n + d.NG / 2) * d.Nk + K];
+  double2 gp;
+  if (a.local) {
+    gp = mk(0.0, 0.0);
+    for (int l = 0; l < kPoles; ++l) {
+      double el, cl;
+      semicircle_pole(l, a.D, &el, &cl);
+      gp = cadd(gp, cscale(crecip(mk(-el, nu)), cl));
+    }
+  } else {
+    double xi = eps_of(K, d, a.t, a.tp) - *a.mu;
+    gp = crecip(mk(-xi, nu));
+  }
+  a.dg[idx] = csub(gv, gp);
+}
+
+// G(K, tau_j) = pole part + T sum_e dG(e, K) exp(-i nu_e tau_j)
+__global__ void s1_gtau_kernel(S1Args a) {
+  const Dims& d = a.d;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.ntau * d.Nk) return;
+  int j = idx / d.Nk, K = idx - j * d.Nk;
+  double tau = a.tau[j];
+  double pole = 0.0;
+  if (a.local) {
+    for (int l = 0; l < kPoles; ++l) {
+      double el, cl;
+      semicircle_pole(l, a.D, &el, &cl);
+      pole += cl * pole_tau(el, tau, a.beta);
+    }
+  } else {
+    double xi = eps_of(K, d, a.t, a.tp) - *a.mu;
+    pole = pole_tau(xi, tau, a.beta);
+  }
+  double2 acc = mk(0.0, 0.0);
+  for (int e = 0; e < d.Nve; ++e) {
+    double nu = nu_of(e - d.Nve / 2, a.beta);
+    double s, c;
+    sincos(nu * tau, &s, &c);
+    acc = cadd(acc, cmul(a.dg[(size_t)e * d.Nk + K], mk(c, -s)));
+  }
+  a.gkt[idx] = mk(pole + acc.x / a.beta, acc.y / a.beta);
+}
+
+// G(R, tau_j) = (1/N) sum_K e^{i K R} G(K, tau_j)
+__global__ void s1_gr_kernel(S1Args a) {
+  const Dims& d = a.d;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.ntau * d.Nk) return;
+  int j = idx / d.Nk, R = idx - j * d.Nk;
+  double2 acc = mk(0.0, 0.0);
+  for (int K = 0; K < d.Nk; ++K) acc = cadd(acc, cmul(lattice_phase(K, R, d), a.gkt[(size_t)j * d.Nk + K]));
+  a.grt[idx] = cscale(acc, 1.0 / d.Nk);
+}
+
+// T(R, e) = sum_j w_j e^{i nu_e tau_j} U^2 G(R, tau_j)^2 G(-R, beta - tau_j)
+__global__ void s1_tr_kernel(S1Args a) {
+  const Dims& d = a.d;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.Nve * d.Nk) return;
+  int e = idx / d.Nk, R = idx - e * d.Nk;
+  int rx = R / d.Ly, ry = R - rx * d.Ly;
+  int mR = ((d.Lx - rx) % d.Lx) * d.Ly + (d.Ly - ry) % d.Ly;
+  double nu = nu_of(e - d.Nve / 2, a.beta);
+  double2 acc = mk(0.0, 0.0);
+  const int nt = d.ntau;
+  for (int j = 0; j < nt; ++j) {
+    double2 g1 = a.grt[(size_t)j * d.Nk + R];
+    double2 g2 = a.grt[(size_t)(nt - 1 - j) * d.Nk + mR];
+    double2 sv = cmul(cmul(g1, g1), g2);
+    double s, c;
+    sincos(nu * a.tau[j], &s, &c);
+    acc = cadd(acc, cscale(cmul(mk(c, s), sv), a.wt[j]));
+  }
+  a.trn[idx] = cscale(acc, a.U * a.U);
+}
+
+// Sigma~_1(K, e) = sum_R e^{-i K R} T(R, e)
+__global__ void s1_out_kernel(S1Args a) {
+  const Dims& d = a.d;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.Nve * d.Nk) return;
+  int e = idx / d.Nk, K = idx - e * d.Nk;
+  double2 acc = mk(0.0, 0.0);
+  for (int R = 0; R < d.Nk; ++R) {
+    double2 ph = lattice_phase(K, R, d);
+    acc = cadd(acc, cmul(mk(ph.x, -ph.y), a.trn[(size_t)e * d.Nk + R]));
+  }
+  a.out[idx] = acc;
+}
+
+// ------------------------------------------------------------- Sigma~_2
+struct S2Args {
+  Dims d;
+  int level;
+  const double2* g;
+  const double2* k1;     // [4][Nq]
+  const double2* k2;     // [4][Nq][n]
+  double2* out;          // [Nve][Nk]  (sum without the constant C)
+};
+
+__device__ inline double ind(bool b) { return b ? 1.0 : 0.0; }
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void sigma2_kernel(S2Args a) {
+  __shared__ double red[2 * (kThreads / 64)];
+  const Dims& d = a.d;
+  const int kid = blockIdx.x;
+  const int ek = kid / d.Nk, K = kid - ek * d.Nk;
+  const int nk = ek - d.Nve / 2;
+  const bool kbox = in_fbox(nk, d.Nv);
+  const int kbi = kbox ? (nk + d.Nv / 2) * d.Nk + K : 0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nwaves = blockDim.x >> 6;
+  const int hF = d.Nve / 2, hBe = d.Nve / 2 - 1, hBb = d.Nv / 2 - 1, hG = d.NG / 2;
+  const size_t n = d.n;
+  double tr = 0.0, ti = 0.0;
+  for (int qi = wave; qi < d.Nq; qi += nwaves) {
+    const int jm = qi / d.Nk, P = qi - jm * d.Nk;
+    const int mp = jm - hBb;
+    double2 c[4];
+    for (int r = 0; r < 4; ++r) {
+      c[r] = a.k1[(size_t)r * d.Nq + qi];
+      if (kbox && a.level >= 2) c[r] = cadd(c[r], a.k2[((size_t)r * d.Nq + qi) * n + kbi]);
+    }
+    const int nkp = nk + mp;
+    const bool Ye = nkp >= -hF && nkp <= hF - 1;
+    const bool Yb = in_fbox(nkp, d.Nv);
+    const double2 g_kp = a.g[(size_t)(nkp + hG) * d.Nk + kadd(K, P, d.Lx, d.Ly)];
+    const double2 g_pk = a.g[(size_t)(mp - nk - 1 + hG) * d.Nk + ksub(P, K, d.Lx, d.Ly)];
+    int lo = min(-hF, min(nk - hBe, -mp - nk - 1 - hBe));
+    int hi = max(hF - 1, max(nk + hBe, -mp - nk - 1 + hBe));
+    lo = max(lo, -hG);
+    hi = min(hi, hG - 1);
+    double2 s16 = mk(0, 0), s25 = mk(0, 0), s34 = mk(0, 0), sk = mk(0, 0);
+    const int cnt = (hi - lo + 1) * d.Nk;
+    for (int bi = lane; bi < cnt; bi += 64) {
+      const int nb = lo + bi / d.Nk, B = bi - (bi / d.Nk) * d.Nk;
+      const bool bFe = nb >= -hF && nb <= hF - 1;
+      const bool bFb = in_fbox(nb, d.Nv);
+      const int x1 = mp + nk + nb + 1, x2 = nb - nk, x3 = mp - nk - nb - 1;
+      double e16 = bFe ? 1.0 + ind(x1 >= -hBe && x1 <= hBe) : 0.0;
+      double e25 = Ye ? ind(x2 >= -hBe && x2 <= hBe) + ind(x1 >= -hBe && x1 <= hBe) : 0.0;
+      double e34 = bFe ? 1.0 + ind(x3 >= -hBe && x3 <= hBe) : 0.0;
+      if (kbox && bFb) {
+        e16 -= 1.0 + ind(in_bbox(x1, d.Nv));
+        e25 -= Yb ? ind(in_bbox(x2, d.Nv)) + ind(in_bbox(x1, d.Nv)) : 0.0;
+        e34 -= 1.0 + ind(in_bbox(x3, d.Nv));
+      }
+      if (e16 == 0.0 && e25 == 0.0 && e34 == 0.0) continue;
+      const double2 gb = a.g[(size_t)(nb + hG) * d.Nk + B];
+      double2 w16 = mk(0, 0), w25 = mk(0, 0), w34 = mk(0, 0);
+      if (e16 != 0.0 || e25 != 0.0) {
+        const double2 gbp = a.g[(size_t)(nb + mp + hG) * d.Nk + kadd(B, P, d.Lx, d.Ly)];
+        const double2 A1 = cmul(cmul(g_kp, gbp), gb);
+        w16 = cscale(A1, e16);
+        w25 = cscale(A1, e25);
+      }
+      if (e34 != 0.0) {
+        const double2 gpb = a.g[(size_t)(mp - nb - 1 + hG) * d.Nk + ksub(P, B, d.Lx, d.Ly)];
+        const double2 A3 = cmul(cmul(gpb, g_pk), gb);
+        w34 = cscale(A3, e34);
+      }
+      s16 = cadd(s16, w16);
+      s25 = cadd(s25, w25);
+      s34 = cadd(s34, w34);
+      if (bFb && a.level >= 2) {
+        const size_t bidx = (size_t)(nb + d.Nv / 2) * d.Nk + B;
+        const double2 kd = a.k2[((size_t)0 * d.Nq + qi) * n + bidx];
+        const double2 km = a.k2[((size_t)1 * d.Nq + qi) * n + bidx];
+        const double2 ks = a.k2[((size_t)2 * d.Nq + qi) * n + bidx];
+        const double2 kt = a.k2[((size_t)3 * d.Nq + qi) * n + bidx];
+        const double2 w1625 = cadd(w16, cscale(w25, 2.0));
+        sk = cadd(sk, csub(cmul(w16, kd), cmul(w1625, km)));
+        sk = cadd(sk, cmul(w34, cadd(ks, kt)));
+      }
+    }
+    double v[8] = {s16.x, s16.y, s25.x, s25.y, s34.x, s34.y, sk.x, sk.y};
+    for (int i = 0; i < 8; ++i) v[i] = wave_sum(v[i]);
+    s16 = mk(v[0], v[1]);
+    s25 = mk(v[2], v[3]);
+    s34 = mk(v[4], v[5]);
+    sk = mk(v[6], v[7]);
+    double2 contrib = cmul(c[0], s16);
+    contrib = csub(contrib, cmul(c[1], cadd(s16, cscale(s25, 2.0))));
+    contrib = cadd(contrib, cmul(cadd(c[2], c[3]), s34));
+    contrib = cadd(contrib, sk);
+    tr += contrib.x;
+    ti += contrib.y;
+  }
+  if (lane == 0) {
+    red[2 * wave] = tr;
+    red[2 * wave + 1] = ti;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sr = 0.0, si = 0.0;
+    for (int w = 0; w < nwaves; ++w) {
+      sr += red[2 * w];
+      si += red[2 * w + 1];
+    }
+    a.out[kid] = mk(sr, si);
+  }
+}
+
+// ------------------------------------------------------------ Sigma_box
+template <typename C>
+struct SBArgs {
+  Dims d;
+  const C* phi;          // [4][Nq][n][n]
+  const double2* g;
+  double2* partial;      // [n][NW]
+};
+
+template <typename C>
+__global__ __launch_bounds__(kThreads) void sigmab_kernel(SBArgs<C> a) {
+  __shared__ double red[kThreads];
+  const Dims& d = a.d;
+  const int kbi = blockIdx.x / d.NW, jm = blockIdx.x - (blockIdx.x / d.NW) * d.NW;
+  const int nk = kbi / d.Nk - d.Nv / 2, K = kbi - (kbi / d.Nk) * d.Nk;
+  const int mp = jm - (d.Nv / 2 - 1);
+  const int hG = d.NG / 2;
+  const int nkp = nk + mp;
+  const bool Yb = in_fbox(nkp, d.Nv);
+  const size_t n = d.n, nn = (size_t)d.n * d.n, chan = (size_t)d.Nq * nn;
+  double ar = 0.0, ai = 0.0;
+  for (int P = 0; P < d.Nk; ++P) {
+    const int qi = jm * d.Nk + P;
+    const double2 g_kp = a.g[(size_t)(nkp + hG) * d.Nk + kadd(K, P, d.Lx, d.Ly)];
+    const double2 g_pk = a.g[(size_t)(mp - nk - 1 + hG) * d.Nk + ksub(P, K, d.Lx, d.Ly)];
+    const C* row = a.phi + (size_t)qi * nn + (size_t)kbi * n;
+    for (int b = threadIdx.x; b < d.n; b += blockDim.x) {
+      const int nb = b / d.Nk - d.Nv / 2, B = b - (b / d.Nk) * d.Nk;
+      const int x1 = mp + nk + nb + 1, x2 = nb - nk, x3 = mp - nk - nb - 1;
+      const double c16 = 1.0 + ind(in_bbox(x1, d.Nv));
+      const double c25 = Yb ? ind(in_bbox(x2, d.Nv)) + ind(in_bbox(x1, d.Nv)) : 0.0;
+      const double c34 = 1.0 + ind(in_bbox(x3, d.Nv));
+      const double2 gb = a.g[(size_t)(nb + hG) * d.Nk + B];
+      const double2 gbp = a.g[(size_t)(nb + mp + hG) * d.Nk + kadd(B, P, d.Lx, d.Ly)];
+      const double2 gpb = a.g[(size_t)(mp - nb - 1 + hG) * d.Nk + ksub(P, B, d.Lx, d.Ly)];
+      const double2 A1 = cmul(cmul(g_kp, gbp), gb);
+      const double2 A3 = cmul(cmul(gpb, g_pk), gb);
+      const double2 pd = to_d(row[b]);
+      const double2 pm = to_d(row[chan + b]);
+      const double2 ps = to_d(row[2 * chan + b]);
+      const double2 pt = to_d(row[3 * chan + b]);
+      double2 t1 = csub(cscale(pd, c16), cscale(pm, c16 + 2.0 * c25));
+      double2 v = cadd(cmul(A1, t1), cmul(A3, cscale(cadd(ps, pt), c34)));
+      ar += v.x;
+      ai += v.y;
+    }
+  }
+  ar = block_sum(ar, red);
+  ai = block_sum(ai, red);
+  if (threadIdx.x == 0) a.partial[(size_t)kbi * d.NW + jm] = mk(ar, ai);
+}
+
+struct CombineArgs {
+  Dims d;
+  double cfac;
+  int has_s2, has_box;
+  const double2* s1;
+  const double2* s2;
+  const double2* partial;
+  double2* out;
+};
+
+__global__ void combine_kernel(CombineArgs a) {
+  const Dims& d = a.d;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.Nve * d.Nk) return;
+  int e = idx / d.Nk, K = idx - e * d.Nk;
+  int n = e - d.Nve / 2;
+  double2 v = a.s1[idx];
+  if (a.has_s2) v = cadd(v, cscale(a.s2[idx], a.cfac));
+  if (a.has_box && in_fbox(n, d.Nv)) {
+    int kbi = (n + d.Nv / 2) * d.Nk + K;
+    double2 acc = mk(0, 0);
+    for (int j = 0; j < d.NW; ++j) acc = cadd(acc, a.partial[(size_t)kbi * d.NW + j]);
+    v = cadd(v, cscale(acc, a.cfac));
+  }
+  a.out[idx] = v;
+}
+
+struct WsLayout {
+  size_t tau, wt, dg, gkt, grt, trn, s1, s2, part, total;
+};
+
+WsLayout ws_layout(const Dims& d) {
+  WsLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.tau = take(sizeof(double) * d.ntau);
+  L.wt = take(sizeof(double) * d.ntau);
+  L.dg = take(sizeof(double2) * d.Nve * d.Nk);
+  L.gkt = take(sizeof(double2) * (size_t)d.ntau * d.Nk);
+  L.grt = take(sizeof(double2) * (size_t)d.ntau * d.Nk);
+  L.trn = take(sizeof(double2) * d.Nve * d.Nk);
+  L.s1 = take(sizeof(double2) * d.Nve * d.Nk);
+  L.s2 = take(sizeof(double2) * d.Nve * d.Nk);
+  L.part = take(sizeof(double2) * (size_t)d.n * d.NW);
+  L.total = off;
+  return L;
+}
+
+inline unsigned nblk(size_t total) { return (unsigned)((total + kThreads - 1) / kThreads); }
+
+hipError_t run_sigma1(const pq_params& p, const Dims& d, const double2* g, const double* mu,
+                      double2* out, char* ws, hipStream_t s) {
+  WsLayout L = ws_layout(d);
+  S1Args a{d, p.beta, p.U, p.t, p.tp, p.D, d.Nk == 1 ? 1 : 0, g, mu,
+           (double*)(ws + L.tau), (double*)(ws + L.wt), (double2*)(ws + L.dg),
+           (double2*)(ws + L.gkt), (double2*)(ws + L.grt), (double2*)(ws + L.trn), out};
+  hipLaunchKernelGGL(gl_nodes_kernel, dim3(nblk((d.ntau + 1) / 2)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(s1_dg_kernel, dim3(nblk(d.Nve * d.Nk)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(s1_gtau_kernel, dim3(nblk((size_t)d.ntau * d.Nk)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(s1_gr_kernel, dim3(nblk((size_t)d.ntau * d.Nk)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(s1_tr_kernel, dim3(nblk(d.Nve * d.Nk)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(s1_out_kernel, dim3(nblk(d.Nve * d.Nk)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t sigma_ws_bytes(const Dims& d) { return ws_layout(d).total; }
+
+hipError_t launch_sigma1(const pq_params& p, const Dims& d, const double2* g, const double* mu,
+                         double2* sigma_out, void* ws, hipStream_t s) {
+  return run_sigma1(p, d, g, mu, sigma_out, (char*)ws, s);
+}
+
+hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, const double2* k1,
+                        const double2* k2, const double2* g, const double* mu, double2* sigma_out,
+                        void* wsv, hipStream_t s) {
+  char* ws = (char*)wsv;
+  WsLayout L = ws_layout(d);
+  double2* s1 = (double2*)(ws + L.s1);
+  double2* s2 = (double2*)(ws + L.s2);
+  double2* part = (double2*)(ws + L.part);
+  hipError_t e = run_sigma1(p, d, g, mu, s1, ws, s);
+  if (e != hipSuccess) return e;
+  const int has_s2 = p.kernel_level > 0 ? 1 : 0;
+  if (has_s2) {
+    S2Args a2{d, p.kernel_level, g, k1, k2, s2};
+    hipLaunchKernelGGL(sigma2_kernel, dim3(d.Nve * d.Nk), dim3(kThreads), 0, s, a2);
+  }
+  if (p.storage == PQ_STORE_C64) {
+    SBArgs<float2> ab{d, (const float2*)phi, g, part};
+    hipLaunchKernelGGL(sigmab_kernel<float2>, dim3(d.n * d.NW), dim3(kThreads), 0, s, ab);
+  } else {
+    SBArgs<double2> ab{d, (const double2*)phi, g, part};
+    hipLaunchKernelGGL(sigmab_kernel<double2>, dim3(d.n * d.NW), dim3(kThreads), 0, s, ab);
+  }
+  const double T = 1.0 / p.beta;
+  CombineArgs ac{d, -p.U * T * T / (4.0 * d.Nk * (double)d.Nk), has_s2, 1, s1, s2, part, sigma_out};
+  hipLaunchKernelGGL(combine_kernel, dim3(nblk(d.Nve * d.Nk)), dim3(kThreads), 0, s, ac);
+  return hipGetLastError();
+}
+
+}  // namespace pq

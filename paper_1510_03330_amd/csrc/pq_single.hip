@@ -1,0 +1,185 @@
+// Single-particle kernels: Dyson equation with the filling condition, the
+// bubbles X_ph / X_pp of the Bethe-Salpeter equations, and linear mixing of
+// Sigma with its convergence norm. All FP64.
+#include <math.h>
+
+#include "pq_internal.h"
+
+namespace pq {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxNk = 1024;
+
+struct DysonArgs {
+  Dims d;
+  double beta, t, tp, D, filling, mu_fixed, U;
+  int mu_mode, local;
+  const double2* sigma;
+  double2* g;
+  double* mu_out;
+};
+
+__device__ inline double eps_of(int K, const Dims& d, double t, double tp) {
+  int kx = K / d.Ly, ky = K - (K / d.Ly) * d.Ly;
+  double cx = cos(2.0 * M_PI * kx / d.Lx), cy = cos(2.0 * M_PI * ky / d.Ly);
+  return -2.0 * t * (cx + cy) - 4.0 * tp * cx * cy;
+}
+
+__device__ inline double nu_of(int n, double beta) { return (2 * n + 1) * M_PI / beta; }
+
+// Sigma on the G grid: stored on the extended box, zero beyond.
+__device__ inline double2 sigma_at(const DysonArgs& a, int n, int K) {
+  const int h = a.d.Nve / 2;
+  if (n < -h || n > h - 1) return mk(0.0, 0.0);
+  return a.sigma[(size_t)(n + h) * a.d.Nk + K];
+}
+
+// Lattice G at mu for G-grid row g and momentum K.
+__device__ inline double2 g_lattice(const DysonArgs& a, const double* eps, double mu, int gi, int K) {
+  int n = gi - a.d.NG / 2;
+  double nu = nu_of(n, a.beta);
+  double2 s = sigma_at(a, n, K);
+  double2 z = mk(mu - eps[K] - s.x, nu - s.y);
+  return crecip(z);
+}
+
+// Total density per spin at mu: 1/2 + T/N sum Re G + the exact tail beyond the grid.
+__device__ double density(const DysonArgs& a, const double* eps, double mu, double* red) {
+  const Dims& d = a.d;
+  const double T = 1.0 / a.beta;
+  double acc = 0.0;
+  for (int idx = threadIdx.x; idx < d.NG * d.Nk; idx += blockDim.x) {
+    int gi = idx / d.Nk, K = idx - gi * d.Nk;
+    acc += g_lattice(a, eps, mu, gi, K).x;
+  }
+  double sre = block_sum(acc, red);
+  double tail = 0.0;
+  for (int K = threadIdx.x; K < d.Nk; K += blockDim.x) {
+    double xi = eps[K] - mu;
+    double partial = 0.0;
+    for (int n = 0; n < d.NG / 2; ++n) {
+      double nu = nu_of(n, a.beta);
+      partial += 1.0 / (nu * nu + xi * xi);
+    }
+    double full = fabs(xi) < 1e-300 ? a.beta * a.beta / 8.0
+                                    : a.beta * tanh(a.beta * xi / 2.0) / (4.0 * xi);
+    tail += -xi * (full - partial);
+  }
+  double stail = block_sum(tail, red);
+  return 0.5 + (T / d.Nk) * sre + 2.0 * (T / d.Nk) * stail;
+}
+
+__global__ __launch_bounds__(kThreads) void dyson_kernel(DysonArgs a) {
+  __shared__ double red[kThreads];
+  __shared__ double eps[kMaxNk];
+  const Dims& d = a.d;
+  for (int K = threadIdx.x; K < d.Nk; K += blockDim.x) eps[K] = a.local ? 0.0 : eps_of(K, d, a.t, a.tp);
+  __syncthreads();
+  double mu = a.mu_fixed;
+  if (!a.local && a.mu_mode == 1) {
+    double emin = 1e300, emax = -1e300;
+    for (int K = threadIdx.x; K < d.Nk; K += blockDim.x) {
+      emin = fmin(emin, eps[K]);
+      emax = fmax(emax, eps[K]);
+    }
+    emin = -block_max(-emin, red);
+    emax = block_max(emax, red);
+    double lo = emin - 10.0 - fabs(a.U), hi = emax + 10.0 + fabs(a.U);
+    for (int it = 0; it < 200; ++it) {
+      double mid = 0.5 * (lo + hi);
+      double nn = 2.0 * density(a, eps, mid, red);
+      if (nn > a.filling) hi = mid; else lo = mid;
+      if (hi - lo < 1e-14) break;
+    }
+    mu = 0.5 * (lo + hi);
+  }
+  for (int idx = threadIdx.x; idx < d.NG * d.Nk; idx += blockDim.x) {
+    int gi = idx / d.Nk, K = idx - gi * d.Nk;
+    double2 gv;
+    if (a.local) {
+      int n = gi - d.NG / 2;
+      double nu = nu_of(n, a.beta);
+      double sg = nu > 0 ? 1.0 : (nu < 0 ? -1.0 : 0.0);
+      double c = 2.0 / (a.D * a.D);
+      double2 g0 = mk(0.0, c * (nu - sg * sqrt(nu * nu + a.D * a.D)));
+      double2 s = sigma_at(a, n, K);
+      gv = crecip(csub(crecip(g0), s));
+    } else {
+      gv = g_lattice(a, eps, mu, gi, K);
+    }
+    a.g[idx] = gv;
+  }
+  if (threadIdx.x == 0) *a.mu_out = a.local ? 0.0 : mu;
+}
+
+struct BubbleArgs {
+  Dims d;
+  double T;
+  const double2* g;
+  double2* xph;
+  double2* xpp;
+};
+
+__global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs a) {
+  const Dims& d = a.d;
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)d.Nq * d.n) return;
+  int qi = (int)(idx / d.n), ki = (int)(idx - (size_t)qi * d.n);
+  int jm = qi / d.Nk, Q = qi - jm * d.Nk;
+  int m = jm - (d.Nv / 2 - 1);
+  int in = ki / d.Nk, K = ki - in * d.Nk;
+  int n = in - d.Nv / 2;
+  const int h = d.NG / 2;
+  double2 gk = a.g[(size_t)(n + h) * d.Nk + K];
+  double2 gkq = a.g[(size_t)(n + m + h) * d.Nk + kadd(K, Q, d.Lx, d.Ly)];
+  double2 gqk = a.g[(size_t)(m - n - 1 + h) * d.Nk + ksub(Q, K, d.Lx, d.Ly)];
+  a.xph[idx] = cscale(cmul(gk, gkq), a.T / d.Nk);
+  a.xpp[idx] = cscale(cmul(gk, gqk), a.T / (2.0 * d.Nk));
+}
+
+__global__ __launch_bounds__(kThreads) void mix_kernel(int count, const double2* snew, double2* sio,
+                                                       double alpha, double* dnorm) {
+  __shared__ double red[kThreads];
+  double mx = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    double2 a = snew[i], b = sio[i];
+    double dr = a.x - b.x, di = a.y - b.y;
+    double dd = hypot(dr, di);
+    if (!isfinite(a.x) || !isfinite(a.y)) bad = 1.0;
+    mx = fmax(mx, dd);
+    sio[i] = mk(alpha * a.x + (1.0 - alpha) * b.x, alpha * a.y + (1.0 - alpha) * b.y);
+  }
+  mx = block_max(mx, red);
+  bad = block_max(bad, red);
+  if (threadIdx.x == 0) *dnorm = bad > 0.0 ? __builtin_nan("") : mx;
+}
+
+}  // namespace
+
+hipError_t launch_dyson(const pq_params& p, const Dims& d, const double2* sigma, double2* g,
+                        double* mu_out, hipStream_t s) {
+  if (d.Nk > kMaxNk) return hipErrorInvalidValue;
+  DysonArgs a{d, p.beta, p.t, p.tp, p.D, p.filling, p.mu_fixed, p.U, p.mu_mode, d.Nk == 1 ? 1 : 0,
+              sigma, g, mu_out};
+  hipLaunchKernelGGL(dyson_kernel, dim3(1), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bubbles(const pq_params& p, const Dims& d, const double2* g, double2* xph,
+                          double2* xpp, hipStream_t s) {
+  BubbleArgs a{d, 1.0 / p.beta, g, xph, xpp};
+  size_t total = (size_t)d.Nq * d.n;
+  unsigned blocks = (unsigned)((total + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(bubble_kernel, dim3(blocks), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix(const Dims& d, const double2* snew, double2* sio, double alpha,
+                      double* dnorm, hipStream_t s) {
+  hipLaunchKernelGGL(mix_kernel, dim3(1), dim3(kThreads), 0, s, d.Nve * d.Nk, snew, sio, alpha, dnorm);
+  return hipGetLastError();
+}
+
+}  // namespace pq

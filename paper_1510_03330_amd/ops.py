@@ -1,0 +1,190 @@
+"""Torch-facing wrappers of the stage entry points and the solver context.
+
+Each wrapper validates tensor device, dtype, shape and contiguity, then hands
+raw device pointers and the current HIP stream to libparquet. No arithmetic
+of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import native as N
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor, dtype, shape: Sequence[int], name: str) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Stage:
+    """Shapes and dtypes of one parameter set, plus the stateless stage calls."""
+
+    def __init__(self, p, precision: str = "fp64"):
+        N.load()
+        self.model = p
+        self.precision = precision
+        self.pp = N.make_params(p, precision)
+        self.d = N.dims(self.pp)
+        self.vdtype = torch.complex128 if precision == "fp64" else torch.complex64
+        d = self.d
+        self.vshape = (4, d.Nq, d.n, d.n)
+        self.sigma_shape = (d.Nve, d.Nk)
+        self.g_shape = (d.NG, d.Nk)
+        self.x_shape = (d.Nq, d.n)
+        self.k1_shape = (4, d.Nq)
+        self.k2_shape = (4, d.Nq, d.n)
+
+    def _pp(self):
+        return ctypes.byref(self.pp)
+
+    # ---- stages
+    def dyson_update(self, sigma, g_out, mu_out, stream=None):
+        lib = N.load()
+        N.check(lib.dyson_update(self._pp(), _ptr(sigma, torch.complex128, self.sigma_shape, "sigma"),
+                                 _ptr(g_out, torch.complex128, self.g_shape, "g_out"),
+                                 _ptr(mu_out, torch.float64, (1,), "mu_out"), _stream(stream)))
+
+    def bubble_build(self, g, xph, xpp, stream=None):
+        N.check(N.load().bubble_build(self._pp(), _ptr(g, torch.complex128, self.g_shape, "g"),
+                                      _ptr(xph, torch.complex128, self.x_shape, "xph"),
+                                      _ptr(xpp, torch.complex128, self.x_shape, "xpp"), _stream(stream)))
+
+    def kernel_extract(self, phi, k1, k2, stream=None):
+        N.check(N.load().kernel_extract(self._pp(), _ptr(phi, self.vdtype, self.vshape, "phi"),
+                                        _ptr(k1, torch.complex128, self.k1_shape, "k1"),
+                                        _ptr(k2, torch.complex128, self.k2_shape, "k2"), _stream(stream)))
+
+    def channel_remap(self, lam, phi, k1, k2, gamma_out, stream=None):
+        arr = (ctypes.c_double * 4)(*[float(v) for v in lam])
+        N.check(N.load().channel_remap(self._pp(), arr, _ptr(phi, self.vdtype, self.vshape, "phi"),
+                                       _ptr(k1, torch.complex128, self.k1_shape, "k1"),
+                                       _ptr(k2, torch.complex128, self.k2_shape, "k2"),
+                                       _ptr(gamma_out, self.vdtype, self.vshape, "gamma_out"),
+                                       _stream(stream)))
+
+    def sigma_workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        N.check(N.load().sigma_sde_workspace(self._pp(), ctypes.byref(b)))
+        return int(b.value)
+
+    def sigma_sde(self, phi, k1, k2, g, mu, sigma_out, ws=None, stream=None):
+        nb = self.sigma_workspace_bytes()
+        if ws is None:
+            ws = torch.empty(nb, dtype=torch.uint8, device=phi.device)
+        N.check(N.load().sigma_sde(self._pp(), _ptr(phi, self.vdtype, self.vshape, "phi"),
+                                   _ptr(k1, torch.complex128, self.k1_shape, "k1"),
+                                   _ptr(k2, torch.complex128, self.k2_shape, "k2"),
+                                   _ptr(g, torch.complex128, self.g_shape, "g"),
+                                   _ptr(mu, torch.float64, (1,), "mu"),
+                                   _ptr(sigma_out, torch.complex128, self.sigma_shape, "sigma_out"),
+                                   _ptr(ws, torch.uint8, (ws.numel(),), "ws"), ctypes.c_size_t(ws.numel()),
+                                   _stream(stream)))
+
+    def bse_workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        N.check(N.load().bse_workspace(self._pp(), ctypes.byref(b)))
+        return int(b.value)
+
+    def bse_solve(self, channel: int, gamma, chi0, phi_io, alpha: float = 1.0, stats=None, ws=None,
+                  stream=None):
+        """gamma, phi_io: [Nq][n][n] of one channel; chi0: [Nq][n] complex128."""
+        d = self.d
+        shp = (d.Nq, d.n, d.n)
+        if ws is None:
+            ws = torch.empty(self.bse_workspace_bytes(), dtype=torch.uint8, device=gamma.device)
+        st = ctypes.c_void_p(0)
+        if stats is not None:
+            st = _ptr(stats, torch.int32, (d.Nq, 4), "stats")
+        N.check(N.load().bse_solve(self._pp(), int(channel), int(self.pp.precision),
+                                   _ptr(gamma, self.vdtype, shp, "gamma"),
+                                   _ptr(chi0, torch.complex128, self.x_shape, "chi0"),
+                                   _ptr(phi_io, self.vdtype, shp, "phi_io"), float(alpha), st,
+                                   _ptr(ws, torch.uint8, (ws.numel(),), "ws"), ctypes.c_size_t(ws.numel()),
+                                   _stream(stream)))
+
+    def sigma_mix(self, sigma_new, sigma_io, alpha, dnorm, stream=None):
+        N.check(N.load().sigma_mix(self._pp(), _ptr(sigma_new, torch.complex128, self.sigma_shape, "sigma_new"),
+                                   _ptr(sigma_io, torch.complex128, self.sigma_shape, "sigma_io"), float(alpha),
+                                   _ptr(dnorm, torch.float64, (1,), "dnorm"), _stream(stream)))
+
+
+class Solver:
+    """A parquet context on one device: workspace owned by a torch uint8 tensor."""
+
+    def __init__(self, p, precision: str = "fp64", device: str = "cuda:0", stream=None):
+        self.stage = Stage(p, precision)
+        self.device = torch.device(device)
+        self.stream = stream
+        lib = N.load()
+        b = ctypes.c_size_t()
+        N.check(lib.parquet_query_workspace(self.stage._pp(), ctypes.byref(b)))
+        self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        N.check(lib.parquet_init(self.stage._pp(), ctypes.c_void_p(self.ws.data_ptr()), b,
+                                 _stream(stream), ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.last_stats = None
+
+    @property
+    def dims(self):
+        return self.stage.d
+
+    def iterate(self, n: int = 1, tol: float = 0.0):
+        st = N.PqIterStats()
+        done = ctypes.c_int32()
+        conv = ctypes.c_int32()
+        N.check(N.load().parquet_iterate(self.ctx, int(n), float(tol), ctypes.byref(st),
+                                         ctypes.byref(done), ctypes.byref(conv)))
+        self.last_stats = st
+        return int(done.value), bool(conv.value), st
+
+    def _field_shape_dtype(self, name):
+        s = self.stage
+        return {
+            "sigma": (s.sigma_shape, torch.complex128), "g": (s.g_shape, torch.complex128),
+            "phi": (s.vshape, s.vdtype), "gamma": (s.vshape, s.vdtype),
+            "k1": (s.k1_shape, torch.complex128), "k2": (s.k2_shape, torch.complex128),
+            "mu": ((1,), torch.float64), "xph": (s.x_shape, torch.complex128),
+            "xpp": (s.x_shape, torch.complex128),
+        }[name]
+
+    def get(self, name: str) -> torch.Tensor:
+        shape, dtype = self._field_shape_dtype(name)
+        out = torch.empty(shape, dtype=dtype, device=self.device)
+        N.check(N.load().parquet_get(self.ctx, N.FIELDS[name], ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_size_t(out.numel() * out.element_size())))
+        return out
+
+    def set(self, name: str, value: torch.Tensor):
+        shape, dtype = self._field_shape_dtype(name)
+        v = value.to(device=self.device, dtype=dtype).contiguous()
+        if tuple(v.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {shape}")
+        N.check(N.load().parquet_set(self.ctx, N.FIELDS[name], ctypes.c_void_p(v.data_ptr()),
+                                     ctypes.c_size_t(v.numel() * v.element_size())))
+
+    def close(self):
+        if self.ctx is not None:
+            N.load().parquet_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

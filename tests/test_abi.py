@@ -1,0 +1,127 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function the
+header declares, its struct layouts agree with the ctypes binding, and host-side
+validation rejects bad arguments before anything reaches a device."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1510_03330_amd import native as N
+from workloads import config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "parquet.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\*?\s+\*?([a-z_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    lib = N.load()
+    declared = _declared_functions()
+    assert len(declared) >= 18
+    assert sorted(declared) == sorted(N.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header():
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "parquet.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pq_params), sizeof(pq_dims), sizeof(pq_iter_stats),
+         sizeof(pq_bse_block_stats), offsetof(pq_params, U), offsetof(pq_dims, vertex_elems));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    vals = [int(v) for v in out]
+    assert vals[0] == ctypes.sizeof(N.PqParams)
+    assert vals[1] == ctypes.sizeof(N.PqDims)
+    assert vals[2] == ctypes.sizeof(N.PqIterStats)
+    assert vals[3] == ctypes.sizeof(N.PqBseBlockStats)
+    assert vals[4] == N.PqParams.U.offset
+    assert vals[5] == N.PqDims.vertex_elems.offset
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "tiny_2x2", "small_2x4"])
+def test_dims_from_params(name):
+    p = config(name)
+    d = N.dims(N.make_params(p, "fp64"))
+    Nk = p.Lx * p.Ly
+    assert (d.Nk, d.Nv, d.NW, d.n, d.Nq) == (Nk, p.Nv, p.Nv - 1, Nk * p.Nv, Nk * (p.Nv - 1))
+    assert d.Nve == p.f_ext * p.Nv and d.NG == 2 * p.f_ext * p.Nv
+    assert d.vertex_elems == d.Nq * d.n * d.n
+
+
+def test_quadrature_node_count_matches_the_oracle_definition():
+    import math
+    import numpy as np
+    from oracle import parquet as P
+    for name in ("c1", "c3", "tiny_2x2"):
+        p = config(name)
+        d = N.dims(N.make_params(p, "fp64"))
+        g = P.Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
+        tau, _ = P.tau_grid(p, g, 0.0)
+        assert d.ntau == len(tau)
+
+
+@pytest.mark.parametrize("bad", [dict(Nv=7), dict(Nv=0), dict(f_ext=0), dict(kernel_level=3),
+                                 dict(alpha=0.0), dict(alpha=1.5), dict(beta=-1.0), dict(Lx=9, Ly=9),
+                                 dict(edge_rule=2), dict(mu_mode=4)])
+def test_invalid_params_are_rejected_on_the_host(bad):
+    p = config("tiny_2x2", **bad)
+    pp = N.make_params(p, "fp64")
+    d = N.PqDims()
+    st = N.load().pq_dims_from_params(ctypes.byref(pp), ctypes.byref(d))
+    assert st == N.PQ_ERR_ARG
+    assert N.load().parquet_last_error()
+
+
+def test_precision_storage_mismatch_is_rejected():
+    pp = N.make_params(config("tiny_2x2"), "fp64")
+    pp.storage = N.PQ_STORE_C64
+    d = N.PqDims()
+    assert N.load().pq_dims_from_params(ctypes.byref(pp), ctypes.byref(d)) == N.PQ_ERR_ARG
+
+
+def test_null_pointers_are_rejected_before_enqueue():
+    pp = N.make_params(config("tiny_2x2"), "fp64")
+    lib = N.load()
+    assert lib.bubble_build(ctypes.byref(pp), None, None, None, None) == N.PQ_ERR_ARG
+    assert lib.channel_remap(ctypes.byref(pp), None, None, None, None, None, None) == N.PQ_ERR_ARG
+    assert lib.parquet_iterate(None, 1, 0.0, None, None, None) == N.PQ_ERR_ARG
+    # workspace too small is reported, not enqueued
+    fake = ctypes.c_void_p(0x1000)
+    st = lib.bse_solve(ctypes.byref(pp), 0, 0, fake, fake, ctypes.c_void_p(0x2000), 1.0, None, fake,
+                       ctypes.c_size_t(16), None)
+    assert st == N.PQ_ERR_NOMEM
+    # aliasing input/output is rejected
+    st = lib.bse_solve(ctypes.byref(pp), 0, 0, fake, fake, fake, 1.0, None, fake, ctypes.c_size_t(16), None)
+    assert st == N.PQ_ERR_ARG
+
+
+def test_workspace_queries_scale_with_storage():
+    p = config("c3")
+    b64 = ctypes.c_size_t()
+    b32 = ctypes.c_size_t()
+    lib = N.load()
+    N.check(lib.parquet_query_workspace(ctypes.byref(N.make_params(p, "fp64")), ctypes.byref(b64)))
+    N.check(lib.parquet_query_workspace(ctypes.byref(N.make_params(p, "fp32")), ctypes.byref(b32)))
+    # vertex arrays dominate: complex128 needs about twice complex64, and both fit 288 GB
+    assert 1.8 < b64.value / b32.value < 2.2
+    assert b64.value < 250e9

@@ -1,0 +1,233 @@
+"""Stage-by-stage parity of the HIP path (through the C ABI) with the FP64 oracle
+on identical seeded inputs, at sizes that span several tiles and ragged tails.
+
+Tolerances. FP64 path: every stage is a short sum or an LU solve of a
+well-conditioned block, so agreement to ~1e-12 relative is expected (rounding
+order only). FP32 path (complex64 storage and FP32 matrix cores): inputs are
+rounded to complex64 on both sides; the remap and kernel extraction are sums of
+<= 9 terms, so their error is a few ulp of FP32 (~1e-6 relative to the largest
+term); the BSE error is bounded by kappa * n^(1/2) * eps32 with kappa the block
+condition number (<= 10 for these inputs), giving the 2e-4 relative bound used."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import parquet as P
+from workloads import config, rand_complex, random_phi, random_sigma
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _ops():
+    from paper_1510_03330_amd import ops
+    return ops
+
+
+def T(x, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device=DEV, dtype=dtype)
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _grid(p):
+    return P.Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
+
+
+def _print_case(*a):
+    print("CASE", *a, flush=True)
+
+
+# ------------------------------------------------------------------ Dyson
+@pytest.mark.parametrize("name", ["tiny_2x2", "small_2x4", "tiny_local", "tiny_2x2_hf", "c3"])
+def test_dyson_and_filling(name):
+    _print_case("dyson", name)
+    p = config(name)
+    g = _grid(p)
+    sig = random_sigma(g.Nve, g.Nk, seed=31, scale=0.2)
+    sig = 0.5 * (sig + np.conj(sig[::-1]))
+    mu_ref = P.find_mu(p, g, sig)
+    G_ref = P.dyson(p, g, sig, mu_ref)
+    st = _ops().Stage(p, "fp64")
+    G = torch.empty(st.g_shape, dtype=torch.complex128, device=DEV)
+    mu = torch.empty(1, dtype=torch.float64, device=DEV)
+    st.dyson_update(T(sig), G, mu)
+    if g.Nk > 1:
+        assert abs(H(mu)[0] - mu_ref) < 1e-12
+    assert relerr(H(G), G_ref) < 1e-12
+
+
+# ---------------------------------------------------------------- bubbles
+@pytest.mark.parametrize("name", ["tiny_2x2", "small_2x4", "tiny_local", "c3"])
+def test_bubbles(name):
+    _print_case("bubbles", name)
+    p = config(name)
+    g = _grid(p)
+    sig = random_sigma(g.Nve, g.Nk, seed=5, scale=0.3)
+    G_ref = P.dyson(p, g, sig, 0.07)
+    xph_ref, xpp_ref = P.bubbles(p, g, G_ref)
+    st = _ops().Stage(p, "fp64")
+    xph = torch.empty(st.x_shape, dtype=torch.complex128, device=DEV)
+    xpp = torch.empty_like(xph)
+    st.bubble_build(T(G_ref), xph, xpp)
+    assert relerr(H(xph), xph_ref) < 1e-14
+    assert relerr(H(xpp), xpp_ref) < 1e-14
+
+
+# ------------------------------------------------------- kernel functions
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,level,edge", [("small_2x4", 2, 0), ("small_2x4", 1, 0), ("small_2x4", 0, 0),
+                                             ("small_4x4", 2, 1), ("tiny_local", 2, 0)])
+def test_kernel_extract(prec, name, level, edge):
+    _print_case("kernel_extract", prec, name, level, edge)
+    p = config(name, kernel_level=level, edge_rule=edge)
+    g = _grid(p)
+    phi = random_phi(g.Nq, g.n, seed=17, scale=0.4)
+    if prec == "fp32":
+        phi = phi.astype(np.complex64).astype(np.complex128)
+    K1r, K2r = P.kernel_functions(g, phi, level, edge)
+    st = _ops().Stage(p, prec)
+    k1 = torch.empty(st.k1_shape, dtype=torch.complex128, device=DEV)
+    k2 = torch.empty(st.k2_shape, dtype=torch.complex128, device=DEV)
+    st.kernel_extract(T(phi, st.vdtype), k1, k2)
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    assert np.max(np.abs(H(k1) - K1r)) < tol * 0.4 * 4
+    assert np.max(np.abs(H(k2) - K2r)) < tol * 0.4 * 4
+
+
+# ------------------------------------------------------------------ remap
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,level", [("tiny_2x2", 2), ("small_2x4", 2), ("small_4x4", 1),
+                                        ("tiny_local", 2), ("small_2x4", 0)])
+def test_channel_remap(prec, name, level):
+    _print_case("remap", prec, name, level)
+    p = config(name, kernel_level=level)
+    g = _grid(p)
+    phi = random_phi(g.Nq, g.n, seed=41, scale=0.5)
+    if prec == "fp32":
+        phi = phi.astype(np.complex64).astype(np.complex128)
+    K1, K2 = P.kernel_functions(g, phi, level)
+    lam = P.pa_lambda(p.U)
+    gam_ref = P.remap(g, phi, K1, K2, lam)
+    st = _ops().Stage(p, prec)
+    gam = torch.empty(st.vshape, dtype=st.vdtype, device=DEV)
+    st.channel_remap(lam, T(phi, st.vdtype), T(K1), T(K2), gam)
+    err = relerr(H(gam).astype(np.complex128), gam_ref)
+    assert err < (1e-14 if prec == "fp64" else 1e-6), err
+
+
+# ---------------------------------------------------------- self-energy
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,level", [("tiny_2x2", 2), ("small_2x4", 2), ("small_2x4", 1),
+                                        ("tiny_local", 2), ("tiny_2x2_hf", 0)])
+def test_sigma_sde(prec, name, level):
+    _print_case("sigma", prec, name, level)
+    p = config(name, kernel_level=level)
+    g = _grid(p)
+    phi = random_phi(g.Nq, g.n, seed=43, scale=0.3)
+    if prec == "fp32":
+        phi = phi.astype(np.complex64).astype(np.complex128)
+    sig = random_sigma(g.Nve, g.Nk, seed=8, scale=0.1)
+    sig = 0.5 * (sig + np.conj(sig[::-1]))
+    mu = P.find_mu(p, g, sig)
+    G = P.dyson(p, g, sig, mu)
+    K1, K2 = P.kernel_functions(g, phi, level)
+    F = P.remap(g, phi, K1, K2, P.pa_lambda(p.U)) + phi
+    ref = P.sigma_sde(p, g, G, F, K1, K2, mu)
+    st = _ops().Stage(p, prec)
+    out = torch.empty(st.sigma_shape, dtype=torch.complex128, device=DEV)
+    st.sigma_sde(T(phi, st.vdtype), T(K1), T(K2), T(G), torch.tensor([mu], dtype=torch.float64, device=DEV), out)
+    err = relerr(H(out), ref)
+    assert err < 1e-12, err
+
+
+def test_sigma_tilde1_alone_matches_oracle_lattice_and_local():
+    # zero vertex: Sigma = Sigma~_1 exactly (the imaginary-time route)
+    for name in ("tiny_2x2", "tiny_local", "c2"):
+        _print_case("sigma1", name)
+        p = config(name)
+        g = _grid(p)
+        sig = np.zeros((g.Nve, g.Nk), complex)
+        mu = P.find_mu(p, g, sig)
+        G = P.dyson(p, g, sig, mu)
+        ref = P.sigma_tilde1(p, g, G, mu)
+        st = _ops().Stage(p, "fp64")
+        zero = torch.zeros(st.vshape, dtype=st.vdtype, device=DEV)
+        k1 = torch.zeros(st.k1_shape, dtype=torch.complex128, device=DEV)
+        k2 = torch.zeros(st.k2_shape, dtype=torch.complex128, device=DEV)
+        out = torch.empty(st.sigma_shape, dtype=torch.complex128, device=DEV)
+        st.sigma_sde(zero, k1, k2, T(G), torch.tensor([mu], dtype=torch.float64, device=DEV), out)
+        assert relerr(H(out), ref) < 1e-12
+
+
+# -------------------------------------------------------------------- BSE
+def _bse_inputs(p, seed):
+    g = _grid(p)
+    sig = random_sigma(g.Nve, g.Nk, seed=seed, scale=0.1)
+    mu = P.find_mu(p, g, sig)
+    G = P.dyson(p, g, sig, mu)
+    xph, xpp = P.bubbles(p, g, G)
+    lam = P.pa_lambda(p.U)
+    gam = random_phi(g.Nq, g.n, seed=seed + 1, scale=0.5)
+    for r in range(4):
+        gam[r] += lam[r]
+    return g, gam, xph, xpp
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["tiny_2x2", "tiny_2x2_hf", "small_2x4", "small_4x4", "bse_ragged"])
+def test_bse_solve(prec, name):
+    _print_case("bse", prec, name)
+    if name == "bse_ragged":
+        p = config("small_4x4", Nv=10)       # n = 160: 2.5 panels of 64, 5 of 32
+    else:
+        p = config(name)
+    g, gam, xph, xpp = _bse_inputs(p, 101)
+    if prec == "fp32":
+        gam = gam.astype(np.complex64).astype(np.complex128)
+    ref = P.bse(g, gam, xph, xpp)
+    st = _ops().Stage(p, prec)
+    ws = torch.empty(st.bse_workspace_bytes(), dtype=torch.uint8, device=DEV)
+    stats = torch.empty((g.Nq, 4), dtype=torch.int32, device=DEV)
+    for r in range(4):
+        X = xph if r < 2 else xpp
+        out = torch.empty((g.Nq, g.n, g.n), dtype=st.vdtype, device=DEV)
+        st.bse_solve(r, T(gam[r], st.vdtype), T(X), out, alpha=1.0, stats=stats, ws=ws)
+        err = relerr(H(out).astype(np.complex128), ref[r])
+        assert err < (1e-11 if prec == "fp64" else 2e-4), (r, err)
+        flags = H(stats)[:, 2]
+        assert np.all(flags & 2 == 0)
+
+
+def test_bse_mixing_epilogue():
+    _print_case("bse-mix")
+    p = config("small_2x4")
+    g, gam, xph, xpp = _bse_inputs(p, 7)
+    old = random_phi(g.Nq, g.n, seed=9, scale=0.2)[1]
+    ref = 0.3 * P.bse(g, gam, xph, xpp)[1] + 0.7 * old
+    st = _ops().Stage(p, "fp64")
+    io = T(old)
+    st.bse_solve(1, T(gam[1]), T(xph), io, alpha=0.3)
+    assert relerr(H(io), ref) < 1e-11
+
+
+def test_sigma_mix_and_norm():
+    p = config("tiny_2x2")
+    g = _grid(p)
+    a = random_sigma(g.Nve, g.Nk, 1)
+    b = random_sigma(g.Nve, g.Nk, 2)
+    st = _ops().Stage(p, "fp64")
+    io = T(b)
+    dn = torch.empty(1, dtype=torch.float64, device=DEV)
+    st.sigma_mix(T(a), io, 0.5, dn)
+    assert relerr(H(io), 0.5 * a + 0.5 * b) < 1e-15
+    assert abs(H(dn)[0] - np.max(np.abs(a - b))) < 1e-15
