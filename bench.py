@@ -36,6 +36,21 @@ def bse_flops_per_launch(d) -> float:
     return d.Nq * (32.0 / 3.0) * float(d.n) ** 3
 
 
+def measured_traffic():
+    """HBM bytes per BSE launch from the committed counter runs, or None when the
+    kernel source has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "bse_traffic_8x8_nv16_c64.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_dispatch"]
+
+
 def run_gpu(p, precision, steps, warmup):
     import torch
     from paper_1510_03330_amd.ops import Solver
@@ -162,6 +177,8 @@ def main():
     ap.add_argument("--ttc", action="store_true", help="also measure time to converged Sigma (1e-6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c3")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 2 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU q-sharding "
@@ -170,6 +187,14 @@ def main():
 
     from workloads import config
     p = config(args.workload)
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float64, device="cuda:0")   # 2 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
 
     print(f"[bench] fp32 path: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     r32 = run_gpu(p, "fp32", args.steps, args.warmup)
@@ -183,7 +208,7 @@ def main():
     launch_ms = sum(r32["bse_ms"]) / len(r32["bse_ms"]) / 4.0
     achieved = flops / (launch_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": None,
+            "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(),
             "kernel": "bse_gj_kernel<float,64> (one launch = one channel, %d blocks of n=%d)" % (d.Nq, d.n),
             "avg_launch_ms": round(launch_ms, 3), "algorithmic_flops_per_launch": flops}
 
