@@ -3,27 +3,33 @@
 //     A F = Gamma,   A = 1 - s Gamma diag(X),
 // followed by Phi <- alpha (F - Gamma) + (1 - alpha) Phi.
 //
-// One workgroup owns one q block for its whole life (persistent per block):
-// blocked Gauss-Jordan elimination on the augmented [A | B] (B = Gamma) with
-// panel width NB and no row exchanges. Per panel J:
-//   (a) factor the NB x NB diagonal block in LDS, A_JJ = L_JJ U_JJ, and invert
-//       both triangular factors in LDS;
-//   (b) row panel    U_JK = L_JJ^-1 A_JK for every column right of the panel in
-//       A and every column of B;
-//   (c) multipliers  M_IJ = A_IJ U_JJ^-1 for every row, stored k-major
-//       (MT[k][i] = (U_JJ^-T A_IJ^T)[k][i]) so matrix-core operand loads coalesce;
-//   (d) update       A_IK -= M_IJ U_JK, B_I -= M_IJ U_JB for all rows I != J.
-// After the last panel every row block satisfies U_JJ F_J = B_J, and
-// F_J = U_JJ^-1 B_J is fused with the Phi epilogue. Steps (b), (c), (d) and the
-// final solve are complex products on the matrix cores, built from four real
-// MFMAs per complex product: v_mfma_f32_32x32x2f32 (complex64) or
-// v_mfma_f64_16x16x4f64 (complex128), each wave owning 32 x 32 output tiles.
+// Blocked Gauss-Jordan elimination on the augmented [A | B] (B = Gamma) with
+// panel width NB and no row exchanges, batched over all q blocks of a channel:
+// every step is one kernel launch over (q block, tile) grids. Per panel J:
+//   (a) bse_diag:   factor the NB x NB diagonal block in LDS, A_JJ = L_JJ U_JJ,
+//                   and invert both triangular factors (one workgroup per block);
+//   (b) bse_panel:  row panel U_JK = L_JJ^-1 A_JK for every column right of the
+//                   panel in A and every column of B (in place, row tiles
+//                   bottom-up), and
+//   (c)             multipliers M_IJ = A_IJ U_JJ^-1 for every row, stored k-major
+//                   (MT[k][i] = (U_JJ^-T A_IJ^T)[k][i]) so operand loads coalesce;
+//   (d) bse_update: A_IK -= M_IJ U_JK, B_I -= M_IJ U_JB for all rows I != J, a
+//                   rank-NB update; each wave owns a 64 x 32 (complex64) or
+//                   32 x 32 (complex128) tile and reads both operands straight
+//                   from L1/L2, so no LDS is needed and four waves share a SIMD.
+// After the last panel every row block satisfies U_JJ F_J = B_J; bse_final
+// applies F_J = U_JJ^-1 B_J fused with the Phi epilogue. Steps (b)-(d) and the
+// final solve are complex products on the matrix cores, four real MFMAs per
+// complex product: v_mfma_f32_32x32x2f32 (complex64) or v_mfma_f64_16x16x4f64
+// (complex128).
 //
 // No row exchanges: A is the identity minus the small-norm kernel s Gamma X,
 // and every leading principal block of it stays invertible while the BSE is
 // away from its instability. The pivot monitor records min|u_jj| / max|u_jj|
 // per block and flags weak or non-finite blocks.
 #include <float.h>
+
+#include <algorithm>
 
 #include "pq_internal.h"
 
@@ -67,12 +73,12 @@ template <> struct Mma<double> {  // v_mfma_f64_16x16x4f64
   }
 };
 
-// A 32 x 32 complex output tile owned by one wave.
-template <typename T>
+// A WM x WN complex output tile owned by one wave (default 32 x 32).
+template <typename T, int WM = 32, int WN = 32>
 struct WTile {
   using M = Mma<T>;
   using C = typename cplx_of<T>::type;
-  static constexpr int SR = 32 / M::TM, SC = 32 / M::TN;
+  static constexpr int SR = WM / M::TM, SC = WN / M::TN;
   typename M::acc_t re[SR][SC], im[SR][SC];
 
   __device__ void zero() {
@@ -125,22 +131,6 @@ struct WTile {
         im[x][y] = M::mma(sub ? -ai : ai, b[y].x, im[x][y]);
       }
   }
-};
-
-template <typename T>
-struct BseArgs {
-  using C = typename cplx_of<T>::type;
-  Dims d;
-  T sign;
-  double alpha;
-  float weak_ratio;
-  const C* gamma;        // [Nq][n][n]
-  const double2* chi0;   // [Nq][n]
-  C* phi;                // [Nq][n][n]
-  C* A;                  // workspace [Nq][n][n]
-  C* B;                  // workspace [Nq][n][n]
-  C* MT;                 // workspace [Nq][NB][n]
-  pq_bse_block_stats* stats;
 };
 
 template <typename C> __device__ inline C cz();
@@ -245,35 +235,39 @@ __device__ void invert_upper(C (*D)[NB + 1], C (*X)[NB + 1], int jb) {
   }
 }
 
-template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void bse_gj_kernel(BseArgs<T> a) {
-  using C = typename cplx_of<T>::type;
-  using M = Mma<T>;
-  using WT = WTile<T>;
-  constexpr int SR = WT::SR, SC = WT::SC, KSTEPS = NB / M::KS;
-  // LDS arena: the diagonal block D and X (L^-1 in step (b), U^-1 in step (c) and
-  // the final solve) during steps (a)-(c); the 128-row multiplier strip S[k][i]
-  // during step (d).
-  constexpr size_t kDiagBytes = 2 * sizeof(C) * NB * (NB + 1);
-  constexpr size_t kStripBytes = sizeof(C) * NB * 128;
-  __shared__ __align__(16) char arena[kDiagBytes > kStripBytes ? kDiagBytes : kStripBytes];
-  C (*D)[NB + 1] = (C (*)[NB + 1])arena;
-  C (*X)[NB + 1] = (C (*)[NB + 1])(arena + sizeof(C) * NB * (NB + 1));
-  C (*S)[128] = (C (*)[128])arena;
-  __shared__ double pst[3];
-  const int n = a.d.n;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int qi = blockIdx.x;
-  const size_t nn = (size_t)n * n;
-  const C* G = a.gamma + (size_t)qi * nn;
-  C* A = a.A + (size_t)qi * nn;
-  C* B = a.B + (size_t)qi * nn;
-  C* MT = a.MT + (size_t)qi * NB * n;
-  const double2* x = a.chi0 + (size_t)qi * n;
 
-  // A = 1 - s Gamma diag(X), B = Gamma
-  for (size_t idx = t; idx < nn; idx += blockDim.x) {
+template <typename T>
+struct BseCtx {
+  using C = typename cplx_of<T>::type;
+  int n, Nq, nJ;
+  T sign;
+  double alpha;
+  float weak_ratio;
+  const C* gamma;        // [Nq][n][n]
+  const double2* chi0;   // [Nq][n]
+  C* phi;                // [Nq][n][n]
+  C* A;                  // [Nq][n][n]
+  C* B;                  // [Nq][n][n]
+  C* MT;                 // [Nq][NB][n]
+  C* LI;                 // [Nq][NB][NB]   L^-1 of the current panel
+  C* UI;                 // [Nq][nJ][NB][NB] U^-1 of every panel
+  double* pst;           // [Nq][4]  min |pivot|, max |pivot|, non-finite seen
+  pq_bse_block_stats* stats;
+};
+
+// ------------------------------------------------------------------- init
+// A = 1 - s Gamma diag(X), B = Gamma
+template <typename T>
+__global__ __launch_bounds__(kThreads) void bse_init_kernel(BseCtx<T> a) {
+  using C = typename cplx_of<T>::type;
+  const int blk = blockIdx.y;
+  const int n = a.n;
+  const size_t nn = (size_t)n * n;
+  const C* G = a.gamma + (size_t)blk * nn;
+  C* A = a.A + (size_t)blk * nn;
+  C* B = a.B + (size_t)blk * nn;
+  const double2* x = a.chi0 + (size_t)blk * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn; idx += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
     const C g = G[idx];
     const double2 xv = x[j];
@@ -284,32 +278,77 @@ void bse_gj_kernel(BseArgs<T> a) {
     A[idx] = v;
     B[idx] = g;
   }
-  if (t == 0) { pst[0] = DBL_MAX; pst[1] = 0.0; pst[2] = 0.0; }
-  __threadfence_block();
-  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double* ps = a.pst + (size_t)blk * 4;
+    ps[0] = DBL_MAX;
+    ps[1] = 0.0;
+    ps[2] = 0.0;
+  }
+}
 
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int jb = min(NB, n - j0);
-    const int ncols = (n - j0 - jb) + n;
-    // (a) diagonal block: factor and invert
-    for (int idx = t; idx < NB * NB; idx += blockDim.x) {
-      const int r = idx / NB, c = idx - (idx / NB) * NB;
-      D[r][c] = (r < jb && c < jb) ? A[(size_t)(j0 + r) * n + j0 + c] : cz<C>();
-    }
-    __syncthreads();
-    factor_block<C, NB>(D, jb, pst);
-    invert_lower<C, NB>(D, X, jb);
-    for (int idx = t; idx < jb * jb; idx += blockDim.x) {
-      const int r = idx / jb, c = idx - (idx / jb) * jb;
-      A[(size_t)(j0 + r) * n + j0 + c] = D[r][c];
-    }
-    // (b) U_JK = L^-1 A_JK: each wave owns 32-column strips, all NB rows
-    for (int cs = wave; cs * 32 < ncols; cs += kWaves) {
-      WT acc[NB / 32];
-#pragma unroll
-      for (int rt = 0; rt < NB / 32; ++rt) acc[rt].zero();
+// ------------------------------------------------------------------- diag
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void bse_diag_kernel(BseCtx<T> a, int j0) {
+  using C = typename cplx_of<T>::type;
+  __shared__ C D[NB][NB + 1];
+  __shared__ C X[NB][NB + 1];
+  __shared__ double pst[3];
+  const int blk = blockIdx.x, t = threadIdx.x, n = a.n;
+  const int jb = min(NB, n - j0);
+  C* A = a.A + (size_t)blk * n * n;
+  double* gps = a.pst + (size_t)blk * 4;
+  if (t < 3) pst[t] = gps[t];
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+    const int r = idx / NB, c = idx - (idx / NB) * NB;
+    D[r][c] = (r < jb && c < jb) ? A[(size_t)(j0 + r) * n + j0 + c] : cz<C>();
+  }
+  __syncthreads();
+  factor_block<C, NB>(D, jb, pst);
+  for (int idx = t; idx < jb * jb; idx += blockDim.x) {
+    const int r = idx / jb, c = idx - (idx / jb) * jb;
+    A[(size_t)(j0 + r) * n + j0 + c] = D[r][c];
+  }
+  invert_lower<C, NB>(D, X, jb);
+  C* LI = a.LI + (size_t)blk * NB * NB;
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) LI[idx] = X[idx / NB][idx % NB];
+  __syncthreads();
+  invert_upper<C, NB>(D, X, jb);
+  C* UI = a.UI + ((size_t)blk * a.nJ + j0 / NB) * NB * NB;
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) UI[idx] = X[idx / NB][idx % NB];
+  if (t < 3) gps[t] = pst[t];
+}
+
+// ------------------------------------------------------------------ panel
+// x < nwb: row-panel workgroups, 4 column strips of 32 each (one per wave);
+// x >= nwb: multiplier workgroups, 4 row strips of 32 each.
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
+  using C = typename cplx_of<T>::type;
+  using M = Mma<T>;
+  using WT = WTile<T>;
+  constexpr int SR = WT::SR, SC = WT::SC, KSTEPS = NB / M::KS;
+  __shared__ C X[NB][NB + 1];
+  const int blk = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
+  const int jb = min(NB, n - j0);
+  const int ncols = (n - j0 - jb) + n;
+  C* A = a.A + (size_t)blk * n * n;
+  C* B = a.B + (size_t)blk * n * n;
+  const bool rowpanel = (int)blockIdx.x < nwb;
+  const C* src = rowpanel ? a.LI + (size_t)blk * NB * NB : a.UI + ((size_t)blk * a.nJ + j0 / NB) * NB * NB;
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) X[idx / NB][idx % NB] = src[idx];
+  __syncthreads();
+  if (rowpanel) {
+    // U_JK = L^-1 A_JK in place; row tile rt of L^-1 A reads input rows only up
+    // to the end of tile rt, so the tiles go bottom-up.
+    const int cs = blockIdx.x * kWaves + wave;
+    if (cs * 32 >= ncols) return;
+    for (int rt = NB / 32 - 1; rt >= 0; --rt) {
+      WT acc;
+      acc.zero();
+      const int kend = min(jb, rt * 32 + 32);
 #pragma unroll 2
       for (int ks = 0; ks < KSTEPS; ++ks) {
+        if (ks * M::KS >= kend) break;
         C bv[SC];
 #pragma unroll
         for (int y = 0; y < SC; ++y) {
@@ -317,31 +356,28 @@ void bse_gj_kernel(BseArgs<T> a) {
           const int k = ks * M::KS + M::b_k(lane);
           bv[y] = (col < ncols && k < jb) ? colptr(A, B, n, j0, jb, col)[(size_t)(j0 + k) * n] : cz<C>();
         }
+        C av[SR];
 #pragma unroll
-        for (int rt = 0; rt < NB / 32; ++rt) {
-          C av[SR];
-#pragma unroll
-          for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
-          acc[rt].mac(av, bv, false);
-        }
+        for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
+        acc.mac(av, bv, false);
       }
-#pragma unroll
-      for (int rt = 0; rt < NB / 32; ++rt) {
-        acc[rt].store([&](int r, int c, C v) {
-          const int row = rt * 32 + r, col = cs * 32 + c;
-          if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
-        });
-      }
+      acc.store([&](int r, int c, C v) {
+        const int row = rt * 32 + r, col = cs * 32 + c;
+        if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
+      });
     }
-    __syncthreads();
-    invert_upper<C, NB>(D, X, jb);
-    // (c) MT = U^-T A_IJ^T (rows k of the panel, columns i = all rows of A)
-    for (int is = wave; is * 32 < n; is += kWaves) {
-      WT acc[NB / 32];
-#pragma unroll
-      for (int rt = 0; rt < NB / 32; ++rt) acc[rt].zero();
+  } else {
+    // MT = U^-T A_IJ^T: rows k of the panel, columns i = every row of A
+    const int is = (blockIdx.x - nwb) * kWaves + wave;
+    if (is * 32 >= n) return;
+    C* MT = a.MT + (size_t)blk * NB * n;
+    for (int rt = 0; rt < NB / 32; ++rt) {
+      WT acc;
+      acc.zero();
+      const int kend = min(jb, rt * 32 + 32);              // (U^-1)^T is lower triangular
 #pragma unroll 2
       for (int ks = 0; ks < KSTEPS; ++ks) {
+        if (ks * M::KS >= kend) break;
         C bv[SC];
 #pragma unroll
         for (int y = 0; y < SC; ++y) {
@@ -349,160 +385,188 @@ void bse_gj_kernel(BseArgs<T> a) {
           const int k = ks * M::KS + M::b_k(lane);
           bv[y] = (i < n && k < jb) ? A[(size_t)i * n + j0 + k] : cz<C>();
         }
+        C av[SR];
 #pragma unroll
-        for (int rt = 0; rt < NB / 32; ++rt) {
-          C av[SR];
-#pragma unroll
-          for (int xx = 0; xx < SR; ++xx) {
-            const int row = rt * 32 + xx * M::TM + M::a_row(lane);      // output row c
-            const int k = ks * M::KS + M::a_k(lane);
-            av[xx] = X[k][row];                                          // (U^-1)^T[row][k]
-          }
-          acc[rt].mac(av, bv, false);
+        for (int xx = 0; xx < SR; ++xx) {
+          const int row = rt * 32 + xx * M::TM + M::a_row(lane);        // output row
+          const int k = ks * M::KS + M::a_k(lane);
+          av[xx] = X[k][row];                                            // (U^-1)^T[row][k]
         }
+        acc.mac(av, bv, false);
       }
-#pragma unroll
-      for (int rt = 0; rt < NB / 32; ++rt) {
-        acc[rt].store([&](int r, int c, C v) {
-          const int row = rt * 32 + r, i = is * 32 + c;
-          if (row < jb && i < n) MT[(size_t)row * n + i] = v;
-        });
-      }
+      acc.store([&](int r, int c, C v) {
+        const int row = rt * 32 + r, i = is * 32 + c;
+        if (row < jb && i < n) MT[(size_t)row * n + i] = v;
+      });
     }
-    __threadfence_block();
-    __syncthreads();
-    // (d) update of every row outside the panel: C[i][col] -= sum_k MT[k][i] U[k][col].
-    // The workgroup stages the multipliers of a 128-row block in LDS; each wave
-    // owns 32 rows of it and streams the 32-column tiles of the row panel U,
-    // which the four waves read at about the same time (L1/L2 reuse).
-    const int nct = (ncols + 31) / 32;
-    for (int rb = 0; rb * 128 < n; ++rb) {
-      __syncthreads();
-      for (int idx = t; idx < NB * 128; idx += blockDim.x) {
-        const int k = idx >> 7, x = idx & 127;
-        const int i = rb * 128 + x;
-        S[k][x] = (k < jb && i < n) ? MT[(size_t)k * n + i] : cz<C>();
-      }
-      __syncthreads();
-      const int i0 = rb * 128 + wave * 32;
-      if (i0 >= n || (i0 >= j0 && i0 + 32 <= j0 + jb)) continue;
-      for (int ct = 0; ct < nct; ++ct) {
-        WT acc;
-        C* cb[SC];
-        bool cok[SC];
-#pragma unroll
-        for (int y = 0; y < SC; ++y) {
-          const int col = ct * 32 + y * M::TN + M::b_col(lane);
-          cok[y] = col < ncols;
-          cb[y] = colptr(A, B, n, j0, jb, cok[y] ? col : 0);
-        }
-        acc.load([&](int r, int c) -> C {
-          const int i = i0 + r;
-          const int y = c / M::TN;
-          const bool ok = cok[y] && i < n && !(i >= j0 && i < j0 + jb);
-          return ok ? cb[y][(size_t)i * n] : cz<C>();
-        });
-#pragma unroll 4
-        for (int ks = 0; ks < KSTEPS; ++ks) {
-          C av[SR], bv[SC];
-          const int k = ks * M::KS + M::b_k(lane);
-#pragma unroll
-          for (int y = 0; y < SC; ++y)
-            bv[y] = (cok[y] && k < jb) ? cb[y][(size_t)(j0 + k) * n] : cz<C>();
-#pragma unroll
-          for (int xx = 0; xx < SR; ++xx)
-            av[xx] = S[ks * M::KS + M::a_k(lane)][wave * 32 + xx * M::TM + M::a_row(lane)];
-          acc.mac(av, bv, true);
-        }
-        acc.store([&](int r, int c, C v) {
-          const int i = i0 + r;
-          const int y = c / M::TN;
-          if (cok[y] && i < n && !(i >= j0 && i < j0 + jb)) cb[y][(size_t)i * n] = v;
-        });
-      }
-    }
-    __threadfence_block();
-    __syncthreads();
   }
+}
 
-  // F_J = U_JJ^-1 B_J, then Phi <- alpha (F - Gamma) + (1 - alpha) Phi
-  C* P = a.phi + (size_t)qi * nn;
+// ----------------------------------------------------------------- update
+// C[i][col] -= sum_k MT[k][i] U[k][col] for every row i outside the panel.
+// Workgroup tile (2 UWM) x (2 UWN), waves 2 x 2, each wave a UWM x UWN tile.
+template <typename T, int NB>
+struct UpdCfg {
+  static constexpr int UWM = sizeof(T) == 4 ? 64 : 32, UWN = 32;
+  static constexpr int WGM = 2 * UWM, WGN = 2 * UWN;
+};
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
+  using C = typename cplx_of<T>::type;
+  using M = Mma<T>;
+  using CF = UpdCfg<T, NB>;
+  using UT = WTile<T, CF::UWM, CF::UWN>;
+  constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS;
+  const int blk = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = a.n;
+  const int jb = min(NB, n - j0);
+  const int ncols = (n - j0 - jb) + n;
+  const int rb = blockIdx.x / ncb, cbk = blockIdx.x - (blockIdx.x / ncb) * ncb;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int i0 = rb * CF::WGM + wr * CF::UWM;
+  const int c0 = cbk * CF::WGN + wc * CF::UWN;
+  if (i0 >= n || c0 >= ncols || (i0 >= j0 && i0 + CF::UWM <= j0 + jb)) return;
+  C* A = a.A + (size_t)blk * n * n;
+  C* B = a.B + (size_t)blk * n * n;
+  const C* MT = a.MT + (size_t)blk * NB * n;
+  C* cb[USC];
+  bool cok[USC];
+#pragma unroll
+  for (int y = 0; y < USC; ++y) {
+    const int col = c0 + y * M::TN + M::b_col(lane);
+    cok[y] = col < ncols;
+    cb[y] = colptr(A, B, n, j0, jb, cok[y] ? col : 0);
+  }
+  UT acc;
+  acc.load([&](int r, int c) -> C {
+    const int i = i0 + r;
+    const int y = c / M::TN;
+    const bool ok = cok[y] && i < n && !(i >= j0 && i < j0 + jb);
+    return ok ? cb[y][(size_t)i * n] : cz<C>();
+  });
+#pragma unroll 4
+  for (int ks = 0; ks < KSTEPS; ++ks) {
+    C av[USR], bv[USC];
+    const int k = ks * M::KS + M::b_k(lane);
+#pragma unroll
+    for (int y = 0; y < USC; ++y) bv[y] = (cok[y] && k < jb) ? cb[y][(size_t)(j0 + k) * n] : cz<C>();
+    const int ka = ks * M::KS + M::a_k(lane);
+#pragma unroll
+    for (int xx = 0; xx < USR; ++xx) {
+      const int i = i0 + xx * M::TM + M::a_row(lane);
+      av[xx] = (i < n && ka < jb) ? MT[(size_t)ka * n + i] : cz<C>();
+    }
+    acc.mac(av, bv, true);
+  }
+  acc.store([&](int r, int c, C v) {
+    const int i = i0 + r;
+    const int y = c / M::TN;
+    if (cok[y] && i < n && !(i >= j0 && i < j0 + jb)) cb[y][(size_t)i * n] = v;
+  });
+}
+
+// ------------------------------------------------------------------ final
+// F_J = U_JJ^-1 B_J for every panel J, then Phi <- alpha (F - Gamma) + (1 - alpha) Phi.
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void bse_final_kernel(BseCtx<T> a, int nstripw) {
+  using C = typename cplx_of<T>::type;
+  using M = Mma<T>;
+  using WT = WTile<T>;
+  constexpr int SR = WT::SR, SC = WT::SC, KSTEPS = NB / M::KS;
+  __shared__ C X[NB][NB + 1];
+  const int blk = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
+  const int J = blockIdx.x / nstripw, sw = blockIdx.x - (blockIdx.x / nstripw) * nstripw;
+  const int j0 = J * NB, jb = min(NB, n - j0);
+  const size_t nn = (size_t)n * n;
+  const C* UI = a.UI + ((size_t)blk * a.nJ + J) * NB * NB;
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) X[idx / NB][idx % NB] = UI[idx];
+  __syncthreads();
+  if (blockIdx.x == 0 && t == 0 && a.stats) {
+    const double* ps = a.pst + (size_t)blk * 4;
+    pq_bse_block_stats st;
+    const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
+    st.min_pivot = (float)ratio;
+    st.growth = (float)ps[1];
+    st.flags = (ps[2] > 0.0 ? 2 : 0) | (ratio < a.weak_ratio ? 1 : 0);
+    st.reserved = 0;
+    a.stats[blk] = st;
+  }
+  const int cs = sw * kWaves + wave;
+  if (cs * 32 >= n) return;
+  const C* B = a.B + (size_t)blk * nn;
+  const C* G = a.gamma + (size_t)blk * nn;
+  C* P = a.phi + (size_t)blk * nn;
   const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
   const bool mix = a.alpha != 1.0;
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int jb = min(NB, n - j0);
-    __syncthreads();
-    for (int idx = t; idx < NB * NB; idx += blockDim.x) {
-      const int r = idx / NB, c = idx - (idx / NB) * NB;
-      D[r][c] = (r < jb && c < jb) ? A[(size_t)(j0 + r) * n + j0 + c] : cz<C>();
-    }
-    __syncthreads();
-    // only the U part is needed (the L part is already applied)
-    invert_upper<C, NB>(D, X, jb);
-    for (int cs = wave; cs * 32 < n; cs += kWaves) {
-      WT acc[NB / 32];
-#pragma unroll
-      for (int rt = 0; rt < NB / 32; ++rt) acc[rt].zero();
+  for (int rt = 0; rt < NB / 32; ++rt) {
+    WT acc;
+    acc.zero();
 #pragma unroll 2
-      for (int ks = 0; ks < KSTEPS; ++ks) {
-        C bv[SC];
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+      if (ks * M::KS + M::KS <= rt * 32) continue;        // U^-1 upper triangular
+      C bv[SC];
 #pragma unroll
-        for (int y = 0; y < SC; ++y) {
-          const int col = cs * 32 + y * M::TN + M::b_col(lane);
-          const int k = ks * M::KS + M::b_k(lane);
-          bv[y] = (col < n && k < jb) ? B[(size_t)(j0 + k) * n + col] : cz<C>();
-        }
-#pragma unroll
-        for (int rt = 0; rt < NB / 32; ++rt) {
-          C av[SR];
-#pragma unroll
-          for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
-          acc[rt].mac(av, bv, false);
-        }
+      for (int y = 0; y < SC; ++y) {
+        const int col = cs * 32 + y * M::TN + M::b_col(lane);
+        const int k = ks * M::KS + M::b_k(lane);
+        bv[y] = (col < n && k < jb) ? B[(size_t)(j0 + k) * n + col] : cz<C>();
       }
+      C av[SR];
 #pragma unroll
-      for (int rt = 0; rt < NB / 32; ++rt) {
-        acc[rt].store([&](int r, int c, C f) {
-          const int row = rt * 32 + r, col = cs * 32 + c;
-          if (row < jb && col < n) {
-            const size_t idx = (size_t)(j0 + row) * n + col;
-            const C g = G[idx];
-            C v;
-            v.x = f.x - g.x;
-            v.y = f.y - g.y;
-            if (mix) {
-              const C old = P[idx];
-              v.x = al * v.x + be * old.x;
-              v.y = al * v.y + be * old.y;
-            }
-            P[idx] = v;
-          }
-        });
-      }
+      for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
+      acc.mac(av, bv, false);
     }
-  }
-  if (t == 0 && a.stats) {
-    pq_bse_block_stats st;
-    const double ratio = pst[1] > 0.0 ? pst[0] / pst[1] : 0.0;
-    st.min_pivot = (float)ratio;
-    st.growth = (float)pst[1];
-    st.flags = (pst[2] > 0.0 ? 2 : 0) | (ratio < a.weak_ratio ? 1 : 0);
-    st.reserved = 0;
-    a.stats[qi] = st;
+    acc.store([&](int r, int c, C f) {
+      const int row = rt * 32 + r, col = cs * 32 + c;
+      if (row < jb && col < n) {
+        const size_t idx = (size_t)(j0 + row) * n + col;
+        const C g = G[idx];
+        C v;
+        v.x = f.x - g.x;
+        v.y = f.y - g.y;
+        if (mix) {
+          const C old = P[idx];
+          v.x = al * v.x + be * old.x;
+          v.y = al * v.y + be * old.y;
+        }
+        P[idx] = v;
+      }
+    });
   }
 }
 
 template <typename T>
 constexpr int panel_width() { return sizeof(T) == 4 ? 64 : 32; }
 
+struct BseLayout {
+  size_t A, B, MT, LI, UI, pst, total;
+};
+
+template <typename T>
+BseLayout bse_layout(const Dims& d) {
+  using C = typename cplx_of<T>::type;
+  constexpr int NB = panel_width<T>();
+  const size_t nn = (size_t)d.n * d.n;
+  const int nJ = (d.n + NB - 1) / NB;
+  BseLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off += align256(b); return o; };
+  L.A = take(sizeof(C) * nn * d.Nq);
+  L.B = take(sizeof(C) * nn * d.Nq);
+  L.MT = take(sizeof(C) * (size_t)NB * d.n * d.Nq);
+  L.LI = take(sizeof(C) * (size_t)NB * NB * d.Nq);
+  L.UI = take(sizeof(C) * (size_t)NB * NB * nJ * d.Nq);
+  L.pst = take(sizeof(double) * 4 * (size_t)d.Nq);
+  L.total = off;
+  return L;
+}
+
 }  // namespace
 
 size_t bse_ws_bytes(const pq_params& p, const Dims& d, int precision) {
   (void)p;
-  const size_t es = precision == PQ_PREC_FP64 ? sizeof(double2) : sizeof(float2);
-  const int nb = precision == PQ_PREC_FP64 ? panel_width<double>() : panel_width<float>();
-  const size_t nn = (size_t)d.n * d.n;
-  return align256(es * nn * d.Nq) * 2 + align256(es * (size_t)nb * d.n * d.Nq);
+  return precision == PQ_PREC_FP64 ? bse_layout<double>(d).total : bse_layout<float>(d).total;
 }
 
 template <typename T>
@@ -511,22 +575,43 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
                           hipStream_t s) {
   using C = typename cplx_of<T>::type;
   constexpr int NB = panel_width<T>();
+  using CF = UpdCfg<T, NB>;
   static const double kSign[4] = {1.0, 1.0, -1.0, 1.0};
-  const size_t nn = (size_t)d.n * d.n;
+  const BseLayout L = bse_layout<T>(d);
   char* w = (char*)ws;
-  BseArgs<T> a;
-  a.d = d;
+  BseCtx<T> a;
+  a.n = d.n;
+  a.Nq = d.Nq;
+  a.nJ = (d.n + NB - 1) / NB;
   a.sign = (T)kSign[channel];
   a.alpha = alpha;
   a.weak_ratio = weak;
   a.gamma = (const C*)gamma;
   a.chi0 = chi0;
   a.phi = (C*)phi_io;
-  a.A = (C*)w;
-  a.B = (C*)(w + align256(sizeof(C) * nn * d.Nq));
-  a.MT = (C*)(w + 2 * align256(sizeof(C) * nn * d.Nq));
+  a.A = (C*)(w + L.A);
+  a.B = (C*)(w + L.B);
+  a.MT = (C*)(w + L.MT);
+  a.LI = (C*)(w + L.LI);
+  a.UI = (C*)(w + L.UI);
+  a.pst = (double*)(w + L.pst);
   a.stats = stats;
-  hipLaunchKernelGGL((bse_gj_kernel<T, NB>), dim3(d.Nq), dim3(kThreads), 0, s, a);
+  const int n = d.n;
+  const unsigned init_x = (unsigned)std::min<size_t>(1024, ((size_t)n * n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL((bse_init_kernel<T>), dim3(init_x, d.Nq), dim3(kThreads), 0, s, a);
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int jb = std::min(NB, n - j0);
+    const int ncols = (n - j0 - jb) + n;
+    hipLaunchKernelGGL((bse_diag_kernel<T, NB>), dim3(d.Nq), dim3(kThreads), 0, s, a, j0);
+    const int nwb = ((ncols + 31) / 32 + kWaves - 1) / kWaves;
+    const int nwc = ((n + 31) / 32 + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL((bse_panel_kernel<T, NB>), dim3(nwb + nwc, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
+    const int nrb = (n + CF::WGM - 1) / CF::WGM;
+    const int ncb = (ncols + CF::WGN - 1) / CF::WGN;
+    hipLaunchKernelGGL((bse_update_kernel<T, NB>), dim3(nrb * ncb, d.Nq), dim3(kThreads), 0, s, a, j0, ncb);
+  }
+  const int nstripw = ((n + 31) / 32 + kWaves - 1) / kWaves;
+  hipLaunchKernelGGL((bse_final_kernel<T, NB>), dim3(a.nJ * nstripw, d.Nq), dim3(kThreads), 0, s, a, nstripw);
   return hipGetLastError();
 }
 
