@@ -31,8 +31,8 @@ PEAK_HBM = 8000.0        # GB/s
 
 
 def bse_flops_per_launch(d) -> float:
-    """Algorithmic work of one channel's BSE: (32/3) n^3 real flops per q block
-    (complex LU 8/3 n^3 + two n-RHS triangular solves 8 n^3)."""
+    """LU-equivalent work of one channel's BSE solve: (32/3) n^3 real flops per q
+    block (complex LU 8/3 n^3 + two n-RHS triangular solves 8 n^3)."""
     return d.Nq * (32.0 / 3.0) * float(d.n) ** 3
 
 
@@ -62,19 +62,27 @@ def run_gpu(p, precision, steps, warmup):
     torch.cuda.synchronize()
     bse_ms = []
     stage = [0.0] * 8
+    kern_ms = [0.0] * 5
+    kern_n = [0] * 5
+    upd_flops = 0.0
     t0 = time.perf_counter()
     for _ in range(steps):
         _, _, st = s.iterate(1)
         bse_ms.append(st.ms_stage[5])
         for i in range(8):
             stage[i] += st.ms_stage[i] / steps
+        for i in range(5):
+            kern_ms[i] += st.ms_bse_kernel[i]
+            kern_n[i] += st.n_bse_launch[i]
+        upd_flops += st.update_flops
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dsig = st.dsigma
     s.close()
     del s
     torch.cuda.empty_cache()
-    return dict(sec=(t1 - t0), steps=steps, bse_ms=bse_ms, stage_ms=stage, dims=d, dsigma=dsig)
+    return dict(sec=(t1 - t0), steps=steps, bse_ms=bse_ms, stage_ms=stage, dims=d, dsigma=dsig,
+                kern_ms=kern_ms, kern_n=kern_n, upd_flops=upd_flops)
 
 
 def time_to_converged(p, precision, tol, max_iter):
@@ -204,13 +212,23 @@ def main():
     r64 = run_gpu(p, "fp64", args.fp64_steps, 1) if args.fp64_steps > 0 else None
     ips64 = (r64["steps"] / r64["sec"]) if r64 else None
 
-    flops = bse_flops_per_launch(d)
-    launch_ms = sum(r32["bse_ms"]) / len(r32["bse_ms"]) / 4.0
-    achieved = flops / (launch_ms * 1e-3) / 1e12
+    # dominant kernel: the rank-NB update of the BSE (per launch: one panel step of
+    # all 960 blocks of a channel); flops = 8 per complex multiply-add it performs
+    n_upd = r32["kern_n"][3]
+    upd_ms = r32["kern_ms"][3] / n_upd
+    upd_flops = r32["upd_flops"] / n_upd
+    achieved = upd_flops / (upd_ms * 1e-3) / 1e12
+    bse_channel_ms = sum(r32["bse_ms"]) / len(r32["bse_ms"]) / 4.0
+    bse_alg = bse_flops_per_launch(d) / (bse_channel_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(),
-            "kernel": "bse_gj_kernel<float,64> (one launch = one channel, %d blocks of n=%d)" % (d.Nq, d.n),
-            "avg_launch_ms": round(launch_ms, 3), "algorithmic_flops_per_launch": flops}
+            "kernel": "bse_update_kernel<float,64> (one launch = one rank-64 panel update of %d blocks, n=%d)"
+                      % (d.Nq, d.n),
+            "avg_launch_ms": round(upd_ms, 3), "flops_per_launch": upd_flops,
+            "bse_solve_lu_equivalent_tflops": round(bse_alg, 2),
+            "bse_solve_ms_per_channel": round(bse_channel_ms, 2),
+            "bse_kernel_ms_per_channel": {k: round(r32["kern_ms"][i] / args.steps, 2) for k, i in
+                                          (("init", 0), ("diag", 1), ("panel", 2), ("update", 3), ("final", 4))}}
 
     out = {
         "metric": "parquet iterations/s + time-to-converged Σ (1e-6) vs FP64 GPU, 8x8 Nv=16",

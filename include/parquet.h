@@ -214,7 +214,13 @@ typedef struct {
   double dsigma;           /* max |Sigma_new - Sigma_old| of the last iteration */
   double mu;               /* mu~ used by the last iteration                    */
   double ms_total;         /* wall time of the last iteration (device events)   */
-  double ms_stage[8];      /* dyson, bubbles, kernels, remap, sigma, bse, mix, other */
+  double ms_stage[8];      /* dyson, bubbles+kernels, -, remap, sigma, bse (4 channels), mix, - */
+  /* BSE of the density channel, per kernel kind (init, diag, panel, update,
+   * final): summed device time of its launches and the number of launches */
+  double ms_bse_kernel[5];
+  int32_t n_bse_launch[5];
+  int32_t reserved;
+  double update_flops;     /* matrix-core flops of those update launches (8 per complex MAC) */
 } pq_iter_stats;
 
 /* Device bytes parquet_init needs in its workspace. */

@@ -214,6 +214,8 @@ struct pq_ctx {
   int iteration;
   hipEvent_t ev[8];
   bool have_events;
+  hipEvent_t bev[512];   // BSE launch timing of one channel
+  bool have_bev;
 };
 
 namespace {
@@ -329,6 +331,9 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
   c->have_events = true;
   for (int i = 0; i < 8; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) c->have_events = false;
+  c->have_bev = true;
+  for (int i = 0; i < 512; ++i)
+    if (hipEventCreate(&c->bev[i]) != hipSuccess) c->have_bev = false;
   hipError_t e;
   const size_t vb = field_bytes(c, PQ_FIELD_PHI);
   if ((e = hipMemsetAsync(c->phi, 0, vb, c->s)) != hipSuccess) goto fail;
@@ -341,6 +346,8 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
 fail:
   for (int i = 0; i < 8; ++i)
     if (c->have_events) hipEventDestroy(c->ev[i]);
+  for (int i = 0; i < 512; ++i)
+    if (c->have_bev) hipEventDestroy(c->bev[i]);
   delete c;
   return hip_fail(e, "parquet_init");
 }
@@ -369,10 +376,16 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
     if ((e = launch_sigma(p, d, c->phi, c->k1, c->k2, c->g, c->mu, c->sigma_new, c->sig_ws, c->s)) != hipSuccess)
       return hip_fail(e, "sigma");
     rec(4);
+    BseTiming tm;
+    tm.ev = c->bev;
+    tm.cap = 256;
+    tm.used = 0;
+    tm.update_flops = 0.0;
+    const bool timing = stats && c->have_bev;
     for (int r = 0; r < 4; ++r) {
       const double2* x = r < 2 ? c->xph : c->xpp;
       e = launch_bse(p, d, r, p.precision, (char*)c->gamma + r * vstride, x, (char*)c->phi + r * vstride,
-                     p.alpha, c->bstats + (size_t)r * d.Nq, c->bse_ws, c->s);
+                     p.alpha, c->bstats + (size_t)r * d.Nq, c->bse_ws, c->s, (timing && r == 0) ? &tm : nullptr);
       if (e != hipSuccess) return hip_fail(e, "bse");
     }
     rec(5);
@@ -398,6 +411,15 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
         hipEventElapsedTime(&ms, c->ev[3], c->ev[4]); stats->ms_stage[4] = ms;
         hipEventElapsedTime(&ms, c->ev[4], c->ev[5]); stats->ms_stage[5] = ms;
         hipEventElapsedTime(&ms, c->ev[5], c->ev[6]); stats->ms_stage[6] = ms;
+      }
+      if (timing) {
+        for (int i = 0; i < tm.used; ++i) {
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, c->bev[2 * i], c->bev[2 * i + 1]);
+          stats->ms_bse_kernel[tm.kind[i]] += ms;
+          stats->n_bse_launch[tm.kind[i]] += 1;
+        }
+        stats->update_flops = tm.update_flops;
       }
       const size_t nb = 4 * (size_t)d.Nq;
       pq_bse_block_stats* hs = new (std::nothrow) pq_bse_block_stats[nb];
@@ -453,6 +475,8 @@ pq_status parquet_destroy(pq_ctx* c) {
   if (!c) return PQ_OK;
   if (c->have_events)
     for (int i = 0; i < 8; ++i) hipEventDestroy(c->ev[i]);
+  if (c->have_bev)
+    for (int i = 0; i < 512; ++i) hipEventDestroy(c->bev[i]);
   delete c;
   return PQ_OK;
 }

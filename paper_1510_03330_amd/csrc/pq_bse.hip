@@ -287,8 +287,10 @@ __global__ __launch_bounds__(kThreads) void bse_init_kernel(BseCtx<T> a) {
 }
 
 // ------------------------------------------------------------------- diag
+constexpr int kDiagThreads = kThreads;
+
 template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void bse_diag_kernel(BseCtx<T> a, int j0) {
+__global__ __launch_bounds__(kDiagThreads) void bse_diag_kernel(BseCtx<T> a, int j0) {
   using C = typename cplx_of<T>::type;
   __shared__ C D[NB][NB + 1];
   __shared__ C X[NB][NB + 1];
@@ -572,7 +574,7 @@ size_t bse_ws_bytes(const pq_params& p, const Dims& d, int precision) {
 template <typename T>
 static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, const void* gamma,
                           const double2* chi0, void* phi_io, pq_bse_block_stats* stats, void* ws,
-                          hipStream_t s) {
+                          hipStream_t s, BseTiming* tm) {
   using C = typename cplx_of<T>::type;
   constexpr int NB = panel_width<T>();
   using CF = UpdCfg<T, NB>;
@@ -597,33 +599,58 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   a.pst = (double*)(w + L.pst);
   a.stats = stats;
   const int n = d.n;
+  // event timing around each launch (kind: 0 init, 1 diag, 2 panel, 3 update, 4 final)
+  auto pre = [&](int kind) {
+    if (tm && tm->used < tm->cap) {
+      tm->kind[tm->used] = kind;
+      hipEventRecord(tm->ev[2 * tm->used], s);
+    }
+  };
+  auto post = [&]() {
+    if (tm && tm->used < tm->cap) {
+      hipEventRecord(tm->ev[2 * tm->used + 1], s);
+      tm->used++;
+    }
+  };
+  if (tm) tm->update_flops = 0.0;
   const unsigned init_x = (unsigned)std::min<size_t>(1024, ((size_t)n * n + kThreads - 1) / kThreads);
+  pre(0);
   hipLaunchKernelGGL((bse_init_kernel<T>), dim3(init_x, d.Nq), dim3(kThreads), 0, s, a);
+  post();
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int jb = std::min(NB, n - j0);
     const int ncols = (n - j0 - jb) + n;
-    hipLaunchKernelGGL((bse_diag_kernel<T, NB>), dim3(d.Nq), dim3(kThreads), 0, s, a, j0);
+    pre(1);
+    hipLaunchKernelGGL((bse_diag_kernel<T, NB>), dim3(d.Nq), dim3(kDiagThreads), 0, s, a, j0);
+    post();
     const int nwb = ((ncols + 31) / 32 + kWaves - 1) / kWaves;
     const int nwc = ((n + 31) / 32 + kWaves - 1) / kWaves;
+    pre(2);
     hipLaunchKernelGGL((bse_panel_kernel<T, NB>), dim3(nwb + nwc, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
+    post();
     const int nrb = (n + CF::WGM - 1) / CF::WGM;
     const int ncb = (ncols + CF::WGN - 1) / CF::WGN;
+    pre(3);
     hipLaunchKernelGGL((bse_update_kernel<T, NB>), dim3(nrb * ncb, d.Nq), dim3(kThreads), 0, s, a, j0, ncb);
+    post();
+    if (tm) tm->update_flops += 8.0 * (double)(n - jb) * ncols * jb * d.Nq;
   }
   const int nstripw = ((n + 31) / 32 + kWaves - 1) / kWaves;
+  pre(4);
   hipLaunchKernelGGL((bse_final_kernel<T, NB>), dim3(a.nJ * nstripw, d.Nq), dim3(kThreads), 0, s, a, nstripw);
+  post();
   return hipGetLastError();
 }
 
 hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precision,
                       const void* gamma, const double2* chi0, void* phi_io, double alpha,
-                      pq_bse_block_stats* stats, void* ws, hipStream_t s) {
+                      pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm) {
   if (precision == PQ_PREC_FP64) {
     if (p.storage != PQ_STORE_C128) return hipErrorInvalidValue;
-    return run_bse<double>(d, channel, alpha, 1e-10f, gamma, chi0, phi_io, stats, ws, s);
+    return run_bse<double>(d, channel, alpha, 1e-10f, gamma, chi0, phi_io, stats, ws, s, tm);
   }
   if (p.storage != PQ_STORE_C64) return hipErrorInvalidValue;
-  return run_bse<float>(d, channel, alpha, 1e-3f, gamma, chi0, phi_io, stats, ws, s);
+  return run_bse<float>(d, channel, alpha, 1e-3f, gamma, chi0, phi_io, stats, ws, s, tm);
 }
 
 }  // namespace pq

@@ -43,8 +43,16 @@ hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, cons
 hipError_t launch_sigma1(const pq_params& p, const Dims& d, const double2* g, const double* mu,
                          double2* sigma_out, void* ws, hipStream_t s);
 size_t bse_ws_bytes(const pq_params& p, const Dims& d, int precision);
+// Optional device-event timing of the BSE launches, by kernel kind
+// (0 init, 1 diag, 2 panel, 3 update, 4 final).
+struct BseTiming {
+  hipEvent_t* ev;     // 2 * cap events
+  int cap, used;
+  int kind[256];
+  double update_flops;
+};
 hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precision,
                       const void* gamma, const double2* chi0, void* phi_io, double alpha,
-                      pq_bse_block_stats* stats, void* ws, hipStream_t s);
+                      pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm = nullptr);
 
 }  // namespace pq

@@ -53,7 +53,8 @@ class PqDims(ctypes.Structure):
 class PqIterStats(ctypes.Structure):
     _fields_ = [
         ("iteration", c_int32), ("flagged_blocks", c_int32), ("dsigma", c_double), ("mu", c_double),
-        ("ms_total", c_double), ("ms_stage", c_double * 8),
+        ("ms_total", c_double), ("ms_stage", c_double * 8), ("ms_bse_kernel", c_double * 5),
+        ("n_bse_launch", c_int32 * 5), ("reserved", c_int32), ("update_flops", c_double),
     ]
 
 
