@@ -1,0 +1,190 @@
+"""Parity at the full benchmark size: 8x8 lattice, t' = -0.2, U = 2, beta = 5,
+n = 0.9, Nv = 16 (BSE dimension 1024, 960 transfer blocks per channel), run
+through the solver context exactly as the benchmark runs it (parquet_set of
+Sigma and Phi, one parquet_iterate).
+
+The full vertex (4e9 elements) is too large for the oracle, so the input Phi
+is a seeded low-rank field the oracle can evaluate point by point, and the
+outputs are compared where the oracle can compute them one by one:
+
+* mu, G, both bubbles, K1 and K2: everywhere;
+* Gamma (all four channels): 40000 seeded random box points;
+* Phi after the BSE and the mixing: two whole (channel, q) blocks, one of them
+  the magnetic block at q = (0, (pi, pi)), the most nearly singular one;
+* Sigma after the Schwinger-Dyson equation and the mixing: two points inside
+  the box and one in the extended region;
+* FP32 path only, a property that holds at any size, checked on every block
+  of every channel: the recovered F satisfies (1 - s Gamma X) F = Gamma.
+
+Tolerances follow the stage tests: rounding order only for the FP64 path; for
+the FP32 path the complex64 rounding of Phi and Gamma (~6e-8 relative) enters
+every vertex quantity, and the BSE adds kappa n^(1/2) eps32 with kappa <= 50
+(the magnetic block at (pi, pi) has kappa = 44).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import parquet as P
+from lowrank_vertex import FullVertex, LowRankVertex
+from workloads import config, lowrank_phi_factors, random_sigma
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+SEED_SIGMA, SEED_PHI = 31, 41
+N_GAMMA_POINTS = 40000
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ref():
+    """Oracle values at the sampled points (computed once, shared by both precisions)."""
+    print("CASE full-size oracle", flush=True)
+    p = config("c3")
+    g = P.Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
+    sigma_old = random_sigma(g.Nve, g.Nk, SEED_SIGMA, scale=0.1)
+    u, v = lowrank_phi_factors(g.Nq, g.n, g.Nk, g.Nv, SEED_PHI)
+    phi = LowRankVertex(u, v)
+    lam = P.pa_lambda(p.U)
+    out = dict(p=p, g=g, sigma_old=sigma_old, u=u, v=v)
+    mu = P.find_mu(p, g, sigma_old)
+    G = P.dyson(p, g, sigma_old, mu)
+    xph, xpp = P.bubbles(p, g, G)
+    K1, K2 = P.kernel_functions(g, phi, p.kernel_level, p.edge_rule)
+    out.update(mu=mu, G=G, xph=xph, xpp=xpp, K1=K1, K2=K2)
+    # Gamma at random box points
+    rng = np.random.default_rng(7)
+    qi = rng.integers(0, g.Nq, N_GAMMA_POINTS)
+    ki = rng.integers(0, g.n, N_GAMMA_POINTS)
+    kpi = rng.integers(0, g.n, N_GAMMA_POINTS)
+    out["gpts"] = (qi, ki, kpi)
+    out["gamma_pts"] = P.remap_points(g, phi, K1, K2, lam, qi, ki, kpi)
+    # two whole BSE blocks (+ mixing with the old Phi)
+    q_af = g.qidx(0, (g.Lx // 2) * g.Ly + g.Ly // 2)     # m = 0, Q = (pi, pi)
+    blocks = [(P.CH_M, int(q_af)), (P.CH_S, int(rng.integers(0, g.Nq)))]
+    all_k = np.arange(g.n)
+    out["blocks"] = []
+    for r, q in blocks:
+        kk, kp = np.meshgrid(all_k, all_k, indexing="ij")
+        gam = P.remap_points(g, phi, K1, K2, lam, np.full(kk.shape, q), kk, kp)[r]
+        X = xph if r in (P.CH_D, P.CH_M) else xpp
+        new = P.bse_block(gam, X[q], P.BSE_SIGN[r])
+        mixed = p.alpha * new + (1 - p.alpha) * phi.block(r, q)
+        out["blocks"].append((r, q, mixed))
+    # Sigma: two box points and one extended-region point
+    box_pts = [(0, 0), (-3, 27)]
+    ext_pts = [(p.Nv // 2 + 3, 9)]
+    F = FullVertex(g, phi, K1, K2, lam)
+    s1 = P.sigma_tilde1(p, g, G, mu)
+    pts = box_pts + ext_pts
+    s1_pts = np.array([s1[g.eidx(n), K] for (n, K) in pts])
+    vertex = P.sigma_tilde2(p, g, G, K1, K2, k_list=pts)
+    vertex[:len(box_pts)] += P.sigma_box(p, g, G, F, K1, K2, k_list=box_pts)
+    s_old = np.array([sigma_old[g.eidx(n), K] for (n, K) in pts])
+    out["sigma_pts"] = pts
+    # mixed Sigma = alpha (Sigma~1 + vertex part) + (1 - alpha) Sigma_old; the
+    # vertex part (Sigma~2 + box) is also checked on its own, since it is much
+    # smaller than Sigma~1 for this input
+    out["sigma_base"] = p.alpha * s1_pts + (1 - p.alpha) * s_old
+    out["sigma_vertex"] = p.alpha * vertex
+    return out
+
+
+def _phi_on_device(u, v, dtype):
+    nq, n = u.shape[1], u.shape[2]
+    phi = torch.empty((4, nq, n, n), dtype=dtype, device=DEV)
+    for r in range(4):
+        ur = torch.from_numpy(u[r]).to(device=DEV, dtype=dtype)
+        vt = torch.from_numpy(np.ascontiguousarray(v[r].transpose(0, 2, 1))).to(device=DEV, dtype=dtype)
+        torch.bmm(ur, vt, out=phi[r])
+        del ur, vt
+    return phi
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_full_size_iteration_sampled(ref, prec):
+    print("CASE full-size iteration", prec, flush=True)
+    from paper_1510_03330_amd.ops import Solver
+    p, g = ref["p"], ref["g"]
+    fp64 = prec == "fp64"
+    vt = torch.complex128 if fp64 else torch.complex64
+    s = Solver(p, prec)
+    s.set("sigma", torch.from_numpy(ref["sigma_old"]))
+    phi_old = _phi_on_device(ref["u"], ref["v"], vt)
+    s.set("phi", phi_old)
+    if fp64:
+        del phi_old
+        phi_old = None
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    done, _, stats = s.iterate(1)
+    assert done == 1
+    assert stats.flagged_blocks == 0
+
+    tol_sp = 1e-11 if fp64 else 1e-9        # single-particle stages run in FP64 on both paths
+    tol_v = 1e-11 if fp64 else 2e-6         # vertex sums of <= 9 terms
+    tol_bse = 1e-9 if fp64 else 5e-4
+    tol_sig = 1e-9 if fp64 else 1e-4         # vertex part of Sigma alone
+
+    assert abs(H(s.get("mu"))[0] - ref["mu"]) < tol_sp
+    assert relerr(H(s.get("g")), ref["G"]) < tol_sp
+    assert relerr(H(s.get("xph")), ref["xph"]) < tol_sp
+    assert relerr(H(s.get("xpp")), ref["xpp"]) < tol_sp
+    assert relerr(H(s.get("k1")), ref["K1"]) < tol_v
+    k2 = H(s.get("k2"))
+    for r in range(4):
+        assert relerr(k2[r], ref["K2"][r]) < tol_v * 10, r
+
+    qi, ki, kpi = (torch.from_numpy(a).to(DEV) for a in ref["gpts"])
+    gamma = s.get("gamma")
+    got = H(gamma[:, qi, ki, kpi]).astype(np.complex128)
+    for r in range(4):
+        assert relerr(got[r], ref["gamma_pts"][r]) < tol_v, r
+
+    if not fp64:
+        # property at any size: (1 - s Gamma X) F = Gamma on every block
+        phi_new = s.get("phi")
+        xph = s.get("xph")
+        xpp = s.get("xpp")
+        worst = 0.0
+        a = p.alpha
+        for r in range(4):
+            X = xph if r < 2 else xpp
+            sign = P.BSE_SIGN[r]
+            for q0 in range(0, g.Nq, 32):
+                sl = slice(q0, min(g.Nq, q0 + 32))
+                gm = gamma[r, sl].to(torch.complex128)
+                F = gm + (phi_new[r, sl].to(torch.complex128) - (1 - a) * phi_old[r, sl].to(torch.complex128)) / a
+                res = F - sign * torch.bmm(gm, (X[sl][:, :, None] * F).contiguous()) - gm
+                scale = torch.amax(torch.abs(gm)) + torch.amax(torch.abs(F - gm))
+                worst = max(worst, float(torch.amax(torch.abs(res)) / scale))
+                del gm, F, res
+        print("max relative BSE residual over all blocks:", worst, flush=True)
+        assert worst < 1e-4
+        del phi_new
+    del gamma
+    torch.cuda.empty_cache()
+
+    phi_new = s.get("phi")
+    for r, q, mixed in ref["blocks"]:
+        got = H(phi_new[r, q]).astype(np.complex128)
+        assert relerr(got, mixed) < tol_bse, (r, q, relerr(got, mixed))
+    del phi_new
+
+    sig = H(s.get("sigma"))
+    got = np.array([sig[g.eidx(n), K] for (n, K) in ref["sigma_pts"]])
+    assert relerr(got, ref["sigma_base"] + ref["sigma_vertex"]) < (1e-11 if fp64 else 1e-6)
+    assert relerr(got - ref["sigma_base"], ref["sigma_vertex"]) < tol_sig
+    s.close()
+    del phi_old
+    torch.cuda.empty_cache()

@@ -13,4 +13,5 @@ from .synthetic import (  # noqa: F401
     bse_microbench_gamma,
     random_phi,
     random_sigma,
+    lowrank_phi_factors,
 )

@@ -104,3 +104,24 @@ def random_phi(nq: int, n: int, seed: int, scale: float = 0.1) -> np.ndarray:
 def random_sigma(nfreq: int, nk: int, seed: int, scale: float = 0.2) -> np.ndarray:
     """Seeded random self-energy on [frequency][momentum]."""
     return rand_complex((nfreq, nk), seed, scale)
+
+
+def lowrank_phi_factors(nq: int, n: int, nk: int, nv: int, seed: int, rank: int = 4,
+                        scale: float = 0.1):
+    """Seeded factors of a large reducible-vertex input that is cheap to evaluate
+    point by point: Phi_r[q][k][k'] = sum_j u[r,q,k,j] v[r,q,k',j].
+
+    Used where the full [4][Nq][n][n] array does not fit in host memory (the
+    8x8, Nv = 16 case is 4e9 elements). Each factor row carries an envelope
+    1 / (1 + |nu index| / 4) over the fermionic frequency of its compound
+    index (frequency-major, k = (n + Nv/2) Nk + K), so entries are largest at
+    the box centre and smaller at its edge, as for a vertex that decays with
+    frequency. E|Phi|^2 is about scale^2 at the centre."""
+    fac = np.sqrt(scale / np.sqrt(rank))
+    u = rand_complex((4, nq, n, rank), seed, fac)
+    v = rand_complex((4, nq, n, rank), seed + 1, fac)
+    freq = np.arange(n) // nk - nv // 2 + 0.5
+    env = 1.0 / (1.0 + np.abs(freq) / 4.0)
+    u *= env[None, None, :, None]
+    v *= env[None, None, :, None]
+    return u, v
