@@ -396,9 +396,11 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
         }
         acc.mac(av, bv, false);
       }
+      // rows jb..NB-1 (ragged last panel) come out exactly zero, since U^-1 is
+      // the identity outside the jb x jb block; the update reads them unmasked
       acc.store([&](int r, int c, C v) {
         const int row = rt * 32 + r, i = is * 32 + c;
-        if (row < jb && i < n) MT[(size_t)row * n + i] = v;
+        if (row < NB && i < n) MT[(size_t)row * n + i] = v;
       });
     }
   }
@@ -421,10 +423,13 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   using CF = UpdCfg<T, NB>;
   using UT = WTile<T, CF::UWM, CF::UWN>;
   constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS;
-  const int blk = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = a.n;
+  constexpr int PF = 2;                      // operand prefetch distance (k-steps)
+  const unsigned lid = xcd_linear();
+  const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = a.n;
   const int jb = min(NB, n - j0);
   const int ncols = (n - j0 - jb) + n;
-  const int rb = blockIdx.x / ncb, cbk = blockIdx.x - (blockIdx.x / ncb) * ncb;
+  const int rb = bx / ncb, cbk = bx - (bx / ncb) * ncb;
   const int wr = wave & 1, wc = wave >> 1;
   const int i0 = rb * CF::WGM + wr * CF::UWM;
   const int c0 = cbk * CF::WGN + wc * CF::UWN;
@@ -432,6 +437,11 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   C* A = a.A + (size_t)blk * n * n;
   C* B = a.B + (size_t)blk * n * n;
   const C* MT = a.MT + (size_t)blk * NB * n;
+  // Every load below is unconditional from a clamped, in-bounds address, so
+  // the loads carry no branches and are issued ahead of the matrix-core work.
+  // Lanes of rows or columns that are not stored read finite data that never
+  // reaches an output; panel rows k >= jb (ragged last panel) multiply the
+  // rows of MT that the panel step wrote as zeros.
   C* cb[USC];
   bool cok[USC];
 #pragma unroll
@@ -440,31 +450,42 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
     cok[y] = col < ncols;
     cb[y] = colptr(A, B, n, j0, jb, cok[y] ? col : 0);
   }
+  auto row_ok = [&](int i) { return i < n && !(i >= j0 && i < j0 + jb); };
   UT acc;
-  acc.load([&](int r, int c) -> C {
-    const int i = i0 + r;
-    const int y = c / M::TN;
-    const bool ok = cok[y] && i < n && !(i >= j0 && i < j0 + jb);
-    return ok ? cb[y][(size_t)i * n] : cz<C>();
-  });
-#pragma unroll 4
+  acc.load([&](int r, int c) -> C { return cb[c / M::TN][(size_t)min(i0 + r, n - 1) * n]; });
+  const int kb = M::b_k(lane), ka = M::a_k(lane);
+  const C* bbase[USC];
+#pragma unroll
+  for (int y = 0; y < USC; ++y) bbase[y] = cb[y] + (size_t)j0 * n;
+  const C* abase[USR];
+#pragma unroll
+  for (int xx = 0; xx < USR; ++xx) abase[xx] = MT + (size_t)ka * n + min(i0 + xx * M::TM + M::a_row(lane), n - 1);
+  auto fetch = [&](int ks, C (&av)[USR], C (&bv)[USC]) {
+    const int kk = min(ks * M::KS + kb, jb - 1);
+#pragma unroll
+    for (int y = 0; y < USC; ++y) bv[y] = bbase[y][(size_t)kk * n];
+#pragma unroll
+    for (int xx = 0; xx < USR; ++xx) av[xx] = abase[xx][(size_t)(ks * M::KS) * n];
+  };
+  C av[PF][USR], bv[PF][USC];
+#pragma unroll
+  for (int s = 0; s < PF; ++s) fetch(s, av[s], bv[s]);
+#pragma unroll
   for (int ks = 0; ks < KSTEPS; ++ks) {
-    C av[USR], bv[USC];
-    const int k = ks * M::KS + M::b_k(lane);
+    const int cur = ks % PF;
+    C ca[USR], cbv[USC];
 #pragma unroll
-    for (int y = 0; y < USC; ++y) bv[y] = (cok[y] && k < jb) ? cb[y][(size_t)(j0 + k) * n] : cz<C>();
-    const int ka = ks * M::KS + M::a_k(lane);
+    for (int xx = 0; xx < USR; ++xx) ca[xx] = av[cur][xx];
 #pragma unroll
-    for (int xx = 0; xx < USR; ++xx) {
-      const int i = i0 + xx * M::TM + M::a_row(lane);
-      av[xx] = (i < n && ka < jb) ? MT[(size_t)ka * n + i] : cz<C>();
-    }
-    acc.mac(av, bv, true);
+    for (int y = 0; y < USC; ++y) cbv[y] = bv[cur][y];
+    if (ks + PF < KSTEPS) fetch(ks + PF, av[cur], bv[cur]);
+    __builtin_amdgcn_sched_barrier(0);     // keep the prefetch ahead of this step's MFMAs
+    acc.mac(ca, cbv, true);
   }
   acc.store([&](int r, int c, C v) {
     const int i = i0 + r;
     const int y = c / M::TN;
-    if (cok[y] && i < n && !(i >= j0 && i < j0 + jb)) cb[y][(size_t)i * n] = v;
+    if (cok[y] && row_ok(i)) cb[y][(size_t)i * n] = v;
   });
 }
 

@@ -111,4 +111,17 @@ __device__ inline double block_max(double v, double* red) {
   return r;
 }
 
+// Work-item order for a 2-D grid on the 8 XCDs of the chip. Workgroups are
+// dealt to the XCDs round-robin by linear id; this returns the logical id so
+// that the workgroups one XCD receives are consecutive in logical order (the
+// first eighth of the work goes to XCD 0, and so on), which keeps the operands
+// that neighbouring work items share in that XCD's own L2. A tail that does
+// not divide by 8 keeps the identity order.
+__device__ inline unsigned xcd_linear() {
+  const unsigned total = gridDim.x * gridDim.y;
+  const unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
+  const unsigned per = total >> 3;
+  return lin < (per << 3) ? (lin & 7u) * per + (lin >> 3) : lin;
+}
+
 }  // namespace pq
