@@ -178,7 +178,8 @@ __device__ void factor_block(C (*D)[NB + 1], int jb, double* pst) {
       pst[0] = fmin(pst[0], ap);
       pst[1] = fmax(pst[1], ap);
     }
-    for (int r = c + 1 + t; r < jb; r += blockDim.x) D[r][c] = cdiv(D[r][c], piv);
+    const C rp = cdiv(make_cone<C>(), piv);
+    for (int r = c + 1 + t; r < jb; r += blockDim.x) D[r][c] = cmul(D[r][c], rp);
     __syncthreads();
     const int rem = jb - c - 1;
     for (int idx = t; idx < rem * rem; idx += blockDim.x) {
@@ -189,52 +190,44 @@ __device__ void factor_block(C (*D)[NB + 1], int jb, double* pst) {
   }
 }
 
-// X = L^-1 of the unit-lower part of D (identity outside the jb x jb block).
+// Both triangular inverses of the factored block D = L U (unit L), written
+// into one array: X[i][j] = (L^-1)[i][j] for i > j and (U^-1)[i][j] for i <= j.
+// Wave 0 forward-substitutes L X = I and wave 1 back-substitutes U X = I, one
+// column per lane, so neither needs a barrier: a lane reads only its own
+// column of X (written earlier by itself) and D, which no wave writes here.
+// The k-loops are uniform across the wave (entries a lane does not need are
+// masked by a select), so the D reads are broadcasts.
 template <typename C, int NB>
-__device__ void invert_lower(C (*D)[NB + 1], C (*X)[NB + 1], int jb) {
-  const int t = threadIdx.x;
-  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
-    const int r = idx / NB, c = idx - (idx / NB) * NB;
-    C z = cz<C>();
-    if (r == c) z.x = 1;
-    X[r][c] = z;
-  }
-  __syncthreads();
-  // row by row: X[i][j] = -sum_{k=j}^{i-1} L[i][k] X[k][j]  (j < i)
-  for (int i = 1; i < jb; ++i) {
-    for (int j = t; j < i; j += blockDim.x) {
-      C s = cz<C>();
-      for (int k = j; k < i; ++k) s = cfms(s, D[i][k], X[k][j]);
-      X[i][j] = s;
-    }
-    __syncthreads();
-  }
-}
-
-// X = U^-1 of the upper part of D (zero outside the jb x jb block).
-template <typename C, int NB>
-__device__ void invert_upper(C (*D)[NB + 1], C (*X)[NB + 1], int jb) {
-  const int t = threadIdx.x;
-  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
-    const int r = idx / NB, c = idx - (idx / NB) * NB;
-    X[r][c] = cz<C>();
-  }
-  __syncthreads();
-  // rows bottom-up: X[i][i] = 1/U[i][i], X[i][j] = -(sum_{k=i+1}^{j} U[i][k] X[k][j]) / U[i][i]
-  for (int i = jb - 1; i >= 0; --i) {
-    for (int j = i + t; j < jb; j += blockDim.x) {
-      if (j == i) {
-        X[i][i] = cdiv(make_cone<C>(), D[i][i]);
-      } else {
-        C s = cz<C>();
-        for (int k = i + 1; k <= j; ++k) s = cfms(s, D[i][k], X[k][j]);
-        X[i][j] = cdiv(s, D[i][i]);
+__device__ void invert_triangles(C (*D)[NB + 1], C (*X)[NB + 1], int jb) {
+  const int wave = threadIdx.x >> 6, j = threadIdx.x & 63;
+  if (j >= NB) return;
+  if (wave == 0) {
+    // (L^-1)[i][j] = -sum_{k<i} L[i][k] x_k with x_j = 1, x_k = 0 for k < j
+    for (int i = 1; i < jb; ++i) {
+      C acc = cz<C>();
+#pragma unroll 8
+      for (int k = 0; k < i; ++k) {
+        C xk = X[k][j];
+        if (k <= j) { xk = cz<C>(); if (k == j) xk.x = 1; }
+        acc = cfms(acc, D[i][k], xk);
       }
+      if (i > j) X[i][j] = acc;
     }
-    __syncthreads();
+  } else if (wave == 1) {
+    // (U^-1)[i][j] = (delta_ij - sum_{k>i} U[i][k] x_k) / U[i][i], x_k = 0 for k > j
+    for (int i = jb - 1; i >= 0; --i) {
+      C acc = cz<C>();
+      if (i == j) acc.x = 1;
+#pragma unroll 8
+      for (int k = i + 1; k < jb; ++k) {
+        C xk = X[k][j];
+        if (k > j) xk = cz<C>();
+        acc = cfms(acc, D[i][k], xk);
+      }
+      if (i <= j) X[i][j] = cdiv(acc, D[i][i]);
+    }
   }
 }
-
 
 template <typename T>
 struct BseCtx {
@@ -289,6 +282,10 @@ __global__ __launch_bounds__(kThreads) void bse_init_kernel(BseCtx<T> a) {
 // ------------------------------------------------------------------- diag
 constexpr int kDiagThreads = kThreads;
 
+// LU of the diagonal block A_JJ in LDS and both triangular inverses: LI gets
+// L^-1 (identity outside the jb x jb block), UI[J] gets U^-1 (zero outside).
+// The factored block itself is not written back: later steps read only the
+// inverses.
 template <typename T, int NB>
 __global__ __launch_bounds__(kDiagThreads) void bse_diag_kernel(BseCtx<T> a, int j0) {
   using C = typename cplx_of<T>::type;
@@ -297,30 +294,60 @@ __global__ __launch_bounds__(kDiagThreads) void bse_diag_kernel(BseCtx<T> a, int
   __shared__ double pst[3];
   const int blk = blockIdx.x, t = threadIdx.x, n = a.n;
   const int jb = min(NB, n - j0);
-  C* A = a.A + (size_t)blk * n * n;
+  const C* A = a.A + (size_t)blk * n * n;
   double* gps = a.pst + (size_t)blk * 4;
   if (t < 3) pst[t] = gps[t];
   for (int idx = t; idx < NB * NB; idx += blockDim.x) {
     const int r = idx / NB, c = idx - (idx / NB) * NB;
-    D[r][c] = (r < jb && c < jb) ? A[(size_t)(j0 + r) * n + j0 + c] : cz<C>();
+    const C v = A[(size_t)(j0 + min(r, jb - 1)) * n + j0 + min(c, jb - 1)];
+    D[r][c] = (r < jb && c < jb) ? v : cz<C>();
   }
   __syncthreads();
   factor_block<C, NB>(D, jb, pst);
-  for (int idx = t; idx < jb * jb; idx += blockDim.x) {
-    const int r = idx / jb, c = idx - (idx / jb) * jb;
-    A[(size_t)(j0 + r) * n + j0 + c] = D[r][c];
-  }
-  invert_lower<C, NB>(D, X, jb);
-  C* LI = a.LI + (size_t)blk * NB * NB;
-  for (int idx = t; idx < NB * NB; idx += blockDim.x) LI[idx] = X[idx / NB][idx % NB];
+  invert_triangles<C, NB>(D, X, jb);
   __syncthreads();
-  invert_upper<C, NB>(D, X, jb);
+  C* LI = a.LI + (size_t)blk * NB * NB;
   C* UI = a.UI + ((size_t)blk * a.nJ + j0 / NB) * NB * NB;
-  for (int idx = t; idx < NB * NB; idx += blockDim.x) UI[idx] = X[idx / NB][idx % NB];
+  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+    const int r = idx / NB, c = idx - (idx / NB) * NB;
+    const C x = X[r][c];
+    C l = cz<C>(), u = cz<C>();
+    if (r == c) l.x = 1;
+    if (r > c && r < jb) l = x;
+    if (r <= c && c < jb) u = x;
+    LI[idx] = l;
+    UI[idx] = u;
+  }
   if (t < 3) gps[t] = pst[t];
 }
 
 // ------------------------------------------------------------------ panel
+// acc += sum_{k < NB} a(k) b(k) over one full panel: the a operand comes from
+// LDS through fa(ks, av), the b operand from global memory through fb(ks, bv)
+// with branch-free loads issued PF k-steps ahead of the matrix cores.
+// Triangular operands are used whole (their zero half costs matrix-core time
+// but keeps the loop fixed-length and fully pipelined).
+template <typename T, int NB, class FA, class FB>
+__device__ inline void panel_kloop(WTile<T>& acc, FA fa, FB fb) {
+  using C = typename cplx_of<T>::type;
+  using M = Mma<T>;
+  constexpr int SR = WTile<T>::SR, SC = WTile<T>::SC, KSTEPS = NB / M::KS, PF = 2;
+  C bq[PF][SC];
+#pragma unroll
+  for (int s = 0; s < PF; ++s) fb(s, bq[s]);
+#pragma unroll
+  for (int ks = 0; ks < KSTEPS; ++ks) {
+    const int cur = ks % PF;
+    C bv[SC], av[SR];
+#pragma unroll
+    for (int y = 0; y < SC; ++y) bv[y] = bq[cur][y];
+    if (ks + PF < KSTEPS) fb(ks + PF, bq[cur]);
+    fa(ks, av);
+    __builtin_amdgcn_sched_barrier(0);
+    acc.mac(av, bv, false);
+  }
+}
+
 // x < nwb: row-panel workgroups, 4 column strips of 32 each (one per wave);
 // x >= nwb: multiplier workgroups, 4 row strips of 32 each.
 template <typename T, int NB>
@@ -328,7 +355,7 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
   using WT = WTile<T>;
-  constexpr int SR = WT::SR, SC = WT::SC, KSTEPS = NB / M::KS;
+  constexpr int SR = WT::SR, SC = WT::SC;
   __shared__ C X[NB][NB + 1];
   const int blk = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
   const int jb = min(NB, n - j0);
@@ -339,68 +366,62 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
   const C* src = rowpanel ? a.LI + (size_t)blk * NB * NB : a.UI + ((size_t)blk * a.nJ + j0 / NB) * NB * NB;
   for (int idx = t; idx < NB * NB; idx += blockDim.x) X[idx / NB][idx % NB] = src[idx];
   __syncthreads();
+  const int kb = M::b_k(lane);
   if (rowpanel) {
-    // U_JK = L^-1 A_JK in place; row tile rt of L^-1 A reads input rows only up
-    // to the end of tile rt, so the tiles go bottom-up.
+    // U_JK = L^-1 A_JK in place. Row tile rt of the product needs input rows
+    // <= its own last row only (L^-1 is lower triangular), so the tiles go
+    // bottom-up; the rows an upper tile has already overwritten meet exact
+    // zeros of L^-1.
     const int cs = blockIdx.x * kWaves + wave;
     if (cs * 32 >= ncols) return;
+    const C* cp[SC];
+#pragma unroll
+    for (int y = 0; y < SC; ++y)
+      cp[y] = colptr(A, B, n, j0, jb, min(cs * 32 + y * M::TN + M::b_col(lane), ncols - 1)) + (size_t)j0 * n;
     for (int rt = NB / 32 - 1; rt >= 0; --rt) {
       WT acc;
       acc.zero();
-      const int kend = min(jb, rt * 32 + 32);
-#pragma unroll 2
-      for (int ks = 0; ks < KSTEPS; ++ks) {
-        if (ks * M::KS >= kend) break;
-        C bv[SC];
+      panel_kloop<T, NB>(acc,
+          [&](int ks, C (&av)[SR]) {
 #pragma unroll
-        for (int y = 0; y < SC; ++y) {
-          const int col = cs * 32 + y * M::TN + M::b_col(lane);
-          const int k = ks * M::KS + M::b_k(lane);
-          bv[y] = (col < ncols && k < jb) ? colptr(A, B, n, j0, jb, col)[(size_t)(j0 + k) * n] : cz<C>();
-        }
-        C av[SR];
+            for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
+          },
+          [&](int ks, C (&bv)[SC]) {
+            const int k = min(ks * M::KS + kb, jb - 1);
 #pragma unroll
-        for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
-        acc.mac(av, bv, false);
-      }
+            for (int y = 0; y < SC; ++y) bv[y] = cp[y][(size_t)k * n];
+          });
       acc.store([&](int r, int c, C v) {
         const int row = rt * 32 + r, col = cs * 32 + c;
         if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
       });
     }
   } else {
-    // MT = U^-T A_IJ^T: rows k of the panel, columns i = every row of A
+    // MT = U^-T A_IJ^T: rows k of the panel, columns i = every row of A. Rows
+    // jb..NB-1 (ragged last panel) come out exactly zero, since U^-1 is zero
+    // outside the jb x jb block; the update reads them unmasked.
     const int is = (blockIdx.x - nwb) * kWaves + wave;
     if (is * 32 >= n) return;
     C* MT = a.MT + (size_t)blk * NB * n;
+    const C* rp[SC];
+#pragma unroll
+    for (int y = 0; y < SC; ++y) rp[y] = A + (size_t)min(is * 32 + y * M::TN + M::b_col(lane), n - 1) * n + j0;
     for (int rt = 0; rt < NB / 32; ++rt) {
       WT acc;
       acc.zero();
-      const int kend = min(jb, rt * 32 + 32);              // (U^-1)^T is lower triangular
-#pragma unroll 2
-      for (int ks = 0; ks < KSTEPS; ++ks) {
-        if (ks * M::KS >= kend) break;
-        C bv[SC];
+      panel_kloop<T, NB>(acc,
+          [&](int ks, C (&av)[SR]) {
 #pragma unroll
-        for (int y = 0; y < SC; ++y) {
-          const int i = is * 32 + y * M::TN + M::b_col(lane);
-          const int k = ks * M::KS + M::b_k(lane);
-          bv[y] = (i < n && k < jb) ? A[(size_t)i * n + j0 + k] : cz<C>();
-        }
-        C av[SR];
+            for (int xx = 0; xx < SR; ++xx) av[xx] = X[ks * M::KS + M::a_k(lane)][rt * 32 + xx * M::TM + M::a_row(lane)];
+          },
+          [&](int ks, C (&bv)[SC]) {
+            const int k = min(ks * M::KS + kb, jb - 1);
 #pragma unroll
-        for (int xx = 0; xx < SR; ++xx) {
-          const int row = rt * 32 + xx * M::TM + M::a_row(lane);        // output row
-          const int k = ks * M::KS + M::a_k(lane);
-          av[xx] = X[k][row];                                            // (U^-1)^T[row][k]
-        }
-        acc.mac(av, bv, false);
-      }
-      // rows jb..NB-1 (ragged last panel) come out exactly zero, since U^-1 is
-      // the identity outside the jb x jb block; the update reads them unmasked
+            for (int y = 0; y < SC; ++y) bv[y] = rp[y][k];
+          });
       acc.store([&](int r, int c, C v) {
         const int row = rt * 32 + r, i = is * 32 + c;
-        if (row < NB && i < n) MT[(size_t)row * n + i] = v;
+        if (i < n) MT[(size_t)row * n + i] = v;
       });
     }
   }
@@ -423,7 +444,7 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   using CF = UpdCfg<T, NB>;
   using UT = WTile<T, CF::UWM, CF::UWN>;
   constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS;
-  constexpr int PF = 2;                      // operand prefetch distance (k-steps)
+  constexpr int PF = sizeof(T) == 4 ? 2 : 1;  // operand prefetch distance (k-steps)
   const unsigned lid = xcd_linear();
   const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = a.n;
@@ -496,7 +517,7 @@ __global__ __launch_bounds__(kThreads) void bse_final_kernel(BseCtx<T> a, int ns
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
   using WT = WTile<T>;
-  constexpr int SR = WT::SR, SC = WT::SC, KSTEPS = NB / M::KS;
+  constexpr int SR = WT::SR, SC = WT::SC;
   __shared__ C X[NB][NB + 1];
   const int blk = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
   const int J = blockIdx.x / nstripw, sw = blockIdx.x - (blockIdx.x / nstripw) * nstripw;
@@ -522,40 +543,45 @@ __global__ __launch_bounds__(kThreads) void bse_final_kernel(BseCtx<T> a, int ns
   C* P = a.phi + (size_t)blk * nn;
   const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
   const bool mix = a.alpha != 1.0;
+  const int kb = M::b_k(lane);
+  const C* cp[SC];
+#pragma unroll
+  for (int y = 0; y < SC; ++y) cp[y] = B + (size_t)j0 * n + min(cs * 32 + y * M::TN + M::b_col(lane), n - 1);
   for (int rt = 0; rt < NB / 32; ++rt) {
     WT acc;
     acc.zero();
-#pragma unroll 2
-    for (int ks = 0; ks < KSTEPS; ++ks) {
-      if (ks * M::KS + M::KS <= rt * 32) continue;        // U^-1 upper triangular
-      C bv[SC];
+    panel_kloop<T, NB>(acc,
+        [&](int ks, C (&av)[SR]) {
 #pragma unroll
-      for (int y = 0; y < SC; ++y) {
-        const int col = cs * 32 + y * M::TN + M::b_col(lane);
-        const int k = ks * M::KS + M::b_k(lane);
-        bv[y] = (col < n && k < jb) ? B[(size_t)(j0 + k) * n + col] : cz<C>();
-      }
-      C av[SR];
+          for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
+        },
+        [&](int ks, C (&bv)[SC]) {
+          const int k = min(ks * M::KS + kb, jb - 1);
 #pragma unroll
-      for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
-      acc.mac(av, bv, false);
-    }
-    acc.store([&](int r, int c, C f) {
-      const int row = rt * 32 + r, col = cs * 32 + c;
-      if (row < jb && col < n) {
-        const size_t idx = (size_t)(j0 + row) * n + col;
-        const C g = G[idx];
-        C v;
-        v.x = f.x - g.x;
-        v.y = f.y - g.y;
-        if (mix) {
-          const C old = P[idx];
-          v.x = al * v.x + be * old.x;
-          v.y = al * v.y + be * old.y;
+          for (int y = 0; y < SC; ++y) bv[y] = cp[y][(size_t)k * n];
+        });
+    // epilogue: Gamma and the old Phi are gathered with unconditional loads
+    // from clamped addresses first, then combined and stored where in range
+    auto at = [&](int r, int c) { return (size_t)(j0 + min(rt * 32 + r, jb - 1)) * n + min(cs * 32 + c, n - 1); };
+    WT g, old;
+    g.load([&](int r, int c) { return G[at(r, c)]; });
+    if (mix) old.load([&](int r, int c) { return P[at(r, c)]; });
+#pragma unroll
+    for (int x = 0; x < SR; ++x)
+#pragma unroll
+      for (int y = 0; y < SC; ++y)
+#pragma unroll
+        for (int v = 0; v < M::NV; ++v) {
+          const int row = rt * 32 + x * M::TM + M::c_row(lane, v), col = cs * 32 + y * M::TN + M::c_col(lane);
+          C o;
+          o.x = acc.re[x][y][v] - g.re[x][y][v];
+          o.y = acc.im[x][y][v] - g.im[x][y][v];
+          if (mix) {
+            o.x = al * o.x + be * old.re[x][y][v];
+            o.y = al * o.y + be * old.im[x][y][v];
+          }
+          if (row < jb && col < n) P[(size_t)(j0 + row) * n + col] = o;
         }
-        P[idx] = v;
-      }
-    });
   }
 }
 
