@@ -8,8 +8,9 @@ Schwinger-Dyson self-energy, the four Bethe-Salpeter solves and the mixing.
 
 The reported value is iterations/s of the complex64 path (FP32 matrix-core
 BSE); the plain complex128 path (FP64 matrix cores everywhere) is timed next
-to it. The roofline object covers the dominant kernel, the BSE solve, whose
-launch time comes from HIP events recorded on the solver's stream; the CPU
+to it. The roofline object covers the dominant kernel, the rank-NB trailing
+update of the BSE elimination, whose launch time comes from HIP events
+recorded on the solver's stream around each launch; the CPU
 baseline times the FP64 oracle on a bounded sample of the same workload and
 extrapolates to one iteration.
 """
@@ -37,8 +38,9 @@ def bse_flops_per_launch(d) -> float:
 
 
 def measured_traffic():
-    """HBM bytes per BSE launch from the committed counter runs, or None when the
-    kernel source has changed since they were taken."""
+    """HBM bytes per launch of the BSE update kernel (FETCH_SIZE + WRITE_SIZE,
+    each scaled by what it reads for a plain device copy) from the committed
+    counter runs, or None when the kernel source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "bse_traffic_8x8_nv16_c64.json")
     try:
@@ -189,8 +191,8 @@ def main():
                     help="run a plain 2 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU q-sharding "
-              "is a design note, not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the solver runs on a "
+              "single device; sharding over the transfer q across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     from workloads import config

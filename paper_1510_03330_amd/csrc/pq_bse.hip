@@ -430,25 +430,29 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 // ----------------------------------------------------------------- update
 // C[i][col] -= sum_k MT[k][i] U[k][col] for every row i outside the panel.
 // Workgroup tile (2 UWM) x (2 UWN), waves 2 x 2, each wave a UWM x UWN tile.
-template <typename T, int NB>
+// Tile shape and pipelining of the update: wave tile UWM x UWN, workgroup of
+// 2 x 2 waves, operand prefetch PF k-steps ahead; FULL = the panel is NB wide
+// (every panel but a ragged last one), so the panel rows need no clamping.
+template <typename T, int UWM_, int UWN_, int PF_, int WPE_, bool FULL_>
 struct UpdCfg {
-  static constexpr int UWM = sizeof(T) == 4 ? 64 : 32, UWN = 32;
+  static constexpr int UWM = UWM_, UWN = UWN_, PF = PF_, WPE = WPE_;
+  static constexpr bool FULL = FULL_;
   static constexpr int WGM = 2 * UWM, WGN = 2 * UWN;
 };
+template <typename T, bool FULL>
+using UpdDefault = UpdCfg<T, sizeof(T) == 4 ? 64 : 32, 32, sizeof(T) == 4 ? 2 : 1, 4, FULL>;
 
-template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+template <typename T, int NB, class CF>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CF::WPE)))
 void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
-  using CF = UpdCfg<T, NB>;
   using UT = WTile<T, CF::UWM, CF::UWN>;
-  constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS;
-  constexpr int PF = sizeof(T) == 4 ? 2 : 1;  // operand prefetch distance (k-steps)
+  constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS, PF = CF::PF;
   const unsigned lid = xcd_linear();
   const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = a.n;
-  const int jb = min(NB, n - j0);
+  const int jb = CF::FULL ? NB : min(NB, n - j0);
   const int ncols = (n - j0 - jb) + n;
   const int rb = bx / ncb, cbk = bx - (bx / ncb) * ncb;
   const int wr = wave & 1, wc = wave >> 1;
@@ -477,14 +481,19 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   const int kb = M::b_k(lane), ka = M::a_k(lane);
   const C* bbase[USC];
 #pragma unroll
-  for (int y = 0; y < USC; ++y) bbase[y] = cb[y] + (size_t)j0 * n;
+  for (int y = 0; y < USC; ++y) bbase[y] = cb[y] + (size_t)(j0 + (CF::FULL ? kb : 0)) * n;
   const C* abase[USR];
 #pragma unroll
   for (int xx = 0; xx < USR; ++xx) abase[xx] = MT + (size_t)ka * n + min(i0 + xx * M::TM + M::a_row(lane), n - 1);
   auto fetch = [&](int ks, C (&av)[USR], C (&bv)[USC]) {
-    const int kk = min(ks * M::KS + kb, jb - 1);
+    if (CF::FULL) {
 #pragma unroll
-    for (int y = 0; y < USC; ++y) bv[y] = bbase[y][(size_t)kk * n];
+      for (int y = 0; y < USC; ++y) bv[y] = bbase[y][(size_t)(ks * M::KS) * n];
+    } else {
+      const int kk = min(ks * M::KS + kb, jb - 1);
+#pragma unroll
+      for (int y = 0; y < USC; ++y) bv[y] = bbase[y][(size_t)kk * n];
+    }
 #pragma unroll
     for (int xx = 0; xx < USR; ++xx) av[xx] = abase[xx][(size_t)(ks * M::KS) * n];
   };
@@ -508,6 +517,15 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
     const int y = c / M::TN;
     if (cok[y] && row_ok(i)) cb[y][(size_t)i * n] = v;
   });
+}
+
+template <typename T, int NB, class CF>
+void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, hipStream_t s) {
+  const int jb = std::min(NB, n - j0);
+  const int ncols = (n - j0 - jb) + n;
+  const int nrb = (n + CF::WGM - 1) / CF::WGM;
+  const int ncb = (ncols + CF::WGN - 1) / CF::WGN;
+  hipLaunchKernelGGL((bse_update_kernel<T, NB, CF>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb);
 }
 
 // ------------------------------------------------------------------ final
@@ -624,7 +642,6 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
                           hipStream_t s, BseTiming* tm) {
   using C = typename cplx_of<T>::type;
   constexpr int NB = panel_width<T>();
-  using CF = UpdCfg<T, NB>;
   static const double kSign[4] = {1.0, 1.0, -1.0, 1.0};
   const BseLayout L = bse_layout<T>(d);
   char* w = (char*)ws;
@@ -675,10 +692,11 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     pre(2);
     hipLaunchKernelGGL((bse_panel_kernel<T, NB>), dim3(nwb + nwc, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
     post();
-    const int nrb = (n + CF::WGM - 1) / CF::WGM;
-    const int ncb = (ncols + CF::WGN - 1) / CF::WGN;
     pre(3);
-    hipLaunchKernelGGL((bse_update_kernel<T, NB>), dim3(nrb * ncb, d.Nq), dim3(kThreads), 0, s, a, j0, ncb);
+    if (jb == NB)
+      launch_update<T, NB, UpdDefault<T, true>>(a, n, d.Nq, j0, s);
+    else
+      launch_update<T, NB, UpdDefault<T, false>>(a, n, d.Nq, j0, s);
     post();
     if (tm) tm->update_flops += 8.0 * (double)(n - jb) * ncols * jb * d.Nq;
   }
