@@ -224,13 +224,13 @@ def main():
     bse_alg = bse_flops_per_launch(d) / (bse_channel_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(),
-            "kernel": "bse_update_kernel<float,64> (one launch = one rank-64 panel update of %d blocks, n=%d)"
-                      % (d.Nq, d.n),
+            "kernel": "bse_update_kernel<float,128> (one launch = one rank-128 Gauss-Jordan panel update "
+                      "of %d blocks, n=%d)" % (d.Nq, d.n),
             "avg_launch_ms": round(upd_ms, 3), "flops_per_launch": upd_flops,
             "bse_solve_lu_equivalent_tflops": round(bse_alg, 2),
             "bse_solve_ms_per_channel": round(bse_channel_ms, 2),
             "bse_kernel_ms_per_channel": {k: round(r32["kern_ms"][i] / args.steps, 2) for k, i in
-                                          (("init", 0), ("diag", 1), ("panel", 2), ("update", 3), ("final", 4))}}
+                                          (("init", 0), ("pivot", 1), ("panel", 2), ("update", 3), ("epilogue", 4))}}
 
     out = {
         "metric": "parquet iterations/s + time-to-converged Σ (1e-6) vs FP64 GPU, 8x8 Nv=16",

@@ -4,29 +4,30 @@
 // followed by Phi <- alpha (F - Gamma) + (1 - alpha) Phi.
 //
 // Blocked Gauss-Jordan elimination on the augmented [A | B] (B = Gamma) with
-// panel width NB and no row exchanges, batched over all q blocks of a channel:
-// every step is one kernel launch over (q block, tile) grids. Per panel J:
-//   (a) bse_diag:   factor the NB x NB diagonal block in LDS, A_JJ = L_JJ U_JJ,
-//                   and invert both triangular factors (one workgroup per block);
-//   (b) bse_panel:  row panel U_JK = L_JJ^-1 A_JK for every column right of the
-//                   panel in A and every column of B (in place, row tiles
-//                   bottom-up), and
-//   (c)             multipliers M_IJ = A_IJ U_JJ^-1 for every row, stored k-major
-//                   (MT[k][i] = (U_JJ^-T A_IJ^T)[k][i]) so operand loads coalesce;
-//   (d) bse_update: A_IK -= M_IJ U_JK, B_I -= M_IJ U_JB for all rows I != J, a
+// panel width NB (128 for complex64, 64 for complex128) and no row exchanges,
+// batched over all q blocks of a channel: every step is one kernel launch over
+// (q block, tile) grids. Per panel J:
+//   (a) bse_pivot:  P = A_JJ^-1 by Gauss-Jordan on the NB x NB diagonal block,
+//                   held in registers (one column per thread and a slice of its
+//                   rows), pivot rows and columns broadcast through LDS;
+//   (b) bse_panel:  pivot rows R_JK = P A_JK for every column right of the
+//                   panel in A and every column of B (in place), and the
+//                   multipliers A_IJ copied k-major (MT[k][i] = A[i][J0 + k])
+//                   so that the update's operand loads coalesce;
+//   (c) bse_update: A_IK -= A_IJ R_JK, B_I -= A_IJ R_JB for all rows I != J, a
 //                   rank-NB update; each wave owns a 64 x 32 (complex64) or
 //                   32 x 32 (complex128) tile and reads both operands straight
 //                   from L1/L2, so no LDS is needed and four waves share a SIMD.
-// After the last panel every row block satisfies U_JJ F_J = B_J; bse_final
-// applies F_J = U_JJ^-1 B_J fused with the Phi epilogue. Steps (b)-(d) and the
-// final solve are complex products on the matrix cores, four real MFMAs per
-// complex product: v_mfma_f32_32x32x2f32 (complex64) or v_mfma_f64_16x16x4f64
-// (complex128).
+// After the last panel A is the identity and B holds F; bse_epilogue applies
+// the mixing. Steps (b) and (c) are complex products on the matrix cores, four
+// real MFMAs per complex product: v_mfma_f32_32x32x2f32 (complex64) or
+// v_mfma_f64_16x16x4f64 (complex128).
 //
 // No row exchanges: A is the identity minus the small-norm kernel s Gamma X,
 // and every leading principal block of it stays invertible while the BSE is
-// away from its instability. The pivot monitor records min|u_jj| / max|u_jj|
-// per block and flags weak or non-finite blocks.
+// away from its instability. The pivot monitor records the smallest and
+// largest pivot modulus of the elimination per block (the same pivots an LU
+// factorisation without exchanges meets) and flags weak or non-finite blocks.
 #include <float.h>
 
 #include <algorithm>
@@ -159,74 +160,12 @@ template <typename C> __device__ inline double cabs_d(C a) {
   return sqrt((double)a.x * a.x + (double)a.y * a.y);
 }
 
+
 // Column pointer in the combined column space [A columns right of the panel | B].
 template <typename C>
 __device__ inline C* colptr(C* A, C* B, int n, int j0, int jb, int c) {
   const int ncolA = n - j0 - jb;
   return c < ncolA ? A + (j0 + jb + c) : B + (c - ncolA);
-}
-
-// LU of the jb x jb block in D (no exchanges); pivot stats in pst.
-template <typename C, int NB>
-__device__ void factor_block(C (*D)[NB + 1], int jb, double* pst) {
-  const int t = threadIdx.x;
-  for (int c = 0; c < jb; ++c) {
-    const C piv = D[c][c];
-    if (t == 0) {
-      const double ap = cabs_d(piv);
-      if (!(ap == ap) || ap > DBL_MAX) pst[2] = 1.0;
-      pst[0] = fmin(pst[0], ap);
-      pst[1] = fmax(pst[1], ap);
-    }
-    const C rp = cdiv(make_cone<C>(), piv);
-    for (int r = c + 1 + t; r < jb; r += blockDim.x) D[r][c] = cmul(D[r][c], rp);
-    __syncthreads();
-    const int rem = jb - c - 1;
-    for (int idx = t; idx < rem * rem; idx += blockDim.x) {
-      const int r = c + 1 + idx / rem, cc = c + 1 + idx - (idx / rem) * rem;
-      D[r][cc] = cfms(D[r][cc], D[r][c], D[c][cc]);
-    }
-    __syncthreads();
-  }
-}
-
-// Both triangular inverses of the factored block D = L U (unit L), written
-// into one array: X[i][j] = (L^-1)[i][j] for i > j and (U^-1)[i][j] for i <= j.
-// Wave 0 forward-substitutes L X = I and wave 1 back-substitutes U X = I, one
-// column per lane, so neither needs a barrier: a lane reads only its own
-// column of X (written earlier by itself) and D, which no wave writes here.
-// The k-loops are uniform across the wave (entries a lane does not need are
-// masked by a select), so the D reads are broadcasts.
-template <typename C, int NB>
-__device__ void invert_triangles(C (*D)[NB + 1], C (*X)[NB + 1], int jb) {
-  const int wave = threadIdx.x >> 6, j = threadIdx.x & 63;
-  if (j >= NB) return;
-  if (wave == 0) {
-    // (L^-1)[i][j] = -sum_{k<i} L[i][k] x_k with x_j = 1, x_k = 0 for k < j
-    for (int i = 1; i < jb; ++i) {
-      C acc = cz<C>();
-#pragma unroll 8
-      for (int k = 0; k < i; ++k) {
-        C xk = X[k][j];
-        if (k <= j) { xk = cz<C>(); if (k == j) xk.x = 1; }
-        acc = cfms(acc, D[i][k], xk);
-      }
-      if (i > j) X[i][j] = acc;
-    }
-  } else if (wave == 1) {
-    // (U^-1)[i][j] = (delta_ij - sum_{k>i} U[i][k] x_k) / U[i][i], x_k = 0 for k > j
-    for (int i = jb - 1; i >= 0; --i) {
-      C acc = cz<C>();
-      if (i == j) acc.x = 1;
-#pragma unroll 8
-      for (int k = i + 1; k < jb; ++k) {
-        C xk = X[k][j];
-        if (k > j) xk = cz<C>();
-        acc = cfms(acc, D[i][k], xk);
-      }
-      if (i <= j) X[i][j] = cdiv(acc, D[i][i]);
-    }
-  }
 }
 
 template <typename T>
@@ -241,9 +180,8 @@ struct BseCtx {
   C* phi;                // [Nq][n][n]
   C* A;                  // [Nq][n][n]
   C* B;                  // [Nq][n][n]
-  C* MT;                 // [Nq][NB][n]
-  C* LI;                 // [Nq][NB][NB]   L^-1 of the current panel
-  C* UI;                 // [Nq][nJ][NB][NB] U^-1 of every panel
+  C* MT;                 // [Nq][NB][n]    multipliers of the current panel, k-major
+  C* PI;                 // [Nq][NB][NB]   inverse of the current diagonal block
   double* pst;           // [Nq][4]  min |pivot|, max |pivot|, non-finite seen
   pq_bse_block_stats* stats;
 };
@@ -279,157 +217,172 @@ __global__ __launch_bounds__(kThreads) void bse_init_kernel(BseCtx<T> a) {
   }
 }
 
-// ------------------------------------------------------------------- diag
-constexpr int kDiagThreads = kThreads;
+// ------------------------------------------------------------------ pivot
+// P = A_JJ^-1 by in-place Gauss-Jordan on the diagonal block (identity outside
+// the jb x jb part for a ragged last panel). Thread t holds column j = t % NB
+// of the block for the RPT rows h RPT .. h RPT + RPT - 1, h = t / NB, in
+// registers (RPT = 32 for NB = 128 with 512 threads, 16 for NB = 64). Step c publishes the pivot column and row through LDS (double
+// buffered, one barrier per step), then every thread updates its entries:
+//   row c:           x <- x / p            (column c: x <- 1 / p)
+//   other rows r:    x <- x - D[r][c] D[c][j] / p   (column c: x <- -D[r][c] / p)
+template <int NB> constexpr int pivot_threads() { return NB >= 128 ? 512 : 256; }
 
-// LU of the diagonal block A_JJ in LDS and both triangular inverses: LI gets
-// L^-1 (identity outside the jb x jb block), UI[J] gets U^-1 (zero outside).
-// The factored block itself is not written back: later steps read only the
-// inverses.
 template <typename T, int NB>
-__global__ __launch_bounds__(kDiagThreads) void bse_diag_kernel(BseCtx<T> a, int j0) {
+__global__ __launch_bounds__(pivot_threads<NB>()) void bse_pivot_kernel(BseCtx<T> a, int j0) {
   using C = typename cplx_of<T>::type;
-  __shared__ C D[NB][NB + 1];
-  __shared__ C X[NB][NB + 1];
-  __shared__ double pst[3];
+  constexpr int RPT = NB * NB / pivot_threads<NB>();
+  __shared__ C colbuf[2][NB];
+  __shared__ C rowbuf[2][NB];
   const int blk = blockIdx.x, t = threadIdx.x, n = a.n;
+  const int j = t % NB, h = t / NB, r0 = h * RPT;
   const int jb = min(NB, n - j0);
   const C* A = a.A + (size_t)blk * n * n;
-  double* gps = a.pst + (size_t)blk * 4;
-  if (t < 3) pst[t] = gps[t];
-  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
-    const int r = idx / NB, c = idx - (idx / NB) * NB;
-    const C v = A[(size_t)(j0 + min(r, jb - 1)) * n + j0 + min(c, jb - 1)];
-    D[r][c] = (r < jb && c < jb) ? v : cz<C>();
+  C x[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = r0 + q;
+    const C v = A[(size_t)(j0 + min(r, jb - 1)) * n + j0 + min(j, jb - 1)];
+    C e = cz<C>();
+    if (r == j) e.x = 1;
+    x[q] = (r < jb && j < jb) ? v : e;
   }
-  __syncthreads();
-  factor_block<C, NB>(D, jb, pst);
-  invert_triangles<C, NB>(D, X, jb);
-  __syncthreads();
-  C* LI = a.LI + (size_t)blk * NB * NB;
-  C* UI = a.UI + ((size_t)blk * a.nJ + j0 / NB) * NB * NB;
-  for (int idx = t; idx < NB * NB; idx += blockDim.x) {
-    const int r = idx / NB, c = idx - (idx / NB) * NB;
-    const C x = X[r][c];
-    C l = cz<C>(), u = cz<C>();
-    if (r == c) l.x = 1;
-    if (r > c && r < jb) l = x;
-    if (r <= c && c < jb) u = x;
-    LI[idx] = l;
-    UI[idx] = u;
+  double pmin = DBL_MAX, pmax = 0.0;
+  bool bad = false;
+  for (int c = 0; c < jb; ++c) {
+    const int bf = c & 1;
+    if (j == c) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) colbuf[bf][r0 + q] = x[q];
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (r0 + q == c) rowbuf[bf][j] = x[q];
+    __syncthreads();
+    const C piv = colbuf[bf][c];
+    if (t == 0) {
+      const double ap = cabs_d(piv);
+      if (!(ap == ap) || ap > DBL_MAX) bad = true;
+      pmin = fmin(pmin, ap);
+      pmax = fmax(pmax, ap);
+    }
+    const C p = cdiv(make_cone<C>(), piv);
+    const bool pc = j == c;
+    const C u = pc ? p : cmul(rowbuf[bf][j], p);
+    // the pivot column is read in chunks of 16 entries (wide broadcast reads
+    // issued together), then applied
+#pragma unroll
+    for (int q0 = 0; q0 < RPT; q0 += 16) {
+      C cv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) cv[q] = colbuf[bf][r0 + q0 + q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int r = r0 + q0 + q;
+        const C m = cfms(pc ? cz<C>() : x[q0 + q], cv[q], u);
+        x[q0 + q] = (r == c) ? u : m;
+      }
+    }
   }
-  if (t < 3) gps[t] = pst[t];
+  C* P = a.PI + (size_t)blk * NB * NB;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) P[(size_t)(r0 + q) * NB + j] = x[q];
+  if (t == 0) {
+    double* ps = a.pst + (size_t)blk * 4;
+    ps[0] = fmin(ps[0], pmin);
+    ps[1] = fmax(ps[1], pmax);
+    if (bad) ps[2] = 1.0;
+  }
 }
 
 // ------------------------------------------------------------------ panel
-// acc += sum_{k < NB} a(k) b(k) over one full panel: the a operand comes from
-// LDS through fa(ks, av), the b operand from global memory through fb(ks, bv)
-// with branch-free loads issued PF k-steps ahead of the matrix cores.
-// Triangular operands are used whole (their zero half costs matrix-core time
-// but keeps the loop fixed-length and fully pipelined).
-template <typename T, int NB, class FA, class FB>
-__device__ inline void panel_kloop(WTile<T>& acc, FA fa, FB fb) {
-  using C = typename cplx_of<T>::type;
-  using M = Mma<T>;
-  constexpr int SR = WTile<T>::SR, SC = WTile<T>::SC, KSTEPS = NB / M::KS, PF = 2;
-  C bq[PF][SC];
-#pragma unroll
-  for (int s = 0; s < PF; ++s) fb(s, bq[s]);
-#pragma unroll
-  for (int ks = 0; ks < KSTEPS; ++ks) {
-    const int cur = ks % PF;
-    C bv[SC], av[SR];
-#pragma unroll
-    for (int y = 0; y < SC; ++y) bv[y] = bq[cur][y];
-    if (ks + PF < KSTEPS) fb(ks + PF, bq[cur]);
-    fa(ks, av);
-    __builtin_amdgcn_sched_barrier(0);
-    acc.mac(av, bv, false);
-  }
-}
-
-// x < nwb: row-panel workgroups, 4 column strips of 32 each (one per wave);
-// x >= nwb: multiplier workgroups, 4 row strips of 32 each.
+// x < nwb: pivot-row workgroups, one 32-column strip per wave: R = P A_J,strip
+// for all NB rows of the panel at once (NB / 32 accumulator tiles), written in
+// place after the whole strip has been read. x >= nwb: multiplier workgroups,
+// 32 rows each: A[i][J0 .. J0 + NB) through an LDS transpose into MT[k][i];
+// rows k >= jb of MT (ragged last panel) are written as zeros, so the update
+// reads them unmasked.
 template <typename T, int NB>
 __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
   using WT = WTile<T>;
-  constexpr int SR = WT::SR, SC = WT::SC;
-  __shared__ C X[NB][NB + 1];
+  constexpr int SR = WT::SR, SC = WT::SC, KSTEPS = NB / M::KS, NRT = NB / 32, PF = 2;
+  __shared__ C X[32][NB + 1];
   const int blk = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
   const int jb = min(NB, n - j0);
   const int ncols = (n - j0 - jb) + n;
   C* A = a.A + (size_t)blk * n * n;
   C* B = a.B + (size_t)blk * n * n;
-  const bool rowpanel = (int)blockIdx.x < nwb;
-  const C* src = rowpanel ? a.LI + (size_t)blk * NB * NB : a.UI + ((size_t)blk * a.nJ + j0 / NB) * NB * NB;
-  for (int idx = t; idx < NB * NB; idx += blockDim.x) X[idx / NB][idx % NB] = src[idx];
-  __syncthreads();
-  const int kb = M::b_k(lane);
-  if (rowpanel) {
-    // U_JK = L^-1 A_JK in place. Row tile rt of the product needs input rows
-    // <= its own last row only (L^-1 is lower triangular), so the tiles go
-    // bottom-up; the rows an upper tile has already overwritten meet exact
-    // zeros of L^-1.
+  if ((int)blockIdx.x < nwb) {
     const int cs = blockIdx.x * kWaves + wave;
     if (cs * 32 >= ncols) return;
+    const C* P = a.PI + (size_t)blk * NB * NB;
+    const int kb = M::b_k(lane);
     const C* cp[SC];
 #pragma unroll
     for (int y = 0; y < SC; ++y)
       cp[y] = colptr(A, B, n, j0, jb, min(cs * 32 + y * M::TN + M::b_col(lane), ncols - 1)) + (size_t)j0 * n;
-    for (int rt = NB / 32 - 1; rt >= 0; --rt) {
-      WT acc;
-      acc.zero();
-      panel_kloop<T, NB>(acc,
-          [&](int ks, C (&av)[SR]) {
+    const C* pa[NRT][SR];
 #pragma unroll
-            for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
-          },
-          [&](int ks, C (&bv)[SC]) {
-            const int k = min(ks * M::KS + kb, jb - 1);
+    for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-            for (int y = 0; y < SC; ++y) bv[y] = cp[y][(size_t)k * n];
-          });
-      acc.store([&](int r, int c, C v) {
+      for (int xx = 0; xx < SR; ++xx) pa[rt][xx] = P + (size_t)(rt * 32 + xx * M::TM + M::a_row(lane)) * NB + M::a_k(lane);
+    WT acc[NRT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) acc[rt].zero();
+    // operands for k-step ks: b from the panel rows of this strip (clamped to
+    // the last real row), a from P (rows outside jb x jb are the identity)
+    auto fetch = [&](int ks, C (&av)[NRT][SR], C (&bv)[SC]) {
+      const int k = min(ks * M::KS + kb, jb - 1);
+#pragma unroll
+      for (int y = 0; y < SC; ++y) bv[y] = cp[y][(size_t)k * n];
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int xx = 0; xx < SR; ++xx) av[rt][xx] = pa[rt][xx][ks * M::KS];
+    };
+    C aq[PF][NRT][SR], bq[PF][SC];
+#pragma unroll
+    for (int s = 0; s < PF; ++s) fetch(s, aq[s], bq[s]);
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+      const int cur = ks % PF;
+      C av[NRT][SR], bv[SC];
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int xx = 0; xx < SR; ++xx) av[rt][xx] = aq[cur][rt][xx];
+#pragma unroll
+      for (int y = 0; y < SC; ++y) bv[y] = bq[cur][y];
+      if (ks + PF < KSTEPS) fetch(ks + PF, aq[cur], bq[cur]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt) acc[rt].mac(av[rt], bv, false);
+    }
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+      acc[rt].store([&](int r, int c, C v) {
         const int row = rt * 32 + r, col = cs * 32 + c;
         if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
       });
-    }
   } else {
-    // MT = U^-T A_IJ^T: rows k of the panel, columns i = every row of A. Rows
-    // jb..NB-1 (ragged last panel) come out exactly zero, since U^-1 is zero
-    // outside the jb x jb block; the update reads them unmasked.
-    const int is = (blockIdx.x - nwb) * kWaves + wave;
-    if (is * 32 >= n) return;
+    const int i0 = (blockIdx.x - nwb) * 32;
     C* MT = a.MT + (size_t)blk * NB * n;
-    const C* rp[SC];
-#pragma unroll
-    for (int y = 0; y < SC; ++y) rp[y] = A + (size_t)min(is * 32 + y * M::TN + M::b_col(lane), n - 1) * n + j0;
-    for (int rt = 0; rt < NB / 32; ++rt) {
-      WT acc;
-      acc.zero();
-      panel_kloop<T, NB>(acc,
-          [&](int ks, C (&av)[SR]) {
-#pragma unroll
-            for (int xx = 0; xx < SR; ++xx) av[xx] = X[ks * M::KS + M::a_k(lane)][rt * 32 + xx * M::TM + M::a_row(lane)];
-          },
-          [&](int ks, C (&bv)[SC]) {
-            const int k = min(ks * M::KS + kb, jb - 1);
-#pragma unroll
-            for (int y = 0; y < SC; ++y) bv[y] = rp[y][k];
-          });
-      acc.store([&](int r, int c, C v) {
-        const int row = rt * 32 + r, i = is * 32 + c;
-        if (i < n) MT[(size_t)row * n + i] = v;
-      });
+    for (int idx = t; idx < 32 * NB; idx += kThreads) {
+      const int r = idx / NB, k = idx - (idx / NB) * NB;
+      const C v = A[(size_t)min(i0 + r, n - 1) * n + j0 + min(k, jb - 1)];
+      X[r][k] = k < jb ? v : cz<C>();
+    }
+    __syncthreads();
+    for (int idx = t; idx < 32 * NB; idx += kThreads) {
+      const int k = idx >> 5, r = idx & 31;
+      if (i0 + r < n) MT[(size_t)k * n + i0 + r] = X[r][k];
     }
   }
 }
 
 // ----------------------------------------------------------------- update
-// C[i][col] -= sum_k MT[k][i] U[k][col] for every row i outside the panel.
-// Workgroup tile (2 UWM) x (2 UWN), waves 2 x 2, each wave a UWM x UWN tile.
+// C[i][col] -= sum_k MT[k][i] R[k][col] for every row i outside the panel.
 // Tile shape and pipelining of the update: wave tile UWM x UWN, workgroup of
 // 2 x 2 waves, operand prefetch PF k-steps ahead; FULL = the panel is NB wide
 // (every panel but a ragged last one), so the panel rows need no clamping.
@@ -528,23 +481,15 @@ void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, hipStream_t s) {
   hipLaunchKernelGGL((bse_update_kernel<T, NB, CF>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb);
 }
 
-// ------------------------------------------------------------------ final
-// F_J = U_JJ^-1 B_J for every panel J, then Phi <- alpha (F - Gamma) + (1 - alpha) Phi.
-template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void bse_final_kernel(BseCtx<T> a, int nstripw) {
+// --------------------------------------------------------------- epilogue
+// B holds F after the last panel: Phi <- alpha (F - Gamma) + (1 - alpha) Phi,
+// and the per-block pivot statistics.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a) {
   using C = typename cplx_of<T>::type;
-  using M = Mma<T>;
-  using WT = WTile<T>;
-  constexpr int SR = WT::SR, SC = WT::SC;
-  __shared__ C X[NB][NB + 1];
-  const int blk = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
-  const int J = blockIdx.x / nstripw, sw = blockIdx.x - (blockIdx.x / nstripw) * nstripw;
-  const int j0 = J * NB, jb = min(NB, n - j0);
+  const int blk = blockIdx.y, n = a.n;
   const size_t nn = (size_t)n * n;
-  const C* UI = a.UI + ((size_t)blk * a.nJ + J) * NB * NB;
-  for (int idx = t; idx < NB * NB; idx += blockDim.x) X[idx / NB][idx % NB] = UI[idx];
-  __syncthreads();
-  if (blockIdx.x == 0 && t == 0 && a.stats) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.stats) {
     const double* ps = a.pst + (size_t)blk * 4;
     pq_bse_block_stats st;
     const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
@@ -554,60 +499,30 @@ __global__ __launch_bounds__(kThreads) void bse_final_kernel(BseCtx<T> a, int ns
     st.reserved = 0;
     a.stats[blk] = st;
   }
-  const int cs = sw * kWaves + wave;
-  if (cs * 32 >= n) return;
-  const C* B = a.B + (size_t)blk * nn;
+  const C* F = a.B + (size_t)blk * nn;
   const C* G = a.gamma + (size_t)blk * nn;
   C* P = a.phi + (size_t)blk * nn;
   const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
   const bool mix = a.alpha != 1.0;
-  const int kb = M::b_k(lane);
-  const C* cp[SC];
-#pragma unroll
-  for (int y = 0; y < SC; ++y) cp[y] = B + (size_t)j0 * n + min(cs * 32 + y * M::TN + M::b_col(lane), n - 1);
-  for (int rt = 0; rt < NB / 32; ++rt) {
-    WT acc;
-    acc.zero();
-    panel_kloop<T, NB>(acc,
-        [&](int ks, C (&av)[SR]) {
-#pragma unroll
-          for (int xx = 0; xx < SR; ++xx) av[xx] = X[rt * 32 + xx * M::TM + M::a_row(lane)][ks * M::KS + M::a_k(lane)];
-        },
-        [&](int ks, C (&bv)[SC]) {
-          const int k = min(ks * M::KS + kb, jb - 1);
-#pragma unroll
-          for (int y = 0; y < SC; ++y) bv[y] = cp[y][(size_t)k * n];
-        });
-    // epilogue: Gamma and the old Phi are gathered with unconditional loads
-    // from clamped addresses first, then combined and stored where in range
-    auto at = [&](int r, int c) { return (size_t)(j0 + min(rt * 32 + r, jb - 1)) * n + min(cs * 32 + c, n - 1); };
-    WT g, old;
-    g.load([&](int r, int c) { return G[at(r, c)]; });
-    if (mix) old.load([&](int r, int c) { return P[at(r, c)]; });
-#pragma unroll
-    for (int x = 0; x < SR; ++x)
-#pragma unroll
-      for (int y = 0; y < SC; ++y)
-#pragma unroll
-        for (int v = 0; v < M::NV; ++v) {
-          const int row = rt * 32 + x * M::TM + M::c_row(lane, v), col = cs * 32 + y * M::TN + M::c_col(lane);
-          C o;
-          o.x = acc.re[x][y][v] - g.re[x][y][v];
-          o.y = acc.im[x][y][v] - g.im[x][y][v];
-          if (mix) {
-            o.x = al * o.x + be * old.re[x][y][v];
-            o.y = al * o.y + be * old.im[x][y][v];
-          }
-          if (row < jb && col < n) P[(size_t)(j0 + row) * n + col] = o;
-        }
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn; idx += (size_t)gridDim.x * blockDim.x) {
+    const C f = F[idx], g = G[idx];
+    C v;
+    v.x = f.x - g.x;
+    v.y = f.y - g.y;
+    if (mix) {
+      const C o = P[idx];
+      v.x = al * v.x + be * o.x;
+      v.y = al * v.y + be * o.y;
+    }
+    P[idx] = v;
   }
 }
 
 template <typename T>
-constexpr int panel_width() { return sizeof(T) == 4 ? 64 : 32; }
+constexpr int panel_width() { return sizeof(T) == 4 ? 128 : 64; }
 
 struct BseLayout {
-  size_t A, B, MT, LI, UI, pst, total;
+  size_t A, B, MT, PI, pst, total;
 };
 
 template <typename T>
@@ -615,15 +530,13 @@ BseLayout bse_layout(const Dims& d) {
   using C = typename cplx_of<T>::type;
   constexpr int NB = panel_width<T>();
   const size_t nn = (size_t)d.n * d.n;
-  const int nJ = (d.n + NB - 1) / NB;
   BseLayout L{};
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off += align256(b); return o; };
   L.A = take(sizeof(C) * nn * d.Nq);
   L.B = take(sizeof(C) * nn * d.Nq);
   L.MT = take(sizeof(C) * (size_t)NB * d.n * d.Nq);
-  L.LI = take(sizeof(C) * (size_t)NB * NB * d.Nq);
-  L.UI = take(sizeof(C) * (size_t)NB * NB * nJ * d.Nq);
+  L.PI = take(sizeof(C) * (size_t)NB * NB * d.Nq);
   L.pst = take(sizeof(double) * 4 * (size_t)d.Nq);
   L.total = off;
   return L;
@@ -658,12 +571,11 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   a.A = (C*)(w + L.A);
   a.B = (C*)(w + L.B);
   a.MT = (C*)(w + L.MT);
-  a.LI = (C*)(w + L.LI);
-  a.UI = (C*)(w + L.UI);
+  a.PI = (C*)(w + L.PI);
   a.pst = (double*)(w + L.pst);
   a.stats = stats;
   const int n = d.n;
-  // event timing around each launch (kind: 0 init, 1 diag, 2 panel, 3 update, 4 final)
+  // event timing around each launch (kind: 0 init, 1 pivot, 2 panel, 3 update, 4 epilogue)
   auto pre = [&](int kind) {
     if (tm && tm->used < tm->cap) {
       tm->kind[tm->used] = kind;
@@ -677,18 +589,18 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     }
   };
   if (tm) tm->update_flops = 0.0;
-  const unsigned init_x = (unsigned)std::min<size_t>(1024, ((size_t)n * n + kThreads - 1) / kThreads);
+  const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)n * n + kThreads - 1) / kThreads);
   pre(0);
-  hipLaunchKernelGGL((bse_init_kernel<T>), dim3(init_x, d.Nq), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((bse_init_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a);
   post();
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int jb = std::min(NB, n - j0);
     const int ncols = (n - j0 - jb) + n;
     pre(1);
-    hipLaunchKernelGGL((bse_diag_kernel<T, NB>), dim3(d.Nq), dim3(kDiagThreads), 0, s, a, j0);
+    hipLaunchKernelGGL((bse_pivot_kernel<T, NB>), dim3(d.Nq), dim3(pivot_threads<NB>()), 0, s, a, j0);
     post();
     const int nwb = ((ncols + 31) / 32 + kWaves - 1) / kWaves;
-    const int nwc = ((n + 31) / 32 + kWaves - 1) / kWaves;
+    const int nwc = (n + 31) / 32;
     pre(2);
     hipLaunchKernelGGL((bse_panel_kernel<T, NB>), dim3(nwb + nwc, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
     post();
@@ -700,9 +612,8 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     post();
     if (tm) tm->update_flops += 8.0 * (double)(n - jb) * ncols * jb * d.Nq;
   }
-  const int nstripw = ((n + 31) / 32 + kWaves - 1) / kWaves;
   pre(4);
-  hipLaunchKernelGGL((bse_final_kernel<T, NB>), dim3(a.nJ * nstripw, d.Nq), dim3(kThreads), 0, s, a, nstripw);
+  hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a);
   post();
   return hipGetLastError();
 }

@@ -44,7 +44,7 @@ hipError_t launch_sigma1(const pq_params& p, const Dims& d, const double2* g, co
                          double2* sigma_out, void* ws, hipStream_t s);
 size_t bse_ws_bytes(const pq_params& p, const Dims& d, int precision);
 // Optional device-event timing of the BSE launches, by kernel kind
-// (0 init, 1 diag, 2 panel, 3 update, 4 final).
+// (0 init, 1 pivot, 2 panel, 3 update, 4 epilogue).
 struct BseTiming {
   hipEvent_t* ev;     // 2 * cap events
   int cap, used;
