@@ -15,13 +15,13 @@
 //                   multipliers A_IJ copied k-major (MT[k][i] = A[i][J0 + k])
 //                   so that the update's operand loads coalesce;
 //   (c) bse_update: A_IK -= A_IJ R_JK, B_I -= A_IJ R_JB for all rows I != J, a
-//                   rank-NB update; each wave owns a 64 x 32 (complex64) or
-//                   32 x 32 (complex128) tile and reads both operands straight
-//                   from L1/L2, so no LDS is needed and four waves share a SIMD.
+//                   rank-NB update; each wave owns a 64 x 64 (complex64) or
+//                   32 x 32 (complex128) tile, reads both operands straight
+//                   from L1/L2 (no LDS), and forms each complex product from
+//                   three real matrix products.
 // After the last panel A is the identity and B holds F; bse_epilogue applies
-// the mixing. Steps (b) and (c) are complex products on the matrix cores, four
-// real MFMAs per complex product: v_mfma_f32_32x32x2f32 (complex64) or
-// v_mfma_f64_16x16x4f64 (complex128).
+// the mixing. Steps (b) and (c) are complex products on the matrix cores
+// (v_mfma_f32_32x32x2f32 for complex64, v_mfma_f64_16x16x4f64 for complex128).
 //
 // No row exchanges: A is the identity minus the small-norm kernel s Gamma X,
 // and every leading principal block of it stays invertible while the BSE is
@@ -31,6 +31,7 @@
 #include <float.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "pq_internal.h"
 
@@ -386,21 +387,95 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 // Tile shape and pipelining of the update: wave tile UWM x UWN, workgroup of
 // 2 x 2 waves, operand prefetch PF k-steps ahead; FULL = the panel is NB wide
 // (every panel but a ragged last one), so the panel rows need no clamping.
-template <typename T, int UWM_, int UWN_, int PF_, int WPE_, bool FULL_>
+// M3 = complex products with three real matrix products instead of four:
+//   X1 += (ar + ai) br,  X2 += ar (bi - br),  X3 += ai (br + bi),
+//   Re(ab) = X1 - X3,    Im(ab) = X1 + X2,
+// with X3 started at Re C and X2 at -Im C, so C - ab = (X3 - X1, -X1 - X2).
+template <typename T, int UWM_, int UWN_, int PF_, int WPE_, bool FULL_, bool M3_ = true>
 struct UpdCfg {
   static constexpr int UWM = UWM_, UWN = UWN_, PF = PF_, WPE = WPE_;
-  static constexpr bool FULL = FULL_;
+  static constexpr bool FULL = FULL_, M3 = M3_;
   static constexpr int WGM = 2 * UWM, WGN = 2 * UWN;
 };
+// (the ragged-panel form of the complex64 update uses a 64 x 32 tile: the
+// clamping of panel rows costs registers the 64 x 64 tile does not have)
 template <typename T, bool FULL>
-using UpdDefault = UpdCfg<T, sizeof(T) == 4 ? 64 : 32, 32, sizeof(T) == 4 ? 2 : 1, 4, FULL>;
+using UpdDefault = typename std::conditional<
+    sizeof(T) == 4, typename std::conditional<FULL, UpdCfg<T, 64, 64, 2, 2, true>, UpdCfg<T, 64, 32, 2, 3, false>>::type,
+    UpdCfg<T, 32, 32, 1, 2, FULL>>::type;
+
+// Accumulators of a UWM x UWN complex tile in the three-product form.
+template <typename T, int WM, int WN>
+struct Tile3 {
+  using M = Mma<T>;
+  using C = typename cplx_of<T>::type;
+  static constexpr int SR = WM / M::TM, SC = WN / M::TN;
+  typename M::acc_t x1[SR][SC], x2[SR][SC], x3[SR][SC];
+  template <class F> __device__ void load_c(F f) {     // X1 = 0, X2 = -Im C, X3 = Re C
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < SR; ++a)
+#pragma unroll
+      for (int b = 0; b < SC; ++b)
+#pragma unroll
+        for (int v = 0; v < M::NV; ++v) {
+          const C c = f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l));
+          x1[a][b][v] = (T)0;
+          x2[a][b][v] = -c.y;
+          x3[a][b][v] = c.x;
+        }
+  }
+  __device__ void mac(const C (&av)[SR], const C (&bv)[SC]) {
+    T as[SR], bd[SC], bs[SC];
+#pragma unroll
+    for (int x = 0; x < SR; ++x) as[x] = av[x].x + av[x].y;
+#pragma unroll
+    for (int y = 0; y < SC; ++y) {
+      bd[y] = bv[y].y - bv[y].x;
+      bs[y] = bv[y].x + bv[y].y;
+    }
+#pragma unroll
+    for (int x = 0; x < SR; ++x)
+#pragma unroll
+      for (int y = 0; y < SC; ++y) {
+        x1[x][y] = M::mma(as[x], bv[y].x, x1[x][y]);
+        x2[x][y] = M::mma(av[x].x, bd[y], x2[x][y]);
+        x3[x][y] = M::mma(av[x].y, bs[y], x3[x][y]);
+      }
+  }
+  template <class F> __device__ void store_c(F f) {    // C - ab = (X3 - X1, -X1 - X2)
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < SR; ++a)
+#pragma unroll
+      for (int b = 0; b < SC; ++b)
+#pragma unroll
+        for (int v = 0; v < M::NV; ++v) {
+          C c;
+          c.x = x3[a][b][v] - x1[a][b][v];
+          c.y = -x1[a][b][v] - x2[a][b][v];
+          f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l), c);
+        }
+  }
+};
+
+// The four-product form behind the same interface (acc = C, acc -= ab).
+template <typename T, int WM, int WN>
+struct Tile4 : WTile<T, WM, WN> {
+  using C = typename cplx_of<T>::type;
+  template <class F> __device__ void load_c(F f) { this->load(f); }
+  __device__ void mac(const C (&av)[WTile<T, WM, WN>::SR], const C (&bv)[WTile<T, WM, WN>::SC]) {
+    WTile<T, WM, WN>::mac(av, bv, true);
+  }
+  template <class F> __device__ void store_c(F f) { this->store(f); }
+};
 
 template <typename T, int NB, class CF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CF::WPE)))
 void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
-  using UT = WTile<T, CF::UWM, CF::UWN>;
+  using UT = typename std::conditional<CF::M3, Tile3<T, CF::UWM, CF::UWN>, Tile4<T, CF::UWM, CF::UWN>>::type;
   constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS, PF = CF::PF;
   const unsigned lid = xcd_linear();
   const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
@@ -430,7 +505,7 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   }
   auto row_ok = [&](int i) { return i < n && !(i >= j0 && i < j0 + jb); };
   UT acc;
-  acc.load([&](int r, int c) -> C { return cb[c / M::TN][(size_t)min(i0 + r, n - 1) * n]; });
+  acc.load_c([&](int r, int c) -> C { return cb[c / M::TN][(size_t)min(i0 + r, n - 1) * n]; });
   const int kb = M::b_k(lane), ka = M::a_k(lane);
   const C* bbase[USC];
 #pragma unroll
@@ -463,9 +538,9 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
     for (int y = 0; y < USC; ++y) cbv[y] = bv[cur][y];
     if (ks + PF < KSTEPS) fetch(ks + PF, av[cur], bv[cur]);
     __builtin_amdgcn_sched_barrier(0);     // keep the prefetch ahead of this step's MFMAs
-    acc.mac(ca, cbv, true);
+    acc.mac(ca, cbv);
   }
-  acc.store([&](int r, int c, C v) {
+  acc.store_c([&](int r, int c, C v) {
     const int i = i0 + r;
     const int y = c / M::TN;
     if (cok[y] && row_ok(i)) cb[y][(size_t)i * n] = v;
