@@ -23,6 +23,7 @@ namespace pq {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kRemapThreads = 512;
 
 // ------------------------------------------------------- kernel functions
 template <typename C>
@@ -134,23 +135,29 @@ __device__ inline C axpy(C acc, R c, C v) {
   return acc;
 }
 
-// term tables: geometry (1..4), source channel, and coefficients into the two
-// output channels of the pass (pass 0 -> d, m; pass 1 -> s, t)
-__constant__ int kGeo[2][4] = {{1, 1, 2, 2}, {3, 3, 4, 4}};
-__constant__ int kSrc[2][4] = {{0, 1, 2, 3}, {0, 1, 0, 1}};
+// Coefficients of the eight terms into the two output channels of a pass
+// (pass 0 -> d, m; pass 1 -> s, t), Eqs. PA_Gamma_dm and PA_Gamma_st. Term
+// order within a pass: pass 0: d ph-bar, m ph-bar, s pp, t pp; pass 1:
+// d st-1, m st-1, d st-2, m st-2.
 __constant__ float kCoef[2][4][2] = {
     {{-0.5f, -0.5f}, {-1.5f, 0.5f}, {0.5f, -0.5f}, {1.5f, 0.5f}},
     {{0.5f, -0.5f}, {-1.5f, -0.5f}, {0.5f, 0.5f}, {-1.5f, 0.5f}}};
 
+// One workgroup per (k, m) output plane walks the Nv x 2 x 4 (n', pass, term)
+// source tiles in a fixed order. The permutation of each geometry depends only
+// on (K, Q, K'), so its LDS offsets are tabulated once per workgroup; a
+// kernel-filled tile is written into LDS across all its columns so that the
+// same offsets apply. The next tile's global loads are issued before the
+// current tile is consumed from LDS, so one tile per workgroup is always in
+// flight.
 template <typename C, int EPT>
-__global__ __launch_bounds__(kThreads) void remap_kernel(RemapArgs<C> a) {
+__global__ __launch_bounds__(kRemapThreads) void remap_kernel(RemapArgs<C> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   using R = decltype(C().x);
   const Dims& d = a.d;
   const int Nk = d.Nk, Nk2 = Nk * Nk, ld = Nk + 1;
-  C* tile = (C*)smem;                                   // Nk rows, padded stride ld
-  unsigned char* tadd = (unsigned char*)(smem + sizeof(C) * Nk * ld);
-  unsigned char* tsub = tadd + Nk2;
+  C* tile = (C*)smem;                                              // Nk rows, padded stride ld
+  unsigned short* offs = (unsigned short*)(smem + sizeof(C) * Nk * ld);   // [4][Nk2]
 
   // block -> (k, m); consecutive logical blocks (same k) stay on one XCD
   const int total = gridDim.x;
@@ -160,69 +167,102 @@ __global__ __launch_bounds__(kThreads) void remap_kernel(RemapArgs<C> a) {
   const int nk = kbi / Nk - d.Nv / 2, K = kbi - (kbi / Nk) * Nk;
   const int m = jm - (d.Nv / 2 - 1);
   const size_t n = d.n, nn = (size_t)d.n * d.n, chan = (size_t)d.Nq * nn;
+  const int t = threadIdx.x;
 
-  for (int idx = threadIdx.x; idx < Nk2; idx += blockDim.x) {
-    const int x = idx / Nk, y = idx - (idx / Nk) * Nk;
-    tadd[idx] = (unsigned char)kadd(x, y, d.Lx, d.Ly);
-    tsub[idx] = (unsigned char)ksub(x, y, d.Lx, d.Ly);
+  // output element e = Q Nk + K' reads source (Qp, Kb):
+  //   g0 ph-bar: (K'-K, K+Q)  g1 pp: (K+K'+Q, K')  g2 st-1: (K'-K, Q-K')  g3 st-2: (Q-K-K', K')
+  for (int e = t; e < Nk2; e += kRemapThreads) {
+    const int Q = e / Nk, Kp = e - (e / Nk) * Nk;
+    const int Lx = d.Lx, Ly = d.Ly;
+    const int kpk = ksub(Kp, K, Lx, Ly);
+    offs[0 * Nk2 + e] = (unsigned short)(kpk * ld + kadd(K, Q, Lx, Ly));
+    offs[1 * Nk2 + e] = (unsigned short)(kadd(kadd(K, Kp, Lx, Ly), Q, Lx, Ly) * ld + Kp);
+    offs[2 * Nk2 + e] = (unsigned short)(kpk * ld + ksub(Q, Kp, Lx, Ly));
+    offs[3 * Nk2 + e] = (unsigned short)(ksub(ksub(Q, K, Lx, Ly), Kp, Lx, Ly) * ld + Kp);
   }
-  __syncthreads();
 
-  for (int in2 = 0; in2 < d.Nv; ++in2) {
+  // step s = (n' index, pass, term) -> source tile
+  auto info = [&](int s, int& geo, int& src, int& jmp, int& nb, bool& valid) {
+    const int in2 = s >> 3, pass = (s >> 2) & 1, term = s & 3;
     const int n2 = in2 - d.Nv / 2;
-    for (int pass = 0; pass < 2; ++pass) {
-      C acc0[EPT], acc1[EPT];
+    geo = pass * 2 + (term >> 1);                    // 0 ph-bar, 1 pp, 2 st-1, 3 st-2
+    src = pass == 0 ? term : (term & 1);
+    int mp;
+    if (geo == 0) { mp = n2 - nk; nb = nk + m; }
+    else if (geo == 1) { mp = nk + n2 + m + 1; nb = n2; }
+    else if (geo == 2) { mp = n2 - nk; nb = m - n2 - 1; }
+    else { mp = m - nk - n2 - 1; nb = n2; }
+    valid = in_bbox(mp, d.Nv);
+    jmp = mp + d.Nv / 2 - 1;
+  };
+  C buf[EPT];
+  auto fetch = [&](int s) {
+    int geo, src, jmp, nb;
+    bool valid;
+    info(s, geo, src, jmp, nb, valid);
+    if (!valid) return;
+    if (in_fbox(nb, d.Nv)) {
+      const C* base = a.phi + src * chan + (size_t)kbi * n + (size_t)(nb + d.Nv / 2) * Nk;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int idx = min(t + i * kRemapThreads, Nk2 - 1);
+        const int Qp = idx / Nk, Kb = idx - (idx / Nk) * Nk;
+        buf[i] = base[(size_t)(jmp * Nk + Qp) * nn + Kb];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int idx = min(t + i * kRemapThreads, Nk2 - 1);
+        const size_t qo = (size_t)src * d.Nq + jmp * Nk + idx / Nk;
+        buf[i] = from_d<C>(cadd(a.k1[qo], a.k2[qo * n + kbi]));
+      }
+    }
+  };
+  const int nsteps = d.Nv * 8;
+  fetch(0);
+  C acc0[EPT], acc1[EPT];
+  for (int s = 0; s < nsteps; ++s) {
+    int geo, src, jmp, nb;
+    bool valid;
+    info(s, geo, src, jmp, nb, valid);
+    const int pass = (s >> 2) & 1, term = s & 3;
+    if (term == 0) {
+#pragma unroll
       for (int i = 0; i < EPT; ++i) {
         acc0[i] = czero<C>();
         acc0[i].x = (R)a.lam[2 * pass];
         acc1[i] = czero<C>();
         acc1[i].x = (R)a.lam[2 * pass + 1];
       }
-      for (int term = 0; term < 4; ++term) {
-        const int geo = kGeo[pass][term], src = kSrc[pass][term];
-        int mp, nb;
-        if (geo == 1) { mp = n2 - nk; nb = nk + m; }
-        else if (geo == 2) { mp = nk + n2 + m + 1; nb = n2; }
-        else if (geo == 3) { mp = n2 - nk; nb = m - n2 - 1; }
-        else { mp = m - nk - n2 - 1; nb = n2; }
-        if (!in_bbox(mp, d.Nv)) continue;          // uniform across the block
-        const bool full = in_fbox(nb, d.Nv);
-        const int jmp = mp + d.Nv / 2 - 1;
-        __syncthreads();
-        if (full) {
-          const C* base = a.phi + src * chan + (size_t)kbi * n + (size_t)(nb + d.Nv / 2) * Nk;
-          for (int idx = threadIdx.x; idx < Nk2; idx += blockDim.x) {
-            const int Qp = idx / Nk, Kb = idx - (idx / Nk) * Nk;
-            tile[Qp * ld + Kb] = base[(size_t)(jmp * Nk + Qp) * nn + Kb];
-          }
-        } else {
-          for (int Qp = threadIdx.x; Qp < Nk; Qp += blockDim.x) {
-            const size_t qo = (size_t)src * d.Nq + jmp * Nk + Qp;
-            double2 v = cadd(a.k1[qo], a.k2[qo * n + kbi]);
-            tile[Qp * ld] = from_d<C>(v);
-          }
-        }
-        __syncthreads();
-        const R c0 = (R)kCoef[pass][term][0], c1 = (R)kCoef[pass][term][1];
-        for (int i = 0; i < EPT; ++i) {
-          const int e = threadIdx.x + i * kThreads;
-          if (e < Nk2) {
-            const int Q = e / Nk, Kp = e - (e / Nk) * Nk;
-            int Qp, Kb;
-            if (geo == 1) { Qp = tsub[Kp * Nk + K]; Kb = tadd[K * Nk + Q]; }
-            else if (geo == 2) { Qp = tadd[tadd[K * Nk + Kp] * Nk + Q]; Kb = Kp; }
-            else if (geo == 3) { Qp = tsub[Kp * Nk + K]; Kb = tsub[Q * Nk + Kp]; }
-            else { Qp = tsub[tsub[Q * Nk + K] * Nk + Kp]; Kb = Kp; }
-            const C v = full ? tile[Qp * ld + Kb] : tile[Qp * ld];
-            acc0[i] = axpy(acc0[i], c0, v);
-            acc1[i] = axpy(acc1[i], c1, v);
-          }
-        }
+    }
+    if (valid) {                                   // uniform across the block
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int idx = t + i * kRemapThreads;
+        if (idx < Nk2) tile[(idx / Nk) * ld + idx % Nk] = buf[i];
       }
+      __syncthreads();
+    }
+    if (s + 1 < nsteps) fetch(s + 1);              // in flight while this tile is consumed
+    if (valid) {
+      const R c0 = (R)kCoef[pass][term][0], c1 = (R)kCoef[pass][term][1];
+      const unsigned short* og = offs + geo * Nk2;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = min(t + i * kRemapThreads, Nk2 - 1);
+        const C v = tile[og[e]];
+        acc0[i] = axpy(acc0[i], c0, v);
+        acc1[i] = axpy(acc1[i], c1, v);
+      }
+    }
+    if (term == 3) {
+      const int in2 = s >> 3;
       C* o0 = a.gamma + (size_t)(2 * pass) * chan;
       C* o1 = a.gamma + (size_t)(2 * pass + 1) * chan;
+#pragma unroll
       for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * kThreads;
+        const int e = t + i * kRemapThreads;
         if (e < Nk2) {
           const int Q = e / Nk, Kp = e - (e / Nk) * Nk;
           const size_t off = (size_t)(jm * Nk + Q) * nn + (size_t)kbi * n + (size_t)in2 * Nk + Kp;
@@ -246,24 +286,24 @@ hipError_t run_remap(const Dims& d, const double lam[4], const void* phi, const 
   a.gamma = (C*)gamma;
   const int blocks = d.n * d.NW;
   a.xcd_spread = (blocks % 8 == 0) ? 1 : 0;
-  size_t lds = sizeof(C) * d.Nk * (d.Nk + 1) + 2 * d.Nk * d.Nk;
+  size_t lds = sizeof(C) * d.Nk * (d.Nk + 1) + 4 * sizeof(unsigned short) * d.Nk * d.Nk;
   lds = align256(lds);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)remap_kernel<C, EPT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((remap_kernel<C, EPT>), dim3(blocks), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL((remap_kernel<C, EPT>), dim3(blocks), dim3(kRemapThreads), lds, s, a);
   return hipGetLastError();
 }
 
 template <typename C>
 hipError_t dispatch_remap(const Dims& d, const double lam[4], const void* phi, const double2* k1,
                           const double2* k2, void* gamma, hipStream_t s) {
-  const int need = (d.Nk * d.Nk + kThreads - 1) / kThreads;
+  const int need = (d.Nk * d.Nk + kRemapThreads - 1) / kRemapThreads;
   if (need <= 1) return run_remap<C, 1>(d, lam, phi, k1, k2, gamma, s);
-  if (need <= 4) return run_remap<C, 4>(d, lam, phi, k1, k2, gamma, s);
-  if (need <= 16) return run_remap<C, 16>(d, lam, phi, k1, k2, gamma, s);
+  if (need <= 2) return run_remap<C, 2>(d, lam, phi, k1, k2, gamma, s);
+  if (need <= 8) return run_remap<C, 8>(d, lam, phi, k1, k2, gamma, s);
   return hipErrorInvalidValue;
 }
 
