@@ -8,7 +8,9 @@ Schwinger-Dyson self-energy, the four Bethe-Salpeter solves and the mixing.
 
 The reported value is iterations/s of the complex64 path (FP32 matrix-core
 BSE); the plain complex128 path (FP64 matrix cores everywhere) is timed next
-to it. The roofline object covers the dominant kernel, the rank-NB trailing
+to it, and both are run from the bare-vertex start to a converged self-energy
+(max |Sigma_new - Sigma| < 1e-6) for the time-to-converged figures and the
+distance between the two converged self-energies. The roofline object covers the dominant kernel, the rank-NB trailing
 update of the BSE elimination, whose launch time comes from HIP events
 recorded on the solver's stream around each launch; the CPU
 baseline times the FP64 oracle on a bounded sample of the same workload and
@@ -97,10 +99,11 @@ def time_to_converged(p, precision, tol, max_iter):
     done, conv, st = s.iterate(max_iter, tol)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    sigma = s.get("sigma").cpu()
     s.close()
     del s
     torch.cuda.empty_cache()
-    return dict(sec=t1 - t0, iterations=done, converged=conv, dsigma=st.dsigma)
+    return dict(sec=t1 - t0, iterations=done, converged=conv, dsigma=st.dsigma), sigma
 
 
 class _VirtualVertex:
@@ -184,7 +187,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--ttc", action="store_true", help="also measure time to converged Sigma (1e-6)")
+    ap.add_argument("--no-ttc", action="store_true",
+                    help="skip the time-to-converged-Sigma (1e-6) runs of both paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -257,11 +261,20 @@ def main():
                             ("mix", 6))} if r64 else None),
         "roofline": roof,
     }
-    if args.ttc:
+    if not args.no_ttc:
+        # time from the bare-vertex start to max|Sigma_new - Sigma| < 1e-6 (the solver's
+        # own stopping test), FP32 path vs FP64 path, and how far apart the two
+        # converged self-energies are
         print("[bench] time to converged sigma (fp32)", file=sys.stderr, flush=True)
-        out["time_to_converged_fp32"] = time_to_converged(p, "fp32", 1e-6, 60)
+        t32, s32 = time_to_converged(p, "fp32", 1e-6, 80)
         print("[bench] time to converged sigma (fp64)", file=sys.stderr, flush=True)
-        out["time_to_converged_fp64"] = time_to_converged(p, "fp64", 1e-6, 60)
+        t64, s64 = time_to_converged(p, "fp64", 1e-6, 80)
+        out["time_to_converged_fp32"] = t32
+        out["time_to_converged_fp64"] = t64
+        out["ttc_speedup_fp32_vs_fp64"] = round(t64["sec"] / t32["sec"], 3)
+        out["converged_sigma_fp32_vs_fp64"] = {
+            "max_abs_diff": float((s32 - s64).abs().max()),
+            "max_rel_diff": float((s32 - s64).abs().max() / s64.abs().max())}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)

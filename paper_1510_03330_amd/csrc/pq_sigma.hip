@@ -27,6 +27,7 @@ namespace pq {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kS2Split = 8;      // workgroups per output point of Sigma~_2
 constexpr int kPoles = 128;   // semicircle pole representation (Gauss-Chebyshev)
 
 __device__ inline double nu_of(int n, double beta) { return (2 * n + 1) * M_PI / beta; }
@@ -220,7 +221,7 @@ struct S2Args {
   const double2* g;
   const double2* k1;     // [4][Nq]
   const double2* k2;     // [4][Nq][n]
-  double2* out;          // [Nve][Nk]  (sum without the constant C)
+  double2* out;          // [kS2Split][Nve][Nk]  partial sums (without the constant C)
 };
 
 __device__ inline double ind(bool b) { return b ? 1.0 : 0.0; }
@@ -243,7 +244,8 @@ __global__ __launch_bounds__(kThreads) void sigma2_kernel(S2Args a) {
   const int hF = d.Nve / 2, hBe = d.Nve / 2 - 1, hBb = d.Nv / 2 - 1, hG = d.NG / 2;
   const size_t n = d.n;
   double tr = 0.0, ti = 0.0;
-  for (int qi = wave; qi < d.Nq; qi += nwaves) {
+  // transfers are split over kS2Split workgroups (blockIdx.y) for parallelism
+  for (int qi = blockIdx.y * nwaves + wave; qi < d.Nq; qi += nwaves * gridDim.y) {
     const int jm = qi / d.Nk, P = qi - jm * d.Nk;
     const int mp = jm - hBb;
     double2 c[4];
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void sigma2_kernel(S2Args a) {
       sr += red[2 * w];
       si += red[2 * w + 1];
     }
-    a.out[kid] = mk(sr, si);
+    a.out[(size_t)blockIdx.y * d.Nve * d.Nk + kid] = mk(sr, si);
   }
 }
 
@@ -400,7 +402,11 @@ __global__ void combine_kernel(CombineArgs a) {
   int e = idx / d.Nk, K = idx - e * d.Nk;
   int n = e - d.Nve / 2;
   double2 v = a.s1[idx];
-  if (a.has_s2) v = cadd(v, cscale(a.s2[idx], a.cfac));
+  if (a.has_s2) {
+    double2 acc = mk(0, 0);
+    for (int j = 0; j < kS2Split; ++j) acc = cadd(acc, a.s2[(size_t)j * d.Nve * d.Nk + idx]);
+    v = cadd(v, cscale(acc, a.cfac));
+  }
   if (a.has_box && in_fbox(n, d.Nv)) {
     int kbi = (n + d.Nv / 2) * d.Nk + K;
     double2 acc = mk(0, 0);
@@ -425,7 +431,7 @@ WsLayout ws_layout(const Dims& d) {
   L.grt = take(sizeof(double2) * (size_t)d.ntau * d.Nk);
   L.trn = take(sizeof(double2) * d.Nve * d.Nk);
   L.s1 = take(sizeof(double2) * d.Nve * d.Nk);
-  L.s2 = take(sizeof(double2) * d.Nve * d.Nk);
+  L.s2 = take(sizeof(double2) * kS2Split * d.Nve * d.Nk);
   L.part = take(sizeof(double2) * (size_t)d.n * d.NW);
   L.total = off;
   return L;
@@ -470,7 +476,7 @@ hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, cons
   const int has_s2 = p.kernel_level > 0 ? 1 : 0;
   if (has_s2) {
     S2Args a2{d, p.kernel_level, g, k1, k2, s2};
-    hipLaunchKernelGGL(sigma2_kernel, dim3(d.Nve * d.Nk), dim3(kThreads), 0, s, a2);
+    hipLaunchKernelGGL(sigma2_kernel, dim3(d.Nve * d.Nk, kS2Split), dim3(kThreads), 0, s, a2);
   }
   if (p.storage == PQ_STORE_C64) {
     SBArgs<float2> ab{d, (const float2*)phi, g, part};
