@@ -275,6 +275,24 @@ def main():
         out["converged_sigma_fp32_vs_fp64"] = {
             "max_abs_diff": float((s32 - s64).abs().max()),
             "max_rel_diff": float((s32 - s64).abs().max() / s64.abs().max())}
+        # mixed: FP32 iterations down to a 1e-5 change of Sigma, then FP64 from that state
+        print("[bench] time to converged sigma (fp32 then fp64)", file=sys.stderr, flush=True)
+        import torch
+        from paper_1510_03330_amd.ops import converge_mixed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sm, info = converge_mixed(p, 1e-6, 1e-5, 80)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        smx = sm.get("sigma").cpu()
+        sm.close()
+        del sm
+        torch.cuda.empty_cache()
+        out["time_to_converged_mixed"] = dict(sec=t1 - t0, **info)
+        out["ttc_speedup_mixed_vs_fp64"] = round(t64["sec"] / (t1 - t0), 3)
+        out["converged_sigma_mixed_vs_fp64"] = {
+            "max_abs_diff": float((smx - s64).abs().max()),
+            "max_rel_diff": float((smx - s64).abs().max() / s64.abs().max())}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)

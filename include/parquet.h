@@ -64,17 +64,14 @@ typedef enum {
   PQ_ERR_NOMEM = 3,        /* workspace too small                            */
   PQ_ERR_SINGULAR = 4,     /* a BSE block lost its pivots (see bse stats)    */
   PQ_ERR_NOT_CONVERGED = 5,
-  PQ_ERR_NONFINITE = 6,    /* NaN/Inf in Sigma                               */
-  PQ_ERR_REFINE = 7        /* refinement did not reach its tolerance         */
+  PQ_ERR_NONFINITE = 6     /* NaN/Inf in Sigma                               */
 } pq_status;
 
 typedef enum { PQ_STORE_C128 = 0, PQ_STORE_C64 = 1 } pq_storage;
 
 typedef enum {
   PQ_PREC_FP64 = 0,        /* complex128 elimination, FP64 MFMA              */
-  PQ_PREC_FP32 = 1,        /* complex64 elimination, FP32 MFMA               */
-  PQ_PREC_FP32_REFINE = 2  /* FP32 elimination + one FP64-residual refinement
-                              sweep on blocks the pivot monitor flags        */
+  PQ_PREC_FP32 = 1         /* complex64 elimination, FP32 MFMA               */
 } pq_precision;
 
 typedef enum { PQ_CH_D = 0, PQ_CH_M = 1, PQ_CH_S = 2, PQ_CH_T = 3 } pq_channel;
@@ -244,6 +241,19 @@ pq_status parquet_set(pq_ctx* ctx, int32_t field, const void* dev_src, size_t by
 
 /* Byte size of a field for this context. */
 pq_status parquet_field_bytes(pq_ctx* ctx, int32_t field, size_t* bytes);
+
+/* Copy the iteration state of src into dst: Sigma, mu~, the reducible
+ * vertices Phi_r (converted between complex64 and complex128 storage as the
+ * two contexts require; widening is exact) and the iteration count. Both
+ * contexts must describe the same box (Lx, Ly, Nv, f_ext) and live on the
+ * current device. Typical use: iterate a complex64/FP32 context until the
+ * change of Sigma is small, copy its state into a complex128/FP64 context and
+ * finish there, so that the converged solution carries FP64 accuracy while
+ * most iterations run on the FP32 path (the parquet iteration is a fixed
+ * point map, so the FP32 rounding of the starting state is iterated away).
+ * Enqueued on dst's stream after src's stream has been synchronised;
+ * synchronises dst's stream. PQ_ERR_ARG if the boxes differ. */
+pq_status parquet_copy_state(pq_ctx* dst, pq_ctx* src);
 
 pq_status parquet_destroy(pq_ctx* ctx);
 

@@ -471,6 +471,29 @@ pq_status parquet_set(pq_ctx* c, int32_t field, const void* dev_src, size_t byte
   return e == hipSuccess ? PQ_OK : hip_fail(e, "parquet_set");
 }
 
+pq_status parquet_copy_state(pq_ctx* dst, pq_ctx* src) {
+  PQ_CHECK_ARG(dst && src, "null context");
+  PQ_CHECK_ARG(dst != src, "source and destination are the same context");
+  const Dims& a = dst->d;
+  const Dims& b = src->d;
+  PQ_CHECK_ARG(a.Lx == b.Lx && a.Ly == b.Ly && a.Nv == b.Nv && a.f == b.f,
+               "contexts describe different boxes (%dx%d Nv=%d f=%d vs %dx%d Nv=%d f=%d)", a.Lx, a.Ly,
+               a.Nv, a.f, b.Lx, b.Ly, b.Nv, b.f);
+  hipError_t e = hipStreamSynchronize(src->s);
+  if (e != hipSuccess) return hip_fail(e, "parquet_copy_state (source stream)");
+  const size_t nsig = sizeof(double2) * (size_t)a.Nve * a.Nk;
+  if ((e = hipMemcpyAsync(dst->sigma, src->sigma, nsig, hipMemcpyDeviceToDevice, dst->s)) != hipSuccess)
+    return hip_fail(e, "parquet_copy_state (sigma)");
+  if ((e = hipMemcpyAsync(dst->mu, src->mu, sizeof(double), hipMemcpyDeviceToDevice, dst->s)) != hipSuccess)
+    return hip_fail(e, "parquet_copy_state (mu)");
+  const size_t count = 4 * (size_t)a.Nq * a.n * a.n;
+  if ((e = launch_convert(src->phi, src->p.storage, dst->phi, dst->p.storage, count, dst->s)) != hipSuccess)
+    return hip_fail(e, "parquet_copy_state (phi)");
+  if ((e = hipStreamSynchronize(dst->s)) != hipSuccess) return hip_fail(e, "parquet_copy_state");
+  dst->iteration = src->iteration;
+  return PQ_OK;
+}
+
 pq_status parquet_destroy(pq_ctx* c) {
   if (!c) return PQ_OK;
   if (c->have_events)

@@ -31,6 +31,9 @@ hipError_t launch_bubbles(const pq_params& p, const Dims& d, const double2* g, d
                           double2* xpp, hipStream_t s);
 hipError_t launch_mix(const Dims& d, const double2* snew, double2* sio, double alpha,
                       double* dnorm, hipStream_t s);
+// dst[i] = src[i] between complex64 / complex128 storages (count complex elements)
+hipError_t launch_convert(const void* src, int src_storage, void* dst, int dst_storage, size_t count,
+                          hipStream_t s);
 hipError_t launch_kernel_extract(const pq_params& p, const Dims& d, const void* phi, double2* k1,
                                  double2* k2, hipStream_t s);
 hipError_t launch_remap(const pq_params& p, const Dims& d, const double lam[4], const void* phi,

@@ -3,6 +3,8 @@
 // Sigma with its convergence norm. All FP64.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pq_internal.h"
 
 namespace pq {
@@ -156,7 +158,38 @@ __global__ __launch_bounds__(kThreads) void mix_kernel(int count, const double2*
   if (threadIdx.x == 0) *dnorm = bad > 0.0 ? __builtin_nan("") : mx;
 }
 
+// storage conversion of a vertex array (complex64 <-> complex128, or a copy)
+template <typename S, typename D>
+__global__ __launch_bounds__(kThreads) void convert_kernel(const S* src, D* dst, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const S v = src[i];
+    D w;
+    w.x = v.x;
+    w.y = v.y;
+    dst[i] = w;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_convert(const void* src, int src_storage, void* dst, int dst_storage, size_t count,
+                          hipStream_t s) {
+  const unsigned blocks = (unsigned)std::min<size_t>(8192, (count + kThreads - 1) / kThreads);
+  if (count == 0) return hipSuccess;
+  if (src_storage == PQ_STORE_C64 && dst_storage == PQ_STORE_C128)
+    hipLaunchKernelGGL((convert_kernel<float2, double2>), dim3(blocks), dim3(kThreads), 0, s,
+                       (const float2*)src, (double2*)dst, count);
+  else if (src_storage == PQ_STORE_C128 && dst_storage == PQ_STORE_C64)
+    hipLaunchKernelGGL((convert_kernel<double2, float2>), dim3(blocks), dim3(kThreads), 0, s,
+                       (const double2*)src, (float2*)dst, count);
+  else if (src_storage == PQ_STORE_C64)
+    hipLaunchKernelGGL((convert_kernel<float2, float2>), dim3(blocks), dim3(kThreads), 0, s,
+                       (const float2*)src, (float2*)dst, count);
+  else
+    hipLaunchKernelGGL((convert_kernel<double2, double2>), dim3(blocks), dim3(kThreads), 0, s,
+                       (const double2*)src, (double2*)dst, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_dyson(const pq_params& p, const Dims& d, const double2* sigma, double2* g,
                         double* mu_out, hipStream_t s) {

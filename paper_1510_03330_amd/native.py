@@ -15,20 +15,20 @@ LIB_PATH = os.path.join(HERE, "_lib", "libparquet.so")
 
 # ---------------------------------------------------------------- constants
 PQ_OK, PQ_ERR_ARG, PQ_ERR_HIP, PQ_ERR_NOMEM, PQ_ERR_SINGULAR = 0, 1, 2, 3, 4
-PQ_ERR_NOT_CONVERGED, PQ_ERR_NONFINITE, PQ_ERR_REFINE = 5, 6, 7
+PQ_ERR_NOT_CONVERGED, PQ_ERR_NONFINITE = 5, 6
 PQ_STORE_C128, PQ_STORE_C64 = 0, 1
-PQ_PREC_FP64, PQ_PREC_FP32, PQ_PREC_FP32_REFINE = 0, 1, 2
+PQ_PREC_FP64, PQ_PREC_FP32 = 0, 1
 FIELDS = {"sigma": 0, "g": 1, "phi": 2, "gamma": 3, "k1": 4, "k2": 5, "mu": 6, "xph": 7, "xpp": 8}
 
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_SINGULAR",
-                5: "ERR_NOT_CONVERGED", 6: "ERR_NONFINITE", 7: "ERR_REFINE"}
+                5: "ERR_NOT_CONVERGED", 6: "ERR_NONFINITE"}
 
 # Every entry point the header declares (checked by the CPU test suite).
 EXPORTS = [
     "pq_dims_from_params", "parquet_last_error", "dyson_update", "bubble_build", "kernel_extract",
     "channel_remap", "sigma_sde_workspace", "sigma_sde", "bse_workspace", "bse_solve", "sigma_mix",
     "parquet_query_workspace", "parquet_init", "parquet_iterate", "parquet_get", "parquet_set",
-    "parquet_field_bytes", "parquet_destroy",
+    "parquet_field_bytes", "parquet_copy_state", "parquet_destroy",
 ]
 
 
@@ -105,6 +105,7 @@ def load() -> ctypes.CDLL:
         "parquet_get": [c_void_p, c_int32, c_void_p, c_size_t],
         "parquet_set": [c_void_p, c_int32, c_void_p, c_size_t],
         "parquet_field_bytes": [c_void_p, c_int32, POINTER(c_size_t)],
+        "parquet_copy_state": [c_void_p, c_void_p],
         "parquet_destroy": [c_void_p],
     }
     for name, args in sig.items():

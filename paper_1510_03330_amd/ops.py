@@ -178,6 +178,11 @@ class Solver:
         N.check(N.load().parquet_set(self.ctx, N.FIELDS[name], ctypes.c_void_p(v.data_ptr()),
                                      ctypes.c_size_t(v.numel() * v.element_size())))
 
+    def copy_state_from(self, other: "Solver"):
+        """Take Sigma, mu~, Phi and the iteration count of another context of the
+        same box (converting the vertex storage as needed)."""
+        N.check(N.load().parquet_copy_state(self.ctx, other.ctx))
+
     def close(self):
         if self.ctx is not None:
             N.load().parquet_destroy(self.ctx)
@@ -188,3 +193,23 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def converge_mixed(p, tol: float = 1e-6, switch_tol: float = 1e-5, max_iter: int = 200,
+                   device: str = "cuda:0"):
+    """Iterate the complex64/FP32 path from the bare-vertex start until
+    max|Sigma_new - Sigma| < switch_tol, then continue on the complex128/FP64
+    path from that state until the change is below tol. Returns the FP64 solver
+    and a dict with the iteration counts of both phases."""
+    s32 = Solver(p, "fp32", device)
+    done32, conv32, st32 = s32.iterate(max_iter, switch_tol)
+    torch.cuda.synchronize()
+    s64 = Solver(p, "fp64", device)
+    s64.copy_state_from(s32)
+    s32.close()
+    del s32
+    done64, conv64, st64 = s64.iterate(max(0, max_iter - done32), tol)
+    info = dict(iterations_fp32=done32, iterations_fp64=done64, converged=bool(conv64),
+                dsigma=st64.dsigma if done64 else st32.dsigma)
+    return s64, info
+

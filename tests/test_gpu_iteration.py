@@ -80,3 +80,46 @@ def test_resume_reproduces_next_iterate():
     b.iterate(1)
     assert torch.equal(a.get("sigma"), b.get("sigma"))
     assert torch.equal(a.get("phi"), b.get("phi"))
+
+
+def test_copy_state_between_contexts():
+    """parquet_copy_state: same storage -> the next iterates agree bitwise;
+    complex64 -> complex128 -> the vertex is widened exactly; different boxes
+    are rejected before anything runs."""
+    from paper_1510_03330_amd.native import ParquetError, PQ_ERR_ARG
+    print("CASE copy_state", flush=True)
+    p = config("tiny_2x2")
+    a = _solver(p, "fp64")
+    a.iterate(2)
+    b = _solver(p, "fp64")
+    b.copy_state_from(a)
+    a.iterate(1)
+    b.iterate(1)
+    assert torch.equal(a.get("sigma"), b.get("sigma"))
+    assert torch.equal(a.get("phi"), b.get("phi"))
+    c32 = _solver(p, "fp32")
+    c32.iterate(2)
+    c64 = _solver(p, "fp64")
+    c64.copy_state_from(c32)
+    assert torch.equal(c64.get("phi"), c32.get("phi").to(torch.complex128))
+    assert torch.equal(c64.get("sigma"), c32.get("sigma"))
+    other = _solver(config("small_2x4"), "fp64")
+    with pytest.raises(ParquetError) as e:
+        other.copy_state_from(a)
+    assert e.value.status == PQ_ERR_ARG
+    for s in (a, b, c32, c64, other):
+        s.close()
+
+
+def test_c1_mixed_precision_converges_to_fp64_solution(c1_oracle):
+    """FP32 iterations to 1e-5, then FP64 iterations from that state to the
+    1e-8 tolerance: the converged Sigma and Phi carry FP64 accuracy (the FP32
+    rounding of the hand-over state is iterated away)."""
+    from paper_1510_03330_amd.ops import converge_mixed
+    print("CASE c1 mixed precision", flush=True)
+    p, ref = c1_oracle
+    s, info = converge_mixed(p, tol=p.tol, switch_tol=1e-5, max_iter=200)
+    assert info["converged"] and info["iterations_fp32"] > 0 and info["iterations_fp64"] > 0
+    assert relerr(H(s.get("sigma")), ref.sigma) < 1e-8
+    assert relerr(H(s.get("phi")), ref.phi) < 1e-7
+    s.close()
