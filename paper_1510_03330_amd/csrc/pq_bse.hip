@@ -135,6 +135,87 @@ struct WTile {
   }
 };
 
+// Accumulators of a WM x WN complex tile in the three-product form:
+//   X1 += (ar + ai) br,  X2 += ar (bi - br),  X3 += ai (br + bi),
+//   Re(ab) = X1 - X3,    Im(ab) = X1 + X2
+// (three real matrix products per complex product instead of four).
+template <typename T, int WM, int WN>
+struct Tile3 {
+  using M = Mma<T>;
+  using C = typename cplx_of<T>::type;
+  static constexpr int SR = WM / M::TM, SC = WN / M::TN;
+  typename M::acc_t x1[SR][SC], x2[SR][SC], x3[SR][SC];
+  template <class F> __device__ void load_c(F f) {     // X1 = 0, X2 = -Im C, X3 = Re C
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < SR; ++a)
+#pragma unroll
+      for (int b = 0; b < SC; ++b)
+#pragma unroll
+        for (int v = 0; v < M::NV; ++v) {
+          const C c = f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l));
+          x1[a][b][v] = (T)0;
+          x2[a][b][v] = -c.y;
+          x3[a][b][v] = c.x;
+        }
+  }
+  __device__ void mac(const C (&av)[SR], const C (&bv)[SC]) {
+    T as[SR], bd[SC], bs[SC];
+#pragma unroll
+    for (int x = 0; x < SR; ++x) as[x] = av[x].x + av[x].y;
+#pragma unroll
+    for (int y = 0; y < SC; ++y) {
+      bd[y] = bv[y].y - bv[y].x;
+      bs[y] = bv[y].x + bv[y].y;
+    }
+#pragma unroll
+    for (int x = 0; x < SR; ++x)
+#pragma unroll
+      for (int y = 0; y < SC; ++y) {
+        x1[x][y] = M::mma(as[x], bv[y].x, x1[x][y]);
+        x2[x][y] = M::mma(av[x].x, bd[y], x2[x][y]);
+        x3[x][y] = M::mma(av[x].y, bs[y], x3[x][y]);
+      }
+  }
+  __device__ void zero() {
+#pragma unroll
+    for (int a = 0; a < SR; ++a)
+#pragma unroll
+      for (int b = 0; b < SC; ++b)
+#pragma unroll
+        for (int v = 0; v < M::NV; ++v) { x1[a][b][v] = (T)0; x2[a][b][v] = (T)0; x3[a][b][v] = (T)0; }
+  }
+  // started from zero: ab = (X1 - X3, X1 + X2)
+  template <class F> __device__ void store_prod(F f) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < SR; ++a)
+#pragma unroll
+      for (int b = 0; b < SC; ++b)
+#pragma unroll
+        for (int v = 0; v < M::NV; ++v) {
+          C c;
+          c.x = x1[a][b][v] - x3[a][b][v];
+          c.y = x1[a][b][v] + x2[a][b][v];
+          f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l), c);
+        }
+  }
+  template <class F> __device__ void store_c(F f) {    // C - ab = (X3 - X1, -X1 - X2)
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < SR; ++a)
+#pragma unroll
+      for (int b = 0; b < SC; ++b)
+#pragma unroll
+        for (int v = 0; v < M::NV; ++v) {
+          C c;
+          c.x = x3[a][b][v] - x1[a][b][v];
+          c.y = -x1[a][b][v] - x2[a][b][v];
+          f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l), c);
+        }
+  }
+};
+
 template <typename C> __device__ inline C cz();
 template <> __device__ inline float2 cz<float2>() { return make_float2(0.f, 0.f); }
 template <> __device__ inline double2 cz<double2>() { return make_double2(0.0, 0.0); }
@@ -229,7 +310,8 @@ __global__ __launch_bounds__(kThreads) void bse_init_kernel(BseCtx<T> a) {
 template <int NB> constexpr int pivot_threads() { return NB >= 128 ? 512 : 256; }
 
 template <typename T, int NB>
-__global__ __launch_bounds__(pivot_threads<NB>()) void bse_pivot_kernel(BseCtx<T> a, int j0) {
+__global__ __launch_bounds__(pivot_threads<NB>()) __attribute__((amdgpu_waves_per_eu(NB >= 128 ? 4 : 3)))
+void bse_pivot_kernel(BseCtx<T> a, int j0) {
   using C = typename cplx_of<T>::type;
   constexpr int RPT = NB * NB / pivot_threads<NB>();
   __shared__ C colbuf[2][NB];
@@ -328,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
       for (int xx = 0; xx < SR; ++xx) pa[rt][xx] = P + (size_t)(rt * 32 + xx * M::TM + M::a_row(lane)) * NB + M::a_k(lane);
-    WT acc[NRT];
+    Tile3<T, 32, 32> acc[NRT];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) acc[rt].zero();
     // operands for k-step ks: b from the panel rows of this strip (clamped to
@@ -358,11 +440,11 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
       if (ks + PF < KSTEPS) fetch(ks + PF, aq[cur], bq[cur]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int rt = 0; rt < NRT; ++rt) acc[rt].mac(av[rt], bv, false);
+      for (int rt = 0; rt < NRT; ++rt) acc[rt].mac(av[rt], bv);
     }
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
-      acc[rt].store([&](int r, int c, C v) {
+      acc[rt].store_prod([&](int r, int c, C v) {
         const int row = rt * 32 + r, col = cs * 32 + c;
         if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
       });
@@ -403,61 +485,6 @@ template <typename T, bool FULL>
 using UpdDefault = typename std::conditional<
     sizeof(T) == 4, typename std::conditional<FULL, UpdCfg<T, 64, 64, 2, 2, true>, UpdCfg<T, 64, 32, 2, 3, false>>::type,
     UpdCfg<T, 32, 32, 1, 2, FULL>>::type;
-
-// Accumulators of a UWM x UWN complex tile in the three-product form.
-template <typename T, int WM, int WN>
-struct Tile3 {
-  using M = Mma<T>;
-  using C = typename cplx_of<T>::type;
-  static constexpr int SR = WM / M::TM, SC = WN / M::TN;
-  typename M::acc_t x1[SR][SC], x2[SR][SC], x3[SR][SC];
-  template <class F> __device__ void load_c(F f) {     // X1 = 0, X2 = -Im C, X3 = Re C
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int a = 0; a < SR; ++a)
-#pragma unroll
-      for (int b = 0; b < SC; ++b)
-#pragma unroll
-        for (int v = 0; v < M::NV; ++v) {
-          const C c = f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l));
-          x1[a][b][v] = (T)0;
-          x2[a][b][v] = -c.y;
-          x3[a][b][v] = c.x;
-        }
-  }
-  __device__ void mac(const C (&av)[SR], const C (&bv)[SC]) {
-    T as[SR], bd[SC], bs[SC];
-#pragma unroll
-    for (int x = 0; x < SR; ++x) as[x] = av[x].x + av[x].y;
-#pragma unroll
-    for (int y = 0; y < SC; ++y) {
-      bd[y] = bv[y].y - bv[y].x;
-      bs[y] = bv[y].x + bv[y].y;
-    }
-#pragma unroll
-    for (int x = 0; x < SR; ++x)
-#pragma unroll
-      for (int y = 0; y < SC; ++y) {
-        x1[x][y] = M::mma(as[x], bv[y].x, x1[x][y]);
-        x2[x][y] = M::mma(av[x].x, bd[y], x2[x][y]);
-        x3[x][y] = M::mma(av[x].y, bs[y], x3[x][y]);
-      }
-  }
-  template <class F> __device__ void store_c(F f) {    // C - ab = (X3 - X1, -X1 - X2)
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int a = 0; a < SR; ++a)
-#pragma unroll
-      for (int b = 0; b < SC; ++b)
-#pragma unroll
-        for (int v = 0; v < M::NV; ++v) {
-          C c;
-          c.x = x3[a][b][v] - x1[a][b][v];
-          c.y = -x1[a][b][v] - x2[a][b][v];
-          f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l), c);
-        }
-  }
-};
 
 // The four-product form behind the same interface (acc = C, acc -= ab).
 template <typename T, int WM, int WN>
