@@ -9,11 +9,12 @@
 // (q block, tile) grids. Per panel J:
 //   (a) bse_pivot:  P = A_JJ^-1 by Gauss-Jordan on the NB x NB diagonal block,
 //                   held in registers (one column per thread and a slice of its
-//                   rows), pivot rows and columns broadcast through LDS;
+//                   rows), pivot rows and columns broadcast through LDS; the
+//                   other workgroups of the launch copy the multipliers A_IJ
+//                   k-major (MT[k][i] = A[i][J0 + k]) so that the update's
+//                   operand loads coalesce, while the inversions run;
 //   (b) bse_panel:  pivot rows R_JK = P A_JK for every column right of the
-//                   panel in A and every column of B (in place), and the
-//                   multipliers A_IJ copied k-major (MT[k][i] = A[i][J0 + k])
-//                   so that the update's operand loads coalesce;
+//                   panel in A and every column of B (in place);
 //   (c) bse_update: A_IK -= A_IJ R_JK, B_I -= A_IJ R_JB for all rows I != J, a
 //                   rank-NB update; each wave owns a 64 x 64 (complex64) or
 //                   32 x 32 (complex128) tile, reads both operands straight
@@ -299,6 +300,29 @@ __global__ __launch_bounds__(kThreads) void bse_init_kernel(BseCtx<T> a) {
   }
 }
 
+// Multipliers of panel J: A[i][J0 .. J0 + NB) for 32 rows i0 .. i0 + 31,
+// through an LDS transpose into MT[k][i]; rows k >= jb of MT (ragged last
+// panel) are written as zeros, so the update reads them unmasked.
+template <typename T, int NB>
+__device__ void copy_multipliers(const BseCtx<T>& a, int blk, int j0, int i0,
+                                 typename cplx_of<T>::type (*X)[NB + 1]) {
+  using C = typename cplx_of<T>::type;
+  const int t = threadIdx.x, nt = blockDim.x, n = a.n;
+  const int jb = min(NB, n - j0);
+  const C* A = a.A + (size_t)blk * n * n;
+  C* MT = a.MT + (size_t)blk * NB * n;
+  for (int idx = t; idx < 32 * NB; idx += nt) {
+    const int r = idx / NB, k = idx - (idx / NB) * NB;
+    const C v = A[(size_t)min(i0 + r, n - 1) * n + j0 + min(k, jb - 1)];
+    X[r][k] = k < jb ? v : cz<C>();
+  }
+  __syncthreads();
+  for (int idx = t; idx < 32 * NB; idx += nt) {
+    const int k = idx >> 5, r = idx & 31;
+    if (i0 + r < n) MT[(size_t)k * n + i0 + r] = X[r][k];
+  }
+}
+
 // ------------------------------------------------------------------ pivot
 // P = A_JJ^-1 by in-place Gauss-Jordan on the diagonal block (identity outside
 // the jb x jb part for a ragged last panel). Thread t holds column j = t % NB
@@ -316,7 +340,12 @@ void bse_pivot_kernel(BseCtx<T> a, int j0) {
   constexpr int RPT = NB * NB / pivot_threads<NB>();
   __shared__ C colbuf[2][NB];
   __shared__ C rowbuf[2][NB];
-  const int blk = blockIdx.x, t = threadIdx.x, n = a.n;
+  if (blockIdx.x > 0) {                  // the other workgroups copy the multipliers
+    __shared__ C X[32][NB + 1];
+    copy_multipliers<T, NB>(a, blockIdx.y, j0, (blockIdx.x - 1) * 32, X);
+    return;
+  }
+  const int blk = blockIdx.y, t = threadIdx.x, n = a.n;
   const int j = t % NB, h = t / NB, r0 = h * RPT;
   const int jb = min(NB, n - j0);
   const C* A = a.A + (size_t)blk * n * n;
@@ -378,25 +407,21 @@ void bse_pivot_kernel(BseCtx<T> a, int j0) {
 }
 
 // ------------------------------------------------------------------ panel
-// x < nwb: pivot-row workgroups, one 32-column strip per wave: R = P A_J,strip
-// for all NB rows of the panel at once (NB / 32 accumulator tiles), written in
-// place after the whole strip has been read. x >= nwb: multiplier workgroups,
-// 32 rows each: A[i][J0 .. J0 + NB) through an LDS transpose into MT[k][i];
-// rows k >= jb of MT (ragged last panel) are written as zeros, so the update
-// reads them unmasked.
+// One 32-column strip per wave: R = P A_J,strip for all NB rows of the panel at
+// once (NB / 32 accumulator tiles in the three-product form), written in place
+// after the whole strip has been read.
 template <typename T, int NB>
 __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
   using WT = WTile<T>;
   constexpr int SR = WT::SR, SC = WT::SC, KSTEPS = NB / M::KS, NRT = NB / 32, PF = 2;
-  __shared__ C X[32][NB + 1];
   const int blk = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
   const int jb = min(NB, n - j0);
   const int ncols = (n - j0 - jb) + n;
   C* A = a.A + (size_t)blk * n * n;
   C* B = a.B + (size_t)blk * n * n;
-  if ((int)blockIdx.x < nwb) {
+  {
     const int cs = blockIdx.x * kWaves + wave;
     if (cs * 32 >= ncols) return;
     const C* P = a.PI + (size_t)blk * NB * NB;
@@ -448,19 +473,6 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
         const int row = rt * 32 + r, col = cs * 32 + c;
         if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
       });
-  } else {
-    const int i0 = (blockIdx.x - nwb) * 32;
-    C* MT = a.MT + (size_t)blk * NB * n;
-    for (int idx = t; idx < 32 * NB; idx += kThreads) {
-      const int r = idx / NB, k = idx - (idx / NB) * NB;
-      const C v = A[(size_t)min(i0 + r, n - 1) * n + j0 + min(k, jb - 1)];
-      X[r][k] = k < jb ? v : cz<C>();
-    }
-    __syncthreads();
-    for (int idx = t; idx < 32 * NB; idx += kThreads) {
-      const int k = idx >> 5, r = idx & 31;
-      if (i0 + r < n) MT[(size_t)k * n + i0 + r] = X[r][k];
-    }
   }
 }
 
@@ -699,12 +711,12 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     const int jb = std::min(NB, n - j0);
     const int ncols = (n - j0 - jb) + n;
     pre(1);
-    hipLaunchKernelGGL((bse_pivot_kernel<T, NB>), dim3(d.Nq), dim3(pivot_threads<NB>()), 0, s, a, j0);
+    const int nwc = (n + 31) / 32;
+    hipLaunchKernelGGL((bse_pivot_kernel<T, NB>), dim3(1 + nwc, d.Nq), dim3(pivot_threads<NB>()), 0, s, a, j0);
     post();
     const int nwb = ((ncols + 31) / 32 + kWaves - 1) / kWaves;
-    const int nwc = (n + 31) / 32;
     pre(2);
-    hipLaunchKernelGGL((bse_panel_kernel<T, NB>), dim3(nwb + nwc, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
+    hipLaunchKernelGGL((bse_panel_kernel<T, NB>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
     post();
     pre(3);
     if (jb == NB)
