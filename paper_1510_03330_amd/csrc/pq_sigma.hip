@@ -27,7 +27,6 @@ namespace pq {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kS2Split = 8;      // workgroups per output point of Sigma~_2
 constexpr int kPoles = 128;   // semicircle pole representation (Gauss-Chebyshev)
 
 __device__ inline double nu_of(int n, double beta) { return (2 * n + 1) * M_PI / beta; }
@@ -215,13 +214,24 @@ __global__ void s1_out_kernel(S1Args a) {
 }
 
 // ------------------------------------------------------------- Sigma~_2
+// Re-indexed to native variables (transfer p = (m_p, P), second fermionic
+// argument b = (n_b, B)), every term is a product of a G factor of (k, p), the
+// indicator weights e16, e25, e34 of the summation domain, which depend on the
+// frequencies (n_k, m_p, n_b) only, and momentum-dependent factors of (p, b).
+// The momentum sums are therefore done first, once per (p, n_b):
+//   U1 = sum_B G(b+p) G(b),  U3 = sum_B G(p-b) G(b),
+//   V1d, V1m = sum_B G(b+p) G(b) K2_{d,m}(b;p),  V3st = sum_B G(p-b) G(b) (K2_s + K2_t)(b;p)
+// (the V's for b in the box), and the k sum runs over n_b only:
+//   s16 = G(k+p) sum e16 U1,  s25 = G(k+p) sum e25 U1,  s34 = G(p-k) sum e34 U3,
+//   sk  = G(k+p) sum [e16 V1d - (e16 + 2 e25) V1m] + G(p-k) sum e34 V3st.
 struct S2Args {
   Dims d;
   int level;
   const double2* g;
   const double2* k1;     // [4][Nq]
   const double2* k2;     // [4][Nq][n]
-  double2* out;          // [kS2Split][Nve][Nk]  partial sums (without the constant C)
+  double2* tab;          // [NG][5][Nq]  U1, U3, V1d, V1m, V3st per (n_b, p)
+  double2* out;          // [Nve][Nk]  (sum without the constant C)
 };
 
 __device__ inline double ind(bool b) { return b ? 1.0 : 0.0; }
@@ -231,21 +241,53 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// one wave per (n_b, p): lanes over the momentum B
+__global__ __launch_bounds__(kThreads) void s2_tables_kernel(S2Args a) {
+  const Dims& d = a.d;
+  const int wid = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (wid >= d.NG * d.Nq) return;
+  const int nbi = wid / d.Nq, qi = wid - (wid / d.Nq) * d.Nq;
+  const int hG = d.NG / 2, nb = nbi - hG;
+  const int jm = qi / d.Nk, P = qi - jm * d.Nk, mp = jm - (d.Nv / 2 - 1);
+  const bool r1 = nb + mp >= -hG && nb + mp < hG, r3 = mp - nb - 1 >= -hG && mp - nb - 1 < hG;
+  const bool kb2 = in_fbox(nb, d.Nv) && a.level >= 2;
+  const size_t n = d.n;
+  double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int B = lane; B < d.Nk; B += 64) {
+    const double2 gb = a.g[(size_t)(nb + hG) * d.Nk + B];
+    const double2 g1 = r1 ? a.g[(size_t)(nb + mp + hG) * d.Nk + kadd(B, P, d.Lx, d.Ly)] : mk(0, 0);
+    const double2 g3 = r3 ? a.g[(size_t)(mp - nb - 1 + hG) * d.Nk + ksub(P, B, d.Lx, d.Ly)] : mk(0, 0);
+    const double2 u1 = cmul(g1, gb), u3 = cmul(g3, gb);
+    double2 w1d = mk(0, 0), w1m = mk(0, 0), w3 = mk(0, 0);
+    if (kb2) {
+      const size_t bidx = (size_t)(nb + d.Nv / 2) * d.Nk + B;
+      w1d = cmul(u1, a.k2[((size_t)0 * d.Nq + qi) * n + bidx]);
+      w1m = cmul(u1, a.k2[((size_t)1 * d.Nq + qi) * n + bidx]);
+      w3 = cmul(u3, cadd(a.k2[((size_t)2 * d.Nq + qi) * n + bidx], a.k2[((size_t)3 * d.Nq + qi) * n + bidx]));
+    }
+    v[0] += u1.x; v[1] += u1.y; v[2] += u3.x; v[3] += u3.y;
+    v[4] += w1d.x; v[5] += w1d.y; v[6] += w1m.x; v[7] += w1m.y; v[8] += w3.x; v[9] += w3.y;
+  }
+  for (int i = 0; i < 10; ++i) v[i] = wave_sum(v[i]);
+  if (lane < 5) {
+    const double2 o = mk(v[2 * lane], v[2 * lane + 1]);
+    a.tab[((size_t)nbi * 5 + lane) * d.Nq + qi] = o;
+  }
+}
+
+// one workgroup per k point of the extended box; threads over the transfers p
 __global__ __launch_bounds__(kThreads) void sigma2_kernel(S2Args a) {
-  __shared__ double red[2 * (kThreads / 64)];
+  __shared__ double red[kThreads];
   const Dims& d = a.d;
   const int kid = blockIdx.x;
   const int ek = kid / d.Nk, K = kid - ek * d.Nk;
   const int nk = ek - d.Nve / 2;
   const bool kbox = in_fbox(nk, d.Nv);
   const int kbi = kbox ? (nk + d.Nv / 2) * d.Nk + K : 0;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nwaves = blockDim.x >> 6;
   const int hF = d.Nve / 2, hBe = d.Nve / 2 - 1, hBb = d.Nv / 2 - 1, hG = d.NG / 2;
-  const size_t n = d.n;
+  const size_t n = d.n, nq = d.Nq;
   double tr = 0.0, ti = 0.0;
-  // transfers are split over kS2Split workgroups (blockIdx.y) for parallelism
-  for (int qi = blockIdx.y * nwaves + wave; qi < d.Nq; qi += nwaves * gridDim.y) {
+  for (int qi = threadIdx.x; qi < d.Nq; qi += blockDim.x) {
     const int jm = qi / d.Nk, P = qi - jm * d.Nk;
     const int mp = jm - hBb;
     double2 c[4];
@@ -262,10 +304,8 @@ __global__ __launch_bounds__(kThreads) void sigma2_kernel(S2Args a) {
     int hi = max(hF - 1, max(nk + hBe, -mp - nk - 1 + hBe));
     lo = max(lo, -hG);
     hi = min(hi, hG - 1);
-    double2 s16 = mk(0, 0), s25 = mk(0, 0), s34 = mk(0, 0), sk = mk(0, 0);
-    const int cnt = (hi - lo + 1) * d.Nk;
-    for (int bi = lane; bi < cnt; bi += 64) {
-      const int nb = lo + bi / d.Nk, B = bi - (bi / d.Nk) * d.Nk;
+    double2 a16 = mk(0, 0), a25 = mk(0, 0), a34 = mk(0, 0), kd = mk(0, 0), km = mk(0, 0), kst = mk(0, 0);
+    for (int nb = lo; nb <= hi; ++nb) {
       const bool bFe = nb >= -hF && nb <= hF - 1;
       const bool bFb = in_fbox(nb, d.Nv);
       const int x1 = mp + nk + nb + 1, x2 = nb - nk, x3 = mp - nk - nb - 1;
@@ -278,39 +318,19 @@ __global__ __launch_bounds__(kThreads) void sigma2_kernel(S2Args a) {
         e34 -= 1.0 + ind(in_bbox(x3, d.Nv));
       }
       if (e16 == 0.0 && e25 == 0.0 && e34 == 0.0) continue;
-      const double2 gb = a.g[(size_t)(nb + hG) * d.Nk + B];
-      double2 w16 = mk(0, 0), w25 = mk(0, 0), w34 = mk(0, 0);
-      if (e16 != 0.0 || e25 != 0.0) {
-        const double2 gbp = a.g[(size_t)(nb + mp + hG) * d.Nk + kadd(B, P, d.Lx, d.Ly)];
-        const double2 A1 = cmul(cmul(g_kp, gbp), gb);
-        w16 = cscale(A1, e16);
-        w25 = cscale(A1, e25);
-      }
-      if (e34 != 0.0) {
-        const double2 gpb = a.g[(size_t)(mp - nb - 1 + hG) * d.Nk + ksub(P, B, d.Lx, d.Ly)];
-        const double2 A3 = cmul(cmul(gpb, g_pk), gb);
-        w34 = cscale(A3, e34);
-      }
-      s16 = cadd(s16, w16);
-      s25 = cadd(s25, w25);
-      s34 = cadd(s34, w34);
+      const double2* t = a.tab + (size_t)(nb + hG) * 5 * nq + qi;
+      const double2 u1 = t[0], u3 = t[nq];
+      a16 = cadd(a16, cscale(u1, e16));
+      a25 = cadd(a25, cscale(u1, e25));
+      a34 = cadd(a34, cscale(u3, e34));
       if (bFb && a.level >= 2) {
-        const size_t bidx = (size_t)(nb + d.Nv / 2) * d.Nk + B;
-        const double2 kd = a.k2[((size_t)0 * d.Nq + qi) * n + bidx];
-        const double2 km = a.k2[((size_t)1 * d.Nq + qi) * n + bidx];
-        const double2 ks = a.k2[((size_t)2 * d.Nq + qi) * n + bidx];
-        const double2 kt = a.k2[((size_t)3 * d.Nq + qi) * n + bidx];
-        const double2 w1625 = cadd(w16, cscale(w25, 2.0));
-        sk = cadd(sk, csub(cmul(w16, kd), cmul(w1625, km)));
-        sk = cadd(sk, cmul(w34, cadd(ks, kt)));
+        kd = cadd(kd, cscale(t[2 * nq], e16));
+        km = cadd(km, cscale(t[3 * nq], e16 + 2.0 * e25));
+        kst = cadd(kst, cscale(t[4 * nq], e34));
       }
     }
-    double v[8] = {s16.x, s16.y, s25.x, s25.y, s34.x, s34.y, sk.x, sk.y};
-    for (int i = 0; i < 8; ++i) v[i] = wave_sum(v[i]);
-    s16 = mk(v[0], v[1]);
-    s25 = mk(v[2], v[3]);
-    s34 = mk(v[4], v[5]);
-    sk = mk(v[6], v[7]);
+    const double2 s16 = cmul(g_kp, a16), s25 = cmul(g_kp, a25), s34 = cmul(g_pk, a34);
+    const double2 sk = cadd(cmul(g_kp, csub(kd, km)), cmul(g_pk, kst));
     double2 contrib = cmul(c[0], s16);
     contrib = csub(contrib, cmul(c[1], cadd(s16, cscale(s25, 2.0))));
     contrib = cadd(contrib, cmul(cadd(c[2], c[3]), s34));
@@ -318,19 +338,9 @@ __global__ __launch_bounds__(kThreads) void sigma2_kernel(S2Args a) {
     tr += contrib.x;
     ti += contrib.y;
   }
-  if (lane == 0) {
-    red[2 * wave] = tr;
-    red[2 * wave + 1] = ti;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double sr = 0.0, si = 0.0;
-    for (int w = 0; w < nwaves; ++w) {
-      sr += red[2 * w];
-      si += red[2 * w + 1];
-    }
-    a.out[(size_t)blockIdx.y * d.Nve * d.Nk + kid] = mk(sr, si);
-  }
+  tr = block_sum(tr, red);
+  ti = block_sum(ti, red);
+  if (threadIdx.x == 0) a.out[kid] = mk(tr, ti);
 }
 
 // ------------------------------------------------------------ Sigma_box
@@ -402,11 +412,7 @@ __global__ void combine_kernel(CombineArgs a) {
   int e = idx / d.Nk, K = idx - e * d.Nk;
   int n = e - d.Nve / 2;
   double2 v = a.s1[idx];
-  if (a.has_s2) {
-    double2 acc = mk(0, 0);
-    for (int j = 0; j < kS2Split; ++j) acc = cadd(acc, a.s2[(size_t)j * d.Nve * d.Nk + idx]);
-    v = cadd(v, cscale(acc, a.cfac));
-  }
+  if (a.has_s2) v = cadd(v, cscale(a.s2[idx], a.cfac));
   if (a.has_box && in_fbox(n, d.Nv)) {
     int kbi = (n + d.Nv / 2) * d.Nk + K;
     double2 acc = mk(0, 0);
@@ -417,7 +423,7 @@ __global__ void combine_kernel(CombineArgs a) {
 }
 
 struct WsLayout {
-  size_t tau, wt, dg, gkt, grt, trn, s1, s2, part, total;
+  size_t tau, wt, dg, gkt, grt, trn, s1, s2, tab, part, total;
 };
 
 WsLayout ws_layout(const Dims& d) {
@@ -431,7 +437,8 @@ WsLayout ws_layout(const Dims& d) {
   L.grt = take(sizeof(double2) * (size_t)d.ntau * d.Nk);
   L.trn = take(sizeof(double2) * d.Nve * d.Nk);
   L.s1 = take(sizeof(double2) * d.Nve * d.Nk);
-  L.s2 = take(sizeof(double2) * kS2Split * d.Nve * d.Nk);
+  L.s2 = take(sizeof(double2) * d.Nve * d.Nk);
+  L.tab = take(sizeof(double2) * 5 * (size_t)d.NG * d.Nq);
   L.part = take(sizeof(double2) * (size_t)d.n * d.NW);
   L.total = off;
   return L;
@@ -475,8 +482,10 @@ hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, cons
   if (e != hipSuccess) return e;
   const int has_s2 = p.kernel_level > 0 ? 1 : 0;
   if (has_s2) {
-    S2Args a2{d, p.kernel_level, g, k1, k2, s2};
-    hipLaunchKernelGGL(sigma2_kernel, dim3(d.Nve * d.Nk, kS2Split), dim3(kThreads), 0, s, a2);
+    S2Args a2{d, p.kernel_level, g, k1, k2, (double2*)(ws + L.tab), s2};
+    const unsigned nwav = (unsigned)d.NG * d.Nq, wpb = kThreads / 64;
+    hipLaunchKernelGGL(s2_tables_kernel, dim3((nwav + wpb - 1) / wpb), dim3(kThreads), 0, s, a2);
+    hipLaunchKernelGGL(sigma2_kernel, dim3(d.Nve * d.Nk), dim3(kThreads), 0, s, a2);
   }
   if (p.storage == PQ_STORE_C64) {
     SBArgs<float2> ab{d, (const float2*)phi, g, part};
