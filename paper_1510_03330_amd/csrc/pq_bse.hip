@@ -269,35 +269,26 @@ struct BseCtx {
   pq_bse_block_stats* stats;
 };
 
-// ------------------------------------------------------------------- init
-// A = 1 - s Gamma diag(X), B = Gamma
+// -------------------------------------------------------- first panel
+// The system is never materialised before the elimination: the kernels of the
+// first panel read Gamma and form A = 1 - s Gamma diag(X) on the fly (B starts
+// as Gamma), and their writes create the A and B arrays the later panels use
+// (pivot rows from the pivot-row step, every other row from the update).
+// Element (i, j) of [A | B] in the combined column index j (< n: A, else B).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void bse_init_kernel(BseCtx<T> a) {
+__device__ inline typename cplx_of<T>::type system_elem(const BseCtx<T>& a, int blk, int i, int j) {
   using C = typename cplx_of<T>::type;
-  const int blk = blockIdx.y;
   const int n = a.n;
-  const size_t nn = (size_t)n * n;
-  const C* G = a.gamma + (size_t)blk * nn;
-  C* A = a.A + (size_t)blk * nn;
-  C* B = a.B + (size_t)blk * nn;
-  const double2* x = a.chi0 + (size_t)blk * n;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn; idx += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
-    const C g = G[idx];
-    const double2 xv = x[j];
-    const T sx = a.sign * (T)xv.x, sy = a.sign * (T)xv.y;
-    C v;
-    v.x = (i == j ? (T)1 : (T)0) - (g.x * sx - g.y * sy);
-    v.y = -(g.x * sy + g.y * sx);
-    A[idx] = v;
-    B[idx] = g;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double* ps = a.pst + (size_t)blk * 4;
-    ps[0] = DBL_MAX;
-    ps[1] = 0.0;
-    ps[2] = 0.0;
-  }
+  const bool inA = j < n;
+  const int col = inA ? j : j - n;
+  const C g = a.gamma[(size_t)blk * n * n + (size_t)i * n + col];
+  if (!inA) return g;
+  const double2 xv = a.chi0[(size_t)blk * n + col];
+  const T sx = a.sign * (T)xv.x, sy = a.sign * (T)xv.y;
+  C v;
+  v.x = (i == j ? (T)1 : (T)0) - (g.x * sx - g.y * sy);
+  v.y = -(g.x * sy + g.y * sx);
+  return v;
 }
 
 // Multipliers of panel J: A[i][J0 .. J0 + NB) for 32 rows i0 .. i0 + 31,
@@ -313,7 +304,8 @@ __device__ void copy_multipliers(const BseCtx<T>& a, int blk, int j0, int i0,
   C* MT = a.MT + (size_t)blk * NB * n;
   for (int idx = t; idx < 32 * NB; idx += nt) {
     const int r = idx / NB, k = idx - (idx / NB) * NB;
-    const C v = A[(size_t)min(i0 + r, n - 1) * n + j0 + min(k, jb - 1)];
+    const int i = min(i0 + r, n - 1), j = j0 + min(k, jb - 1);
+    const C v = j0 == 0 ? system_elem(a, blk, i, j) : A[(size_t)i * n + j];
     X[r][k] = k < jb ? v : cz<C>();
   }
   __syncthreads();
@@ -353,7 +345,8 @@ void bse_pivot_kernel(BseCtx<T> a, int j0) {
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = r0 + q;
-    const C v = A[(size_t)(j0 + min(r, jb - 1)) * n + j0 + min(j, jb - 1)];
+    const int ri = j0 + min(r, jb - 1), ci = j0 + min(j, jb - 1);
+    const C v = j0 == 0 ? system_elem(a, blk, ri, ci) : A[(size_t)ri * n + ci];
     C e = cz<C>();
     if (r == j) e.x = 1;
     x[q] = (r < jb && j < jb) ? v : e;
@@ -400,9 +393,10 @@ void bse_pivot_kernel(BseCtx<T> a, int j0) {
   for (int q = 0; q < RPT; ++q) P[(size_t)(r0 + q) * NB + j] = x[q];
   if (t == 0) {
     double* ps = a.pst + (size_t)blk * 4;
-    ps[0] = fmin(ps[0], pmin);
-    ps[1] = fmax(ps[1], pmax);
-    if (bad) ps[2] = 1.0;
+    const bool first = j0 == 0;
+    ps[0] = first ? pmin : fmin(ps[0], pmin);
+    ps[1] = first ? pmax : fmax(ps[1], pmax);
+    ps[2] = (bad || (!first && ps[2] > 0.0)) ? 1.0 : 0.0;
   }
 }
 
@@ -410,7 +404,51 @@ void bse_pivot_kernel(BseCtx<T> a, int j0) {
 // One 32-column strip per wave: R = P A_J,strip for all NB rows of the panel at
 // once (NB / 32 accumulator tiles in the three-product form), written in place
 // after the whole strip has been read.
-template <typename T, int NB>
+// Source of the strip's panel rows: A/B, or (first panel) Gamma with
+// A = 1 - s Gamma diag(X) formed per element. colsrc() gives the per-lane
+// pointer (row j0 of column c) and the diagonal-term data of the column.
+template <typename T>
+struct ColSrc {
+  using C = typename cplx_of<T>::type;
+  const C* p;          // element of row j0 of this column
+  T sx, sy;            // s X[col] for an A column (0 for a B column)
+  int diag;            // row index whose element gets the unit diagonal (-1: none)
+  bool inA;
+  __device__ C at(int k, int n, int j0) const {   // row j0 + k
+    const C g = p[(size_t)k * n];
+    if (!inA) return g;
+    C v;
+    v.x = (j0 + k == diag ? (T)1 : (T)0) - (g.x * sx - g.y * sy);
+    v.y = -(g.x * sy + g.y * sx);
+    return v;
+  }
+};
+
+template <typename T, bool FIRST>
+__device__ inline ColSrc<T> colsrc(const BseCtx<T>& a, int blk, int j0, int jb, int c) {
+  ColSrc<T> r;
+  const int n = a.n;
+  const int ncolA = n - j0 - jb;
+  r.inA = FIRST && c < ncolA;
+  r.diag = -1;
+  r.sx = (T)0;
+  r.sy = (T)0;
+  if (FIRST) {
+    const int col = c < ncolA ? j0 + jb + c : c - ncolA;
+    r.p = a.gamma + (size_t)blk * n * n + (size_t)j0 * n + col;
+    if (r.inA) {
+      const double2 xv = a.chi0[(size_t)blk * n + col];
+      r.sx = a.sign * (T)xv.x;
+      r.sy = a.sign * (T)xv.y;
+      r.diag = col;
+    }
+  } else {
+    r.p = colptr(a.A + (size_t)blk * n * n, a.B + (size_t)blk * n * n, n, j0, jb, c) + (size_t)j0 * n;
+  }
+  return r;
+}
+
+template <typename T, int NB, bool FIRST>
 __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
@@ -426,10 +464,10 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
     if (cs * 32 >= ncols) return;
     const C* P = a.PI + (size_t)blk * NB * NB;
     const int kb = M::b_k(lane);
-    const C* cp[SC];
+    ColSrc<T> cp[SC];
 #pragma unroll
     for (int y = 0; y < SC; ++y)
-      cp[y] = colptr(A, B, n, j0, jb, min(cs * 32 + y * M::TN + M::b_col(lane), ncols - 1)) + (size_t)j0 * n;
+      cp[y] = colsrc<T, FIRST>(a, blk, j0, jb, min(cs * 32 + y * M::TN + M::b_col(lane), ncols - 1));
     const C* pa[NRT][SR];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
@@ -443,7 +481,7 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
     auto fetch = [&](int ks, C (&av)[NRT][SR], C (&bv)[SC]) {
       const int k = min(ks * M::KS + kb, jb - 1);
 #pragma unroll
-      for (int y = 0; y < SC; ++y) bv[y] = cp[y][(size_t)k * n];
+      for (int y = 0; y < SC; ++y) bv[y] = cp[y].at(k, n, j0);
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
@@ -485,12 +523,16 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 //   X1 += (ar + ai) br,  X2 += ar (bi - br),  X3 += ai (br + bi),
 //   Re(ab) = X1 - X3,    Im(ab) = X1 + X2,
 // with X3 started at Re C and X2 at -Im C, so C - ab = (X3 - X1, -X1 - X2).
-template <typename T, int UWM_, int UWN_, int PF_, int WPE_, bool FULL_, bool M3_ = true>
+template <typename T_, int UWM_, int UWN_, int PF_, int WPE_, bool FULL_, bool M3_ = true, bool FIRST_ = false>
 struct UpdCfg {
+  using T = T_;
   static constexpr int UWM = UWM_, UWN = UWN_, PF = PF_, WPE = WPE_;
-  static constexpr bool FULL = FULL_, M3 = M3_;
+  static constexpr bool FULL = FULL_, M3 = M3_, FIRST = FIRST_;
   static constexpr int WGM = 2 * UWM, WGN = 2 * UWN;
 };
+// the same tile configuration for the first panel (C read from Gamma)
+template <class CF>
+using UpdFirst = UpdCfg<typename CF::T, CF::UWM, CF::UWN, CF::PF, CF::WPE, CF::FULL, CF::M3, true>;
 // (the ragged-panel form of the complex64 update uses a 64 x 32 tile: the
 // clamping of panel rows costs registers the 64 x 64 tile does not have)
 template <typename T, bool FULL>
@@ -544,7 +586,16 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   }
   auto row_ok = [&](int i) { return i < n && !(i >= j0 && i < j0 + jb); };
   UT acc;
-  acc.load_c([&](int r, int c) -> C { return cb[c / M::TN][(size_t)min(i0 + r, n - 1) * n]; });
+  if (CF::FIRST) {
+    // first panel: C comes from Gamma (A = 1 - s Gamma diag(X), B = Gamma)
+    ColSrc<T> src[USC];
+#pragma unroll
+    for (int y = 0; y < USC; ++y)
+      src[y] = colsrc<T, true>(a, blk, 0, jb, cok[y] ? c0 + y * M::TN + M::b_col(lane) : 0);
+    acc.load_c([&](int r, int c) -> C { return src[c / M::TN].at(min(i0 + r, n - 1), n, 0); });
+  } else {
+    acc.load_c([&](int r, int c) -> C { return cb[c / M::TN][(size_t)min(i0 + r, n - 1) * n]; });
+  }
   const int kb = M::b_k(lane), ka = M::a_k(lane);
   const C* bbase[USC];
 #pragma unroll
@@ -704,9 +755,6 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   };
   if (tm) tm->update_flops = 0.0;
   const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)n * n + kThreads - 1) / kThreads);
-  pre(0);
-  hipLaunchKernelGGL((bse_init_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a);
-  post();
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int jb = std::min(NB, n - j0);
     const int ncols = (n - j0 - jb) + n;
@@ -716,11 +764,18 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     post();
     const int nwb = ((ncols + 31) / 32 + kWaves - 1) / kWaves;
     pre(2);
-    hipLaunchKernelGGL((bse_panel_kernel<T, NB>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
+    if (j0 == 0)
+      hipLaunchKernelGGL((bse_panel_kernel<T, NB, true>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
+    else
+      hipLaunchKernelGGL((bse_panel_kernel<T, NB, false>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
     post();
     pre(3);
-    if (jb == NB)
+    if (jb == NB && j0 == 0)
+      launch_update<T, NB, UpdFirst<UpdDefault<T, true>>>(a, n, d.Nq, j0, s);
+    else if (jb == NB)
       launch_update<T, NB, UpdDefault<T, true>>(a, n, d.Nq, j0, s);
+    else if (j0 == 0)
+      launch_update<T, NB, UpdFirst<UpdDefault<T, false>>>(a, n, d.Nq, j0, s);
     else
       launch_update<T, NB, UpdDefault<T, false>>(a, n, d.Nq, j0, s);
     post();
