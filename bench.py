@@ -234,7 +234,7 @@ def main():
             "bse_solve_lu_equivalent_tflops": round(bse_alg, 2),
             "bse_solve_ms_per_channel": round(bse_channel_ms, 2),
             "bse_kernel_ms_per_channel": {k: round(r32["kern_ms"][i] / args.steps, 2) for k, i in
-                                          (("init", 0), ("pivot", 1), ("panel", 2), ("update", 3), ("epilogue", 4))}}
+                                          (("pivot", 1), ("pivot_rows", 2), ("update", 3), ("epilogue", 4))}}
 
     out = {
         "metric": "parquet iterations/s + time-to-converged Σ (1e-6) vs FP64 GPU, 8x8 Nv=16",

@@ -167,8 +167,13 @@ pq_status bse_workspace(const pq_params* p, size_t* bytes);
 /* Per-block diagnostics written by bse_solve (device memory, Nq entries). */
 typedef struct {
   float min_pivot;       /* smallest |pivot| / largest |pivot| of the block  */
-  float growth;          /* largest |entry| seen / largest |entry| of A      */
-  int32_t flags;         /* bit 0: weak pivot, bit 1: non-finite, bit 2: refined */
+  float growth;          /* largest |entry| of the inverted diagonal blocks
+                            (a lower bound of |A^-1| for the last block)     */
+  int32_t flags;         /* bit 0: weak (pivot ratio below 1e-3, or growth
+                            above 1e3, on the complex64 path; 1e-10 / 1e12
+                            on the complex128 path), bit 1: non-finite,
+                            bit 2: re-solved in FP64 (complex64 path, at most
+                            8 flagged blocks per call, in q order)          */
   int32_t reserved;
 } pq_bse_block_stats;
 
@@ -177,7 +182,10 @@ typedef struct {
  *   X = X_ph for d, m and X_pp for s, t,
  *   phi_io <- alpha (F - Gamma_r) + (1 - alpha) phi_io   (alpha = 1: plain output).
  * Elimination without row exchanges (A is the identity minus a small-norm
- * kernel); the pivot monitor flags weak blocks in stats (nullable).
+ * kernel); the pivot monitor flags weak blocks in stats (nullable). On the
+ * complex64/FP32 path up to 8 flagged blocks per call (in q order) are solved
+ * again in FP64 from the same Gamma before the mixing (stats bit 2); the
+ * workspace includes the room for that.
  * gamma: [Nq][n][n] (one channel), chi0: [Nq][n] c128, phi_io: [Nq][n][n],
  * both in storage precision; ws: bse_workspace bytes. */
 pq_status bse_solve(const pq_params* p, int32_t channel, int32_t precision,

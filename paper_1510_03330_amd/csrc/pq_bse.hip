@@ -42,6 +42,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kPst = 8;        // per-block pivot-monitor doubles
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
@@ -265,9 +266,15 @@ struct BseCtx {
   C* B;                  // [Nq][n][n]
   C* MT;                 // [Nq][NB][n]    multipliers of the current panel, k-major
   C* PI;                 // [Nq][NB][NB]   inverse of the current diagonal block
-  double* pst;           // [Nq][4]  min |pivot|, max |pivot|, non-finite seen
+  double* pst;           // [Nq][kPst]  min |pivot|, max |pivot|, non-finite seen, re-solved,
+                         //             max |entry| of the diagonal-block inverses
+  double kappa_max;      // flag a block whose diagonal-block inverses exceed this
   pq_bse_block_stats* stats;
+  const int* active;     // nullable: only blocks < *active are solved (re-solve slots)
 };
+
+template <typename T>
+__device__ inline bool inactive(const BseCtx<T>& a, int blk) { return a.active && blk >= *a.active; }
 
 // -------------------------------------------------------- first panel
 // The system is never materialised before the elimination: the kernels of the
@@ -332,6 +339,7 @@ void bse_pivot_kernel(BseCtx<T> a, int j0) {
   constexpr int RPT = NB * NB / pivot_threads<NB>();
   __shared__ C colbuf[2][NB];
   __shared__ C rowbuf[2][NB];
+  if (inactive(a, (int)blockIdx.y)) return;
   if (blockIdx.x > 0) {                  // the other workgroups copy the multipliers
     __shared__ C X[32][NB + 1];
     copy_multipliers<T, NB>(a, blockIdx.y, j0, (blockIdx.x - 1) * 32, X);
@@ -391,12 +399,28 @@ void bse_pivot_kernel(BseCtx<T> a, int j0) {
   C* P = a.PI + (size_t)blk * NB * NB;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) P[(size_t)(r0 + q) * NB + j] = x[q];
+  // largest |entry|^2 of P, read back from this thread's own stores (keeps the
+  // register-resident block free of extra live values)
+  T xm2 = (T)0;
+  for (int q = 0; q < RPT; ++q) {
+    const C v = P[(size_t)(r0 + q) * NB + j];
+    xm2 = fmax(xm2, v.x * v.x + v.y * v.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) xm2 = fmax(xm2, __shfl_xor(xm2, o, 64));
+  __shared__ T wmax[pivot_threads<NB>() / 64];
+  if ((t & 63) == 0) wmax[t >> 6] = xm2;
+  __syncthreads();
+  double xm = 0.0;
+  if (t == 0)
+    for (int w = 0; w < pivot_threads<NB>() / 64; ++w) xm = fmax(xm, sqrt((double)wmax[w]));
   if (t == 0) {
-    double* ps = a.pst + (size_t)blk * 4;
+    double* ps = a.pst + (size_t)blk * kPst;
     const bool first = j0 == 0;
     ps[0] = first ? pmin : fmin(ps[0], pmin);
     ps[1] = first ? pmax : fmax(ps[1], pmax);
     ps[2] = (bad || (!first && ps[2] > 0.0)) ? 1.0 : 0.0;
+    if (first) ps[3] = 0.0;
+    ps[4] = first ? xm : fmax(ps[4], xm);
   }
 }
 
@@ -459,6 +483,7 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
   const int ncols = (n - j0 - jb) + n;
   C* A = a.A + (size_t)blk * n * n;
   C* B = a.B + (size_t)blk * n * n;
+  if (inactive(a, blk)) return;
   {
     const int cs = blockIdx.x * kWaves + wave;
     if (cs * 32 >= ncols) return;
@@ -560,6 +585,7 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS, PF = CF::PF;
   const unsigned lid = xcd_linear();
   const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
+  if (inactive(a, blk)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = a.n;
   const int jb = CF::FULL ? NB : min(NB, n - j0);
   const int ncols = (n - j0 - jb) + n;
@@ -654,13 +680,15 @@ __global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a) {
   using C = typename cplx_of<T>::type;
   const int blk = blockIdx.y, n = a.n;
   const size_t nn = (size_t)n * n;
+  if (inactive(a, blk)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0 && a.stats) {
-    const double* ps = a.pst + (size_t)blk * 4;
+    const double* ps = a.pst + (size_t)blk * kPst;
     pq_bse_block_stats st;
     const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
     st.min_pivot = (float)ratio;
-    st.growth = (float)ps[1];
-    st.flags = (ps[2] > 0.0 ? 2 : 0) | (ratio < a.weak_ratio ? 1 : 0);
+    st.growth = (float)ps[4];
+    st.flags = (ps[2] > 0.0 ? 2 : 0) | ((ratio < a.weak_ratio || ps[4] > a.kappa_max) ? 1 : 0) |
+               (ps[3] > 0.0 ? 4 : 0);
     st.reserved = 0;
     a.stats[blk] = st;
   }
@@ -686,8 +714,16 @@ __global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a) {
 template <typename T>
 constexpr int panel_width() { return sizeof(T) == 4 ? 128 : 64; }
 
+// At most kRefineSlots blocks per channel and iteration are re-solved in FP64
+// on the complex64 path; further flagged blocks keep their FP32 solution (and
+// their flags).
+constexpr int kRefineSlots = 8;
+
 struct BseLayout {
-  size_t A, B, MT, PI, pst, total;
+  size_t A, B, MT, PI, pst;
+  // complex64 path only: FP64 re-solve of flagged blocks
+  size_t list, g64, x64, p64, ws64;
+  size_t total;
 };
 
 template <typename T>
@@ -702,9 +738,77 @@ BseLayout bse_layout(const Dims& d) {
   L.B = take(sizeof(C) * nn * d.Nq);
   L.MT = take(sizeof(C) * (size_t)NB * d.n * d.Nq);
   L.PI = take(sizeof(C) * (size_t)NB * NB * d.Nq);
-  L.pst = take(sizeof(double) * 4 * (size_t)d.Nq);
+  L.pst = take(sizeof(double) * kPst * (size_t)d.Nq);
+  if constexpr (sizeof(T) == 4) {
+    Dims r = d;
+    r.Nq = kRefineSlots;
+    L.list = take(sizeof(int) * (kRefineSlots + 2));
+    L.g64 = take(sizeof(double2) * nn * kRefineSlots);
+    L.x64 = take(sizeof(double2) * (size_t)d.n * kRefineSlots);
+    L.p64 = take(sizeof(double2) * nn * kRefineSlots);
+    L.ws64 = take(bse_layout<double>(r).total);
+  }
   L.total = off;
   return L;
+}
+
+// ------------------------------------------------------ FP64 re-solve
+// Blocks of a complex64 elimination whose pivot monitor reports a weak pivot
+// ratio or a non-finite pivot are solved again in FP64 from Gamma: a single
+// workgroup lists them (list[0..kRefineSlots), count in list[kRefineSlots],
+// total flagged in list[kRefineSlots + 1]), the blocks are gathered into
+// complex128 slots, the complex128 elimination runs on the slots (slots past
+// the count exit at once), and F = Phi64 + Gamma64 replaces B of the block
+// before the mixing epilogue.
+constexpr int kMaxBlocks = 4096;     // Nq < n <= 4096
+
+__global__ __launch_bounds__(kThreads) void refine_list_kernel(const double* pst, int Nq, float weak,
+                                                                double kappa_max, int* list) {
+  __shared__ unsigned char flag[kMaxBlocks];
+  for (int b = threadIdx.x; b < Nq; b += blockDim.x) {
+    const double* ps = pst + (size_t)b * kPst;
+    const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
+    flag[b] = (ps[2] > 0.0 || ratio < weak || ps[4] > kappa_max) ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {           // ordered compaction from LDS
+    int c = 0, tot = 0;
+    for (int b = 0; b < Nq; ++b) {
+      if (flag[b]) {
+        if (c < kRefineSlots) list[c++] = b;
+        ++tot;
+      }
+    }
+    list[kRefineSlots] = c;
+    list[kRefineSlots + 1] = tot;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void refine_gather_kernel(const float2* gamma, const double2* chi0, int n,
+                                                                  const int* list, double2* g64, double2* x64) {
+  const int slot = blockIdx.y;
+  if (slot >= list[kRefineSlots]) return;
+  const int b = list[slot];
+  const size_t nn = (size_t)n * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 v = gamma[(size_t)b * nn + i];
+    g64[(size_t)slot * nn + i] = mk((double)v.x, (double)v.y);
+  }
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x64[(size_t)slot * n + i] = chi0[(size_t)b * n + i];
+}
+
+__global__ __launch_bounds__(kThreads) void refine_scatter_kernel(const double2* p64, const double2* g64, int n,
+                                                                   const int* list, float2* B, double* pst) {
+  const int slot = blockIdx.y;
+  if (slot >= list[kRefineSlots]) return;
+  const int b = list[slot];
+  const size_t nn = (size_t)n * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
+    const double2 f = cadd(p64[(size_t)slot * nn + i], g64[(size_t)slot * nn + i]);
+    B[(size_t)b * nn + i] = mkf((float)f.x, (float)f.y);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) pst[(size_t)b * kPst + 3] = 1.0;
 }
 
 }  // namespace
@@ -715,9 +819,9 @@ size_t bse_ws_bytes(const pq_params& p, const Dims& d, int precision) {
 }
 
 template <typename T>
-static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, const void* gamma,
+static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, double kappa_max, const void* gamma,
                           const double2* chi0, void* phi_io, pq_bse_block_stats* stats, void* ws,
-                          hipStream_t s, BseTiming* tm) {
+                          hipStream_t s, BseTiming* tm, const int* active = nullptr) {
   using C = typename cplx_of<T>::type;
   constexpr int NB = panel_width<T>();
   static const double kSign[4] = {1.0, 1.0, -1.0, 1.0};
@@ -730,6 +834,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   a.sign = (T)kSign[channel];
   a.alpha = alpha;
   a.weak_ratio = weak;
+  a.kappa_max = kappa_max;
   a.gamma = (const C*)gamma;
   a.chi0 = chi0;
   a.phi = (C*)phi_io;
@@ -739,6 +844,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   a.PI = (C*)(w + L.PI);
   a.pst = (double*)(w + L.pst);
   a.stats = stats;
+  a.active = active;
   const int n = d.n;
   // event timing around each launch (kind: 0 init, 1 pivot, 2 panel, 3 update, 4 epilogue)
   auto pre = [&](int kind) {
@@ -781,6 +887,24 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     post();
     if (tm) tm->update_flops += 8.0 * (double)(n - jb) * ncols * jb * d.Nq;
   }
+  if constexpr (sizeof(T) == 4) {
+    // FP64 re-solve of the blocks the pivot monitor flagged (none: empty launches)
+    int* list = (int*)(w + L.list);
+    double2* g64 = (double2*)(w + L.g64);
+    double2* x64 = (double2*)(w + L.x64);
+    double2* p64 = (double2*)(w + L.p64);
+    Dims r = d;
+    r.Nq = kRefineSlots;
+    const unsigned gx = (unsigned)std::min<size_t>(256, ((size_t)n * n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(refine_list_kernel, dim3(1), dim3(kThreads), 0, s, a.pst, d.Nq, weak, kappa_max, list);
+    hipLaunchKernelGGL(refine_gather_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, (const float2*)gamma,
+                       chi0, n, list, g64, x64);
+    hipError_t e = run_bse<double>(r, channel, 1.0, 1e-10f, 1e12, g64, x64, p64, nullptr, w + L.ws64, s, nullptr,
+                                   list + kRefineSlots);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(refine_scatter_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, p64, g64, n, list,
+                       (float2*)a.B, a.pst);
+  }
   pre(4);
   hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a);
   post();
@@ -792,10 +916,12 @@ hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precis
                       pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm) {
   if (precision == PQ_PREC_FP64) {
     if (p.storage != PQ_STORE_C128) return hipErrorInvalidValue;
-    return run_bse<double>(d, channel, alpha, 1e-10f, gamma, chi0, phi_io, stats, ws, s, tm);
+    return run_bse<double>(d, channel, alpha, 1e-10f, 1e12, gamma, chi0, phi_io, stats, ws, s, tm);
   }
   if (p.storage != PQ_STORE_C64) return hipErrorInvalidValue;
-  return run_bse<float>(d, channel, alpha, 1e-3f, gamma, chi0, phi_io, stats, ws, s, tm);
+  // complex64: a block is re-solved in FP64 when its pivot ratio drops below
+  // 1e-3 or a diagonal-block inverse exceeds 1e3 (FP32 error ~ 1e3 eps32 n^1/2)
+  return run_bse<float>(d, channel, alpha, 1e-3f, 1e3, gamma, chi0, phi_io, stats, ws, s, tm);
 }
 
 }  // namespace pq

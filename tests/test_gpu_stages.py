@@ -208,6 +208,52 @@ def test_bse_solve(prec, name):
         assert np.all(flags & 2 == 0)
 
 
+def _near_instability(gam, X, sign, blocks, lam=0.9999):
+    """Rescale the listed blocks (by a complex factor) so that the leading
+    eigenvalue of s Gamma X becomes lam: 1 - s Gamma X is then nearly singular
+    (condition ~1e5, the channel at its instability). Rounded to complex64 like
+    the FP32 inputs."""
+    out = gam.copy()
+    for q in blocks:
+        ev = np.linalg.eigvals(sign * gam[q] * X[q][None, :])
+        out[q] = gam[q] * (lam / ev[np.argmax(np.abs(ev))])
+    return out.astype(np.complex64).astype(np.complex128)
+
+
+@pytest.mark.parametrize("all_blocks", [False, True])
+def test_bse_fp32_flagged_blocks_resolved_in_fp64(all_blocks):
+    """Near the instability the complex64 elimination loses accuracy; the
+    pivot monitor flags such blocks and they are solved again in FP64 (at most
+    8 per channel). Flagged-and-re-solved blocks match the FP64 oracle to
+    FP64 accuracy (kappa eps64), the others keep the FP32 bound; with every
+    block near the instability only the first 8 are re-solved."""
+    _print_case("bse refine", all_blocks)
+    p = config("tiny_2x2")
+    g, gam, xph, xpp = _bse_inputs(p, 202)
+    r = 1
+    sign = P.BSE_SIGN[r]
+    blocks = list(range(g.Nq)) if all_blocks else [1, 5, 9]
+    gam_r = _near_instability(gam[r], xph, sign, blocks)
+    ref = np.stack([P.bse_block(gam_r[q], xph[q], sign) for q in range(g.Nq)])
+    st = _ops().Stage(p, "fp32")
+    ws = torch.empty(st.bse_workspace_bytes(), dtype=torch.uint8, device=DEV)
+    stats = torch.empty((g.Nq, 4), dtype=torch.int32, device=DEV)
+    out = torch.empty((g.Nq, g.n, g.n), dtype=torch.complex64, device=DEV)
+    st.bse_solve(r, T(gam_r, torch.complex64), T(xph), out, alpha=1.0, stats=stats, ws=ws)
+    got = H(out).astype(np.complex128)
+    flags = H(stats)[:, 2]
+    refined = [q for q in range(g.Nq) if flags[q] & 4]
+    flagged = [q for q in range(g.Nq) if flags[q] & 1]
+    assert set(blocks) <= set(flagged), (blocks, flagged)
+    assert refined == sorted(flagged)[:8]
+    for q in range(g.Nq):
+        err = relerr(got[q], ref[q])
+        if q in refined:
+            assert err < 1e-6, (q, err)      # FP64 solve, stored in complex64
+        else:
+            assert err < (1.0 if q in flagged else 2e-4), (q, err)
+
+
 def test_bse_mixing_epilogue():
     _print_case("bse-mix")
     p = config("small_2x4")
