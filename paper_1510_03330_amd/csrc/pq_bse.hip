@@ -548,22 +548,48 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 //   X1 += (ar + ai) br,  X2 += ar (bi - br),  X3 += ai (br + bi),
 //   Re(ab) = X1 - X3,    Im(ab) = X1 + X2,
 // with X3 started at Re C and X2 at -Im C, so C - ab = (X3 - X1, -X1 - X2).
-template <typename T_, int UWM_, int UWN_, int PF_, int WPE_, bool FULL_, bool M3_ = true, bool FIRST_ = false>
+template <typename T_, int UWM_, int UWN_, int PF_, int WPE_, bool FULL_, bool M3_ = true, bool FIRST_ = false,
+          bool NT_ = false>
 struct UpdCfg {
   using T = T_;
   static constexpr int UWM = UWM_, UWN = UWN_, PF = PF_, WPE = WPE_;
-  static constexpr bool FULL = FULL_, M3 = M3_, FIRST = FIRST_;
+  static constexpr bool FULL = FULL_, M3 = M3_, FIRST = FIRST_, NT = NT_;
   static constexpr int WGM = 2 * UWM, WGN = 2 * UWN;
 };
 // the same tile configuration for the first panel (C read from Gamma)
 template <class CF>
-using UpdFirst = UpdCfg<typename CF::T, CF::UWM, CF::UWN, CF::PF, CF::WPE, CF::FULL, CF::M3, true>;
+using UpdFirst = UpdCfg<typename CF::T, CF::UWM, CF::UWN, CF::PF, CF::WPE, CF::FULL, CF::M3, true, CF::NT>;
+
+// C tile element access; NT = streaming (non-temporal) hint, so that the C
+// stream does not evict the operand panels every workgroup of the block reuses
+template <bool NT, typename C>
+__device__ inline C ld_c(const C* p) {
+  if constexpr (NT) {
+    C v;
+    v.x = __builtin_nontemporal_load(&p->x);
+    v.y = __builtin_nontemporal_load(&p->y);
+    return v;
+  } else {
+    return *p;
+  }
+}
+template <bool NT, typename C>
+__device__ inline void st_c(C* p, C v) {
+  if constexpr (NT) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+  } else {
+    *p = v;
+  }
+}
 // (the ragged-panel form of the complex64 update uses a 64 x 32 tile: the
 // clamping of panel rows costs registers the 64 x 64 tile does not have)
 template <typename T, bool FULL>
 using UpdDefault = typename std::conditional<
-    sizeof(T) == 4, typename std::conditional<FULL, UpdCfg<T, 64, 64, 2, 2, true>, UpdCfg<T, 64, 32, 2, 3, false>>::type,
-    UpdCfg<T, 32, 32, 1, 2, FULL>>::type;
+    sizeof(T) == 4,
+    typename std::conditional<FULL, UpdCfg<T, 64, 64, 2, 2, true, true, false, true>,
+                              UpdCfg<T, 64, 32, 2, 3, false, true, false, true>>::type,
+    UpdCfg<T, 32, 32, 1, 2, FULL, true, false, true>>::type;
 
 // The four-product form behind the same interface (acc = C, acc -= ab).
 template <typename T, int WM, int WN>
@@ -620,7 +646,7 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
       src[y] = colsrc<T, true>(a, blk, 0, jb, cok[y] ? c0 + y * M::TN + M::b_col(lane) : 0);
     acc.load_c([&](int r, int c) -> C { return src[c / M::TN].at(min(i0 + r, n - 1), n, 0); });
   } else {
-    acc.load_c([&](int r, int c) -> C { return cb[c / M::TN][(size_t)min(i0 + r, n - 1) * n]; });
+    acc.load_c([&](int r, int c) -> C { return ld_c<CF::NT>(&cb[c / M::TN][(size_t)min(i0 + r, n - 1) * n]); });
   }
   const int kb = M::b_k(lane), ka = M::a_k(lane);
   const C* bbase[USC];
@@ -659,7 +685,7 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   acc.store_c([&](int r, int c, C v) {
     const int i = i0 + r;
     const int y = c / M::TN;
-    if (cok[y] && row_ok(i)) cb[y][(size_t)i * n] = v;
+    if (cok[y] && row_ok(i)) st_c<CF::NT>(&cb[y][(size_t)i * n], v);
   });
 }
 
