@@ -9,10 +9,10 @@
 // (q block, tile) grids. Per panel J:
 //   (a) bse_pivot:  P = A_JJ^-1 by Gauss-Jordan on the NB x NB diagonal block,
 //                   held in registers (one column per thread and a slice of its
-//                   rows), pivot rows and columns broadcast through LDS; the
-//                   other workgroups of the launch copy the multipliers A_IJ
-//                   k-major (MT[k][i] = A[i][J0 + k]) so that the update's
-//                   operand loads coalesce, while the inversions run;
+//                   rows), pivot rows and columns broadcast through LDS, stored
+//                   transposed (k-major); bse_multcopy copies the multipliers
+//                   A_IJ k-major (MT[k][i] = A[i][J0 + k]); k-major operands
+//                   make the matrix-core operand loads of (b) and (c) contiguous;
 //   (b) bse_panel:  pivot rows R_JK = P A_JK for every column right of the
 //                   panel in A and every column of B (in place);
 //   (c) bse_update: A_IK -= A_IJ R_JK, B_I -= A_IJ R_JB for all rows I != J, a
@@ -265,7 +265,8 @@ struct BseCtx {
   C* A;                  // [Nq][n][n]
   C* B;                  // [Nq][n][n]
   C* MT;                 // [Nq][NB][n]    multipliers of the current panel, k-major
-  C* PI;                 // [Nq][NB][NB]   inverse of the current diagonal block
+  C* PI;                 // [Nq][NB][NB]   inverse P of the current diagonal block, transposed:
+                         //                PI[k][r] = P[r][k] (k-major, like MT)
   double* pst;           // [Nq][kPst]  min |pivot|, max |pivot|, non-finite seen, re-solved,
                          //             max |entry| of the diagonal-block inverses
   double kappa_max;      // flag a block whose diagonal-block inverses exceed this
@@ -325,62 +326,94 @@ __device__ void copy_multipliers(const BseCtx<T>& a, int blk, int j0, int i0,
 // ------------------------------------------------------------------ pivot
 // P = A_JJ^-1 by in-place Gauss-Jordan on the diagonal block (identity outside
 // the jb x jb part for a ragged last panel). Thread t holds column j = t % NB
-// of the block for the RPT rows h RPT .. h RPT + RPT - 1, h = t / NB, in
-// registers (RPT = 32 for NB = 128 with 512 threads, 16 for NB = 64). Step c publishes the pivot column and row through LDS (double
-// buffered, one barrier per step), then every thread updates its entries:
+// of the block for the RPT rows r0 .. r0 + RPT - 1 (r0 = RPT t / NB; a wave
+// lies inside one row group, so r0 is wave-uniform) in registers (RPT = 32 for
+// NB = 128 with 512 threads, 16 for NB = 64). Step c publishes the pivot column
+// and row through LDS (double buffered, one barrier per step), then every
+// thread updates its entries:
 //   row c:           x <- x / p            (column c: x <- 1 / p)
 //   other rows r:    x <- x - D[r][c] D[c][j] / p   (column c: x <- -D[r][c] / p)
+// Column c is cleared by its owner once published, so one fused multiply-add
+// form covers every column; row c is overwritten afterwards by the one wave
+// pair that holds it, through a wave-uniform register index.
 template <int NB> constexpr int pivot_threads() { return NB >= 128 ? 512 : 256; }
+
+// 1 / z for a pivot. complex64: z scaled by a power of two so that |z|^2 can
+// neither overflow nor underflow, then one hardware reciprocal (<= 1 ulp).
+__device__ inline float2 pivot_recip(float2 z) {
+  int e;
+  (void)frexpf(fmaxf(fabsf(z.x), fabsf(z.y)), &e);
+  const float a = ldexpf(z.x, -e), b = ldexpf(z.y, -e);
+  const float r = __builtin_amdgcn_rcpf(fmaf(a, a, b * b));
+  return make_float2(ldexpf(a * r, -e), ldexpf(-b * r, -e));
+}
+__device__ inline double2 pivot_recip(double2 z) { return crecip(z); }
 
 template <typename T, int NB>
 __global__ __launch_bounds__(pivot_threads<NB>()) __attribute__((amdgpu_waves_per_eu(NB >= 128 ? 4 : 3)))
 void bse_pivot_kernel(BseCtx<T> a, int j0) {
   using C = typename cplx_of<T>::type;
-  constexpr int RPT = NB * NB / pivot_threads<NB>();
+  constexpr int NT = pivot_threads<NB>();
+  constexpr int RPT = NB * NB / NT;
+  static_assert(NB % 64 == 0, "a wave must lie inside one row group");
   __shared__ C colbuf[2][NB];
   __shared__ C rowbuf[2][NB];
+  __shared__ C pv[NB];
   if (inactive(a, (int)blockIdx.y)) return;
-  if (blockIdx.x > 0) {                  // the other workgroups copy the multipliers
-    __shared__ C X[32][NB + 1];
-    copy_multipliers<T, NB>(a, blockIdx.y, j0, (blockIdx.x - 1) * 32, X);
-    return;
-  }
   const int blk = blockIdx.y, t = threadIdx.x, n = a.n;
-  const int j = t % NB, h = t / NB, r0 = h * RPT;
+  const int j = t % NB;
+  const int r0 = __builtin_amdgcn_readfirstlane(t / NB) * RPT;
   const int jb = min(NB, n - j0);
   const C* A = a.A + (size_t)blk * n * n;
-  C x[RPT];
+  T xr[RPT], xi[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = r0 + q;
     const int ri = j0 + min(r, jb - 1), ci = j0 + min(j, jb - 1);
     const C v = j0 == 0 ? system_elem(a, blk, ri, ci) : A[(size_t)ri * n + ci];
-    C e = cz<C>();
-    if (r == j) e.x = 1;
-    x[q] = (r < jb && j < jb) ? v : e;
+    const bool in = r < jb && j < jb;
+    xr[q] = in ? v.x : (r == j ? (T)1 : (T)0);
+    xi[q] = in ? v.y : (T)0;
   }
-  double pmin = DBL_MAX, pmax = 0.0;
-  bool bad = false;
   for (int c = 0; c < jb; ++c) {
     const int bf = c & 1;
+    const int cr = c - r0;                                 // wave-uniform
+    const bool own_row = (unsigned)cr < (unsigned)RPT;     // wave-uniform
     if (j == c) {
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) colbuf[bf][r0 + q] = x[q];
+      for (int q = 0; q < RPT; ++q) {
+        C v;
+        v.x = xr[q];
+        v.y = xi[q];
+        colbuf[bf][r0 + q] = v;
+        xr[q] = (T)0;
+        xi[q] = (T)0;
+      }
     }
+    if (own_row) {
+      C v;
+      if constexpr (sizeof(T) == 4) {
+        v.x = xr[cr];
+        v.y = xi[cr];
+      } else {   // (a dynamic index would put the complex128 block in scratch)
+        v = cz<C>();
 #pragma unroll
-    for (int q = 0; q < RPT; ++q)
-      if (r0 + q == c) rowbuf[bf][j] = x[q];
+        for (int q = 0; q < RPT; ++q)
+          if (q == cr) {
+            v.x = xr[q];
+            v.y = xi[q];
+          }
+      }
+      rowbuf[bf][j] = v;
+    }
     __syncthreads();
     const C piv = colbuf[bf][c];
-    if (t == 0) {
-      const double ap = cabs_d(piv);
-      if (!(ap == ap) || ap > DBL_MAX) bad = true;
-      pmin = fmin(pmin, ap);
-      pmax = fmax(pmax, ap);
-    }
-    const C p = cdiv(make_cone<C>(), piv);
-    const bool pc = j == c;
-    const C u = pc ? p : cmul(rowbuf[bf][j], p);
+    if (t == 0) pv[c] = piv;
+    const C p = pivot_recip(piv);
+    const C rv = rowbuf[bf][j];
+    C u;
+    u.x = j == c ? p.x : rv.x * p.x - rv.y * p.y;
+    u.y = j == c ? p.y : rv.x * p.y + rv.y * p.x;
     // the pivot column is read in chunks of 16 entries (wide broadcast reads
     // issued together), then applied
 #pragma unroll
@@ -390,44 +423,95 @@ void bse_pivot_kernel(BseCtx<T> a, int j0) {
       for (int q = 0; q < 16; ++q) cv[q] = colbuf[bf][r0 + q0 + q];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const int r = r0 + q0 + q;
-        const C m = cfms(pc ? cz<C>() : x[q0 + q], cv[q], u);
-        x[q0 + q] = (r == c) ? u : m;
+        xr[q0 + q] = fma(-cv[q].x, u.x, fma(cv[q].y, u.y, xr[q0 + q]));
+        xi[q0 + q] = fma(-cv[q].x, u.y, fma(-cv[q].y, u.x, xi[q0 + q]));
+      }
+    }
+    if (own_row) {
+      if constexpr (sizeof(T) == 4) {
+        xr[cr] = u.x;
+        xi[cr] = u.y;
+      } else {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+          if (q == cr) {
+            xr[q] = u.x;
+            xi[q] = u.y;
+          }
       }
     }
   }
-  C* P = a.PI + (size_t)blk * NB * NB;
+  C* PT = a.PI + (size_t)blk * NB * NB;     // stored transposed: column j of P is row j of PT
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) P[(size_t)(r0 + q) * NB + j] = x[q];
-  // largest |entry|^2 of P, read back from this thread's own stores (keeps the
-  // register-resident block free of extra live values)
+  for (int q = 0; q < RPT; ++q) {
+    C v;
+    v.x = xr[q];
+    v.y = xi[q];
+    PT[(size_t)j * NB + r0 + q] = v;
+  }
+  // pivot monitor: largest |entry|^2 of P (read back from this thread's own
+  // stores, which keeps the register-resident block free of extra live
+  // values), smallest and largest |pivot|, non-finite pivots
   T xm2 = (T)0;
   for (int q = 0; q < RPT; ++q) {
-    const C v = P[(size_t)(r0 + q) * NB + j];
+    const C v = PT[(size_t)j * NB + r0 + q];
     xm2 = fmax(xm2, v.x * v.x + v.y * v.y);
   }
-  for (int o = 32; o > 0; o >>= 1) xm2 = fmax(xm2, __shfl_xor(xm2, o, 64));
-  __shared__ T wmax[pivot_threads<NB>() / 64];
-  if ((t & 63) == 0) wmax[t >> 6] = xm2;
+  __syncthreads();                                  // pv complete
+  double pmin = DBL_MAX, pmax = 0.0, bad = 0.0;
+  if (t < jb) {
+    const double ap = cabs_d(pv[t]);
+    const bool fin = ap == ap && ap <= DBL_MAX;
+    pmin = fin ? ap : DBL_MAX;
+    pmax = fin ? ap : 0.0;
+    bad = fin ? 0.0 : 1.0;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    xm2 = fmax(xm2, __shfl_xor(xm2, o, 64));
+    pmin = fmin(pmin, __shfl_xor(pmin, o, 64));
+    pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
+    bad = fmax(bad, __shfl_xor(bad, o, 64));
+  }
+  __shared__ double wred[NT / 64][4];
+  if ((t & 63) == 0) {
+    wred[t >> 6][0] = xm2;
+    wred[t >> 6][1] = pmin;
+    wred[t >> 6][2] = pmax;
+    wred[t >> 6][3] = bad;
+  }
   __syncthreads();
-  double xm = 0.0;
-  if (t == 0)
-    for (int w = 0; w < pivot_threads<NB>() / 64; ++w) xm = fmax(xm, sqrt((double)wmax[w]));
   if (t == 0) {
+    double xm = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+      xm = fmax(xm, sqrt(wred[w][0]));
+      pmin = fmin(pmin, wred[w][1]);
+      pmax = fmax(pmax, wred[w][2]);
+      bad = fmax(bad, wred[w][3]);
+    }
     double* ps = a.pst + (size_t)blk * kPst;
     const bool first = j0 == 0;
     ps[0] = first ? pmin : fmin(ps[0], pmin);
     ps[1] = first ? pmax : fmax(ps[1], pmax);
-    ps[2] = (bad || (!first && ps[2] > 0.0)) ? 1.0 : 0.0;
+    ps[2] = (bad > 0.0 || (!first && ps[2] > 0.0)) ? 1.0 : 0.0;
     if (first) ps[3] = 0.0;
     ps[4] = first ? xm : fmax(ps[4], xm);
   }
 }
 
+// Multiplier copy of panel J (independent of the diagonal-block inverse; its
+// own launch, since sharing the inversion launch halves both kernels' slots):
+// 32 rows of A_IJ per workgroup into MT.
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void bse_multcopy_kernel(BseCtx<T> a, int j0) {
+  __shared__ typename cplx_of<T>::type X[32][NB + 1];
+  if (inactive(a, (int)blockIdx.y)) return;
+  copy_multipliers<T, NB>(a, blockIdx.y, j0, blockIdx.x * 32, X);
+}
+
 // ------------------------------------------------------------------ panel
-// One 32-column strip per wave: R = P A_J,strip for all NB rows of the panel at
-// once (NB / 32 accumulator tiles in the three-product form), written in place
-// after the whole strip has been read.
+// One 32-column strip per wave: R = P A_J,strip for RW rows of the panel at
+// once (RW / 32 accumulator tiles in the three-product form; NB / RW waves per
+// strip), written in place after the whole strip has been read.
 // Source of the strip's panel rows: A/B, or (first panel) Gamma with
 // A = 1 - s Gamma diag(X) formed per element. colsrc() gives the per-lane
 // pointer (row j0 of column c) and the diagonal-term data of the column.
@@ -472,12 +556,17 @@ __device__ inline ColSrc<T> colsrc(const BseCtx<T>& a, int blk, int j0, int jb, 
   return r;
 }
 
-template <typename T, int NB, bool FIRST>
+// panel rows per wave: all NB for complex64 (the strip's panel rows are read
+// once); 32 for complex128, whose 64-row strip would hold 192 accumulator
+// registers and run at one wave per SIMD
+template <typename T, int NB> constexpr int panel_rows_per_wave() { return sizeof(T) == 4 ? NB : 32; }
+
+template <typename T, int NB, bool FIRST, int RW = NB, int PFB = 2>
 __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
   using WT = WTile<T>;
-  constexpr int SR = WT::SR, SC = WT::SC, KSTEPS = NB / M::KS, NRT = NB / 32, PF = 2;
+  constexpr int SR = WT::SR, SC = WT::SC, KSTEPS = NB / M::KS, NRT = RW / 32, WPS = NB / RW, PFA = 2;
   const int blk = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
   const int jb = min(NB, n - j0);
   const int ncols = (n - j0 - jb) + n;
@@ -485,9 +574,10 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
   C* B = a.B + (size_t)blk * n * n;
   if (inactive(a, blk)) return;
   {
-    const int cs = blockIdx.x * kWaves + wave;
+    const int ws = blockIdx.x * kWaves + wave;
+    const int cs = ws / WPS, rb = (ws % WPS) * RW;      // strip, first panel row of this wave
     if (cs * 32 >= ncols) return;
-    const C* P = a.PI + (size_t)blk * NB * NB;
+    const C* PT = a.PI + (size_t)blk * NB * NB;   // P transposed (k-major)
     const int kb = M::b_k(lane);
     ColSrc<T> cp[SC];
 #pragma unroll
@@ -497,35 +587,41 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-      for (int xx = 0; xx < SR; ++xx) pa[rt][xx] = P + (size_t)(rt * 32 + xx * M::TM + M::a_row(lane)) * NB + M::a_k(lane);
+      for (int xx = 0; xx < SR; ++xx) pa[rt][xx] = PT + (size_t)M::a_k(lane) * NB + rb + rt * 32 + xx * M::TM + M::a_row(lane);
     Tile3<T, 32, 32> acc[NRT];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) acc[rt].zero();
     // operands for k-step ks: b from the panel rows of this strip (clamped to
-    // the last real row), a from P (rows outside jb x jb are the identity)
-    auto fetch = [&](int ks, C (&av)[NRT][SR], C (&bv)[SC]) {
-      const int k = min(ks * M::KS + kb, jb - 1);
-#pragma unroll
-      for (int y = 0; y < SC; ++y) bv[y] = cp[y].at(k, n, j0);
+    // the last real row; first touch of these rows, from HBM, so fetched PFB
+    // k-steps ahead), a from P (rows outside jb x jb are the identity; shared
+    // by every strip of the block, from L2, PFA k-steps ahead)
+    auto fetch_a = [&](int ks, C (&av)[NRT][SR]) {
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-        for (int xx = 0; xx < SR; ++xx) av[rt][xx] = pa[rt][xx][ks * M::KS];
+        for (int xx = 0; xx < SR; ++xx) av[rt][xx] = pa[rt][xx][(size_t)ks * M::KS * NB];
     };
-    C aq[PF][NRT][SR], bq[PF][SC];
+    auto fetch_b = [&](int ks, C (&bv)[SC]) {
+      const int k = min(ks * M::KS + kb, jb - 1);
 #pragma unroll
-    for (int s = 0; s < PF; ++s) fetch(s, aq[s], bq[s]);
+      for (int y = 0; y < SC; ++y) bv[y] = cp[y].at(k, n, j0);
+    };
+    C aq[PFA][NRT][SR], bq[PFB][SC];
+#pragma unroll
+    for (int s = 0; s < PFB; ++s) fetch_b(s, bq[s]);
+#pragma unroll
+    for (int s = 0; s < PFA; ++s) fetch_a(s, aq[s]);
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
-      const int cur = ks % PF;
       C av[NRT][SR], bv[SC];
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-        for (int xx = 0; xx < SR; ++xx) av[rt][xx] = aq[cur][rt][xx];
+        for (int xx = 0; xx < SR; ++xx) av[rt][xx] = aq[ks % PFA][rt][xx];
 #pragma unroll
-      for (int y = 0; y < SC; ++y) bv[y] = bq[cur][y];
-      if (ks + PF < KSTEPS) fetch(ks + PF, aq[cur], bq[cur]);
+      for (int y = 0; y < SC; ++y) bv[y] = bq[ks % PFB][y];
+      if (ks + PFB < KSTEPS) fetch_b(ks + PFB, bq[ks % PFB]);
+      if (ks + PFA < KSTEPS) fetch_a(ks + PFA, aq[ks % PFA]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt) acc[rt].mac(av[rt], bv);
@@ -533,7 +629,7 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
       acc[rt].store_prod([&](int r, int c, C v) {
-        const int row = rt * 32 + r, col = cs * 32 + c;
+        const int row = rb + rt * 32 + r, col = cs * 32 + c;
         if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
       });
   }
@@ -892,14 +988,16 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     const int ncols = (n - j0 - jb) + n;
     pre(1);
     const int nwc = (n + 31) / 32;
-    hipLaunchKernelGGL((bse_pivot_kernel<T, NB>), dim3(1 + nwc, d.Nq), dim3(pivot_threads<NB>()), 0, s, a, j0);
+    hipLaunchKernelGGL((bse_pivot_kernel<T, NB>), dim3(1, d.Nq), dim3(pivot_threads<NB>()), 0, s, a, j0);
+    hipLaunchKernelGGL((bse_multcopy_kernel<T, NB>), dim3(nwc, d.Nq), dim3(kThreads), 0, s, a, j0);
     post();
-    const int nwb = ((ncols + 31) / 32 + kWaves - 1) / kWaves;
+    constexpr int RW = panel_rows_per_wave<T, NB>();
+    const int nwb = ((ncols + 31) / 32 * (NB / RW) + kWaves - 1) / kWaves;
     pre(2);
     if (j0 == 0)
-      hipLaunchKernelGGL((bse_panel_kernel<T, NB, true>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
+      hipLaunchKernelGGL((bse_panel_kernel<T, NB, true, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
     else
-      hipLaunchKernelGGL((bse_panel_kernel<T, NB, false>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
+      hipLaunchKernelGGL((bse_panel_kernel<T, NB, false, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
     post();
     pre(3);
     if (jb == NB && j0 == 0)
