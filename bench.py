@@ -106,6 +106,73 @@ def time_to_converged(p, precision, tol, max_iter):
     return dict(sec=t1 - t0, iterations=done, converged=conv, dsigma=st.dsigma), sigma
 
 
+def bse_microbench(reps: int = 5, stress_lam: float = 0.99):
+    """BSE microbenchmark on the 4x4, Nv = 16 box (n = 256, 240 blocks), magnetic
+    channel: Gamma blocks i.i.d. complex N(0, 1/n), block q from PCG64(1510 + q);
+    X the particle-hole bubble of the GPU path at the bare-vertex start state;
+    a stress variant rescales each block so that the leading eigenvalue of
+    s Gamma X is 0.99. Each precision is timed with the device synchronised
+    around `reps` solves; the complex64 solutions F = Gamma + Phi are compared
+    with the complex128 one (max |dF| / max |F|), and the blocks the pivot
+    monitor flagged / re-solved in FP64 are counted."""
+    import numpy as np
+    import torch
+    from paper_1510_03330_amd.ops import Solver, Stage
+    from workloads import bse_microbench_gamma, config
+
+    dev = "cuda:0"
+    p = config("c2")
+    s = Solver(p, "fp64", device=dev)
+    st64 = Stage(p, "fp64")
+    d = st64.d
+    g = torch.empty(st64.g_shape, dtype=torch.complex128, device=dev)
+    mu = torch.empty(1, dtype=torch.float64, device=dev)
+    st64.dyson_update(s.get("sigma"), g, mu)
+    xph = torch.empty(st64.x_shape, dtype=torch.complex128, device=dev)
+    xpp = torch.empty(st64.x_shape, dtype=torch.complex128, device=dev)
+    st64.bubble_build(g, xph, xpp)
+    s.close()
+    del s
+    gam = bse_microbench_gamma(d.n, range(d.Nq))
+    x = xph.cpu().numpy()
+    stressed = gam.copy()
+    for q in range(d.Nq):
+        ev = np.linalg.eigvals(gam[q] * x[q][None, :])
+        stressed[q] = gam[q] * (stress_lam / ev[np.argmax(np.abs(ev))])
+    work = d.Nq * (32.0 / 3.0) * float(d.n) ** 3
+    out = {"workload": "4x4, Nv=16: 240 blocks of n=256, magnetic channel", "reps": reps}
+    for name, gm in (("iid", gam), ("stress_%g" % stress_lam, stressed)):
+        gm = gm.astype(np.complex64).astype(np.complex128)     # one input for all precisions
+        res, ref = {}, None
+        for prec in ("fp64", "fp32", "bf16x3"):
+            stg = Stage(p, prec)
+            gt = torch.from_numpy(gm).to(device=dev, dtype=stg.vdtype)
+            ws = torch.empty(stg.bse_workspace_bytes(), dtype=torch.uint8, device=dev)
+            stats = torch.empty((d.Nq, 4), dtype=torch.int32, device=dev)
+            o = torch.empty((d.Nq, d.n, d.n), dtype=stg.vdtype, device=dev)
+            stg.bse_solve(1, gt, xph, o, 1.0, stats, ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                stg.bse_solve(1, gt, xph, o, 1.0, stats, ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            f = o.to(torch.complex128) + gt.to(torch.complex128)      # F = Gamma + Phi
+            fl = stats[:, 2].cpu()
+            r = {"ms_per_channel": round(ms, 3), "lu_equivalent_tflops": round(work / (ms * 1e-3) / 1e12, 2),
+                 "flagged_blocks": int(((fl & 1) != 0).sum()), "refined_blocks": int(((fl & 4) != 0).sum())}
+            if ref is None:
+                ref = f
+            else:
+                r["max_rel_diff_vs_fp64"] = float((f - ref).abs().max() / ref.abs().max())
+            res[prec] = r
+            del gt, ws, stats, o, f
+        out[name] = res
+        del ref
+        torch.cuda.empty_cache()
+    return out
+
+
 class _VirtualVertex:
     """Deterministic pseudo-random stand-in for a [4][Nq][n][n] vertex too large
     for host memory; supports the fancy indexing the oracle uses."""
@@ -187,6 +254,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--bf16x3-steps", type=int, default=3)
+    ap.add_argument("--no-microbench", action="store_true",
+                    help="skip the 4x4 Nv=16 BSE microbenchmark")
     ap.add_argument("--no-ttc", action="store_true",
                     help="skip the time-to-converged-Sigma (1e-6) runs of both paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -217,6 +287,9 @@ def main():
     print(f"[bench] fp32 {ips:.3f} it/s; fp64 path: steps {args.fp64_steps}", file=sys.stderr, flush=True)
     r64 = run_gpu(p, "fp64", args.fp64_steps, 1) if args.fp64_steps > 0 else None
     ips64 = (r64["steps"] / r64["sec"]) if r64 else None
+    print(f"[bench] bf16x3 path: steps {args.bf16x3_steps}", file=sys.stderr, flush=True)
+    r3 = run_gpu(p, "bf16x3", args.bf16x3_steps, 1) if args.bf16x3_steps > 0 else None
+    ips3 = (r3["steps"] / r3["sec"]) if r3 else None
 
     # dominant kernel: the rank-NB update of the BSE (per launch: one panel step of
     # all 960 blocks of a channel); flops = 8 per complex multiply-add it performs
@@ -260,6 +333,10 @@ def main():
                            (("dyson", 0), ("bubbles_kernels", 1), ("remap", 3), ("sigma", 4), ("bse", 5),
                             ("mix", 6))} if r64 else None),
         "roofline": roof,
+        "bf16x3_iterations_per_s": round(ips3, 4) if ips3 else None,
+        "bf16x3_update_avg_launch_ms": (round(r3["kern_ms"][3] / r3["kern_n"][3], 3) if r3 else None),
+        "stage_ms_bf16x3": ({k: round(r3["stage_ms"][i], 3) for k, i in
+                             (("remap", 3), ("sigma", 4), ("bse", 5))} if r3 else None),
     }
     if not args.no_ttc:
         # time from the bare-vertex start to max|Sigma_new - Sigma| < 1e-6 (the solver's
@@ -293,6 +370,31 @@ def main():
         out["converged_sigma_mixed_vs_fp64"] = {
             "max_abs_diff": float((smx - s64).abs().max()),
             "max_rel_diff": float((smx - s64).abs().max() / s64.abs().max())}
+        # BF16x3 updates: alone, and as the first phase of the mixed schedule
+        print("[bench] time to converged sigma (bf16x3)", file=sys.stderr, flush=True)
+        t3, s3 = time_to_converged(p, "bf16x3", 1e-6, 80)
+        out["time_to_converged_bf16x3"] = t3
+        out["ttc_speedup_bf16x3_vs_fp64"] = round(t64["sec"] / t3["sec"], 3)
+        out["converged_sigma_bf16x3_vs_fp64"] = {
+            "max_abs_diff": float((s3 - s64).abs().max()),
+            "max_rel_diff": float((s3 - s64).abs().max() / s64.abs().max())}
+        print("[bench] time to converged sigma (bf16x3 then fp64)", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sm, info = converge_mixed(p, 1e-6, 1e-5, 80, low="bf16x3")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        smx = sm.get("sigma").cpu()
+        sm.close()
+        del sm
+        torch.cuda.empty_cache()
+        out["time_to_converged_mixed_bf16x3"] = dict(sec=t1 - t0, **info)
+        out["converged_sigma_mixed_bf16x3_vs_fp64"] = {
+            "max_abs_diff": float((smx - s64).abs().max()),
+            "max_rel_diff": float((smx - s64).abs().max() / s64.abs().max())}
+    if not args.no_microbench:
+        print("[bench] BSE microbenchmark (4x4, Nv=16)", file=sys.stderr, flush=True)
+        out["bse_microbench_4x4_nv16"] = bse_microbench()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)

@@ -71,7 +71,13 @@ typedef enum { PQ_STORE_C128 = 0, PQ_STORE_C64 = 1 } pq_storage;
 
 typedef enum {
   PQ_PREC_FP64 = 0,        /* complex128 elimination, FP64 MFMA              */
-  PQ_PREC_FP32 = 1         /* complex64 elimination, FP32 MFMA               */
+  PQ_PREC_FP32 = 1,        /* complex64 elimination, FP32 MFMA               */
+  PQ_PREC_BF16X3 = 2       /* complex64 elimination whose rank-NB updates
+                              split each FP32 operand into two bf16 parts and
+                              keep three of the four cross products on the
+                              bf16 matrix cores, FP32 accumulation (per-product
+                              relative error ~1e-5); every other step as
+                              PQ_PREC_FP32                                    */
 } pq_precision;
 
 typedef enum { PQ_CH_D = 0, PQ_CH_M = 1, PQ_CH_S = 2, PQ_CH_T = 3 } pq_channel;

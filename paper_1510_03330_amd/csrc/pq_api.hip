@@ -49,7 +49,11 @@ bool make_dims(const pq_params* p, Dims* d) {
   if (p->storage != PQ_STORE_C64 && p->storage != PQ_STORE_C128) { set_error("bad storage"); return false; }
   if (p->precision == PQ_PREC_FP64 && p->storage != PQ_STORE_C128) { set_error("FP64 BSE needs complex128 storage"); return false; }
   if (p->precision == PQ_PREC_FP32 && p->storage != PQ_STORE_C64) { set_error("FP32 BSE needs complex64 storage"); return false; }
-  if (p->precision != PQ_PREC_FP64 && p->precision != PQ_PREC_FP32) { set_error("precision %d not available", p->precision); return false; }
+  if (p->precision == PQ_PREC_BF16X3 && p->storage != PQ_STORE_C64) { set_error("BF16x3 BSE needs complex64 storage"); return false; }
+  if (p->precision != PQ_PREC_FP64 && p->precision != PQ_PREC_FP32 && p->precision != PQ_PREC_BF16X3) {
+    set_error("precision %d not available", p->precision);
+    return false;
+  }
   if (!(p->beta > 0.0) || !isfinite(p->U) || !isfinite(p->beta)) { set_error("beta must be > 0 and U finite"); return false; }
   if (!(p->alpha > 0.0 && p->alpha <= 1.0)) { set_error("alpha must be in (0, 1]"); return false; }
   if (p->Lx * p->Ly == 1 && !(p->D > 0.0)) { set_error("local mode needs D > 0"); return false; }

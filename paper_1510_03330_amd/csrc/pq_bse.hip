@@ -50,7 +50,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Mma;
 
 template <> struct Mma<float> {   // v_mfma_f32_32x32x2f32
-  static constexpr int TM = 32, TN = 32, KS = 2, NV = 16;
+  static constexpr int TM = 32, TN = 32, KS = 2, NV = 16, KV = 1;
   using acc_t = floatx16;
   __device__ static int a_row(int l) { return l & 31; }
   __device__ static int a_k(int l) { return l >> 5; }
@@ -64,7 +64,7 @@ template <> struct Mma<float> {   // v_mfma_f32_32x32x2f32
 };
 
 template <> struct Mma<double> {  // v_mfma_f64_16x16x4f64
-  static constexpr int TM = 16, TN = 16, KS = 4, NV = 4;
+  static constexpr int TM = 16, TN = 16, KS = 4, NV = 4, KV = 1;
   using acc_t = doublex4;
   __device__ static int a_row(int l) { return l & 15; }
   __device__ static int a_k(int l) { return l >> 4; }
@@ -76,6 +76,33 @@ template <> struct Mma<double> {  // v_mfma_f64_16x16x4f64
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
+
+// BF16x3 products on v_mfma_f32_32x32x16_bf16: lane l supplies A[l % 32][k]
+// and B[k][l % 32] for the 8 consecutive k = 8 (l / 32) .. + 7 of a 16-deep
+// step (KV = 8 values per lane); the accumulator layout is that of every
+// 32 x 32 matrix-core product (checked with an exact small-integer probe).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+struct MmaBF3 {
+  static constexpr int TM = 32, TN = 32, KS = 16, NV = 16, KV = 8;
+  using acc_t = floatx16;
+  __device__ static int a_row(int l) { return l & 31; }
+  __device__ static int a_k(int l) { return 8 * (l >> 5); }
+  __device__ static int b_col(int l) { return l & 31; }
+  __device__ static int b_k(int l) { return 8 * (l >> 5); }
+  __device__ static int c_row(int l, int v) { return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3); }
+  __device__ static int c_col(int l) { return l & 31; }
+  __device__ static acc_t mma(bf16x8 a, bf16x8 b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// v = hi + lo + r with hi = bf16(v), lo = bf16(v - hi) (round to nearest) and
+// |r| <= 2^-18 |v|; a product ab is then hi_a hi_b + hi_a lo_b + lo_a hi_b up
+// to ~3 2^-18 |ab| (the lo_a lo_b term and the remainders are dropped)
+__device__ inline void split_bf16(float v, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
 
 // A WM x WN complex output tile owned by one wave (default 32 x 32).
 template <typename T, int WM = 32, int WN = 32>
@@ -179,6 +206,14 @@ struct Tile3 {
         x3[x][y] = M::mma(av[x].y, bs[y], x3[x][y]);
       }
   }
+  __device__ void mac(const C (&av)[SR][1], const C (&bv)[SC][1]) {
+    C a1[SR], b1[SC];
+#pragma unroll
+    for (int x = 0; x < SR; ++x) a1[x] = av[x][0];
+#pragma unroll
+    for (int y = 0; y < SC; ++y) b1[y] = bv[y][0];
+    mac(a1, b1);
+  }
   __device__ void zero() {
 #pragma unroll
     for (int a = 0; a < SR; ++a)
@@ -201,6 +236,93 @@ struct Tile3 {
           c.y = x1[a][b][v] + x2[a][b][v];
           f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l), c);
         }
+  }
+  template <class F> __device__ void store_c(F f) {    // C - ab = (X3 - X1, -X1 - X2)
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < SR; ++a)
+#pragma unroll
+      for (int b = 0; b < SC; ++b)
+#pragma unroll
+        for (int v = 0; v < M::NV; ++v) {
+          C c;
+          c.x = x3[a][b][v] - x1[a][b][v];
+          c.y = -x1[a][b][v] - x2[a][b][v];
+          f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l), c);
+        }
+  }
+};
+
+// Three-product complex tile (as Tile3) on BF16x3 split products, complex64
+// operands: X1 += (ar + ai) br, X2 += ar (bi - br), X3 += ai (br + bi), each
+// real product as three bf16 matrix-core products with FP32 accumulation.
+template <int WM, int WN>
+struct Tile3BF {
+  using M = MmaBF3;
+  using C = float2;
+  static constexpr int SR = WM / M::TM, SC = WN / M::TN;
+  M::acc_t x1[SR][SC], x2[SR][SC], x3[SR][SC];
+  template <class F> __device__ void load_c(F f) {     // X1 = 0, X2 = -Im C, X3 = Re C
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < SR; ++a)
+#pragma unroll
+      for (int b = 0; b < SC; ++b)
+#pragma unroll
+        for (int v = 0; v < M::NV; ++v) {
+          const C c = f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l));
+          x1[a][b][v] = 0.f;
+          x2[a][b][v] = -c.y;
+          x3[a][b][v] = c.x;
+        }
+  }
+  __device__ void mac(const C (&av)[SR][M::KV], const C (&bv)[SC][M::KV]) {
+    bf16x8 sh[SR], sl[SR], rh[SR], rl[SR], ih[SR], il[SR];
+#pragma unroll
+    for (int x = 0; x < SR; ++x)
+#pragma unroll
+      for (int i = 0; i < M::KV; ++i) {
+        __bf16 h, lo;
+        split_bf16(av[x][i].x + av[x][i].y, h, lo);
+        sh[x][i] = h;
+        sl[x][i] = lo;
+        split_bf16(av[x][i].x, h, lo);
+        rh[x][i] = h;
+        rl[x][i] = lo;
+        split_bf16(av[x][i].y, h, lo);
+        ih[x][i] = h;
+        il[x][i] = lo;
+      }
+    bf16x8 bh[SC], bl[SC], dh[SC], dl[SC], eh[SC], el[SC];
+#pragma unroll
+    for (int y = 0; y < SC; ++y)
+#pragma unroll
+      for (int i = 0; i < M::KV; ++i) {
+        __bf16 h, lo;
+        split_bf16(bv[y][i].x, h, lo);
+        bh[y][i] = h;
+        bl[y][i] = lo;
+        split_bf16(bv[y][i].y - bv[y][i].x, h, lo);
+        dh[y][i] = h;
+        dl[y][i] = lo;
+        split_bf16(bv[y][i].x + bv[y][i].y, h, lo);
+        eh[y][i] = h;
+        el[y][i] = lo;
+      }
+#pragma unroll
+    for (int x = 0; x < SR; ++x)
+#pragma unroll
+      for (int y = 0; y < SC; ++y) {
+        x1[x][y] = M::mma(sl[x], bh[y], x1[x][y]);
+        x1[x][y] = M::mma(sh[x], bl[y], x1[x][y]);
+        x1[x][y] = M::mma(sh[x], bh[y], x1[x][y]);
+        x2[x][y] = M::mma(rl[x], dh[y], x2[x][y]);
+        x2[x][y] = M::mma(rh[x], dl[y], x2[x][y]);
+        x2[x][y] = M::mma(rh[x], dh[y], x2[x][y]);
+        x3[x][y] = M::mma(il[x], eh[y], x3[x][y]);
+        x3[x][y] = M::mma(ih[x], el[y], x3[x][y]);
+        x3[x][y] = M::mma(ih[x], eh[y], x3[x][y]);
+      }
   }
   template <class F> __device__ void store_c(F f) {    // C - ab = (X3 - X1, -X1 - X2)
     const int l = threadIdx.x & 63;
@@ -645,16 +767,16 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 //   Re(ab) = X1 - X3,    Im(ab) = X1 + X2,
 // with X3 started at Re C and X2 at -Im C, so C - ab = (X3 - X1, -X1 - X2).
 template <typename T_, int UWM_, int UWN_, int PF_, int WPE_, bool FULL_, bool M3_ = true, bool FIRST_ = false,
-          bool NT_ = false>
+          bool NT_ = false, bool BF3_ = false>
 struct UpdCfg {
   using T = T_;
   static constexpr int UWM = UWM_, UWN = UWN_, PF = PF_, WPE = WPE_;
-  static constexpr bool FULL = FULL_, M3 = M3_, FIRST = FIRST_, NT = NT_;
+  static constexpr bool FULL = FULL_, M3 = M3_, FIRST = FIRST_, NT = NT_, BF3 = BF3_;
   static constexpr int WGM = 2 * UWM, WGN = 2 * UWN;
 };
 // the same tile configuration for the first panel (C read from Gamma)
 template <class CF>
-using UpdFirst = UpdCfg<typename CF::T, CF::UWM, CF::UWN, CF::PF, CF::WPE, CF::FULL, CF::M3, true, CF::NT>;
+using UpdFirst = UpdCfg<typename CF::T, CF::UWM, CF::UWN, CF::PF, CF::WPE, CF::FULL, CF::M3, true, CF::NT, CF::BF3>;
 
 // C tile element access; NT = streaming (non-temporal) hint, so that the C
 // stream does not evict the operand panels every workgroup of the block reuses
@@ -687,13 +809,26 @@ using UpdDefault = typename std::conditional<
                               UpdCfg<T, 64, 32, 2, 3, false, true, false, true>>::type,
     UpdCfg<T, 32, 32, 1, 2, FULL, true, false, true>>::type;
 
+// BF16x3 update (complex64 operands split into bf16 pairs in registers): the
+// 64 x 64 wave tile holds its three accumulators (192 registers) plus the split
+// operands, one wave per SIMD
+template <bool FULL>
+using UpdBF3 = UpdCfg<float, 64, 64, 1, 1, FULL, true, false, true, true>;
+template <typename T, bool FULL, bool BF3>
+using UpdSel = typename std::conditional<BF3, UpdBF3<FULL>, UpdDefault<T, FULL>>::type;
+
 // The four-product form behind the same interface (acc = C, acc -= ab).
 template <typename T, int WM, int WN>
 struct Tile4 : WTile<T, WM, WN> {
   using C = typename cplx_of<T>::type;
   template <class F> __device__ void load_c(F f) { this->load(f); }
-  __device__ void mac(const C (&av)[WTile<T, WM, WN>::SR], const C (&bv)[WTile<T, WM, WN>::SC]) {
-    WTile<T, WM, WN>::mac(av, bv, true);
+  __device__ void mac(const C (&av)[WTile<T, WM, WN>::SR][1], const C (&bv)[WTile<T, WM, WN>::SC][1]) {
+    C a1[WTile<T, WM, WN>::SR], b1[WTile<T, WM, WN>::SC];
+#pragma unroll
+    for (int x = 0; x < WTile<T, WM, WN>::SR; ++x) a1[x] = av[x][0];
+#pragma unroll
+    for (int y = 0; y < WTile<T, WM, WN>::SC; ++y) b1[y] = bv[y][0];
+    WTile<T, WM, WN>::mac(a1, b1, true);
   }
   template <class F> __device__ void store_c(F f) { this->store(f); }
 };
@@ -702,9 +837,12 @@ template <typename T, int NB, class CF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CF::WPE)))
 void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   using C = typename cplx_of<T>::type;
-  using M = Mma<T>;
-  using UT = typename std::conditional<CF::M3, Tile3<T, CF::UWM, CF::UWN>, Tile4<T, CF::UWM, CF::UWN>>::type;
-  constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS, PF = CF::PF;
+  static_assert(!CF::BF3 || sizeof(T) == 4, "BF16x3 products take complex64 operands");
+  using M = typename std::conditional<CF::BF3, MmaBF3, Mma<T>>::type;
+  using UT = typename std::conditional<
+      CF::BF3, Tile3BF<CF::UWM, CF::UWN>,
+      typename std::conditional<CF::M3, Tile3<T, CF::UWM, CF::UWN>, Tile4<T, CF::UWM, CF::UWN>>::type>::type;
+  constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS, PF = CF::PF, KV = M::KV;
   const unsigned lid = xcd_linear();
   const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
   if (inactive(a, blk)) return;
@@ -751,29 +889,37 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   const C* abase[USR];
 #pragma unroll
   for (int xx = 0; xx < USR; ++xx) abase[xx] = MT + (size_t)ka * n + min(i0 + xx * M::TM + M::a_row(lane), n - 1);
-  auto fetch = [&](int ks, C (&av)[USR], C (&bv)[USC]) {
-    if (CF::FULL) {
+  // each lane takes KV consecutive k per step (1 for the FP32 / FP64 products)
+  auto fetch = [&](int ks, C (&av)[USR][KV], C (&bv)[USC][KV]) {
 #pragma unroll
-      for (int y = 0; y < USC; ++y) bv[y] = bbase[y][(size_t)(ks * M::KS) * n];
-    } else {
-      const int kk = min(ks * M::KS + kb, jb - 1);
+    for (int i = 0; i < KV; ++i) {
+      if (CF::FULL) {
 #pragma unroll
-      for (int y = 0; y < USC; ++y) bv[y] = bbase[y][(size_t)kk * n];
+        for (int y = 0; y < USC; ++y) bv[y][i] = bbase[y][(size_t)(ks * M::KS + i) * n];
+      } else {
+        const int kk = min(ks * M::KS + kb + i, jb - 1);
+#pragma unroll
+        for (int y = 0; y < USC; ++y) bv[y][i] = bbase[y][(size_t)kk * n];
+      }
+#pragma unroll
+      for (int xx = 0; xx < USR; ++xx) av[xx][i] = abase[xx][(size_t)(ks * M::KS + i) * n];
     }
-#pragma unroll
-    for (int xx = 0; xx < USR; ++xx) av[xx] = abase[xx][(size_t)(ks * M::KS) * n];
   };
-  C av[PF][USR], bv[PF][USC];
+  C av[PF][USR][KV], bv[PF][USC][KV];
 #pragma unroll
   for (int s = 0; s < PF; ++s) fetch(s, av[s], bv[s]);
 #pragma unroll
   for (int ks = 0; ks < KSTEPS; ++ks) {
     const int cur = ks % PF;
-    C ca[USR], cbv[USC];
+    C ca[USR][KV], cbv[USC][KV];
 #pragma unroll
-    for (int xx = 0; xx < USR; ++xx) ca[xx] = av[cur][xx];
+    for (int xx = 0; xx < USR; ++xx)
 #pragma unroll
-    for (int y = 0; y < USC; ++y) cbv[y] = bv[cur][y];
+      for (int i = 0; i < KV; ++i) ca[xx][i] = av[cur][xx][i];
+#pragma unroll
+    for (int y = 0; y < USC; ++y)
+#pragma unroll
+      for (int i = 0; i < KV; ++i) cbv[y][i] = bv[cur][y][i];
     if (ks + PF < KSTEPS) fetch(ks + PF, av[cur], bv[cur]);
     __builtin_amdgcn_sched_barrier(0);     // keep the prefetch ahead of this step's MFMAs
     acc.mac(ca, cbv);
@@ -940,7 +1086,7 @@ size_t bse_ws_bytes(const pq_params& p, const Dims& d, int precision) {
   return precision == PQ_PREC_FP64 ? bse_layout<double>(d).total : bse_layout<float>(d).total;
 }
 
-template <typename T>
+template <typename T, bool BF3 = false>
 static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, double kappa_max, const void* gamma,
                           const double2* chi0, void* phi_io, pq_bse_block_stats* stats, void* ws,
                           hipStream_t s, BseTiming* tm, const int* active = nullptr) {
@@ -1001,13 +1147,13 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     post();
     pre(3);
     if (jb == NB && j0 == 0)
-      launch_update<T, NB, UpdFirst<UpdDefault<T, true>>>(a, n, d.Nq, j0, s);
+      launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, s);
     else if (jb == NB)
-      launch_update<T, NB, UpdDefault<T, true>>(a, n, d.Nq, j0, s);
+      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, s);
     else if (j0 == 0)
-      launch_update<T, NB, UpdFirst<UpdDefault<T, false>>>(a, n, d.Nq, j0, s);
+      launch_update<T, NB, UpdFirst<UpdSel<T, false, BF3>>>(a, n, d.Nq, j0, s);
     else
-      launch_update<T, NB, UpdDefault<T, false>>(a, n, d.Nq, j0, s);
+      launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, s);
     post();
     if (tm) tm->update_flops += 8.0 * (double)(n - jb) * ncols * jb * d.Nq;
   }
@@ -1045,6 +1191,8 @@ hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precis
   if (p.storage != PQ_STORE_C64) return hipErrorInvalidValue;
   // complex64: a block is re-solved in FP64 when its pivot ratio drops below
   // 1e-3 or a diagonal-block inverse exceeds 1e3 (FP32 error ~ 1e3 eps32 n^1/2)
+  if (precision == PQ_PREC_BF16X3)
+    return run_bse<float, true>(d, channel, alpha, 1e-3f, 1e3, gamma, chi0, phi_io, stats, ws, s, tm);
   return run_bse<float>(d, channel, alpha, 1e-3f, 1e3, gamma, chi0, phi_io, stats, ws, s, tm);
 }
 

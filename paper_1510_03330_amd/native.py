@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "_lib", "libparquet.so")
 PQ_OK, PQ_ERR_ARG, PQ_ERR_HIP, PQ_ERR_NOMEM, PQ_ERR_SINGULAR = 0, 1, 2, 3, 4
 PQ_ERR_NOT_CONVERGED, PQ_ERR_NONFINITE = 5, 6
 PQ_STORE_C128, PQ_STORE_C64 = 0, 1
-PQ_PREC_FP64, PQ_PREC_FP32 = 0, 1
+PQ_PREC_FP64, PQ_PREC_FP32, PQ_PREC_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": PQ_PREC_FP64, "fp32": PQ_PREC_FP32, "bf16x3": PQ_PREC_BF16X3}
 FIELDS = {"sigma": 0, "g": 1, "phi": 2, "gamma": 3, "k1": 4, "k2": 5, "mu": 6, "xph": 7, "xpp": 8}
 
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_SINGULAR",
@@ -126,8 +127,8 @@ def check(status: int):
 
 def make_params(p, precision: str = "fp64") -> PqParams:
     """pq_params from any object with the ModelParams attributes."""
-    if precision not in ("fp64", "fp32"):
-        raise ValueError(f"precision {precision!r} not available (fp64, fp32)")
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision {precision!r} not available ({', '.join(PRECISIONS)})")
     out = PqParams()
     out.Lx, out.Ly, out.Nv = int(p.Lx), int(p.Ly), int(p.Nv)
     out.f_ext = int(p.f_ext)
@@ -135,7 +136,7 @@ def make_params(p, precision: str = "fp64") -> PqParams:
     out.edge_rule = int(p.edge_rule)
     out.mu_mode = int(p.mu_mode)
     out.storage = PQ_STORE_C128 if precision == "fp64" else PQ_STORE_C64
-    out.precision = PQ_PREC_FP64 if precision == "fp64" else PQ_PREC_FP32
+    out.precision = PRECISIONS[precision]
     out.U, out.beta, out.t, out.tp = float(p.U), float(p.beta), float(p.t), float(p.tp)
     out.filling, out.D, out.mu_fixed, out.alpha = float(p.filling), float(p.D), float(p.mu_fixed), float(p.alpha)
     return out

@@ -196,12 +196,15 @@ class Solver:
 
 
 def converge_mixed(p, tol: float = 1e-6, switch_tol: float = 1e-5, max_iter: int = 200,
-                   device: str = "cuda:0"):
-    """Iterate the complex64/FP32 path from the bare-vertex start until
-    max|Sigma_new - Sigma| < switch_tol, then continue on the complex128/FP64
-    path from that state until the change is below tol. Returns the FP64 solver
-    and a dict with the iteration counts of both phases."""
-    s32 = Solver(p, "fp32", device)
+                   device: str = "cuda:0", low: str = "fp32"):
+    """Iterate the complex64 path (precision ``low``: "fp32" or "bf16x3") from
+    the bare-vertex start until max|Sigma_new - Sigma| < switch_tol, then
+    continue on the complex128/FP64 path from that state until the change is
+    below tol. Returns the FP64 solver and a dict with the iteration counts of
+    both phases (the first under the key iterations_fp32)."""
+    if low not in ("fp32", "bf16x3"):
+        raise ValueError(f"low precision {low!r} must be fp32 or bf16x3")
+    s32 = Solver(p, low, device)
     done32, conv32, st32 = s32.iterate(max_iter, switch_tol)
     torch.cuda.synchronize()
     s64 = Solver(p, "fp64", device)

@@ -125,3 +125,27 @@ def test_workspace_queries_scale_with_storage():
     # vertex arrays dominate: complex128 needs about twice complex64, and both fit 288 GB
     assert 1.8 < b64.value / b32.value < 2.2
     assert b64.value < 250e9
+
+
+def test_precision_storage_pairs():
+    """BF16x3 and FP32 eliminate complex64 storage, FP64 complex128; other
+    pairs and unknown precisions are rejected on the host."""
+    p = config("c3")
+    lib = N.load()
+    d = N.PqDims()
+    for prec in ("fp64", "fp32", "bf16x3"):
+        pp = N.make_params(p, prec)
+        assert pp.precision == N.PRECISIONS[prec]
+        N.check(lib.pq_dims_from_params(ctypes.byref(pp), ctypes.byref(d)))
+    b32, b3 = ctypes.c_size_t(), ctypes.c_size_t()
+    N.check(lib.parquet_query_workspace(ctypes.byref(N.make_params(p, "fp32")), ctypes.byref(b32)))
+    N.check(lib.parquet_query_workspace(ctypes.byref(N.make_params(p, "bf16x3")), ctypes.byref(b3)))
+    assert b32.value == b3.value
+    bad = N.make_params(p, "bf16x3")
+    bad.storage = N.PQ_STORE_C128
+    assert lib.pq_dims_from_params(ctypes.byref(bad), ctypes.byref(d)) == N.PQ_ERR_ARG
+    bad = N.make_params(p, "fp32")
+    bad.precision = 3
+    assert lib.pq_dims_from_params(ctypes.byref(bad), ctypes.byref(d)) == N.PQ_ERR_ARG
+    with pytest.raises(ValueError):
+        N.make_params(p, "fp16")
