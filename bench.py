@@ -89,7 +89,32 @@ def run_gpu(p, precision, steps, warmup):
                 kern_ms=kern_ms, kern_n=kern_n, upd_flops=upd_flops)
 
 
-def time_to_converged(p, precision, tol, max_iter):
+def hbm_copy_rate(gib: int = 4, reps: int = 5) -> float:
+    """GB/s (read + write) of a plain device-to-device tensor copy of `gib` GiB:
+    the practical ceiling of a kernel that reads and writes equal volumes."""
+    import torch
+    a = torch.ones((gib << 30) // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2.0 * a.numel() * 4
+    del a, b
+    torch.cuda.empty_cache()
+    return nbytes / (ms * 1e-3) / 1e9
+
+
+def time_to_converged(p, precision, tol, max_iter, tight_tol=None):
+    """Time from the bare-vertex start to max|Sigma_new - Sigma| < tol. With
+    tight_tol the solver then continues (untimed) to that tolerance and the
+    tightly converged Sigma is returned as well (the accuracy reference)."""
     import torch
     from paper_1510_03330_amd.ops import Solver
 
@@ -100,10 +125,22 @@ def time_to_converged(p, precision, tol, max_iter):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sigma = s.get("sigma").cpu()
+    tight = None
+    if tight_tol is not None:
+        more, tconv, tst = s.iterate(max_iter, tight_tol)
+        tight = s.get("sigma").cpu()
     s.close()
     del s
     torch.cuda.empty_cache()
-    return dict(sec=t1 - t0, iterations=done, converged=conv, dsigma=st.dsigma), sigma
+    info = dict(sec=t1 - t0, iterations=done, converged=conv, dsigma=st.dsigma)
+    if tight_tol is not None:
+        info["reference"] = dict(tol=tight_tol, extra_iterations=more, converged=tconv, dsigma=tst.dsigma)
+    return (info, sigma, tight) if tight_tol is not None else (info, sigma)
+
+
+def sigma_distance(s, ref):
+    return {"max_abs_diff": float((s - ref).abs().max()),
+            "max_rel_diff": float((s - ref).abs().max() / ref.abs().max())}
 
 
 def bse_microbench(reps: int = 5, stress_lam: float = 0.99):
@@ -309,6 +346,17 @@ def main():
             "bse_kernel_ms_per_channel": {k: round(r32["kern_ms"][i] / args.steps, 2) for k, i in
                                           (("pivot", 1), ("pivot_rows", 2), ("update", 3), ("epilogue", 4))}}
 
+    # remap: algorithmic bytes (read the 4 Phi arrays, write the 4 Gamma arrays
+    # once) over its stage time, against the HBM peak and against a plain copy
+    copy_gbs = hbm_copy_rate()
+    remap_ms = r32["stage_ms"][3]
+    remap_bytes = 8.0 * d.Nq * float(d.n) ** 2 * 8
+    remap_gbs = remap_bytes / (remap_ms * 1e-3) / 1e9
+    remap_roof = {"bound": "hbm", "ms": round(remap_ms, 3), "algorithmic_bytes": remap_bytes,
+                  "achieved": round(remap_gbs, 1), "peak": PEAK_HBM, "unit": "GB/s",
+                  "frac": round(remap_gbs / PEAK_HBM, 4), "copy_ceiling": round(copy_gbs, 1),
+                  "frac_of_copy_ceiling": round(remap_gbs / copy_gbs, 4)}
+
     out = {
         "metric": "parquet iterations/s + time-to-converged Σ (1e-6) vs FP64 GPU, 8x8 Nv=16",
         "value": round(ips, 4),
@@ -333,6 +381,7 @@ def main():
                            (("dyson", 0), ("bubbles_kernels", 1), ("remap", 3), ("sigma", 4), ("bse", 5),
                             ("mix", 6))} if r64 else None),
         "roofline": roof,
+        "remap": remap_roof,
         "bf16x3_iterations_per_s": round(ips3, 4) if ips3 else None,
         "bf16x3_update_avg_launch_ms": (round(r3["kern_ms"][3] / r3["kern_n"][3], 3) if r3 else None),
         "stage_ms_bf16x3": ({k: round(r3["stage_ms"][i], 3) for k, i in
@@ -340,18 +389,20 @@ def main():
     }
     if not args.no_ttc:
         # time from the bare-vertex start to max|Sigma_new - Sigma| < 1e-6 (the solver's
-        # own stopping test), FP32 path vs FP64 path, and how far apart the two
-        # converged self-energies are
+        # own stopping test) for each schedule. Accuracy: every converged Sigma is
+        # compared with the FP64 fixed point converged further to 1e-10 (untimed);
+        # a run stopped at a 1e-6 change is itself ~1e-6 from its fixed point, so
+        # comparing two 1e-6-converged runs measures the stopping rule, not the
+        # arithmetic
         print("[bench] time to converged sigma (fp32)", file=sys.stderr, flush=True)
         t32, s32 = time_to_converged(p, "fp32", 1e-6, 80)
         print("[bench] time to converged sigma (fp64)", file=sys.stderr, flush=True)
-        t64, s64 = time_to_converged(p, "fp64", 1e-6, 80)
+        t64, s64, sref = time_to_converged(p, "fp64", 1e-6, 80, tight_tol=1e-10)
         out["time_to_converged_fp32"] = t32
         out["time_to_converged_fp64"] = t64
         out["ttc_speedup_fp32_vs_fp64"] = round(t64["sec"] / t32["sec"], 3)
-        out["converged_sigma_fp32_vs_fp64"] = {
-            "max_abs_diff": float((s32 - s64).abs().max()),
-            "max_rel_diff": float((s32 - s64).abs().max() / s64.abs().max())}
+        out["converged_sigma_fp64_vs_fixed_point"] = sigma_distance(s64, sref)
+        out["converged_sigma_fp32_vs_fixed_point"] = sigma_distance(s32, sref)
         # mixed: FP32 iterations down to a 1e-5 change of Sigma, then FP64 from that state
         print("[bench] time to converged sigma (fp32 then fp64)", file=sys.stderr, flush=True)
         import torch
@@ -367,17 +418,13 @@ def main():
         torch.cuda.empty_cache()
         out["time_to_converged_mixed"] = dict(sec=t1 - t0, **info)
         out["ttc_speedup_mixed_vs_fp64"] = round(t64["sec"] / (t1 - t0), 3)
-        out["converged_sigma_mixed_vs_fp64"] = {
-            "max_abs_diff": float((smx - s64).abs().max()),
-            "max_rel_diff": float((smx - s64).abs().max() / s64.abs().max())}
+        out["converged_sigma_mixed_vs_fixed_point"] = sigma_distance(smx, sref)
         # BF16x3 updates: alone, and as the first phase of the mixed schedule
         print("[bench] time to converged sigma (bf16x3)", file=sys.stderr, flush=True)
         t3, s3 = time_to_converged(p, "bf16x3", 1e-6, 80)
         out["time_to_converged_bf16x3"] = t3
         out["ttc_speedup_bf16x3_vs_fp64"] = round(t64["sec"] / t3["sec"], 3)
-        out["converged_sigma_bf16x3_vs_fp64"] = {
-            "max_abs_diff": float((s3 - s64).abs().max()),
-            "max_rel_diff": float((s3 - s64).abs().max() / s64.abs().max())}
+        out["converged_sigma_bf16x3_vs_fixed_point"] = sigma_distance(s3, sref)
         print("[bench] time to converged sigma (bf16x3 then fp64)", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -389,9 +436,7 @@ def main():
         del sm
         torch.cuda.empty_cache()
         out["time_to_converged_mixed_bf16x3"] = dict(sec=t1 - t0, **info)
-        out["converged_sigma_mixed_bf16x3_vs_fp64"] = {
-            "max_abs_diff": float((smx - s64).abs().max()),
-            "max_rel_diff": float((smx - s64).abs().max() / s64.abs().max())}
+        out["converged_sigma_mixed_bf16x3_vs_fixed_point"] = sigma_distance(smx, sref)
     if not args.no_microbench:
         print("[bench] BSE microbenchmark (4x4, Nv=16)", file=sys.stderr, flush=True)
         out["bse_microbench_4x4_nv16"] = bse_microbench()
