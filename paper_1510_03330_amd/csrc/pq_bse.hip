@@ -694,11 +694,14 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
   const int ncols = (n - j0 - jb) + n;
   C* A = a.A + (size_t)blk * n * n;
   C* B = a.B + (size_t)blk * n * n;
-  if (inactive(a, blk)) return;
+  static_assert(kWaves % WPS == 0, "the waves of one strip share a workgroup");
+  if (inactive(a, blk)) return;                 // uniform over the workgroup
   {
     const int ws = blockIdx.x * kWaves + wave;
     const int cs = ws / WPS, rb = (ws % WPS) * RW;      // strip, first panel row of this wave
-    if (cs * 32 >= ncols) return;
+    // a wave past the last strip computes nothing but still meets the barrier
+    // below (both waves of a strip are live or neither is)
+    const bool live = cs * 32 < ncols;
     const C* PT = a.PI + (size_t)blk * NB * NB;   // P transposed (k-major)
     const int kb = M::b_k(lane);
     ColSrc<T> cp[SC];
@@ -729,6 +732,7 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
       for (int y = 0; y < SC; ++y) bv[y] = cp[y].at(k, n, j0);
     };
     C aq[PFA][NRT][SR], bq[PFB][SC];
+    if (live) {
 #pragma unroll
     for (int s = 0; s < PFB; ++s) fetch_b(s, bq[s]);
 #pragma unroll
@@ -748,12 +752,18 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt) acc[rt].mac(av[rt], bv);
     }
+    }
+    // The pivot rows are overwritten in place: with several waves per strip,
+    // every wave must have read all NB panel rows of the strip first.
+    if constexpr (WPS > 1) __syncthreads();
+    if (live) {
 #pragma unroll
-    for (int rt = 0; rt < NRT; ++rt)
-      acc[rt].store_prod([&](int r, int c, C v) {
-        const int row = rb + rt * 32 + r, col = cs * 32 + c;
-        if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
-      });
+      for (int rt = 0; rt < NRT; ++rt)
+        acc[rt].store_prod([&](int r, int c, C v) {
+          const int row = rb + rt * 32 + r, col = cs * 32 + c;
+          if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
+        });
+    }
   }
 }
 

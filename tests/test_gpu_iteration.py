@@ -27,10 +27,17 @@ def relerr(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-@pytest.mark.parametrize("name", ["tiny_2x2", "small_2x4", "tiny_local"])
-def test_first_iterations_match_oracle(name):
-    print("CASE iterations", name, flush=True)
-    p = config(name)
+@pytest.mark.parametrize("name,over", [("tiny_2x2", {}), ("small_2x4", {}), ("tiny_local", {}),
+                                       ("tiny_2x2", dict(kernel_level=0, f_ext=1)),
+                                       ("tiny_2x2", dict(kernel_level=1, f_ext=3)),
+                                       ("tiny_local", dict(kernel_level=0, f_ext=1)),
+                                       ("tiny_local", dict(kernel_level=1, f_ext=2, U=3.0, beta=2.0))])
+def test_first_iterations_match_oracle(name, over):
+    """Three whole iterations against the oracle, also at the kernel levels and
+    regulation boxes the ablation study runs (level 0 truncation, level 1,
+    f_ext 1..3)."""
+    print("CASE iterations", name, over, flush=True)
+    p = config(name, **over)
     g = P.Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
     st = P.init_state(p, g)
     s = _solver(p, "fp64")

@@ -218,6 +218,29 @@ def test_bse_solve(prec, name):
         assert np.all(flags & 2 == 0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("name", ["bse_ragged", "c2"])
+def test_bse_repeat_is_bitwise_identical(prec, name):
+    """Solving the same blocks again with the same workspace gives the same
+    bits: no step reads a value another workgroup, or a wave of the same
+    workgroup, is still writing (the pivot-row step overwrites its input rows
+    in place; with several waves per column strip they all read first)."""
+    _print_case("bse repeat", prec, name)
+    p = config("small_4x4", Nv=10) if name == "bse_ragged" else config(name)
+    g, gam, xph, xpp = _bse_inputs(p, 303)
+    st = _ops().Stage(p, prec)
+    ws = torch.empty(st.bse_workspace_bytes(), dtype=torch.uint8, device=DEV)
+    G = T(gam[1], st.vdtype)
+    X = T(xph)
+    outs = []
+    for _ in range(3):
+        out = torch.empty((g.Nq, g.n, g.n), dtype=st.vdtype, device=DEV)
+        st.bse_solve(1, G, X, out, alpha=1.0, ws=ws)
+        outs.append(out)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
 @pytest.fixture(scope="module")
 def c2_bse():
     """BSE microbenchmark inputs on the 4x4, Nv = 16 box (n = 256, 240 blocks):
