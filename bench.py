@@ -210,6 +210,65 @@ def bse_microbench(reps: int = 5, stress_lam: float = 0.99):
     return out
 
 
+def kernel_study(max_iter: int = 600, tol: float = 1e-8, chunk: int = 10):
+    """Kernel-level and regulation ablation on synthetic inputs, after the
+    paper's convergence claims for its local validation problem: the
+    momentum-independent model (Nk = 1, fixed semicircle bath of half-bandwidth
+    D = 2, half filling, beta = 2), complex128 path, bare-vertex start, linear
+    mixing alpha. For kernel level 0 (truncation), 1 (K1) and 2 (K1 + K2) and
+    regulation box f_ext = 1 (the box itself) or 2: whether the iteration
+    reaches max|dSigma| < tol, or after how many iterations it diverges
+    (max|dSigma| > 1e2 or non-finite), for U = 2 .. 4; and the box convergence
+    of Sigma(i nu_0) in Nv at U = 2."""
+    import math as _m
+    from paper_1510_03330_amd.native import ParquetError
+    from paper_1510_03330_amd.ops import Solver
+    from workloads import config
+
+    base = config("c1").replace(beta=2.0, D=2.0, tol=tol)
+
+    def solve(**kw):
+        p = base.replace(**kw)
+        rec = dict(kw)
+        s = Solver(p, "fp64", device="cuda:0")
+        t0 = time.perf_counter()
+        done, conv, diverged, dmin, last = 0, False, False, float("inf"), float("nan")
+        try:
+            while done < max_iter and not conv:
+                k, conv, st = s.iterate(min(chunk, max_iter - done), tol)
+                done += k
+                last = st.dsigma
+                if not _m.isfinite(last) or last > 1e2:
+                    diverged = True
+                    break
+                dmin = min(dmin, last)
+        except ParquetError as e:                              # non-finite Sigma or a singular block
+            diverged = True
+            rec["error"] = str(e)
+        rec.update(converged=bool(conv), diverged=diverged, iterations=done, dsigma=last, min_dsigma=dmin)
+        if conv:
+            sig = s.get("sigma").cpu()
+            s0 = complex(sig[sig.shape[0] // 2, 0])            # Sigma(i nu_0)
+            rec["sigma_nu0"] = [s0.real, s0.imag]
+        rec["sec"] = round(time.perf_counter() - t0, 3)
+        s.close()
+        return rec
+
+    out = {"study": "kernel level / regulation box / U range, local model with a semicircle bath (D=2), "
+                    "beta=2, half filling, complex128",
+           "max_iter": max_iter, "tol": tol, "u_range": [], "box_convergence": []}
+    for alpha in (0.3, 0.1):
+        for level, f_ext in ((0, 2), (1, 2), (2, 2), (2, 1)):
+            for U in (2.0, 2.5, 3.0, 3.5, 4.0):
+                print(f"[study] alpha {alpha} level {level} f_ext {f_ext} U {U}", file=sys.stderr, flush=True)
+                out["u_range"].append(solve(alpha=alpha, kernel_level=level, f_ext=f_ext, U=U, Nv=32))
+    for level in (0, 1, 2):
+        for Nv in (8, 16, 24, 32, 48, 64):
+            print(f"[study] box level {level} Nv {Nv}", file=sys.stderr, flush=True)
+            out["box_convergence"].append(solve(alpha=0.3, kernel_level=level, f_ext=2, U=2.0, Nv=Nv))
+    return out
+
+
 class _VirtualVertex:
     """Deterministic pseudo-random stand-in for a [4][Nq][n][n] vertex too large
     for host memory; supports the fancy indexing the oracle uses."""
@@ -294,6 +353,8 @@ def main():
     ap.add_argument("--bf16x3-steps", type=int, default=3)
     ap.add_argument("--no-microbench", action="store_true",
                     help="skip the 4x4 Nv=16 BSE microbenchmark")
+    ap.add_argument("--study", action="store_true",
+                    help="run only the kernel-level / regulation / U-range study (one JSON line)")
     ap.add_argument("--no-ttc", action="store_true",
                     help="skip the time-to-converged-Sigma (1e-6) runs of both paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -306,6 +367,9 @@ def main():
               "single device; sharding over the transfer q across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
+    if args.study:
+        print(json.dumps(kernel_study()))
+        return
     from workloads import config
     p = config(args.workload)
     if args.calibrate_copy:
