@@ -38,7 +38,9 @@ closed-form first iteration and the printed product form; Sigma~_1 against
 growing direct Matsubara sums and the atomic limit; sigma_box and sigma_tilde2
 (through the whole BSE -> remap -> SDE chain) against the closed-form
 third-order ladder diagrams, whose particle-hole and particle-particle parts
-cancel at particle-hole symmetry.
+cancel at particle-hole symmetry; a local box Lambda (full parquet / parquet
+DGA input) against the scalar special cases and the crossing identities of F
+for a crossing-symmetric Lambda.
 """
 from __future__ import annotations
 
@@ -389,6 +391,47 @@ def pa_lambda(U: float):
     return (U, -U, 2.0 * U, 0.0)
 
 
+def lambda_at(grid: Grid, lam, r, m, n, n2):
+    """Lambda_r(q; k, k') at transfer frequency m and fermionic frequencies n, n'
+    (results section, full parquet / parquet DGA: the fully irreducible vertex
+    is local, so the momenta do not enter). lam is either the four scalars of
+    the parquet approximation or an array [4][Nv-1][Nv][Nv] on the box, index
+    [r][m + Nv/2 - 1][n + Nv/2][n' + Nv/2]."""
+    if np.ndim(lam) == 1:
+        return lam[r]
+    arr = np.asarray(lam)
+    return arr[r][np.asarray(m) + grid.Nv // 2 - 1, np.asarray(n) + grid.Nv // 2, np.asarray(n2) + grid.Nv // 2]
+
+
+def crossing_lambda(grid: Grid, U: float, lam_d, lam_m):
+    """A local Lambda on the box that obeys the crossing relations between the
+    particle-hole and particle-particle channels (crossing-symmetry subsection,
+    which states that Lambda obeys the same relations as F), built from given
+    d and m parts [Nv-1][Nv][Nv]: at (m; n, n') with partner transfer
+    m' = m - n - n' - 1 in the box,
+        Lambda_s(m) = 1/2 Lambda_d(m') - 3/2 Lambda_m(m'),
+        Lambda_t(m) = 1/2 Lambda_d(m') + 1/2 Lambda_m(m'),
+    which makes Lambda_d = 1/2 Lambda_s + 3/2 Lambda_t and
+    Lambda_m = -1/2 Lambda_s + 1/2 Lambda_t hold at the inverse partner
+    n + n' + m + 1; s and t keep their parquet-approximation values (2U, 0)
+    where the partner lies outside the box."""
+    nw, nv = grid.Nv - 1, grid.Nv
+    out = np.empty((4, nw, nv, nv), dtype=np.complex128)
+    out[0], out[1] = lam_d, lam_m
+    out[2], out[3] = 2.0 * U, 0.0
+    for jm in range(nw):
+        m = jm - (nv // 2 - 1)
+        for i1 in range(nv):
+            for i2 in range(nv):
+                n, n2 = i1 - nv // 2, i2 - nv // 2
+                mp = m - n - n2 - 1
+                if grid.in_bbox(mp):
+                    jp = mp + nv // 2 - 1
+                    out[2, jm, i1, i2] = 0.5 * lam_d[jp, i1, i2] - 1.5 * lam_m[jp, i1, i2]
+                    out[3, jm, i1, i2] = 0.5 * lam_d[jp, i1, i2] + 0.5 * lam_m[jp, i1, i2]
+    return out
+
+
 def remap_points(grid: Grid, phi, K1, K2, lam, qi, ki, kpi):
     """Gamma_r (r = d, m, s, t) at the given box points (arrays of compound
     indices), Eqs. PA_Gamma_dm / PA_Gamma_st with the kernel fill."""
@@ -404,7 +447,7 @@ def remap_points(grid: Grid, phi, K1, K2, lam, qi, ki, kpi):
         return accessor(grid, phi, K1, K2, r, a_n, a_K, b_n, b_K, p_m, p_Q)
 
     t = _remap_terms(grid, P, n, K, n2, Kp, m, Q)
-    return np.stack(_combine_gamma(t, lam))
+    return np.stack(_combine_gamma(t, [lambda_at(grid, lam, r, m, n, n2) for r in range(4)]))
 
 
 def remap(grid: Grid, phi, K1, K2, lam, chunk: int = 1 << 22):
@@ -675,16 +718,20 @@ def init_state(p, grid: Optional[Grid] = None) -> State:
     return State(sigma=sigma0, phi=phi, mu=mu0)
 
 
-def iterate(p, st: State, grid: Optional[Grid] = None, return_parts: bool = False):
+def iterate(p, st: State, grid: Optional[Grid] = None, return_parts: bool = False, lam=None):
     """One parquet iteration in the order Dyson -> bubbles -> kernels -> remap ->
     Schwinger-Dyson -> Bethe-Salpeter -> mixing (reading: the SDE and the BSE use
-    the same G and Phi, so they are independent within an iteration)."""
+    the same G and Phi, so they are independent within an iteration). lam: the
+    fully irreducible vertex, the parquet-approximation scalars by default or a
+    local array on the box (lambda_at); the auxiliary vertex F~ of the
+    regulation keeps the parquet-approximation values, so a box Lambda enters
+    Sigma through F - F~ in the box part."""
     grid = grid or Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
     mu = find_mu(p, grid, st.sigma)
     G = dyson(p, grid, st.sigma, mu)
     xph, xpp = bubbles(p, grid, G)
     K1, K2 = kernel_functions(grid, st.phi, p.kernel_level, p.edge_rule)
-    lam = pa_lambda(p.U)
+    lam = pa_lambda(p.U) if lam is None else lam
     gamma = remap(grid, st.phi, K1, K2, lam)
     F = full_vertex(gamma, st.phi)
     sigma_new = sigma_sde(p, grid, G, F, K1, K2, mu)
@@ -701,12 +748,12 @@ def iterate(p, st: State, grid: Optional[Grid] = None, return_parts: bool = Fals
     return new
 
 
-def solve(p, max_iter: int = 200, tol: Optional[float] = None, callback=None) -> State:
+def solve(p, max_iter: int = 200, tol: Optional[float] = None, callback=None, lam=None) -> State:
     grid = Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
     tol = p.tol if tol is None else tol
     st = init_state(p, grid)
     for _ in range(max_iter):
-        st = iterate(p, st, grid)
+        st = iterate(p, st, grid, lam=lam)
         if callback is not None:
             callback(st)
         if st.last_dsigma < tol:

@@ -14,4 +14,5 @@ from .synthetic import (  # noqa: F401
     random_phi,
     random_sigma,
     lowrank_phi_factors,
+    lambda_box_parts,
 )

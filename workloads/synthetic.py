@@ -96,6 +96,29 @@ def bse_microbench_gamma(n: int, blocks, base_seed: int = 1510) -> np.ndarray:
     return out
 
 
+def lambda_box_parts(nv: int, seed: int, scale: float = 0.3, n_inner=None, symmetric: bool = True):
+    """Two seeded complex arrays [Nv-1][Nv][Nv] (bosonic index, two fermionic
+    indices of a box of Nv fermionic frequencies) for the density and magnetic
+    parts of a local fully irreducible vertex, nonzero only where all three
+    frequency indices lie within n_inner of the box centre (None: the whole
+    box); symmetric: equal under exchange of the two fermionic indices."""
+    rng = np.random.default_rng(seed)
+    nw = nv - 1
+    out = []
+    for _ in range(2):
+        a = (rng.standard_normal((nw, nv, nv)) + 1j * rng.standard_normal((nw, nv, nv))) * (scale / np.sqrt(2.0))
+        if symmetric:
+            a = 0.5 * (a + a.transpose(0, 2, 1))
+        if n_inner is not None:
+            m = np.arange(nw) - (nv // 2 - 1)
+            f = np.arange(nv) - nv // 2
+            keep = ((np.abs(m) <= n_inner)[:, None, None] & (np.abs(f + 0.5) <= n_inner + 0.5)[None, :, None]
+                    & (np.abs(f + 0.5) <= n_inner + 0.5)[None, None, :])
+            a = np.where(keep, a, 0.0)
+        out.append(a.astype(np.complex128))
+    return out[0], out[1]
+
+
 def random_phi(nq: int, n: int, seed: int, scale: float = 0.1) -> np.ndarray:
     """Four seeded random reducible-vertex arrays, layout [channel][q][k][k']."""
     return rand_complex((4, nq, n, n), seed, scale)
