@@ -145,10 +145,14 @@ pq_status kernel_extract(const pq_params* p, const void* phi, void* k1, void* k2
  * with the stored Phi when every argument is inside the box and the kernel
  * value K1(p) + [k1 in box] K2(k1;p) + [k2 in box] K2(k2;p) otherwise (zero
  * when the transfer p leaves the bosonic box). lambda: 4 host doubles
- * (the parquet approximation uses U, -U, 2U, 0). phi, gamma_out:
- * [4][Nq][n][n] storage precision, must not alias. */
-pq_status channel_remap(const pq_params* p, const double lambda[4], const void* phi,
-                        const void* k1, const void* k2, void* gamma_out,
+ * (the parquet approximation uses U, -U, 2U, 0). lambda_box: nullable device
+ * array [4][Nv-1][Nv][Nv] complex128, a local fully irreducible vertex
+ * Lambda_r(m; n, n') (results section: full parquet / parquet DGA take a
+ * local Lambda, extended outside the box by U, -U, 2U, 0), index
+ * [r][m + Nv/2 - 1][n + Nv/2][n' + Nv/2], used in place of lambda at every
+ * momentum. phi, gamma_out: [4][Nq][n][n] storage precision, must not alias. */
+pq_status channel_remap(const pq_params* p, const double lambda[4], const void* lambda_box,
+                        const void* phi, const void* k1, const void* k2, void* gamma_out,
                         pq_stream stream);
 
 /* Workspace bytes for sigma_sde. */
@@ -161,11 +165,14 @@ pq_status sigma_sde_workspace(const pq_params* p, size_t* bytes);
  * Sigma_box: (F - F~) over the box, F = Gamma + Phi built from Phi by the
  * parquet equations (no Gamma input needed), F~ from the kernel functions.
  * FP64 accumulation throughout. phi: [4][Nq][n][n]; k1, k2: kernel tables;
- * g: [NG][Nk]; mu: device double from dyson_update; sigma_out: [Nve][Nk]
- * c128. ws: device workspace of sigma_sde_workspace bytes. */
+ * lambda_box: nullable, the box Lambda of channel_remap; its difference from
+ * (U, -U, 2U, 0) is part of F - F~ and adds to Sigma_box (F~ keeps the
+ * parquet-approximation values); g: [NG][Nk]; mu: device double from
+ * dyson_update; sigma_out: [Nve][Nk] c128. ws: device workspace of
+ * sigma_sde_workspace bytes. */
 pq_status sigma_sde(const pq_params* p, const void* phi, const void* k1,
-                    const void* k2, const void* g, const void* mu, void* sigma_out,
-                    void* ws, size_t ws_bytes, pq_stream stream);
+                    const void* k2, const void* lambda_box, const void* g, const void* mu,
+                    void* sigma_out, void* ws, size_t ws_bytes, pq_stream stream);
 
 /* Workspace bytes for bse_solve on one channel. */
 pq_status bse_workspace(const pq_params* p, size_t* bytes);
@@ -216,7 +223,10 @@ typedef enum {
   PQ_FIELD_K2 = 5,     /* [4][Nq][n] c128          */
   PQ_FIELD_MU = 6,     /* 1 double                 */
   PQ_FIELD_XPH = 7,    /* [Nq][n] c128             */
-  PQ_FIELD_XPP = 8     /* [Nq][n] c128             */
+  PQ_FIELD_XPP = 8,    /* [Nq][n] c128             */
+  PQ_FIELD_LAMBDA = 9  /* [4][Nv-1][Nv][Nv] c128: local Lambda on the box (channel_remap's
+                          lambda_box); (U, -U, 2U, 0) after init; setting it makes the
+                          context iterate with it (full parquet / parquet DGA input) */
 } pq_field;
 
 typedef struct {

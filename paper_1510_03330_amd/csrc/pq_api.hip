@@ -130,14 +130,14 @@ pq_status kernel_extract(const pq_params* p, const void* phi, void* k1, void* k2
              "kernel_extract");
 }
 
-pq_status channel_remap(const pq_params* p, const double lambda[4], const void* phi, const void* k1,
-                        const void* k2, void* gamma_out, pq_stream stream) {
+pq_status channel_remap(const pq_params* p, const double lambda[4], const void* lambda_box, const void* phi,
+                        const void* k1, const void* k2, void* gamma_out, pq_stream stream) {
   Dims d;
   if (!make_dims(p, &d)) return PQ_ERR_ARG;
   PQ_CHECK_ARG(lambda && phi && k1 && k2 && gamma_out, "null pointer");
   PQ_CHECK_ARG(phi != gamma_out, "phi and gamma_out must not alias");
-  return enq(launch_remap(*p, d, lambda, phi, (const double2*)k1, (const double2*)k2, gamma_out,
-                          (hipStream_t)stream), "channel_remap");
+  return enq(launch_remap(*p, d, lambda, (const double2*)lambda_box, phi, (const double2*)k1,
+                          (const double2*)k2, gamma_out, (hipStream_t)stream), "channel_remap");
 }
 
 pq_status sigma_sde_workspace(const pq_params* p, size_t* bytes) {
@@ -149,8 +149,8 @@ pq_status sigma_sde_workspace(const pq_params* p, size_t* bytes) {
 }
 
 pq_status sigma_sde(const pq_params* p, const void* phi, const void* k1, const void* k2,
-                    const void* g, const void* mu, void* sigma_out, void* ws, size_t ws_bytes,
-                    pq_stream stream) {
+                    const void* lambda_box, const void* g, const void* mu, void* sigma_out, void* ws,
+                    size_t ws_bytes, pq_stream stream) {
   Dims d;
   if (!make_dims(p, &d)) return PQ_ERR_ARG;
   PQ_CHECK_ARG(phi && k1 && k2 && g && mu && sigma_out && ws, "null pointer");
@@ -158,8 +158,8 @@ pq_status sigma_sde(const pq_params* p, const void* phi, const void* k1, const v
     set_error("sigma_sde workspace %zu < %zu bytes", ws_bytes, sigma_ws_bytes(d));
     return PQ_ERR_NOMEM;
   }
-  return enq(launch_sigma(*p, d, phi, (const double2*)k1, (const double2*)k2, (const double2*)g,
-                          (const double*)mu, (double2*)sigma_out, ws, (hipStream_t)stream),
+  return enq(launch_sigma(*p, d, phi, (const double2*)k1, (const double2*)k2, (const double2*)lambda_box,
+                          (const double2*)g, (const double*)mu, (double2*)sigma_out, ws, (hipStream_t)stream),
              "sigma_sde");
 }
 
@@ -210,7 +210,8 @@ struct pq_ctx {
   hipStream_t s;
   char* ws;
   size_t ws_bytes;
-  double2 *sigma, *sigma_new, *g, *xph, *xpp, *k1, *k2;
+  double2 *sigma, *sigma_new, *g, *xph, *xpp, *k1, *k2, *lam;
+  bool has_lam;            // a box Lambda was set (else the scalars (U, -U, 2U, 0))
   double *mu, *dnorm;
   void *phi, *gamma, *bse_ws, *sig_ws;
   size_t bse_bytes, sig_bytes;
@@ -225,7 +226,7 @@ struct pq_ctx {
 namespace {
 
 struct CtxLayout {
-  size_t sigma, sigma_new, g, mu, dnorm, xph, xpp, k1, k2, phi, gamma, bse, sig, bstats, total;
+  size_t sigma, sigma_new, g, mu, dnorm, xph, xpp, k1, k2, lam, phi, gamma, bse, sig, bstats, total;
   size_t bse_bytes, sig_bytes;
 };
 
@@ -243,6 +244,7 @@ CtxLayout ctx_layout(const pq_params& p, const Dims& d) {
   L.xpp = take(sizeof(double2) * (size_t)d.Nq * d.n);
   L.k1 = take(sizeof(double2) * 4 * (size_t)d.Nq);
   L.k2 = take(sizeof(double2) * 4 * (size_t)d.Nq * d.n);
+  L.lam = take(sizeof(double2) * 4 * (size_t)d.NW * d.Nv * d.Nv);
   const size_t vb = elem_bytes(p) * (size_t)d.Nq * d.n * d.n * 4;
   L.phi = take(vb);
   L.gamma = take(vb);
@@ -267,6 +269,7 @@ size_t field_bytes(const pq_ctx* c, int f) {
     case PQ_FIELD_MU: return sizeof(double);
     case PQ_FIELD_XPH:
     case PQ_FIELD_XPP: return sizeof(double2) * (size_t)d.Nq * d.n;
+    case PQ_FIELD_LAMBDA: return sizeof(double2) * 4 * (size_t)d.NW * d.Nv * d.Nv;
     default: return 0;
   }
 }
@@ -282,6 +285,7 @@ void* field_ptr(pq_ctx* c, int f) {
     case PQ_FIELD_MU: return c->mu;
     case PQ_FIELD_XPH: return c->xph;
     case PQ_FIELD_XPP: return c->xpp;
+    case PQ_FIELD_LAMBDA: return c->lam;
     default: return nullptr;
   }
 }
@@ -324,6 +328,8 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
   c->xpp = (double2*)(w + L.xpp);
   c->k1 = (double2*)(w + L.k1);
   c->k2 = (double2*)(w + L.k2);
+  c->lam = (double2*)(w + L.lam);
+  c->has_lam = false;
   c->phi = w + L.phi;
   c->gamma = w + L.gamma;
   c->bse_ws = w + L.bse;
@@ -342,6 +348,7 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
   const size_t vb = field_bytes(c, PQ_FIELD_PHI);
   if ((e = hipMemsetAsync(c->phi, 0, vb, c->s)) != hipSuccess) goto fail;
   if ((e = hipMemsetAsync(c->sigma, 0, field_bytes(c, PQ_FIELD_SIGMA), c->s)) != hipSuccess) goto fail;
+  if ((e = launch_lambda_fill(d, c->p.U, c->lam, c->s)) != hipSuccess) goto fail;
   if ((e = launch_dyson(c->p, d, c->sigma, c->g, c->mu, c->s)) != hipSuccess) goto fail;
   if ((e = launch_sigma1(c->p, d, c->g, c->mu, c->sigma, c->sig_ws, c->s)) != hipSuccess) goto fail;
   if ((e = hipStreamSynchronize(c->s)) != hipSuccess) goto fail;
@@ -375,9 +382,12 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
     if ((e = launch_bubbles(p, d, c->g, c->xph, c->xpp, c->s)) != hipSuccess) return hip_fail(e, "bubbles");
     if ((e = launch_kernel_extract(p, d, c->phi, c->k1, c->k2, c->s)) != hipSuccess) return hip_fail(e, "kernels");
     rec(2);
-    if ((e = launch_remap(p, d, lam, c->phi, c->k1, c->k2, c->gamma, c->s)) != hipSuccess) return hip_fail(e, "remap");
+    const double2* lam_box = c->has_lam ? c->lam : nullptr;
+    if ((e = launch_remap(p, d, lam, lam_box, c->phi, c->k1, c->k2, c->gamma, c->s)) != hipSuccess)
+      return hip_fail(e, "remap");
     rec(3);
-    if ((e = launch_sigma(p, d, c->phi, c->k1, c->k2, c->g, c->mu, c->sigma_new, c->sig_ws, c->s)) != hipSuccess)
+    if ((e = launch_sigma(p, d, c->phi, c->k1, c->k2, lam_box, c->g, c->mu, c->sigma_new, c->sig_ws, c->s)) !=
+        hipSuccess)
       return hip_fail(e, "sigma");
     rec(4);
     BseTiming tm;
@@ -472,6 +482,7 @@ pq_status parquet_set(pq_ctx* c, int32_t field, const void* dev_src, size_t byte
   PQ_CHECK_ARG(b > 0 && bytes == b, "field %d needs %zu bytes, got %zu", field, b, bytes);
   hipError_t e = hipMemcpyAsync(field_ptr(c, field), dev_src, b, hipMemcpyDeviceToDevice, c->s);
   if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  if (e == hipSuccess && field == PQ_FIELD_LAMBDA) c->has_lam = true;
   return e == hipSuccess ? PQ_OK : hip_fail(e, "parquet_set");
 }
 
@@ -493,8 +504,14 @@ pq_status parquet_copy_state(pq_ctx* dst, pq_ctx* src) {
   const size_t count = 4 * (size_t)a.Nq * a.n * a.n;
   if ((e = launch_convert(src->phi, src->p.storage, dst->phi, dst->p.storage, count, dst->s)) != hipSuccess)
     return hip_fail(e, "parquet_copy_state (phi)");
+  if (src->has_lam) {
+    if ((e = hipMemcpyAsync(dst->lam, src->lam, field_bytes(src, PQ_FIELD_LAMBDA), hipMemcpyDeviceToDevice,
+                            dst->s)) != hipSuccess)
+      return hip_fail(e, "parquet_copy_state (lambda)");
+  }
   if ((e = hipStreamSynchronize(dst->s)) != hipSuccess) return hip_fail(e, "parquet_copy_state");
   dst->iteration = src->iteration;
+  if (src->has_lam) dst->has_lam = true;
   return PQ_OK;
 }
 

@@ -36,12 +36,14 @@ hipError_t launch_convert(const void* src, int src_storage, void* dst, int dst_s
                           hipStream_t s);
 hipError_t launch_kernel_extract(const pq_params& p, const Dims& d, const void* phi, double2* k1,
                                  double2* k2, hipStream_t s);
-hipError_t launch_remap(const pq_params& p, const Dims& d, const double lam[4], const void* phi,
-                        const double2* k1, const double2* k2, void* gamma, hipStream_t s);
+// lam_box (nullable): local Lambda_r(m; n, n') on the box, [4][NW][Nv][Nv] c128, in place of lam
+hipError_t launch_remap(const pq_params& p, const Dims& d, const double lam[4], const double2* lam_box,
+                        const void* phi, const double2* k1, const double2* k2, void* gamma, hipStream_t s);
+hipError_t launch_lambda_fill(const Dims& d, double U, double2* lam_box, hipStream_t s);
 size_t sigma_ws_bytes(const Dims& d);
 hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, const double2* k1,
-                        const double2* k2, const double2* g, const double* mu, double2* sigma_out,
-                        void* ws, hipStream_t s);
+                        const double2* k2, const double2* lam_box, const double2* g, const double* mu,
+                        double2* sigma_out, void* ws, hipStream_t s);
 // Sigma~_1 alone (used for the bare-vertex start)
 hipError_t launch_sigma1(const pq_params& p, const Dims& d, const double2* g, const double* mu,
                          double2* sigma_out, void* ws, hipStream_t s);

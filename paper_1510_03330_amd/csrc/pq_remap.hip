@@ -117,6 +117,7 @@ template <typename C>
 struct RemapArgs {
   Dims d;
   double lam[4];
+  const double2* lam_box;   // nullable: local Lambda_r(m; n, n') on the box, [4][NW][Nv][Nv]
   const C* phi;
   const double2* k1;
   const double2* k2;
@@ -227,12 +228,26 @@ __global__ __launch_bounds__(kRemapThreads) void remap_kernel(RemapArgs<C> a) {
     info(s, geo, src, jmp, nb, valid);
     const int pass = (s >> 2) & 1, term = s & 3;
     if (term == 0) {
+      // Lambda of the two output channels at (m; n, n'): constant over the
+      // momentum plane, since the fully irreducible vertex is local
+      C l0 = czero<C>(), l1 = czero<C>();
+      if (a.lam_box) {
+        const size_t cs = (size_t)d.NW * d.Nv * d.Nv;
+        const size_t li = ((size_t)jm * d.Nv + kbi / Nk) * d.Nv + (s >> 3);
+        const double2 v0 = a.lam_box[(size_t)(2 * pass) * cs + li];
+        const double2 v1 = a.lam_box[(size_t)(2 * pass + 1) * cs + li];
+        l0.x = (R)v0.x;
+        l0.y = (R)v0.y;
+        l1.x = (R)v1.x;
+        l1.y = (R)v1.y;
+      } else {
+        l0.x = (R)a.lam[2 * pass];
+        l1.x = (R)a.lam[2 * pass + 1];
+      }
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
-        acc0[i] = czero<C>();
-        acc0[i].x = (R)a.lam[2 * pass];
-        acc1[i] = czero<C>();
-        acc1[i].x = (R)a.lam[2 * pass + 1];
+        acc0[i] = l0;
+        acc1[i] = l1;
       }
     }
     if (valid) {                                   // uniform across the block
@@ -275,11 +290,12 @@ __global__ __launch_bounds__(kRemapThreads) void remap_kernel(RemapArgs<C> a) {
 }
 
 template <typename C, int EPT>
-hipError_t run_remap(const Dims& d, const double lam[4], const void* phi, const double2* k1,
-                     const double2* k2, void* gamma, hipStream_t s) {
+hipError_t run_remap(const Dims& d, const double lam[4], const double2* lam_box, const void* phi,
+                     const double2* k1, const double2* k2, void* gamma, hipStream_t s) {
   RemapArgs<C> a;
   a.d = d;
   for (int i = 0; i < 4; ++i) a.lam[i] = lam[i];
+  a.lam_box = lam_box;
   a.phi = (const C*)phi;
   a.k1 = k1;
   a.k2 = k2;
@@ -298,13 +314,22 @@ hipError_t run_remap(const Dims& d, const double lam[4], const void* phi, const 
 }
 
 template <typename C>
-hipError_t dispatch_remap(const Dims& d, const double lam[4], const void* phi, const double2* k1,
-                          const double2* k2, void* gamma, hipStream_t s) {
+hipError_t dispatch_remap(const Dims& d, const double lam[4], const double2* lam_box, const void* phi,
+                          const double2* k1, const double2* k2, void* gamma, hipStream_t s) {
   const int need = (d.Nk * d.Nk + kRemapThreads - 1) / kRemapThreads;
-  if (need <= 1) return run_remap<C, 1>(d, lam, phi, k1, k2, gamma, s);
-  if (need <= 2) return run_remap<C, 2>(d, lam, phi, k1, k2, gamma, s);
-  if (need <= 8) return run_remap<C, 8>(d, lam, phi, k1, k2, gamma, s);
+  if (need <= 1) return run_remap<C, 1>(d, lam, lam_box, phi, k1, k2, gamma, s);
+  if (need <= 2) return run_remap<C, 2>(d, lam, lam_box, phi, k1, k2, gamma, s);
+  if (need <= 8) return run_remap<C, 8>(d, lam, lam_box, phi, k1, k2, gamma, s);
   return hipErrorInvalidValue;
+}
+
+// Lambda_r = (U, -U, 2U, 0) at every point of a [4][NW][Nv][Nv] box array
+__global__ __launch_bounds__(kThreads) void lambda_fill_kernel(double2* lam, size_t per_channel, double U) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 4 * per_channel) return;
+  const int r = (int)(i / per_channel);
+  const double v = r == 0 ? U : r == 1 ? -U : r == 2 ? 2.0 * U : 0.0;
+  lam[i] = mk(v, 0.0);
 }
 
 }  // namespace
@@ -323,11 +348,18 @@ hipError_t launch_kernel_extract(const pq_params& p, const Dims& d, const void* 
   return hipGetLastError();
 }
 
-hipError_t launch_remap(const pq_params& p, const Dims& d, const double lam[4], const void* phi,
-                        const double2* k1, const double2* k2, void* gamma, hipStream_t s) {
+hipError_t launch_remap(const pq_params& p, const Dims& d, const double lam[4], const double2* lam_box,
+                        const void* phi, const double2* k1, const double2* k2, void* gamma, hipStream_t s) {
   if (d.Nk > 64) return hipErrorInvalidValue;
-  if (p.storage == PQ_STORE_C64) return dispatch_remap<float2>(d, lam, phi, k1, k2, gamma, s);
-  return dispatch_remap<double2>(d, lam, phi, k1, k2, gamma, s);
+  if (p.storage == PQ_STORE_C64) return dispatch_remap<float2>(d, lam, lam_box, phi, k1, k2, gamma, s);
+  return dispatch_remap<double2>(d, lam, lam_box, phi, k1, k2, gamma, s);
+}
+
+hipError_t launch_lambda_fill(const Dims& d, double U, double2* lam_box, hipStream_t s) {
+  const size_t per = (size_t)d.NW * d.Nv * d.Nv;
+  hipLaunchKernelGGL(lambda_fill_kernel, dim3((unsigned)((4 * per + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                     lam_box, per, U);
+  return hipGetLastError();
 }
 
 }  // namespace pq

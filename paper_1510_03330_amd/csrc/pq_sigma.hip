@@ -395,6 +395,84 @@ __global__ __launch_bounds__(kThreads) void sigmab_kernel(SBArgs<C> a) {
   if (threadIdx.x == 0) a.partial[(size_t)kbi * d.NW + jm] = mk(ar, ai);
 }
 
+// ------------------------------------------------- local Lambda in the box
+// A box Lambda that differs from (U, -U, 2U, 0) adds to Sigma_box the
+// Schwinger-Dyson sum of dLambda over the box, with dLambda_dm = Lambda_d -
+// Lambda_m - 2U and dLambda_st = Lambda_s + Lambda_t - 2U at (m; n, n'). Since
+// Lambda is local, the momentum sums factor through two bubble-like tables
+//   B1(n', m; Q) = sum_K' G(n'+m, K'+Q) G(n', K'),
+//   B2(n', m; Q) = sum_K' G(m-n'-1, Q-K') G(n', K'),
+// and Sigma_box(n, K) gains
+//   sum_{n', m} [dLambda_dm sum_Q G(n+m, K+Q) B1 + dLambda_st sum_Q G(m-n-1, Q-K) B2]
+// (times the Schwinger-Dyson constant, applied in combine_kernel).
+struct LamArgs {
+  Dims d;
+  double U;
+  const double2* g;
+  const double2* lam;     // [4][NW][Nv][Nv]
+  double2* b1;            // [Nv][NW][Nk]
+  double2* b2;
+  double2* out;           // [n] (box k)
+};
+
+__device__ inline double2 g_at(const LamArgs& a, int nu, int K) {
+  return a.g[(size_t)(nu + a.d.NG / 2) * a.d.Nk + K];
+}
+
+__global__ __launch_bounds__(kThreads) void lam_tables_kernel(LamArgs a) {
+  const Dims& d = a.d;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.Nv * d.NW * d.Nk) return;
+  const int Q = idx % d.Nk, jm = (idx / d.Nk) % d.NW, i2 = idx / (d.Nk * d.NW);
+  const int n2 = i2 - d.Nv / 2, m = jm - (d.Nv / 2 - 1);
+  double2 s1 = mk(0, 0), s2 = mk(0, 0);
+  for (int Kp = 0; Kp < d.Nk; ++Kp) {
+    const double2 gk = g_at(a, n2, Kp);
+    s1 = cadd(s1, cmul(g_at(a, n2 + m, kadd(Kp, Q, d.Lx, d.Ly)), gk));
+    s2 = cadd(s2, cmul(g_at(a, m - n2 - 1, ksub(Q, Kp, d.Lx, d.Ly)), gk));
+  }
+  a.b1[idx] = s1;
+  a.b2[idx] = s2;
+}
+
+// one workgroup per box k = (n, K); threads over (n', m)
+__global__ __launch_bounds__(kThreads) void lam_sigma_kernel(LamArgs a) {
+  __shared__ double red[2][kThreads];
+  const Dims& d = a.d;
+  const int kbi = blockIdx.x, i1 = kbi / d.Nk, K = kbi - (kbi / d.Nk) * d.Nk;
+  const int n = i1 - d.Nv / 2;
+  const size_t cs = (size_t)d.NW * d.Nv * d.Nv;
+  double sr = 0.0, si = 0.0;
+  for (int pr = threadIdx.x; pr < d.Nv * d.NW; pr += blockDim.x) {
+    const int i2 = pr / d.NW, jm = pr - (pr / d.NW) * d.NW;
+    const int m = jm - (d.Nv / 2 - 1);
+    const size_t li = ((size_t)jm * d.Nv + i1) * d.Nv + i2;
+    const double2 ldm = csub(csub(a.lam[li], a.lam[cs + li]), mk(2.0 * a.U, 0.0));
+    const double2 lst = csub(cadd(a.lam[2 * cs + li], a.lam[3 * cs + li]), mk(2.0 * a.U, 0.0));
+    double2 t1 = mk(0, 0), t2 = mk(0, 0);
+    const double2* b1 = a.b1 + ((size_t)i2 * d.NW + jm) * d.Nk;
+    const double2* b2 = a.b2 + ((size_t)i2 * d.NW + jm) * d.Nk;
+    for (int Q = 0; Q < d.Nk; ++Q) {
+      t1 = cadd(t1, cmul(g_at(a, n + m, kadd(K, Q, d.Lx, d.Ly)), b1[Q]));
+      t2 = cadd(t2, cmul(g_at(a, m - n - 1, ksub(Q, K, d.Lx, d.Ly)), b2[Q]));
+    }
+    const double2 v = cadd(cmul(ldm, t1), cmul(lst, t2));
+    sr += v.x;
+    si += v.y;
+  }
+  red[0][threadIdx.x] = sr;
+  red[1][threadIdx.x] = si;
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.out[kbi] = mk(red[0][0], red[1][0]);
+}
+
 struct CombineArgs {
   Dims d;
   double cfac;
@@ -402,6 +480,7 @@ struct CombineArgs {
   const double2* s1;
   const double2* s2;
   const double2* partial;
+  const double2* lam_part;   // nullable: the box-Lambda term per box k
   double2* out;
 };
 
@@ -417,13 +496,14 @@ __global__ void combine_kernel(CombineArgs a) {
     int kbi = (n + d.Nv / 2) * d.Nk + K;
     double2 acc = mk(0, 0);
     for (int j = 0; j < d.NW; ++j) acc = cadd(acc, a.partial[(size_t)kbi * d.NW + j]);
+    if (a.lam_part) acc = cadd(acc, a.lam_part[kbi]);
     v = cadd(v, cscale(acc, a.cfac));
   }
   a.out[idx] = v;
 }
 
 struct WsLayout {
-  size_t tau, wt, dg, gkt, grt, trn, s1, s2, tab, part, total;
+  size_t tau, wt, dg, gkt, grt, trn, s1, s2, tab, part, lb1, lb2, lpart, total;
 };
 
 WsLayout ws_layout(const Dims& d) {
@@ -440,6 +520,9 @@ WsLayout ws_layout(const Dims& d) {
   L.s2 = take(sizeof(double2) * d.Nve * d.Nk);
   L.tab = take(sizeof(double2) * 5 * (size_t)d.NG * d.Nq);
   L.part = take(sizeof(double2) * (size_t)d.n * d.NW);
+  L.lb1 = take(sizeof(double2) * (size_t)d.Nv * d.NW * d.Nk);
+  L.lb2 = take(sizeof(double2) * (size_t)d.Nv * d.NW * d.Nk);
+  L.lpart = take(sizeof(double2) * (size_t)d.n);
   L.total = off;
   return L;
 }
@@ -471,8 +554,8 @@ hipError_t launch_sigma1(const pq_params& p, const Dims& d, const double2* g, co
 }
 
 hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, const double2* k1,
-                        const double2* k2, const double2* g, const double* mu, double2* sigma_out,
-                        void* wsv, hipStream_t s) {
+                        const double2* k2, const double2* lam_box, const double2* g, const double* mu,
+                        double2* sigma_out, void* wsv, hipStream_t s) {
   char* ws = (char*)wsv;
   WsLayout L = ws_layout(d);
   double2* s1 = (double2*)(ws + L.s1);
@@ -494,8 +577,15 @@ hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, cons
     SBArgs<double2> ab{d, (const double2*)phi, g, part};
     hipLaunchKernelGGL(sigmab_kernel<double2>, dim3(d.n * d.NW), dim3(kThreads), 0, s, ab);
   }
+  double2* lpart = nullptr;
+  if (lam_box) {
+    lpart = (double2*)(ws + L.lpart);
+    LamArgs al{d, p.U, g, lam_box, (double2*)(ws + L.lb1), (double2*)(ws + L.lb2), lpart};
+    hipLaunchKernelGGL(lam_tables_kernel, dim3(nblk((size_t)d.Nv * d.NW * d.Nk)), dim3(kThreads), 0, s, al);
+    hipLaunchKernelGGL(lam_sigma_kernel, dim3(d.n), dim3(kThreads), 0, s, al);
+  }
   const double T = 1.0 / p.beta;
-  CombineArgs ac{d, -p.U * T * T / (4.0 * d.Nk * (double)d.Nk), has_s2, 1, s1, s2, part, sigma_out};
+  CombineArgs ac{d, -p.U * T * T / (4.0 * d.Nk * (double)d.Nk), has_s2, 1, s1, s2, part, lpart, sigma_out};
   hipLaunchKernelGGL(combine_kernel, dim3(nblk(d.Nve * d.Nk)), dim3(kThreads), 0, s, ac);
   return hipGetLastError();
 }

@@ -19,7 +19,8 @@ PQ_ERR_NOT_CONVERGED, PQ_ERR_NONFINITE = 5, 6
 PQ_STORE_C128, PQ_STORE_C64 = 0, 1
 PQ_PREC_FP64, PQ_PREC_FP32, PQ_PREC_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": PQ_PREC_FP64, "fp32": PQ_PREC_FP32, "bf16x3": PQ_PREC_BF16X3}
-FIELDS = {"sigma": 0, "g": 1, "phi": 2, "gamma": 3, "k1": 4, "k2": 5, "mu": 6, "xph": 7, "xpp": 8}
+FIELDS = {"sigma": 0, "g": 1, "phi": 2, "gamma": 3, "k1": 4, "k2": 5, "mu": 6, "xph": 7, "xpp": 8,
+          "lambda": 9}
 
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_SINGULAR",
                 5: "ERR_NOT_CONVERGED", 6: "ERR_NONFINITE"}
@@ -91,9 +92,9 @@ def load() -> ctypes.CDLL:
         "dyson_update": [P, c_void_p, c_void_p, c_void_p, c_void_p],
         "bubble_build": [P, c_void_p, c_void_p, c_void_p, c_void_p],
         "kernel_extract": [P, c_void_p, c_void_p, c_void_p, c_void_p],
-        "channel_remap": [P, POINTER(c_double), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+        "channel_remap": [P, POINTER(c_double), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
         "sigma_sde_workspace": [P, POINTER(c_size_t)],
-        "sigma_sde": [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+        "sigma_sde": [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                       c_size_t, c_void_p],
         "bse_workspace": [P, POINTER(c_size_t)],
         "bse_solve": [P, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_double, c_void_p,

@@ -48,6 +48,7 @@ class Stage:
         self.x_shape = (d.Nq, d.n)
         self.k1_shape = (4, d.Nq)
         self.k2_shape = (4, d.Nq, d.n)
+        self.lam_shape = (4, d.NW, d.Nv, d.Nv)
 
     def _pp(self):
         return ctypes.byref(self.pp)
@@ -69,9 +70,11 @@ class Stage:
                                         _ptr(k1, torch.complex128, self.k1_shape, "k1"),
                                         _ptr(k2, torch.complex128, self.k2_shape, "k2"), _stream(stream)))
 
-    def channel_remap(self, lam, phi, k1, k2, gamma_out, stream=None):
+    def channel_remap(self, lam, phi, k1, k2, gamma_out, lam_box=None, stream=None):
+        """lam: 4 scalars; lam_box (optional): [4][Nv-1][Nv][Nv] complex128 local Lambda."""
         arr = (ctypes.c_double * 4)(*[float(v) for v in lam])
-        N.check(N.load().channel_remap(self._pp(), arr, _ptr(phi, self.vdtype, self.vshape, "phi"),
+        lb = ctypes.c_void_p(0) if lam_box is None else _ptr(lam_box, torch.complex128, self.lam_shape, "lam_box")
+        N.check(N.load().channel_remap(self._pp(), arr, lb, _ptr(phi, self.vdtype, self.vshape, "phi"),
                                        _ptr(k1, torch.complex128, self.k1_shape, "k1"),
                                        _ptr(k2, torch.complex128, self.k2_shape, "k2"),
                                        _ptr(gamma_out, self.vdtype, self.vshape, "gamma_out"),
@@ -82,13 +85,14 @@ class Stage:
         N.check(N.load().sigma_sde_workspace(self._pp(), ctypes.byref(b)))
         return int(b.value)
 
-    def sigma_sde(self, phi, k1, k2, g, mu, sigma_out, ws=None, stream=None):
+    def sigma_sde(self, phi, k1, k2, g, mu, sigma_out, ws=None, lam_box=None, stream=None):
         nb = self.sigma_workspace_bytes()
         if ws is None:
             ws = torch.empty(nb, dtype=torch.uint8, device=phi.device)
+        lb = ctypes.c_void_p(0) if lam_box is None else _ptr(lam_box, torch.complex128, self.lam_shape, "lam_box")
         N.check(N.load().sigma_sde(self._pp(), _ptr(phi, self.vdtype, self.vshape, "phi"),
                                    _ptr(k1, torch.complex128, self.k1_shape, "k1"),
-                                   _ptr(k2, torch.complex128, self.k2_shape, "k2"),
+                                   _ptr(k2, torch.complex128, self.k2_shape, "k2"), lb,
                                    _ptr(g, torch.complex128, self.g_shape, "g"),
                                    _ptr(mu, torch.float64, (1,), "mu"),
                                    _ptr(sigma_out, torch.complex128, self.sigma_shape, "sigma_out"),
@@ -160,7 +164,7 @@ class Solver:
             "phi": (s.vshape, s.vdtype), "gamma": (s.vshape, s.vdtype),
             "k1": (s.k1_shape, torch.complex128), "k2": (s.k2_shape, torch.complex128),
             "mu": ((1,), torch.float64), "xph": (s.x_shape, torch.complex128),
-            "xpp": (s.x_shape, torch.complex128),
+            "xpp": (s.x_shape, torch.complex128), "lambda": (s.lam_shape, torch.complex128),
         }[name]
 
     def get(self, name: str) -> torch.Tensor:

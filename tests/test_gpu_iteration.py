@@ -54,6 +54,46 @@ def test_first_iterations_match_oracle(name, over):
     s.close()
 
 
+@pytest.mark.parametrize("name,crossing", [("tiny_2x2", False), ("tiny_local", True), ("small_2x4", True)])
+def test_iterations_with_box_lambda(name, crossing):
+    """Full parquet / parquet DGA input: a local Lambda on the box set on the
+    context (PQ_FIELD_LAMBDA); three iterations against the oracle. crossing:
+    a crossing-symmetric Lambda (crossing_lambda) perturbed within an inner
+    box of two frequencies, else a general perturbation in every channel."""
+    from workloads import lambda_box_parts
+    print("CASE iterations box lambda", name, crossing, flush=True)
+    p = config(name)
+    g = P.Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
+    if crossing:
+        ld, lm = lambda_box_parts(g.Nv, seed=91, scale=0.3, n_inner=1, symmetric=True)
+        lam = P.crossing_lambda(g, p.U, ld + p.U, lm - p.U)
+    else:
+        pa = P.pa_lambda(p.U)
+        a, b = lambda_box_parts(g.Nv, seed=92, scale=0.3, symmetric=False)
+        c, e = lambda_box_parts(g.Nv, seed=93, scale=0.3, symmetric=False)
+        lam = np.stack([pa[r] + part for r, part in enumerate((a, b, c, e))])
+    st = P.init_state(p, g)
+    s = _solver(p, "fp64")
+    s.set("lambda", torch.from_numpy(lam))
+    assert np.max(np.abs(H(s.get("lambda")) - lam)) == 0.0
+    for it in range(3):
+        st = P.iterate(p, st, g, lam=lam)
+        done, conv, stats = s.iterate(1)
+        assert done == 1
+        assert relerr(H(s.get("sigma")), st.sigma) < 1e-11
+        assert relerr(H(s.get("phi")), st.phi) < 1e-11
+    s.close()
+
+
+def test_lambda_field_defaults_to_parquet_approximation():
+    p = config("tiny_2x2")
+    s = _solver(p, "fp32")
+    lam = H(s.get("lambda"))
+    for r, v in enumerate((p.U, -p.U, 2 * p.U, 0.0)):
+        assert np.all(lam[r] == v)
+    s.close()
+
+
 @pytest.fixture(scope="module")
 def c1_oracle():
     p = config("c1")

@@ -18,7 +18,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import parquet as P
-from workloads import bse_microbench_gamma, config, rand_complex, random_phi, random_sigma
+from workloads import bse_microbench_gamma, config, lambda_box_parts, rand_complex, random_phi, random_sigma
 
 pytestmark = pytest.mark.gpu
 
@@ -129,6 +129,35 @@ def test_channel_remap(prec, name, level):
     assert err < (1e-14 if prec == "fp64" else 1e-6), err
 
 
+def _box_lambda(p, g, seed):
+    """A general local Lambda on the box: the parquet-approximation values plus
+    seeded perturbations in every channel, not symmetric under n <-> n' (so an
+    index exchange between the two sides would show)."""
+    pa = P.pa_lambda(p.U)
+    ld, lm = lambda_box_parts(g.Nv, seed=seed, scale=0.4, symmetric=False)
+    ls, lt = lambda_box_parts(g.Nv, seed=seed + 1, scale=0.4, symmetric=False)
+    return np.stack([pa[r] + part for r, part in enumerate((ld, lm, ls, lt))])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,level", [("tiny_2x2", 2), ("small_2x4", 0), ("tiny_local", 2)])
+def test_channel_remap_box_lambda(prec, name, level):
+    _print_case("remap box lambda", prec, name, level)
+    p = config(name, kernel_level=level)
+    g = _grid(p)
+    phi = random_phi(g.Nq, g.n, seed=45, scale=0.5)
+    if prec == "fp32":
+        phi = phi.astype(np.complex64).astype(np.complex128)
+    K1, K2 = P.kernel_functions(g, phi, level)
+    lam = _box_lambda(p, g, 61)
+    gam_ref = P.remap(g, phi, K1, K2, lam)
+    st = _ops().Stage(p, prec)
+    gam = torch.empty(st.vshape, dtype=st.vdtype, device=DEV)
+    st.channel_remap(P.pa_lambda(p.U), T(phi, st.vdtype), T(K1), T(K2), gam, lam_box=T(lam))
+    err = relerr(H(gam).astype(np.complex128), gam_ref)
+    assert err < (1e-14 if prec == "fp64" else 1e-6), err
+
+
 # ---------------------------------------------------------- self-energy
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("name,level", [("tiny_2x2", 2), ("small_2x4", 2), ("small_2x4", 1),
@@ -152,6 +181,37 @@ def test_sigma_sde(prec, name, level):
     st.sigma_sde(T(phi, st.vdtype), T(K1), T(K2), T(G), torch.tensor([mu], dtype=torch.float64, device=DEV), out)
     err = relerr(H(out), ref)
     assert err < 1e-12, err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,level", [("tiny_2x2", 2), ("small_2x4", 1), ("tiny_local", 0)])
+def test_sigma_sde_box_lambda(prec, name, level):
+    """A box Lambda enters Sigma through F - F~ of the box part (F~ keeps the
+    parquet-approximation values): the GPU's factorised momentum sums against
+    the oracle's box sum over the full vertex."""
+    _print_case("sigma box lambda", prec, name, level)
+    p = config(name, kernel_level=level)
+    g = _grid(p)
+    phi = random_phi(g.Nq, g.n, seed=47, scale=0.3)
+    if prec == "fp32":
+        phi = phi.astype(np.complex64).astype(np.complex128)
+    sig = random_sigma(g.Nve, g.Nk, seed=9, scale=0.1)
+    sig = 0.5 * (sig + np.conj(sig[::-1]))
+    mu = P.find_mu(p, g, sig)
+    G = P.dyson(p, g, sig, mu)
+    K1, K2 = P.kernel_functions(g, phi, level)
+    lam = _box_lambda(p, g, 71)
+    F = P.remap(g, phi, K1, K2, lam) + phi
+    ref = P.sigma_sde(p, g, G, F, K1, K2, mu)
+    st = _ops().Stage(p, prec)
+    out = torch.empty(st.sigma_shape, dtype=torch.complex128, device=DEV)
+    st.sigma_sde(T(phi, st.vdtype), T(K1), T(K2), T(G), torch.tensor([mu], dtype=torch.float64, device=DEV), out,
+                 lam_box=T(lam))
+    assert relerr(H(out), ref) < 1e-12
+    # the Lambda term is really present: without it the result differs
+    out0 = torch.empty_like(out)
+    st.sigma_sde(T(phi, st.vdtype), T(K1), T(K2), T(G), torch.tensor([mu], dtype=torch.float64, device=DEV), out0)
+    assert relerr(H(out0), ref) > 1e-6
 
 
 def test_sigma_tilde1_alone_matches_oracle_lattice_and_local():
