@@ -258,6 +258,21 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
 pq_status parquet_iterate(pq_ctx* ctx, int32_t n_iter, double tol, pq_iter_stats* stats,
                           int32_t* iters_done, int32_t* converged);
 
+/* Iterate several contexts at once, for many small instances that do not fill
+ * the GPU alone (each may have its own box and parameters). On first use each
+ * context captures one whole iteration (the launches of parquet_iterate,
+ * without timing) into a HIP graph on its stream, again after its box Lambda
+ * setting changed. Every round replays the graphs of the contexts that are
+ * still active, each on its own stream, then reads each norm (one
+ * synchronisation per context per round) and retires the converged ones
+ * (max|Sigma_new - Sigma_old| < tol, tol <= 0: never) and those with a
+ * non-finite self-energy (status PQ_ERR_NONFINITE, the others continue).
+ * ctxs: count contexts with distinct, created (non-null) streams;
+ * iters_done, converged: host arrays of count entries, nullable. Not for
+ * contexts another thread uses at the same time. */
+pq_status parquet_iterate_batch(pq_ctx* const* ctxs, int32_t count, int32_t n_iter, double tol,
+                                int32_t* iters_done, int32_t* converged);
+
 /* Copy a state field out of / into the context (device-to-device, on the
  * context stream; synchronises). bytes must equal the field size. */
 pq_status parquet_get(pq_ctx* ctx, int32_t field, void* dev_dst, size_t bytes);

@@ -7,6 +7,8 @@
 
 #include <new>
 
+#include <vector>
+
 #include "pq_internal.h"
 
 namespace pq {
@@ -221,6 +223,9 @@ struct pq_ctx {
   bool have_events;
   hipEvent_t bev[512];   // BSE launch timing of one channel
   bool have_bev;
+  hipGraphExec_t graph;  // one whole iteration captured on s (parquet_iterate_batch)
+  bool have_graph;
+  bool graph_has_lam;    // the box Lambda setting the graph was captured with
 };
 
 namespace {
@@ -290,6 +295,47 @@ void* field_ptr(pq_ctx* c, int f) {
   }
 }
 
+// The launches of one iteration on the context stream: Dyson -> bubbles ->
+// kernels -> remap -> Schwinger-Dyson -> BSE (4 channels) -> mixing (writes
+// dnorm). Nothing here waits on the host, allocates or clears memory, so the
+// sequence can be captured into a graph (record = false, tm = nullptr).
+hipError_t enqueue_iteration(pq_ctx* c, bool record, BseTiming* tm, const char** where) {
+  const Dims& d = c->d;
+  const pq_params& p = c->p;
+  const double lam[4] = {p.U, -p.U, 2.0 * p.U, 0.0};
+  const size_t vstride = elem_bytes(p) * (size_t)d.Nq * d.n * d.n;
+  const double2* lam_box = c->has_lam ? c->lam : nullptr;
+  hipError_t e;
+  auto rec = [&](int i) { if (record) hipEventRecord(c->ev[i], c->s); };
+  rec(0);
+  if ((e = launch_dyson(p, d, c->sigma, c->g, c->mu, c->s)) != hipSuccess) { *where = "dyson"; return e; }
+  rec(1);
+  if ((e = launch_bubbles(p, d, c->g, c->xph, c->xpp, c->s)) != hipSuccess) { *where = "bubbles"; return e; }
+  if ((e = launch_kernel_extract(p, d, c->phi, c->k1, c->k2, c->s)) != hipSuccess) { *where = "kernels"; return e; }
+  rec(2);
+  if ((e = launch_remap(p, d, lam, lam_box, c->phi, c->k1, c->k2, c->gamma, c->s)) != hipSuccess) {
+    *where = "remap";
+    return e;
+  }
+  rec(3);
+  if ((e = launch_sigma(p, d, c->phi, c->k1, c->k2, lam_box, c->g, c->mu, c->sigma_new, c->sig_ws, c->s)) !=
+      hipSuccess) {
+    *where = "sigma";
+    return e;
+  }
+  rec(4);
+  for (int r = 0; r < 4; ++r) {
+    const double2* x = r < 2 ? c->xph : c->xpp;
+    e = launch_bse(p, d, r, p.precision, (char*)c->gamma + r * vstride, x, (char*)c->phi + r * vstride, p.alpha,
+                   c->bstats + (size_t)r * d.Nq, c->bse_ws, c->s, r == 0 ? tm : nullptr);
+    if (e != hipSuccess) { *where = "bse"; return e; }
+  }
+  rec(5);
+  if ((e = launch_mix(d, c->sigma_new, c->sigma, p.alpha, c->dnorm, c->s)) != hipSuccess) { *where = "mix"; return e; }
+  rec(6);
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -338,6 +384,8 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
   c->sig_bytes = L.sig_bytes;
   c->bstats = (pq_bse_block_stats*)(w + L.bstats);
   c->iteration = 0;
+  c->have_graph = false;
+  c->graph_has_lam = false;
   c->have_events = true;
   for (int i = 0; i < 8; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) c->have_events = false;
@@ -368,43 +416,19 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
   PQ_CHECK_ARG(c, "null context");
   PQ_CHECK_ARG(n_iter >= 0, "n_iter must be >= 0");
   const Dims& d = c->d;
-  const pq_params& p = c->p;
-  const double lam[4] = {p.U, -p.U, 2.0 * p.U, 0.0};
-  const size_t vstride = elem_bytes(p) * (size_t)d.Nq * d.n * d.n;
   int done = 0, conv = 0;
   pq_status st = PQ_OK;
   for (int it = 0; it < n_iter; ++it) {
     hipError_t e = hipSuccess;
-    auto rec = [&](int i) { if (c->have_events) hipEventRecord(c->ev[i], c->s); };
-    rec(0);
-    if ((e = launch_dyson(p, d, c->sigma, c->g, c->mu, c->s)) != hipSuccess) return hip_fail(e, "dyson");
-    rec(1);
-    if ((e = launch_bubbles(p, d, c->g, c->xph, c->xpp, c->s)) != hipSuccess) return hip_fail(e, "bubbles");
-    if ((e = launch_kernel_extract(p, d, c->phi, c->k1, c->k2, c->s)) != hipSuccess) return hip_fail(e, "kernels");
-    rec(2);
-    const double2* lam_box = c->has_lam ? c->lam : nullptr;
-    if ((e = launch_remap(p, d, lam, lam_box, c->phi, c->k1, c->k2, c->gamma, c->s)) != hipSuccess)
-      return hip_fail(e, "remap");
-    rec(3);
-    if ((e = launch_sigma(p, d, c->phi, c->k1, c->k2, lam_box, c->g, c->mu, c->sigma_new, c->sig_ws, c->s)) !=
-        hipSuccess)
-      return hip_fail(e, "sigma");
-    rec(4);
     BseTiming tm;
     tm.ev = c->bev;
     tm.cap = 256;
     tm.used = 0;
     tm.update_flops = 0.0;
     const bool timing = stats && c->have_bev;
-    for (int r = 0; r < 4; ++r) {
-      const double2* x = r < 2 ? c->xph : c->xpp;
-      e = launch_bse(p, d, r, p.precision, (char*)c->gamma + r * vstride, x, (char*)c->phi + r * vstride,
-                     p.alpha, c->bstats + (size_t)r * d.Nq, c->bse_ws, c->s, (timing && r == 0) ? &tm : nullptr);
-      if (e != hipSuccess) return hip_fail(e, "bse");
-    }
-    rec(5);
-    if ((e = launch_mix(d, c->sigma_new, c->sigma, p.alpha, c->dnorm, c->s)) != hipSuccess) return hip_fail(e, "mix");
-    rec(6);
+    const char* where = nullptr;
+    if ((e = enqueue_iteration(c, c->have_events, timing ? &tm : nullptr, &where)) != hipSuccess)
+      return hip_fail(e, where);
     double dn = 0.0, mu = 0.0;
     if ((e = hipMemcpyAsync(&dn, c->dnorm, sizeof(double), hipMemcpyDeviceToHost, c->s)) != hipSuccess) return hip_fail(e, "norm copy");
     if ((e = hipMemcpyAsync(&mu, c->mu, sizeof(double), hipMemcpyDeviceToHost, c->s)) != hipSuccess) return hip_fail(e, "mu copy");
@@ -456,6 +480,75 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
   }
   if (iters_done) *iters_done = done;
   if (converged) *converged = conv;
+  return st;
+}
+
+pq_status parquet_iterate_batch(pq_ctx* const* ctxs, int32_t count, int32_t n_iter, double tol,
+                                int32_t* iters_done, int32_t* converged) {
+  PQ_CHECK_ARG(ctxs && count >= 0 && n_iter >= 0, "bad batch arguments");
+  for (int i = 0; i < count; ++i) {
+    PQ_CHECK_ARG(ctxs[i], "null context %d", i);
+    PQ_CHECK_ARG(ctxs[i]->s != nullptr, "context %d has the null stream (graphs need a created stream)", i);
+    for (int j = 0; j < i; ++j)
+      PQ_CHECK_ARG(ctxs[j] != ctxs[i] && ctxs[j]->s != ctxs[i]->s, "contexts %d and %d share a stream", j, i);
+  }
+  for (int i = 0; i < count; ++i) {
+    pq_ctx* c = ctxs[i];
+    if (c->have_graph && c->graph_has_lam != c->has_lam) {
+      hipGraphExecDestroy(c->graph);
+      c->have_graph = false;
+    }
+    if (!c->have_graph) {
+      hipGraph_t g = nullptr;
+      const char* where = nullptr;
+      hipError_t e = hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "graph capture (begin)");
+      hipError_t ei = enqueue_iteration(c, false, nullptr, &where);
+      e = hipStreamEndCapture(c->s, &g);
+      if (ei != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return hip_fail(ei, where);
+      }
+      if (e != hipSuccess) return hip_fail(e, "graph capture (end)");
+      e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+      c->have_graph = true;
+      c->graph_has_lam = c->has_lam;
+    }
+    if (iters_done) iters_done[i] = 0;
+    if (converged) converged[i] = 0;
+  }
+  std::vector<char> active(count, 1);
+  std::vector<double> dn(count, 0.0);
+  pq_status st = PQ_OK;
+  for (int it = 0; it < n_iter; ++it) {
+    bool any = false;
+    for (int i = 0; i < count; ++i) {
+      if (!active[i]) continue;
+      any = true;
+      hipError_t e = hipGraphLaunch(ctxs[i]->graph, ctxs[i]->s);
+      if (e != hipSuccess) return hip_fail(e, "graph launch");
+    }
+    if (!any) break;
+    for (int i = 0; i < count; ++i) {
+      if (!active[i]) continue;
+      pq_ctx* c = ctxs[i];
+      hipError_t e = hipMemcpyAsync(&dn[i], c->dnorm, sizeof(double), hipMemcpyDeviceToHost, c->s);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+      if (e != hipSuccess) return hip_fail(e, "batch iteration");
+      c->iteration++;
+      if (iters_done) iters_done[i]++;
+      if (!(dn[i] == dn[i])) {
+        set_error("non-finite self-energy in context %d at iteration %d", i, c->iteration);
+        st = PQ_ERR_NONFINITE;
+        active[i] = 0;
+      } else if (tol > 0.0 && dn[i] < tol) {
+        if (converged) converged[i] = 1;
+        active[i] = 0;
+      }
+    }
+  }
   return st;
 }
 
@@ -517,6 +610,7 @@ pq_status parquet_copy_state(pq_ctx* dst, pq_ctx* src) {
 
 pq_status parquet_destroy(pq_ctx* c) {
   if (!c) return PQ_OK;
+  if (c->have_graph) hipGraphExecDestroy(c->graph);
   if (c->have_events)
     for (int i = 0; i < 8; ++i) hipEventDestroy(c->ev[i]);
   if (c->have_bev)

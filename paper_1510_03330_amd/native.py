@@ -30,7 +30,7 @@ EXPORTS = [
     "pq_dims_from_params", "parquet_last_error", "dyson_update", "bubble_build", "kernel_extract",
     "channel_remap", "sigma_sde_workspace", "sigma_sde", "bse_workspace", "bse_solve", "sigma_mix",
     "parquet_query_workspace", "parquet_init", "parquet_iterate", "parquet_get", "parquet_set",
-    "parquet_field_bytes", "parquet_copy_state", "parquet_destroy",
+    "parquet_field_bytes", "parquet_copy_state", "parquet_iterate_batch", "parquet_destroy",
 ]
 
 
@@ -108,6 +108,8 @@ def load() -> ctypes.CDLL:
         "parquet_set": [c_void_p, c_int32, c_void_p, c_size_t],
         "parquet_field_bytes": [c_void_p, c_int32, POINTER(c_size_t)],
         "parquet_copy_state": [c_void_p, c_void_p],
+        "parquet_iterate_batch": [POINTER(c_void_p), c_int32, c_int32, c_double, POINTER(c_int32),
+                                  POINTER(c_int32)],
         "parquet_destroy": [c_void_p],
     }
     for name, args in sig.items():

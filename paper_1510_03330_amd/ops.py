@@ -138,6 +138,8 @@ class Solver:
         b = ctypes.c_size_t()
         N.check(lib.parquet_query_workspace(self.stage._pp(), ctypes.byref(b)))
         self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+        if stream is not None:
+            self.ws.record_stream(stream)      # the context's work runs on its own stream
         ctx = ctypes.c_void_p()
         N.check(lib.parquet_init(self.stage._pp(), ctypes.c_void_p(self.ws.data_ptr()), b,
                                  _stream(stream), ctypes.byref(ctx)))
@@ -197,6 +199,110 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def iterate_batch(solvers, n_iter: int, tol: float = 0.0):
+    """Iterate several solvers concurrently (parquet_iterate_batch): each must
+    own a created stream (Solver(..., stream=torch.cuda.Stream())). Returns the
+    per-solver (iterations done, converged) lists."""
+    n = len(solvers)
+    arr = (ctypes.c_void_p * n)(*[s.ctx.value for s in solvers])
+    done = (ctypes.c_int32 * n)()
+    conv = (ctypes.c_int32 * n)()
+    st = N.load().parquet_iterate_batch(arr, n, int(n_iter), float(tol), done, conv)
+    if st not in (N.PQ_OK, N.PQ_ERR_NONFINITE):
+        N.check(st)
+    return [int(x) for x in done], [bool(x) for x in conv]
+
+
+class BatchRunner:
+    """Solve many parquet instances to convergence on one device.
+
+    Instances run concurrently, each in its own context and stream with its
+    iteration captured in a graph (parquet_iterate_batch); at most `width` at a
+    time and within `mem_budget` bytes of workspace, new instances starting as
+    others finish. `autotune` picks the width from `widths` by timing a few
+    batched iterations of copies of the median instance (instance-iterations
+    per second) before the run."""
+
+    def __init__(self, params, precision: str = "fp32", device: str = "cuda:0",
+                 mem_budget: float = 200e9, widths=(1, 2, 4, 8, 16, 32)):
+        self.params = list(params)
+        self.precision = precision
+        self.device = device
+        self.mem_budget = float(mem_budget)
+        self.widths = tuple(widths)
+        self.width = None
+        self.tuning = {}
+
+    def _bytes(self, p):
+        b = ctypes.c_size_t()
+        N.check(N.load().parquet_query_workspace(ctypes.byref(N.make_params(p, self.precision)), ctypes.byref(b)))
+        return int(b.value)
+
+    def autotune(self, probe_iters: int = 3):
+        import time
+        sizes = sorted((self._bytes(p), i) for i, p in enumerate(self.params))
+        p_med = self.params[sizes[len(sizes) // 2][1]]
+        nb = self._bytes(p_med)
+        best = None
+        for w in self.widths:
+            if w > len(self.params) or w * nb > self.mem_budget:
+                break
+            solvers = [Solver(p_med, self.precision, self.device, stream=torch.cuda.Stream(self.device))
+                       for _ in range(w)]
+            iterate_batch(solvers, 1)                       # graph capture + first replay
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            iterate_batch(solvers, probe_iters)
+            torch.cuda.synchronize()
+            rate = w * probe_iters / (time.perf_counter() - t0)
+            self.tuning[w] = rate
+            for s in solvers:
+                s.close()
+            del solvers
+            torch.cuda.empty_cache()
+            if best is None or rate > self.tuning[best]:
+                best = w
+        self.width = best or 1
+        return self.width
+
+    def run(self, tol: float = 1e-6, max_iter: int = 200, chunk: int = 5):
+        """Returns one record per instance: iterations, converged, seconds from
+        its start to its end (wall, shared with the instances beside it)."""
+        import time
+        width = self.width or self.autotune()
+        pending = list(range(len(self.params)))
+        active = []                 # (index, solver, start time, iterations)
+        out = [None] * len(self.params)
+        used = 0.0
+        t_all = time.perf_counter()
+        while pending or active:
+            while pending and len(active) < width:
+                i = pending[0]
+                nb = self._bytes(self.params[i])
+                if active and used + nb > self.mem_budget:
+                    break
+                pending.pop(0)
+                s = Solver(self.params[i], self.precision, self.device, stream=torch.cuda.Stream(self.device))
+                active.append([i, s, time.perf_counter(), 0, nb])
+                used += nb
+            done, conv = iterate_batch([a[1] for a in active], chunk, tol)
+            keep = []
+            for a, d, c in zip(active, done, conv):
+                a[3] += d
+                finished = c or a[3] >= max_iter or d < chunk
+                if finished:
+                    sig = a[1].get("sigma")
+                    out[a[0]] = dict(iterations=a[3], converged=bool(c), sec=time.perf_counter() - a[2],
+                                     finite=bool(torch.isfinite(torch.view_as_real(sig)).all()))
+                    a[1].close()
+                    used -= a[4]
+                else:
+                    keep.append(a)
+            active = keep
+            torch.cuda.empty_cache()
+        return out, time.perf_counter() - t_all
 
 
 def converge_mixed(p, tol: float = 1e-6, switch_tol: float = 1e-5, max_iter: int = 200,
