@@ -269,6 +269,59 @@ def kernel_study(max_iter: int = 600, tol: float = 1e-8, chunk: int = 10):
     return out
 
 
+def batch_study(tol: float = 1e-6, max_iter: int = 150):
+    """Many small instances on one GPU: 64 instances of the 4x4 lattice (t = 1,
+    t' = 0, half filling) with Nv in {8, 16, 24, 32} (n = 128..512) and
+    U in {1, 1.5, 2, 2.5} x beta in {2, 3, 4, 5}, complex64/FP32 path, each
+    iterated from the bare-vertex start to max|dSigma| < tol. Batched: graph
+    replay of many contexts at once (BatchRunner, width autotuned); serial:
+    the same instances one after another with parquet_iterate."""
+    import torch
+    from paper_1510_03330_amd.ops import BatchRunner, Solver
+    from workloads import config
+
+    params = [config("c2", Nv=nv, U=u, beta=b) for nv in (8, 16, 24, 32) for u in (1.0, 1.5, 2.0, 2.5)
+              for b in (2.0, 3.0, 4.0, 5.0)]
+    runner = BatchRunner(params, precision="fp32", mem_budget=200e9, widths=(1, 2, 4, 8, 16, 32))
+    print("[batch] autotune", file=sys.stderr, flush=True)
+    width = runner.autotune()
+    print(f"[batch] width {width}: batched run", file=sys.stderr, flush=True)
+    recs, t_batch = runner.run(tol=tol, max_iter=max_iter)
+    iters = sum(r["iterations"] for r in recs)
+    print("[batch] serial run", file=sys.stderr, flush=True)
+    from paper_1510_03330_amd.native import ParquetError
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    serial_iters = 0
+    for p, r in zip(params, recs):          # the same iterations, one instance after another
+        s = Solver(p, "fp32", device="cuda:0")
+        try:
+            done, conv, _ = s.iterate(r["iterations"], tol)
+        except ParquetError:                # the instance diverged (non-finite Sigma)
+            done = r["iterations"]
+        serial_iters += done
+        s.close()
+        del s
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    by_nv = {}
+    for p, r in zip(params, recs):
+        e = by_nv.setdefault(p.Nv, {"instances": 0, "converged": 0, "diverged": 0, "iterations": 0})
+        e["instances"] += 1
+        e["converged"] += int(r["converged"])
+        e["diverged"] += int(not r["finite"])
+        e["iterations"] += r["iterations"]
+    return {"mode": "batch", "workload": "64 instances, 4x4 lattice, Nv 8/16/24/32, U 1..2.5, beta 2..5, fp32",
+            "tol": tol, "max_iter": max_iter, "width": width,
+            "autotune_instance_iterations_per_s": {str(k): round(v, 2) for k, v in runner.tuning.items()},
+            "batched_sec": round(t_batch, 3), "batched_instance_iterations": iters,
+            "batched_instance_iterations_per_s": round(iters / t_batch, 2),
+            "serial_sec": round(t_serial, 3), "serial_instance_iterations": serial_iters,
+            "speedup_vs_serial": round(t_serial / t_batch, 3),
+            "converged": sum(int(r["converged"]) for r in recs), "by_nv": by_nv}
+
+
 class _VirtualVertex:
     """Deterministic pseudo-random stand-in for a [4][Nq][n][n] vertex too large
     for host memory; supports the fancy indexing the oracle uses."""
@@ -355,6 +408,8 @@ def main():
                     help="skip the 4x4 Nv=16 BSE microbenchmark")
     ap.add_argument("--study", action="store_true",
                     help="run only the kernel-level / regulation / U-range study (one JSON line)")
+    ap.add_argument("--batch", action="store_true",
+                    help="run only the 64-instance batched-solver study (one JSON line)")
     ap.add_argument("--no-ttc", action="store_true",
                     help="skip the time-to-converged-Sigma (1e-6) runs of both paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -369,6 +424,9 @@ def main():
 
     if args.study:
         print(json.dumps(kernel_study()))
+        return
+    if args.batch:
+        print(json.dumps(batch_study()))
         return
     from workloads import config
     p = config(args.workload)

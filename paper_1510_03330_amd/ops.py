@@ -201,9 +201,41 @@ class Solver:
             pass
 
 
+_hip = None
+_stream_pool = {}     # device -> streams not bound to a context
+
+
+def new_stream(device: str = "cuda:0"):
+    """A stream of its own for one context (hipStreamCreate, default priority),
+    wrapped for torch; torch.cuda.Stream() draws from a small recycled pool, so
+    two of those can be the same stream. Streams are never destroyed: a
+    tensor recorded on a stream (the context workspace) makes torch's
+    allocator record an event on that stream when the tensor is freed, which
+    may happen after the context is gone. release_stream returns one for reuse."""
+    global _hip
+    pool = _stream_pool.setdefault(str(device), [])
+    if pool:
+        return pool.pop()
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipStreamCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        _hip.hipStreamCreate.restype = ctypes.c_int
+    with torch.cuda.device(device):
+        h = ctypes.c_void_p()
+        if _hip.hipStreamCreate(ctypes.byref(h)) != 0:
+            raise RuntimeError("hipStreamCreate failed")
+        return torch.cuda.ExternalStream(h.value, device=torch.device(device))
+
+
+def release_stream(stream):
+    """Give a stream from new_stream back once no context uses it."""
+    stream.synchronize()
+    _stream_pool.setdefault(str(stream.device), []).append(stream)
+
+
 def iterate_batch(solvers, n_iter: int, tol: float = 0.0):
     """Iterate several solvers concurrently (parquet_iterate_batch): each must
-    own a created stream (Solver(..., stream=torch.cuda.Stream())). Returns the
+    own a stream of its own (Solver(..., stream=new_stream())). Returns the
     per-solver (iterations done, converged) lists."""
     n = len(solvers)
     arr = (ctypes.c_void_p * n)(*[s.ctx.value for s in solvers])
@@ -249,8 +281,8 @@ class BatchRunner:
         for w in self.widths:
             if w > len(self.params) or w * nb > self.mem_budget:
                 break
-            solvers = [Solver(p_med, self.precision, self.device, stream=torch.cuda.Stream(self.device))
-                       for _ in range(w)]
+            streams = [new_stream(self.device) for _ in range(w)]
+            solvers = [Solver(p_med, self.precision, self.device, stream=st) for st in streams]
             iterate_batch(solvers, 1)                       # graph capture + first replay
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -258,10 +290,12 @@ class BatchRunner:
             torch.cuda.synchronize()
             rate = w * probe_iters / (time.perf_counter() - t0)
             self.tuning[w] = rate
-            for s in solvers:
-                s.close()
-            del solvers
+            for sv in solvers:
+                sv.close()
+            del solvers, sv
             torch.cuda.empty_cache()
+            for st in streams:
+                release_stream(st)
             if best is None or rate > self.tuning[best]:
                 best = w
         self.width = best or 1
@@ -284,8 +318,9 @@ class BatchRunner:
                 if active and used + nb > self.mem_budget:
                     break
                 pending.pop(0)
-                s = Solver(self.params[i], self.precision, self.device, stream=torch.cuda.Stream(self.device))
-                active.append([i, s, time.perf_counter(), 0, nb])
+                st = new_stream(self.device)
+                s = Solver(self.params[i], self.precision, self.device, stream=st)
+                active.append([i, s, time.perf_counter(), 0, nb, st])
                 used += nb
             done, conv = iterate_batch([a[1] for a in active], chunk, tol)
             keep = []
@@ -297,7 +332,9 @@ class BatchRunner:
                     out[a[0]] = dict(iterations=a[3], converged=bool(c), sec=time.perf_counter() - a[2],
                                      finite=bool(torch.isfinite(torch.view_as_real(sig)).all()))
                     a[1].close()
+                    a[1] = None
                     used -= a[4]
+                    release_stream(a[5])
                 else:
                     keep.append(a)
             active = keep

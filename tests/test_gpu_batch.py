@@ -26,8 +26,8 @@ def _ops():
 
 def _pair(p, prec):
     ops = _ops()
-    a = ops.Solver(p, prec, DEV, stream=torch.cuda.Stream(DEV))
-    b = ops.Solver(p, prec, DEV, stream=torch.cuda.Stream(DEV))
+    a = ops.Solver(p, prec, DEV, stream=ops.new_stream(DEV))
+    b = ops.Solver(p, prec, DEV, stream=ops.new_stream(DEV))
     return a, b
 
 
@@ -60,8 +60,8 @@ def test_concurrent_batch_of_different_boxes_matches_one_by_one():
     print("CASE batch of boxes", flush=True)
     ops = _ops()
     ps = [config("tiny_2x2"), config("small_2x4", U=1.2), config("tiny_local"), config("small_4x4", Nv=6)]
-    batch = [ops.Solver(p, "fp64", DEV, stream=torch.cuda.Stream(DEV)) for p in ps]
-    single = [ops.Solver(p, "fp64", DEV, stream=torch.cuda.Stream(DEV)) for p in ps]
+    batch = [ops.Solver(p, "fp64", DEV, stream=ops.new_stream(DEV)) for p in ps]
+    single = [ops.Solver(p, "fp64", DEV, stream=ops.new_stream(DEV)) for p in ps]
     done, conv = ops.iterate_batch(batch, 4)
     assert done == [4] * len(ps)
     for s in single:
