@@ -210,6 +210,41 @@ pq_status bse_solve(const pq_params* p, int32_t channel, int32_t precision,
 pq_status sigma_mix(const pq_params* p, const void* sigma_new, void* sigma_io,
                     double alpha, void* dnorm_out, pq_stream stream);
 
+/* ------------------------------------------------------ learned warm start */
+
+/* Second-level kernel approximation of the reducible vertex on the whole box
+ * (Sec. "Two-level kernel approximations"): phi_out_r(q; k, k') = K1_r(q) +
+ * K2_r(k; q) + K2_r(k'; q), from k1 [4][Nq] and k2 [4][Nq][n] complex128;
+ * phi_out [4][Nq][n][n] in the storage precision of p. Used to start the
+ * iteration from predicted kernel functions instead of the bare vertex. */
+pq_status phi_from_kernels(const pq_params* p, const void* k1, const void* k2, void* phi_out,
+                           pq_stream stream);
+
+/* A multilayer perceptron x [batch][w0] -> tanh hidden layers -> linear output
+ * [batch][w_L] (widths: n_layers + 1 host ints). Parameters: params (float)
+ * packed layer by layer as [W_l (w_{l+1} x w_l, row-major), b_l (w_{l+1})],
+ * mlp_param_count entries, and params_bf16, the same array rounded to bf16
+ * (to nearest even; the products use the bf16 weights, biases, activations and
+ * accumulation are FP32). acts: device floats, batch * (w_1 + ... + w_L), the
+ * outputs of every layer, the network output last. Used for the learned warm
+ * start, model parameters -> kernel functions (an addition to the paper's
+ * method, which starts from the bare vertex). */
+pq_status mlp_param_count(const int32_t* widths, int32_t n_layers, size_t* count);
+pq_status mlp_forward(const int32_t* widths, int32_t n_layers, const void* params_bf16, const float* params,
+                      const float* x, float* acts, int32_t batch, pq_stream stream);
+/* Gradient of the mean squared error between the output (last block of acts,
+ * from mlp_forward) and target [batch][w_L] with respect to params (grad:
+ * same layout; the weight gradient is taken at the bf16 weights), and the loss
+ * itself (one device float). scratch: 2 * batch * max(widths) floats. */
+pq_status mlp_backward(const int32_t* widths, int32_t n_layers, const void* params_bf16, const float* x,
+                       const float* acts, const float* target, float* grad, float* loss, float* scratch,
+                       int32_t batch, pq_stream stream);
+/* One bias-corrected Adam step (step counts from 1) on params with moments m,
+ * v (count floats each), refreshing params_bf16; mlp_to_bf16 only refreshes it. */
+pq_status mlp_adam(float* params, void* params_bf16, float* m, float* v, const float* grad, size_t count,
+                   float lr, float beta1, float beta2, float eps, int32_t step, pq_stream stream);
+pq_status mlp_to_bf16(const float* params, void* params_bf16, size_t count, pq_stream stream);
+
 /* ------------------------------------------------------------ context API */
 
 typedef struct pq_ctx pq_ctx;

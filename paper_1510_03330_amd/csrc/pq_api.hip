@@ -203,6 +203,59 @@ pq_status sigma_mix(const pq_params* p, const void* sigma_new, void* sigma_io, d
              "sigma_mix");
 }
 
+// ------------------------------------------------------ learned warm start
+static bool mlp_widths_ok(const int32_t* w, int32_t nl) {
+  if (!w || nl < 1 || nl > 16) return false;
+  for (int l = 0; l <= nl; ++l)
+    if (w[l] < 1 || w[l] > 65536) return false;
+  return true;
+}
+
+pq_status mlp_param_count(const int32_t* widths, int32_t n_layers, size_t* count) {
+  PQ_CHECK_ARG(mlp_widths_ok(widths, n_layers) && count, "bad widths or null output");
+  *count = mlp_count(widths, n_layers);
+  return PQ_OK;
+}
+
+pq_status mlp_forward(const int32_t* widths, int32_t n_layers, const void* params_bf16, const float* params,
+                      const float* x, float* acts, int32_t batch, pq_stream stream) {
+  PQ_CHECK_ARG(mlp_widths_ok(widths, n_layers) && batch >= 1, "bad widths or batch");
+  PQ_CHECK_ARG(params_bf16 && params && x && acts, "null pointer");
+  return enq(launch_mlp_forward(widths, n_layers, params_bf16, params, x, acts, batch, (hipStream_t)stream),
+             "mlp_forward");
+}
+
+pq_status mlp_backward(const int32_t* widths, int32_t n_layers, const void* params_bf16, const float* x,
+                       const float* acts, const float* target, float* grad, float* loss, float* scratch,
+                       int32_t batch, pq_stream stream) {
+  PQ_CHECK_ARG(mlp_widths_ok(widths, n_layers) && batch >= 1, "bad widths or batch");
+  PQ_CHECK_ARG(params_bf16 && x && acts && target && grad && loss && scratch, "null pointer");
+  return enq(launch_mlp_backward(widths, n_layers, params_bf16, x, acts, target, grad, loss, scratch, batch,
+                                 (hipStream_t)stream),
+             "mlp_backward");
+}
+
+pq_status mlp_adam(float* params, void* params_bf16, float* m, float* v, const float* grad, size_t count, float lr,
+                   float beta1, float beta2, float eps, int32_t step, pq_stream stream) {
+  PQ_CHECK_ARG(params && params_bf16 && m && v && grad && count > 0, "null pointer or empty");
+  PQ_CHECK_ARG(step >= 1 && lr > 0.f && beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f, "bad Adam settings");
+  return enq(launch_mlp_adam(params, params_bf16, m, v, grad, count, lr, beta1, beta2, eps, step, (hipStream_t)stream),
+             "mlp_adam");
+}
+
+pq_status mlp_to_bf16(const float* params, void* params_bf16, size_t count, pq_stream stream) {
+  PQ_CHECK_ARG(params && params_bf16 && count > 0, "null pointer or empty");
+  return enq(launch_mlp_to_bf16(params, params_bf16, count, (hipStream_t)stream), "mlp_to_bf16");
+}
+
+pq_status phi_from_kernels(const pq_params* p, const void* k1, const void* k2, void* phi_out, pq_stream stream) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(k1 && k2 && phi_out, "null pointer");
+  return enq(launch_phi_from_kernels(*p, d, (const double2*)k1, (const double2*)k2, phi_out, (hipStream_t)stream),
+             "phi_from_kernels");
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------- context API

@@ -40,6 +40,18 @@ hipError_t launch_kernel_extract(const pq_params& p, const Dims& d, const void* 
 hipError_t launch_remap(const pq_params& p, const Dims& d, const double lam[4], const double2* lam_box,
                         const void* phi, const double2* k1, const double2* k2, void* gamma, hipStream_t s);
 hipError_t launch_lambda_fill(const Dims& d, double U, double2* lam_box, hipStream_t s);
+// learned warm start (pq_mlp.hip)
+size_t mlp_count(const int32_t* widths, int n_layers);
+hipError_t launch_mlp_forward(const int32_t* widths, int n_layers, const void* params_bf16, const float* params,
+                              const float* x, float* acts, int batch, hipStream_t s);
+hipError_t launch_mlp_backward(const int32_t* widths, int n_layers, const void* params_bf16, const float* x,
+                               const float* acts, const float* target, float* grad, float* loss, float* scratch,
+                               int batch, hipStream_t s);
+hipError_t launch_mlp_adam(float* params, void* params_bf16, float* m, float* v, const float* grad, size_t count,
+                           float lr, float beta1, float beta2, float eps, int step, hipStream_t s);
+hipError_t launch_mlp_to_bf16(const float* params, void* params_bf16, size_t count, hipStream_t s);
+hipError_t launch_phi_from_kernels(const pq_params& p, const Dims& d, const double2* k1, const double2* k2,
+                                   void* phi, hipStream_t s);
 size_t sigma_ws_bytes(const Dims& d);
 hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, const double2* k1,
                         const double2* k2, const double2* lam_box, const double2* g, const double* mu,

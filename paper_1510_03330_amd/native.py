@@ -31,6 +31,7 @@ EXPORTS = [
     "channel_remap", "sigma_sde_workspace", "sigma_sde", "bse_workspace", "bse_solve", "sigma_mix",
     "parquet_query_workspace", "parquet_init", "parquet_iterate", "parquet_get", "parquet_set",
     "parquet_field_bytes", "parquet_copy_state", "parquet_iterate_batch", "parquet_destroy",
+    "phi_from_kernels", "mlp_param_count", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_to_bf16",
 ]
 
 
@@ -110,6 +111,14 @@ def load() -> ctypes.CDLL:
         "parquet_copy_state": [c_void_p, c_void_p],
         "parquet_iterate_batch": [POINTER(c_void_p), c_int32, c_int32, c_double, POINTER(c_int32),
                                   POINTER(c_int32)],
+        "phi_from_kernels": [P, c_void_p, c_void_p, c_void_p, c_void_p],
+        "mlp_param_count": [POINTER(c_int32), c_int32, POINTER(c_size_t)],
+        "mlp_forward": [POINTER(c_int32), c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p],
+        "mlp_backward": [POINTER(c_int32), c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                         c_void_p, c_int32, c_void_p],
+        "mlp_adam": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, ctypes.c_float, ctypes.c_float,
+                     ctypes.c_float, ctypes.c_float, c_int32, c_void_p],
+        "mlp_to_bf16": [c_void_p, c_void_p, c_size_t, c_void_p],
         "parquet_destroy": [c_void_p],
     }
     for name, args in sig.items():

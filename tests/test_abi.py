@@ -19,7 +19,7 @@ HEADER = os.path.join(ROOT, "include", "parquet.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\*?\s+\*?([a-z_]+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\*?\s+\*?([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
