@@ -322,6 +322,66 @@ def batch_study(tol: float = 1e-6, max_iter: int = 150):
             "converged": sum(int(r["converged"]) for r in recs), "by_nv": by_nv}
 
 
+def warmstart_study(tol: float = 1e-6, max_iter: int = 400):
+    """Learned warm start on the momentum-independent problem (semicircle bath,
+    D = 2, half filling, Nv = 16, alpha = 0.5): converged kernel functions of
+    a 12 x 12 grid U in [0.5, 1.5] x beta in [2, 5] (complex128, to 1e-8)
+    train a 2 -> 3 x 512 -> (K1, K2) perceptron on the GPU; 24 seeded held-out
+    (U, beta) are then solved to tol from the bare vertex and from the vertex
+    rebuilt from the predicted kernels, in complex128."""
+    import numpy as np
+    import torch
+    from paper_1510_03330_amd import warmstart as W
+    from paper_1510_03330_amd.ops import Solver
+    from workloads import config
+
+    base = config("c1", Nv=16, beta=2.0, D=2.0, alpha=0.5)
+    grid = [base.replace(U=float(u), beta=float(b)) for u in np.linspace(0.5, 1.5, 12)
+            for b in np.linspace(2.0, 5.0, 12)]
+    print("[warmstart] training data", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ps, k1s, k2s, dropped = [], [], [], 0
+    for p in grid:
+        conv, it, k1, k2 = W.converged_kernels(p, "fp64", tol=1e-8, max_iter=600)
+        if conv:
+            ps.append(p), k1s.append(k1), k2s.append(k2)
+        else:
+            dropped += 1
+    t_data = time.perf_counter() - t0
+    print(f"[warmstart] {len(ps)} samples; training", file=sys.stderr, flush=True)
+    pred = W.KernelPredictor(base, hidden=(512, 512, 512), seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = pred.fit(ps, k1s, k2s, steps=3000, batch=64, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rng = np.random.default_rng(10000)
+    held = [base.replace(U=float(rng.uniform(0.55, 1.45)), beta=float(rng.uniform(2.1, 4.9))) for _ in range(24)]
+    print("[warmstart] held-out solves", file=sys.stderr, flush=True)
+    rows = []
+    for p in held:
+        k1, k2 = pred.predict(p)
+        warm = W.solve_timed(p, "fp64", tol, max_iter, warm=(k1, k2))
+        bare = W.solve_timed(p, "fp64", tol, max_iter)
+        rows.append(dict(U=p.U, beta=p.beta, bare=bare, warm=warm))
+    it_b = np.array([r["bare"]["iterations"] for r in rows])
+    it_w = np.array([r["warm"]["iterations"] for r in rows])
+    s_b = sum(r["bare"]["sec"] for r in rows)
+    s_w = sum(r["warm"]["sec"] for r in rows)
+    return {"mode": "warmstart", "workload": "local model, semicircle bath D=2, half filling, Nv=16, alpha=0.5",
+            "network": "2 -> 512 -> 512 -> 512 -> %d (tanh, bf16 weights, FP32 accumulate)" % pred.nout,
+            "train_samples": len(ps), "train_dropped_not_converged": dropped, "data_sec": round(t_data, 2),
+            "train_steps": 3000, "train_sec": round(t_train, 2), "loss_first_last": [hist[0][1], hist[-1][1]],
+            "held_out": len(rows), "tol": tol,
+            "iterations_bare_mean": float(it_b.mean()), "iterations_warm_mean": float(it_w.mean()),
+            "iterations_ratio_mean": float((it_w / it_b).mean()),
+            "sec_bare_total": round(s_b, 3), "sec_warm_total": round(s_w, 3),
+            "all_converged": bool(all(r["warm"]["converged"] and r["bare"]["converged"] for r in rows)),
+            "fallbacks": int(sum(r["warm"]["fallback"] for r in rows)),
+            "cases": [{"U": round(r["U"], 4), "beta": round(r["beta"], 4), "bare": r["bare"]["iterations"],
+                       "warm": r["warm"]["iterations"]} for r in rows]}
+
+
 class _VirtualVertex:
     """Deterministic pseudo-random stand-in for a [4][Nq][n][n] vertex too large
     for host memory; supports the fancy indexing the oracle uses."""
@@ -410,6 +470,8 @@ def main():
                     help="run only the kernel-level / regulation / U-range study (one JSON line)")
     ap.add_argument("--batch", action="store_true",
                     help="run only the 64-instance batched-solver study (one JSON line)")
+    ap.add_argument("--warmstart", action="store_true",
+                    help="run only the learned warm-start study (one JSON line)")
     ap.add_argument("--no-ttc", action="store_true",
                     help="skip the time-to-converged-Sigma (1e-6) runs of both paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -427,6 +489,9 @@ def main():
         return
     if args.batch:
         print(json.dumps(batch_study()))
+        return
+    if args.warmstart:
+        print(json.dumps(warmstart_study()))
         return
     from workloads import config
     p = config(args.workload)
