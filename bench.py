@@ -326,9 +326,10 @@ def warmstart_study(tol: float = 1e-6, max_iter: int = 400):
     """Learned warm start on the momentum-independent problem (semicircle bath,
     D = 2, half filling, Nv = 16, alpha = 0.5): converged kernel functions of
     a 12 x 12 grid U in [0.5, 1.5] x beta in [2, 5] (complex128, to 1e-8)
-    train a 2 -> 3 x 512 -> (K1, K2) perceptron on the GPU; 24 seeded held-out
+    train a 2 -> 3 x 512 -> (K1, K2, Sigma) perceptron on the GPU; 24 seeded held-out
     (U, beta) are then solved to tol from the bare vertex and from the vertex
-    rebuilt from the predicted kernels, in complex128."""
+    rebuilt from the predicted kernels with the predicted self-energy (and,
+    for comparison, with the bare self-energy), in complex128."""
     import numpy as np
     import torch
     from paper_1510_03330_amd import warmstart as W
@@ -340,11 +341,11 @@ def warmstart_study(tol: float = 1e-6, max_iter: int = 400):
             for b in np.linspace(2.0, 5.0, 12)]
     print("[warmstart] training data", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    ps, k1s, k2s, dropped = [], [], [], 0
+    ps, k1s, k2s, sigs, dropped = [], [], [], [], 0
     for p in grid:
-        conv, it, k1, k2 = W.converged_kernels(p, "fp64", tol=1e-8, max_iter=600)
+        conv, it, k1, k2, sig = W.converged_kernels(p, "fp64", tol=1e-8, max_iter=600)
         if conv:
-            ps.append(p), k1s.append(k1), k2s.append(k2)
+            ps.append(p), k1s.append(k1), k2s.append(k2), sigs.append(sig)
         else:
             dropped += 1
     t_data = time.perf_counter() - t0
@@ -352,7 +353,7 @@ def warmstart_study(tol: float = 1e-6, max_iter: int = 400):
     pred = W.KernelPredictor(base, hidden=(512, 512, 512), seed=0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = pred.fit(ps, k1s, k2s, steps=3000, batch=64, lr=1e-3)
+    hist = pred.fit(ps, k1s, k2s, sigs, steps=3000, batch=64, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     rng = np.random.default_rng(10000)
@@ -360,21 +361,24 @@ def warmstart_study(tol: float = 1e-6, max_iter: int = 400):
     print("[warmstart] held-out solves", file=sys.stderr, flush=True)
     rows = []
     for p in held:
-        k1, k2 = pred.predict(p)
-        warm = W.solve_timed(p, "fp64", tol, max_iter, warm=(k1, k2))
+        k1, k2, sig = pred.predict(p)
+        warm = W.solve_timed(p, "fp64", tol, max_iter, warm=(k1, k2, sig))
+        warm_phi = W.solve_timed(p, "fp64", tol, max_iter, warm=(k1, k2))
         bare = W.solve_timed(p, "fp64", tol, max_iter)
-        rows.append(dict(U=p.U, beta=p.beta, bare=bare, warm=warm))
+        rows.append(dict(U=p.U, beta=p.beta, bare=bare, warm=warm, warm_phi=warm_phi))
     it_b = np.array([r["bare"]["iterations"] for r in rows])
     it_w = np.array([r["warm"]["iterations"] for r in rows])
+    it_p = np.array([r["warm_phi"]["iterations"] for r in rows])
     s_b = sum(r["bare"]["sec"] for r in rows)
     s_w = sum(r["warm"]["sec"] for r in rows)
     return {"mode": "warmstart", "workload": "local model, semicircle bath D=2, half filling, Nv=16, alpha=0.5",
-            "network": "2 -> 512 -> 512 -> 512 -> %d (tanh, bf16 weights, FP32 accumulate)" % pred.nout,
+            "network": "2 -> 512 -> 512 -> 512 -> %d (K1, K2, Sigma; tanh, bf16 weights, FP32 accumulate)" % pred.nout,
             "train_samples": len(ps), "train_dropped_not_converged": dropped, "data_sec": round(t_data, 2),
             "train_steps": 3000, "train_sec": round(t_train, 2), "loss_first_last": [hist[0][1], hist[-1][1]],
             "held_out": len(rows), "tol": tol,
             "iterations_bare_mean": float(it_b.mean()), "iterations_warm_mean": float(it_w.mean()),
             "iterations_ratio_mean": float((it_w / it_b).mean()),
+            "iterations_warm_phi_only_mean": float(it_p.mean()),
             "sec_bare_total": round(s_b, 3), "sec_warm_total": round(s_w, 3),
             "all_converged": bool(all(r["warm"]["converged"] and r["bare"]["converged"] for r in rows)),
             "fallbacks": int(sum(r["warm"]["fallback"] for r in rows)),

@@ -92,8 +92,9 @@ class MLP:
 
 
 class KernelPredictor:
-    """(U, beta) -> K1 [4][Nq], K2 [4][Nq][n] for one box, with input scaling
-    and per-output standardisation fitted on the training set."""
+    """(U, beta) -> K1 [4][Nq], K2 [4][Nq][n] and the self-energy [Nve][Nk]
+    for one box, with input scaling and per-output standardisation fitted on
+    the training set."""
 
     def __init__(self, base, hidden=(512, 512, 512), device: str = "cuda:0", seed: int = 0):
         self.base = base
@@ -101,7 +102,8 @@ class KernelPredictor:
         d = self.stage.d
         self.nk1 = 4 * d.Nq
         self.nk2 = 4 * d.Nq * d.n
-        self.nout = 2 * (self.nk1 + self.nk2)
+        self.nsig = d.Nve * d.Nk
+        self.nout = 2 * (self.nk1 + self.nk2 + self.nsig)
         self.mlp = MLP([2, *hidden, self.nout], device, seed)
         self.device = torch.device(device)
 
@@ -112,12 +114,13 @@ class KernelPredictor:
         return (x - self.x_mean) / self.x_std
 
     @staticmethod
-    def _flat(k1, k2):
-        return torch.cat([torch.view_as_real(k1).reshape(-1), torch.view_as_real(k2).reshape(-1)])
+    def _flat(k1, k2, sig):
+        return torch.cat([torch.view_as_real(k1).reshape(-1), torch.view_as_real(k2).reshape(-1),
+                          torch.view_as_real(sig).reshape(-1)])
 
-    def fit(self, params, k1s, k2s, steps=3000, batch=64, lr=1e-3):
+    def fit(self, params, k1s, k2s, sigs, steps=3000, batch=64, lr=1e-3):
         x = self._x(params)
-        y = torch.stack([self._flat(a, b) for a, b in zip(k1s, k2s)]).to(torch.float64)
+        y = torch.stack([self._flat(a, b, c) for a, b, c in zip(k1s, k2s, sigs)]).to(torch.float64)
         self.x_mean, self.x_std = x.mean(0), x.std(0).clamp_min(1e-6)
         self.y_mean, self.y_std = y.mean(0), y.std(0).clamp_min(1e-12)
         X = self._scale_x(x)
@@ -129,9 +132,11 @@ class KernelPredictor:
         _, out = self.mlp.forward(X)
         y = out[0].to(torch.float64) * self.y_std + self.y_mean
         d = self.stage.d
-        k1 = torch.view_as_complex(y[:2 * self.nk1].reshape(-1, 2).contiguous()).reshape(4, d.Nq)
-        k2 = torch.view_as_complex(y[2 * self.nk1:].reshape(-1, 2).contiguous()).reshape(4, d.Nq, d.n)
-        return k1.contiguous(), k2.contiguous()
+        a, b = 2 * self.nk1, 2 * (self.nk1 + self.nk2)
+        k1 = torch.view_as_complex(y[:a].reshape(-1, 2).contiguous()).reshape(4, d.Nq)
+        k2 = torch.view_as_complex(y[a:b].reshape(-1, 2).contiguous()).reshape(4, d.Nq, d.n)
+        sig = torch.view_as_complex(y[b:].reshape(-1, 2).contiguous()).reshape(d.Nve, d.Nk)
+        return k1.contiguous(), k2.contiguous(), sig.contiguous()
 
 
 def phi_from_kernels(p, precision: str, k1: torch.Tensor, k2: torch.Tensor, phi_out: torch.Tensor):
@@ -142,23 +147,25 @@ def phi_from_kernels(p, precision: str, k1: torch.Tensor, k2: torch.Tensor, phi_
 
 
 def converged_kernels(p, precision: str = "fp64", tol: float = 1e-8, max_iter: int = 400):
-    """Solve from the bare start; returns (converged, iterations, K1, K2) of the
-    last iteration (the kernel functions of the converged vertex)."""
+    """Solve from the bare start; returns (converged, iterations, K1, K2, Sigma)
+    of the last iteration (the kernel functions of the converged vertex)."""
     s = Solver(p, precision)
     try:
         done, conv, _ = s.iterate(max_iter, tol)
     except N.ParquetError:
         s.close()
-        return False, max_iter, None, None
-    k1, k2 = s.get("k1"), s.get("k2")
+        return False, max_iter, None, None, None
+    k1, k2, sig = s.get("k1"), s.get("k2"), s.get("sigma")
     s.close()
-    return conv, done, k1, k2
+    return conv, done, k1, k2, sig
 
 
 def solve_timed(p, precision, tol, max_iter, warm=None):
     """Iterations and seconds to max|dSigma| < tol from the bare start, or from
-    the vertex rebuilt from predicted kernels (warm = (k1, k2)); a warm start
-    that does not converge is retried from the bare start (counted in both)."""
+    the vertex rebuilt from predicted kernels (warm = (k1, k2) or (k1, k2,
+    sigma), the latter also starting the self-energy from the prediction); a
+    warm start that does not converge is retried from the bare start (counted
+    in both)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = Solver(p, precision)
@@ -167,6 +174,8 @@ def solve_timed(p, precision, tol, max_iter, warm=None):
         phi_from_kernels(p, precision, warm[0], warm[1], phi)
         s.set("phi", phi)
         del phi
+        if len(warm) > 2:
+            s.set("sigma", warm[2])
     try:
         done, conv, _ = s.iterate(max_iter, tol)
     except N.ParquetError:

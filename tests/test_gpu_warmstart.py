@@ -87,17 +87,17 @@ def test_warm_start_pipeline_small():
     ws = _ws()
     base = config("tiny_local", Nv=8, alpha=0.5)
     train = [base.replace(U=u, beta=b) for u in (0.6, 0.8, 1.0, 1.2) for b in (2.0, 3.0, 4.0)]
-    k1s, k2s, ps = [], [], []
+    k1s, k2s, sigs, ps = [], [], [], []
     for p in train:
-        conv, it, k1, k2 = ws.converged_kernels(p, "fp64", tol=1e-9)
+        conv, it, k1, k2, sig = ws.converged_kernels(p, "fp64", tol=1e-9)
         assert conv
-        ps.append(p), k1s.append(k1), k2s.append(k2)
+        ps.append(p), k1s.append(k1), k2s.append(k2), sigs.append(sig)
     pred = ws.KernelPredictor(base, hidden=(64, 64), seed=0)
-    hist = pred.fit(ps, k1s, k2s, steps=400, batch=12, lr=3e-3)
+    hist = pred.fit(ps, k1s, k2s, sigs, steps=400, batch=12, lr=3e-3)
     assert hist[-1][1] < hist[0][1]
     held = base.replace(U=0.9, beta=2.5)
-    k1, k2 = pred.predict(held)
-    warm = ws.solve_timed(held, "fp64", 1e-9, 300, warm=(k1, k2))
+    k1, k2, sig = pred.predict(held)
+    warm = ws.solve_timed(held, "fp64", 1e-9, 300, warm=(k1, k2, sig))
     bare = ws.solve_timed(held, "fp64", 1e-9, 300)
     assert warm["converged"] and bare["converged"] and not warm["fallback"]
     from paper_1510_03330_amd.ops import Solver
