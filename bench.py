@@ -520,7 +520,8 @@ def main():
     ips3 = (r3["steps"] / r3["sec"]) if r3 else None
 
     # dominant kernel: the rank-NB update of the BSE (per launch: one panel step of
-    # all 960 blocks of a channel); flops = 8 per complex multiply-add it performs
+    # all 960 blocks of a channel, forward or back substitution); flops = 8 per
+    # complex multiply-add it performs, averaged over its launches
     n_upd = r32["kern_n"][3]
     upd_ms = r32["kern_ms"][3] / n_upd
     upd_flops = r32["upd_flops"] / n_upd
@@ -529,8 +530,9 @@ def main():
     bse_alg = bse_flops_per_launch(d) / (bse_channel_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(),
-            "kernel": "bse_update_kernel<float,128> (one launch = one rank-128 Gauss-Jordan panel update "
-                      "of %d blocks, n=%d)" % (d.Nq, d.n),
+            "kernel": "bse_update_kernel<float,128> (one launch = one rank-128 update of %d blocks, n=%d: "
+                      "the rows below a panel in the forward sweep or the rows above it in the back "
+                      "substitution)" % (d.Nq, d.n),
             "avg_launch_ms": round(upd_ms, 3), "flops_per_launch": upd_flops,
             "bse_solve_lu_equivalent_tflops": round(bse_alg, 2),
             "bse_solve_ms_per_channel": round(bse_channel_ms, 2),

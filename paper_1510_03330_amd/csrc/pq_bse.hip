@@ -3,10 +3,10 @@
 //     A F = Gamma,   A = 1 - s Gamma diag(X),
 // followed by Phi <- alpha (F - Gamma) + (1 - alpha) Phi.
 //
-// Blocked Gauss-Jordan elimination on the augmented [A | B] (B = Gamma) with
-// panel width NB (128 for complex64, 64 for complex128) and no row exchanges,
+// Blocked elimination without row exchanges on the augmented [A | B]
+// (B = Gamma) with panel width NB (128 for complex64, 64 for complex128),
 // batched over all q blocks of a channel: every step is one kernel launch over
-// (q block, tile) grids. Per panel J:
+// (q block, tile) grids. A forward sweep over the panels J = 0, 1, ...:
 //   (a) bse_pivot:  P = A_JJ^-1 by Gauss-Jordan on the NB x NB diagonal block,
 //                   held in registers (one column per thread and a slice of its
 //                   rows), pivot rows and columns broadcast through LDS, stored
@@ -15,14 +15,21 @@
 //                   make the matrix-core operand loads of (b) and (c) contiguous;
 //   (b) bse_panel:  pivot rows R_JK = P A_JK for every column right of the
 //                   panel in A and every column of B (in place);
-//   (c) bse_update: A_IK -= A_IJ R_JK, B_I -= A_IJ R_JB for all rows I != J, a
-//                   rank-NB update; each wave owns a 64 x 64 (complex64) or
-//                   32 x 32 (complex128) tile, reads both operands straight
-//                   from L1/L2 (no LDS), and forms each complex product from
-//                   three real matrix products.
-// After the last panel A is the identity and B holds F; bse_epilogue applies
-// the mixing. Steps (b) and (c) are complex products on the matrix cores
-// (v_mfma_f32_32x32x2f32 for complex64, v_mfma_f64_16x16x4f64 for complex128).
+//   (c) bse_update: A_IK -= A_IJ R_JK, B_I -= A_IJ R_JB for the rows I below
+//                   the panel, a rank-NB update; each wave owns a 64 x 64
+//                   (complex64) or 32 x 32 (complex128) tile, reads both
+//                   operands straight from L1/L2 (no LDS), and forms each
+//                   complex product from three real matrix products;
+// leaves in A the block unit upper triangular factor U (the scaled pivot
+// rows) and in B the right-hand sides Y of U F = Y. The back substitution then
+// runs over the panels from the last one down: B_I -= U_IJ B_J for the rows I
+// above panel J, with the same update kernel (multipliers copied by
+// bse_multcopy). This is (4/3) n^3 complex multiply-adds per block, the work of
+// an LU factorisation and two n-column triangular solves; full Gauss-Jordan,
+// which also clears U, would take 1.5 n^3. B then holds F, and bse_epilogue
+// applies the mixing. Steps (b) and (c) are complex products on the matrix
+// cores (v_mfma_f32_32x32x2f32 for complex64, v_mfma_f64_16x16x4f64 for
+// complex128).
 //
 // No row exchanges: A is the identity minus the small-norm kernel s Gamma X,
 // and every leading principal block of it stays invertible while the BSE is
@@ -423,15 +430,21 @@ __device__ inline typename cplx_of<T>::type system_elem(const BseCtx<T>& a, int 
 
 // Multipliers of panel J: A[i][J0 .. J0 + NB) for 32 rows i0 .. i0 + 31,
 // through an LDS transpose into MT[k][i]; rows k >= jb of MT (ragged last
-// panel) are written as zeros, so the update reads them unmasked.
+// panel) are written as zeros, so the update reads them unmasked. The rows
+// i < J0 are the entries U_IJ the back substitution needs (final once the
+// forward sweep reaches panel J): except for the last panel, whose MT the back
+// substitution reads directly, they go transposed into A[J0 + k][i], the part
+// of A left of the diagonal block in the panel's rows, which holds multipliers
+// already consumed by the earlier panels (same row stride n as MT).
 template <typename T, int NB>
 __device__ void copy_multipliers(const BseCtx<T>& a, int blk, int j0, int i0,
                                  typename cplx_of<T>::type (*X)[NB + 1]) {
   using C = typename cplx_of<T>::type;
   const int t = threadIdx.x, nt = blockDim.x, n = a.n;
   const int jb = min(NB, n - j0);
-  const C* A = a.A + (size_t)blk * n * n;
+  C* A = a.A + (size_t)blk * n * n;
   C* MT = a.MT + (size_t)blk * NB * n;
+  C* UT = j0 != (a.nJ - 1) * NB ? A + (size_t)j0 * n : MT;
   for (int idx = t; idx < 32 * NB; idx += nt) {
     const int r = idx / NB, k = idx - (idx / NB) * NB;
     const int i = min(i0 + r, n - 1), j = j0 + min(k, jb - 1);
@@ -441,7 +454,7 @@ __device__ void copy_multipliers(const BseCtx<T>& a, int blk, int j0, int i0,
   __syncthreads();
   for (int idx = t; idx < 32 * NB; idx += nt) {
     const int k = idx >> 5, r = idx & 31;
-    if (i0 + r < n) MT[(size_t)k * n + i0 + r] = X[r][k];
+    if (i0 + r < n) (i0 + r < j0 ? UT : MT)[(size_t)k * n + i0 + r] = X[r][k];
   }
 }
 
@@ -768,7 +781,10 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 }
 
 // ----------------------------------------------------------------- update
-// C[i][col] -= sum_k MT[k][i] R[k][col] for every row i outside the panel.
+// C[i][col] -= sum_k MT[k][i] R[k][col] for the rows row_lo <= i < row_hi and
+// the combined columns col_lo <= col < ncols: the forward step takes the rows
+// below the panel and every column right of it in A and B, the back
+// substitution the rows above the panel and the columns of B.
 // Tile shape and pipelining of the update: wave tile UWM x UWN, workgroup of
 // 2 x 2 waves, operand prefetch PF k-steps ahead; FULL = the panel is NB wide
 // (every panel but a ragged last one), so the panel rows need no clamping.
@@ -845,7 +861,8 @@ struct Tile4 : WTile<T, WM, WN> {
 
 template <typename T, int NB, class CF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CF::WPE)))
-void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
+void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int col_lo,
+                       const typename cplx_of<T>::type* mt0, size_t mt_bs) {
   using C = typename cplx_of<T>::type;
   static_assert(!CF::BF3 || sizeof(T) == 4, "BF16x3 products take complex64 operands");
   using M = typename std::conditional<CF::BF3, MmaBF3, Mma<T>>::type;
@@ -861,12 +878,12 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   const int ncols = (n - j0 - jb) + n;
   const int rb = bx / ncb, cbk = bx - (bx / ncb) * ncb;
   const int wr = wave & 1, wc = wave >> 1;
-  const int i0 = rb * CF::WGM + wr * CF::UWM;
-  const int c0 = cbk * CF::WGN + wc * CF::UWN;
-  if (i0 >= n || c0 >= ncols || (i0 >= j0 && i0 + CF::UWM <= j0 + jb)) return;
+  const int i0 = row_lo + rb * CF::WGM + wr * CF::UWM;
+  const int c0 = col_lo + cbk * CF::WGN + wc * CF::UWN;
+  if (i0 >= row_hi || c0 >= ncols) return;
   C* A = a.A + (size_t)blk * n * n;
   C* B = a.B + (size_t)blk * n * n;
-  const C* MT = a.MT + (size_t)blk * NB * n;
+  const C* MT = mt0 + (size_t)blk * mt_bs;      // multipliers, k-major with row stride n
   // Every load below is unconditional from a clamped, in-bounds address, so
   // the loads carry no branches and are issued ahead of the matrix-core work.
   // Lanes of rows or columns that are not stored read finite data that never
@@ -880,7 +897,6 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
     cok[y] = col < ncols;
     cb[y] = colptr(A, B, n, j0, jb, cok[y] ? col : 0);
   }
-  auto row_ok = [&](int i) { return i < n && !(i >= j0 && i < j0 + jb); };
   UT acc;
   if (CF::FIRST) {
     // first panel: C comes from Gamma (A = 1 - s Gamma diag(X), B = Gamma)
@@ -937,17 +953,25 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb) {
   acc.store_c([&](int r, int c, C v) {
     const int i = i0 + r;
     const int y = c / M::TN;
-    if (cok[y] && row_ok(i)) st_c<CF::NT>(&cb[y][(size_t)i * n], v);
+    if (cok[y] && i < row_hi) st_c<CF::NT>(&cb[y][(size_t)i * n], v);
   });
 }
 
+// rows [row_lo, row_hi) with 0 <= row_lo < row_hi <= n, outside the panel;
+// combined columns [col_lo, ncols) with col_lo <= n - j0 - jb; multipliers from
+// MT, or (ut, back substitution of a full panel that is not the last one) from
+// the transposed copy in A's rows J0 .. J0 + NB
 template <typename T, int NB, class CF>
-void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, hipStream_t s) {
+void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int row_hi, int col_lo, bool ut,
+                   hipStream_t s) {
+  const auto* mt0 = ut ? a.A + (size_t)j0 * n : a.MT;
+  const size_t mt_bs = ut ? (size_t)n * n : (size_t)NB * n;
   const int jb = std::min(NB, n - j0);
   const int ncols = (n - j0 - jb) + n;
-  const int nrb = (n + CF::WGM - 1) / CF::WGM;
-  const int ncb = (ncols + CF::WGN - 1) / CF::WGN;
-  hipLaunchKernelGGL((bse_update_kernel<T, NB, CF>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb);
+  const int nrb = (row_hi - row_lo + CF::WGM - 1) / CF::WGM;
+  const int ncb = (ncols - col_lo + CF::WGN - 1) / CF::WGN;
+  hipLaunchKernelGGL((bse_update_kernel<T, NB, CF>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb, row_lo,
+                     row_hi, col_lo, mt0, mt_bs);
 }
 
 // --------------------------------------------------------------- epilogue
@@ -1155,17 +1179,38 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     else
       hipLaunchKernelGGL((bse_panel_kernel<T, NB, false, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
     post();
+    // forward step: the rows below the panel (none below the last one)
+    if (j0 + jb < n) {
+      pre(3);
+      const int lo = j0 + jb;
+      if (jb == NB && j0 == 0)
+        launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, lo, n, 0, false, s);
+      else if (jb == NB)
+        launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, lo, n, 0, false, s);
+      else if (j0 == 0)
+        launch_update<T, NB, UpdFirst<UpdSel<T, false, BF3>>>(a, n, d.Nq, j0, lo, n, 0, false, s);
+      else
+        launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, lo, n, 0, false, s);
+      post();
+      if (tm) tm->update_flops += 8.0 * (double)(n - lo) * ncols * jb * d.Nq;
+    }
+  }
+  // Back substitution: the rows of panel J of B hold F once every later panel
+  // has been subtracted from them, so going from the last panel down, the
+  // rows above panel J take B_I -= U_IJ F_J, with U_IJ the entries the
+  // pivot-row steps of the earlier panels left in A, which the multiplier
+  // copy of the forward sweep stored k-major (in MT for the last panel, in A
+  // left of the diagonal block for the others).
+  const int last = (a.nJ - 1) * NB;
+  for (int j0 = last; j0 > 0; j0 -= NB) {
+    const int jb = std::min(NB, n - j0);
     pre(3);
-    if (jb == NB && j0 == 0)
-      launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, s);
-    else if (jb == NB)
-      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, s);
-    else if (j0 == 0)
-      launch_update<T, NB, UpdFirst<UpdSel<T, false, BF3>>>(a, n, d.Nq, j0, s);
+    if (jb == NB)
+      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, j0 != last, s);
     else
-      launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, s);
+      launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, false, s);
     post();
-    if (tm) tm->update_flops += 8.0 * (double)(n - jb) * ncols * jb * d.Nq;
+    if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
   }
   if constexpr (sizeof(T) == 4) {
     // FP64 re-solve of the blocks the pivot monitor flagged (none: empty launches)
