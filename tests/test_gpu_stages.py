@@ -278,6 +278,67 @@ def test_bse_solve(prec, name):
         assert np.all(flags & 2 == 0)
 
 
+_DEEP = {}
+
+
+def _deep_inputs(nv):
+    """Inputs of the deep-panel case (cached: each size is shared by the three
+    precisions; 1.1 / 2.1 GB of complex128 per channel)."""
+    if nv not in _DEEP:
+        _DEEP.clear()
+        p = config("small_2x4", Nv=nv)
+        g = _grid(p)
+        sig = random_sigma(g.Nve, g.Nk, seed=211, scale=0.1)
+        mu = P.find_mu(p, g, sig)
+        G = P.dyson(p, g, sig, mu)
+        xph, xpp = P.bubbles(p, g, G)
+        lam = P.pa_lambda(p.U)
+        rng = np.random.default_rng(5)
+        qs = sorted({0, 1, g.Nq // 2, g.Nq - 1, *(int(q) for q in rng.integers(0, g.Nq, 2))})
+        chans = []
+        for r, seed in ((P.CH_M, 223), (P.CH_S, 227)):
+            gam = rand_complex((g.Nq, g.n, g.n), seed, 0.5) + lam[r]
+            X = xph if r < 2 else xpp
+            chans.append((r, gam, X))
+        _DEEP[nv] = (p, g, qs, chans)
+    return _DEEP[nv]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("nv", [52, 64])
+def test_bse_deep_panels_sampled_blocks(prec, nv):
+    """Many panels: 2x4 lattice with Nv = 52 (n = 416: three full panels of 128
+    and a ragged one of 32; six of 64 and a ragged one) or Nv = 64 (n = 512:
+    four full panels of 128, eight of 64). The back substitution then takes its
+    multipliers from the copy stored in A for every panel but the last, which
+    the small cases never reach. One particle-hole (m) and one particle-particle
+    (s) channel, six sampled blocks of each checked against the oracle with the
+    bound of the C2 microbenchmark test, max|dF| <= 8 kappa n^(1/2) eps max|F|
+    (Phi = F - Gamma is ~70 times smaller than F here). A wrong multiplier in
+    the back substitution gives an error of the size of Phi itself, 10^4 times
+    the bound."""
+    _print_case("bse deep", prec, nv)
+    p, g, qs, chans = _deep_inputs(nv)
+    st = _ops().Stage(p, prec)
+    ws = torch.empty(st.bse_workspace_bytes(), dtype=torch.uint8, device=DEV)
+    for r, gam, X in chans:
+        if prec != "fp64":
+            gam = gam.astype(np.complex64).astype(np.complex128)
+        out = torch.empty((g.Nq, g.n, g.n), dtype=st.vdtype, device=DEV)
+        st.bse_solve(r, T(gam, st.vdtype), T(X), out, alpha=1.0, ws=ws)
+        got = H(out[qs]).astype(np.complex128)
+        del out
+        sign = P.BSE_SIGN[r]
+        for i, q in enumerate(qs):
+            ref = P.bse_block(gam[q], X[q], sign)
+            kappa = np.linalg.cond(np.eye(g.n) - sign * gam[q] * X[q][None, :])
+            err = float(np.max(np.abs(got[i] - ref)) / np.max(np.abs(ref + gam[q])))
+            bound = 8 * kappa * np.sqrt(g.n) * PRODUCT_EPS[prec]
+            assert err < bound, (r, q, err, bound)
+    del ws
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("name", ["bse_ragged", "c2"])
 def test_bse_repeat_is_bitwise_identical(prec, name):
