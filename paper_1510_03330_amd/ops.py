@@ -140,9 +140,16 @@ class Solver:
         self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
         if stream is not None:
             self.ws.record_stream(stream)      # the context's work runs on its own stream
+        self.ctx = None
+        self.reinit()
+
+    def reinit(self):
+        """Start again from the bare-vertex state (a new context on the same
+        workspace: parquet_init, nothing allocated)."""
+        self.close()
         ctx = ctypes.c_void_p()
-        N.check(lib.parquet_init(self.stage._pp(), ctypes.c_void_p(self.ws.data_ptr()), b,
-                                 _stream(stream), ctypes.byref(ctx)))
+        N.check(N.load().parquet_init(self.stage._pp(), ctypes.c_void_p(self.ws.data_ptr()),
+                                      ctypes.c_size_t(self.ws.numel()), _stream(self.stream), ctypes.byref(ctx)))
         self.ctx = ctx
         self.last_stats = None
 
@@ -343,18 +350,27 @@ class BatchRunner:
 
 
 def converge_mixed(p, tol: float = 1e-6, switch_tol: float = 1e-5, max_iter: int = 200,
-                   device: str = "cuda:0", low: str = "fp32"):
+                   device: str = "cuda:0", low: str = "fp32", solvers=None):
     """Iterate the complex64 path (precision ``low``: "fp32" or "bf16x3") from
     the bare-vertex start until max|Sigma_new - Sigma| < switch_tol, then
     continue on the complex128/FP64 path from that state until the change is
     below tol. Returns the FP64 solver and a dict with the iteration counts of
-    both phases (the first under the key iterations_fp32)."""
+    both phases (the first under the key iterations_fp32). ``solvers``: an
+    already allocated (low, fp64) pair of the same box, re-initialised here
+    (the low one is closed at the switch)."""
     if low not in ("fp32", "bf16x3"):
         raise ValueError(f"low precision {low!r} must be fp32 or bf16x3")
-    s32 = Solver(p, low, device)
+    if solvers is not None:
+        s32, s64 = solvers
+        s32.reinit()
+    else:
+        s32 = Solver(p, low, device)
     done32, conv32, st32 = s32.iterate(max_iter, switch_tol)
     torch.cuda.synchronize()
-    s64 = Solver(p, "fp64", device)
+    if solvers is not None:
+        s64.reinit()
+    else:
+        s64 = Solver(p, "fp64", device)
     s64.copy_state_from(s32)
     s32.close()
     del s32

@@ -170,3 +170,22 @@ def test_c1_mixed_precision_converges_to_fp64_solution(c1_oracle):
     assert relerr(H(s.get("sigma")), ref.sigma) < 1e-8
     assert relerr(H(s.get("phi")), ref.phi) < 1e-7
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_reinit_restarts_from_the_bare_vertex(prec):
+    """Solver.reinit() (a new context on the same workspace) restarts from the
+    bare-vertex state: the iterations after it are bitwise those of a fresh
+    solver, although the workspace still holds the previous run's vertex."""
+    print("CASE reinit", prec, flush=True)
+    p = config("small_2x4")
+    a = _solver(p, prec)
+    a.iterate(4)
+    a.reinit()
+    a.iterate(2)
+    b = _solver(p, prec)
+    b.iterate(2)
+    for f in ("sigma", "phi", "k2"):
+        assert np.array_equal(H(a.get(f)), H(b.get(f))), f
+    a.close()
+    b.close()
