@@ -435,7 +435,10 @@ __device__ inline typename cplx_of<T>::type system_elem(const BseCtx<T>& a, int 
 // forward sweep reaches panel J): except for the last panel, whose MT the back
 // substitution reads directly, they go transposed into A[J0 + k][i], the part
 // of A left of the diagonal block in the panel's rows, which holds multipliers
-// already consumed by the earlier panels (same row stride n as MT).
+// already consumed by the earlier panels (same row stride n as MT). Used for
+// the first panel (multipliers formed from Gamma) and a ragged last panel; the
+// other panels get both parts from the kernels that produce the values (the
+// pivot-row step and the previous update, below).
 template <typename T, int NB>
 __device__ void copy_multipliers(const BseCtx<T>& a, int blk, int j0, int i0,
                                  typename cplx_of<T>::type (*X)[NB + 1]) {
@@ -767,14 +770,22 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
     }
     }
     // The pivot rows are overwritten in place: with several waves per strip,
-    // every wave must have read all NB panel rows of the strip first.
+    // every wave must have read all NB panel rows of the strip first. The A
+    // part of the pivot rows is the U_JK the back substitution needs: it also
+    // goes transposed into A[K][J0 + row], below the diagonal block, where the
+    // multipliers of panel J are no longer needed (the update reads them from
+    // MT), so that the back substitution reads U k-major with no copy step.
     if constexpr (WPS > 1) __syncthreads();
     if (live) {
+      const int ncolA = n - j0 - jb;
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt)
         acc[rt].store_prod([&](int r, int c, C v) {
           const int row = rb + rt * 32 + r, col = cs * 32 + c;
-          if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
+          if (row < jb && col < ncols) {
+            colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
+            if (col < ncolA) A[(size_t)(j0 + jb + col) * n + j0 + row] = v;
+          }
         });
     }
   }
@@ -784,7 +795,12 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
 // C[i][col] -= sum_k MT[k][i] R[k][col] for the rows row_lo <= i < row_hi and
 // the combined columns col_lo <= col < ncols: the forward step takes the rows
 // below the panel and every column right of it in A and B, the back
-// substitution the rows above the panel and the columns of B.
+// substitution the rows above the panel and the columns of B. The forward
+// step's results in the first ntc combined columns (the columns of the next
+// panel) are final multipliers of that panel for the rows below it: those go
+// transposed into mtn[col][i], the next panel's MT, instead of into A (where
+// nothing reads them: the next pivot-row step writes U there); the next
+// panel's diagonal block (rows row_lo .. row_lo + ntc) is stored in A as usual.
 // Tile shape and pipelining of the update: wave tile UWM x UWN, workgroup of
 // 2 x 2 waves, operand prefetch PF k-steps ahead; FULL = the panel is NB wide
 // (every panel but a ragged last one), so the panel rows need no clamping.
@@ -862,7 +878,8 @@ struct Tile4 : WTile<T, WM, WN> {
 template <typename T, int NB, class CF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CF::WPE)))
 void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int col_lo,
-                       const typename cplx_of<T>::type* mt0, size_t mt_bs) {
+                       const typename cplx_of<T>::type* mt0, size_t mt_bs, typename cplx_of<T>::type* mtn,
+                       int ntc) {
   using C = typename cplx_of<T>::type;
   static_assert(!CF::BF3 || sizeof(T) == 4, "BF16x3 products take complex64 operands");
   using M = typename std::conditional<CF::BF3, MmaBF3, Mma<T>>::type;
@@ -950,28 +967,33 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
     __builtin_amdgcn_sched_barrier(0);     // keep the prefetch ahead of this step's MFMAs
     acc.mac(ca, cbv);
   }
+  C* MN = mtn + (size_t)blk * NB * n;
   acc.store_c([&](int r, int c, C v) {
     const int i = i0 + r;
     const int y = c / M::TN;
-    if (cok[y] && i < row_hi) st_c<CF::NT>(&cb[y][(size_t)i * n], v);
+    const bool mult = c0 + c < ntc && i >= row_lo + ntc;
+    if (cok[y] && i < row_hi && !mult) st_c<CF::NT>(&cb[y][(size_t)i * n], v);
+    if (mult && i < row_hi) MN[(size_t)(c0 + c) * n + i] = v;
   });
 }
 
 // rows [row_lo, row_hi) with 0 <= row_lo < row_hi <= n, outside the panel;
 // combined columns [col_lo, ncols) with col_lo <= n - j0 - jb; multipliers from
-// MT, or (ut, back substitution of a full panel that is not the last one) from
-// the transposed copy in A's rows J0 .. J0 + NB
+// mt (k-major [NB][n] per block) or, ut (back substitution of a full panel),
+// from the transposed copy in A's rows J0 .. J0 + NB; the results of the first
+// ntc <= min(NB, n - j0 - jb) combined columns also go transposed into mtn
+// (forward step: the next panel's multipliers)
 template <typename T, int NB, class CF>
 void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int row_hi, int col_lo, bool ut,
-                   hipStream_t s) {
-  const auto* mt0 = ut ? a.A + (size_t)j0 * n : a.MT;
+                   typename cplx_of<T>::type* mt, typename cplx_of<T>::type* mtn, int ntc, hipStream_t s) {
+  const auto* mt0 = ut ? a.A + (size_t)j0 * n : mt;
   const size_t mt_bs = ut ? (size_t)n * n : (size_t)NB * n;
   const int jb = std::min(NB, n - j0);
   const int ncols = (n - j0 - jb) + n;
   const int nrb = (row_hi - row_lo + CF::WGM - 1) / CF::WGM;
   const int ncb = (ncols - col_lo + CF::WGN - 1) / CF::WGN;
   hipLaunchKernelGGL((bse_update_kernel<T, NB, CF>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb, row_lo,
-                     row_hi, col_lo, mt0, mt_bs);
+                     row_hi, col_lo, mt0, mt_bs, mtn ? mtn : mt, mtn ? ntc : 0);
 }
 
 // --------------------------------------------------------------- epilogue
@@ -1038,7 +1060,7 @@ BseLayout bse_layout(const Dims& d) {
   auto take = [&](size_t b) { size_t o = off; off += align256(b); return o; };
   L.A = take(sizeof(C) * nn * d.Nq);
   L.B = take(sizeof(C) * nn * d.Nq);
-  L.MT = take(sizeof(C) * (size_t)NB * d.n * d.Nq);
+  L.MT = take(2 * sizeof(C) * (size_t)NB * d.n * d.Nq);     // panels alternate between two
   L.PI = take(sizeof(C) * (size_t)NB * NB * d.Nq);
   L.pst = take(sizeof(double) * kPst * (size_t)d.Nq);
   if constexpr (sizeof(T) == 4) {
@@ -1163,13 +1185,24 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   };
   if (tm) tm->update_flops = 0.0;
   const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)n * n + kThreads - 1) / kThreads);
+  // Multipliers: two buffers, panel J in buffer J % 2. The multiplier copy
+  // runs for the first panel (formed from Gamma) and a ragged last panel; every
+  // other panel's multipliers come from the previous forward update (rows
+  // below the panel) and the pivot-row steps of the earlier panels (the U
+  // entries above it, stored in A below the diagonal blocks).
+  C* mtb[2] = {a.MT, a.MT + (size_t)NB * n * d.Nq};
+  const int last = (a.nJ - 1) * NB;
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int jb = std::min(NB, n - j0);
     const int ncols = (n - j0 - jb) + n;
+    const int pj = j0 / NB;
     pre(1);
-    const int nwc = (n + 31) / 32;
     hipLaunchKernelGGL((bse_pivot_kernel<T, NB>), dim3(1, d.Nq), dim3(pivot_threads<NB>()), 0, s, a, j0);
-    hipLaunchKernelGGL((bse_multcopy_kernel<T, NB>), dim3(nwc, d.Nq), dim3(kThreads), 0, s, a, j0);
+    if (j0 == 0 || jb < NB) {
+      BseCtx<T> am = a;
+      am.MT = mtb[pj & 1];
+      hipLaunchKernelGGL((bse_multcopy_kernel<T, NB>), dim3((n + 31) / 32, d.Nq), dim3(kThreads), 0, s, am, j0);
+    }
     post();
     constexpr int RW = panel_rows_per_wave<T, NB>();
     const int nwb = ((ncols + 31) / 32 * (NB / RW) + kWaves - 1) / kWaves;
@@ -1179,36 +1212,35 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     else
       hipLaunchKernelGGL((bse_panel_kernel<T, NB, false, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
     post();
-    // forward step: the rows below the panel (none below the last one)
+    // forward step: the rows below the panel (none below the last one); the
+    // full panels before the last are the only ones with rows below
     if (j0 + jb < n) {
       pre(3);
       const int lo = j0 + jb;
-      if (jb == NB && j0 == 0)
-        launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, lo, n, 0, false, s);
-      else if (jb == NB)
-        launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, lo, n, 0, false, s);
-      else if (j0 == 0)
-        launch_update<T, NB, UpdFirst<UpdSel<T, false, BF3>>>(a, n, d.Nq, j0, lo, n, 0, false, s);
+      C* mt = mtb[pj & 1];
+      C* mtn = mtb[(pj + 1) & 1];
+      const int ntc = std::min(NB, n - lo);      // the next panel's columns
+      if (j0 == 0)
+        launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
       else
-        launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, lo, n, 0, false, s);
+        launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
       post();
       if (tm) tm->update_flops += 8.0 * (double)(n - lo) * ncols * jb * d.Nq;
     }
   }
   // Back substitution: the rows of panel J of B hold F once every later panel
   // has been subtracted from them, so going from the last panel down, the
-  // rows above panel J take B_I -= U_IJ F_J, with U_IJ the entries the
-  // pivot-row steps of the earlier panels left in A, which the multiplier
-  // copy of the forward sweep stored k-major (in MT for the last panel, in A
-  // left of the diagonal block for the others).
-  const int last = (a.nJ - 1) * NB;
+  // rows above panel J take B_I -= U_IJ F_J, with U_IJ read k-major from A
+  // below the diagonal blocks (full panels) or from the multiplier copy of a
+  // ragged last panel.
   for (int j0 = last; j0 > 0; j0 -= NB) {
     const int jb = std::min(NB, n - j0);
     pre(3);
     if (jb == NB)
-      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, j0 != last, s);
+      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s);
     else
-      launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, false, s);
+      launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, false, mtb[(j0 / NB) & 1],
+                                                   nullptr, 0, s);
     post();
     if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
   }
