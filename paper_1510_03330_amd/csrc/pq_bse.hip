@@ -700,7 +700,8 @@ __device__ inline ColSrc<T> colsrc(const BseCtx<T>& a, int blk, int j0, int jb, 
 template <typename T, int NB> constexpr int panel_rows_per_wave() { return sizeof(T) == 4 ? NB : 32; }
 
 template <typename T, int NB, bool FIRST, int RW = NB, int PFB = 2>
-__global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
   using WT = WTile<T>;
@@ -711,6 +712,7 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
   C* A = a.A + (size_t)blk * n * n;
   C* B = a.B + (size_t)blk * n * n;
   static_assert(kWaves % WPS == 0, "the waves of one strip share a workgroup");
+  __shared__ C tr_s[kWaves][32][33];            // per-wave transpose tile of the U copy
   if (inactive(a, blk)) return;                 // uniform over the workgroup
   {
     const int ws = blockIdx.x * kWaves + wave;
@@ -775,18 +777,39 @@ __global__ __launch_bounds__(kThreads) void bse_panel_kernel(BseCtx<T> a, int j0
     // goes transposed into A[K][J0 + row], below the diagonal block, where the
     // multipliers of panel J are no longer needed (the update reads them from
     // MT), so that the back substitution reads U k-major with no copy step.
+    // The transpose goes through a per-wave LDS tile (row stride 33: no bank
+    // conflicts on the column-wise writes), so that each store instruction
+    // writes two contiguous 32-element runs of A.
     if constexpr (WPS > 1) __syncthreads();
     if (live) {
       const int ncolA = n - j0 - jb;
+      const bool tr = cs * 32 < ncolA;            // wave-uniform: the strip has A columns
+      C (*ts)[33] = tr_s[wave];
 #pragma unroll
-      for (int rt = 0; rt < NRT; ++rt)
+      for (int rt = 0; rt < NRT; ++rt) {
         acc[rt].store_prod([&](int r, int c, C v) {
           const int row = rb + rt * 32 + r, col = cs * 32 + c;
-          if (row < jb && col < ncols) {
-            colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
-            if (col < ncolA) A[(size_t)(j0 + jb + col) * n + j0 + row] = v;
-          }
+          if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
+          if (tr) ts[c][r] = v;
         });
+        if (tr) {
+          // the LDS tile is private to the wave: a wave-scope fence orders the
+          // writes above before the reads below (and the reads before the
+          // next tile's writes)
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+          for (int it = 0; it < 16; ++it) {
+            const int e = it * 64 + lane, c = e >> 5, r = e & 31;
+            const int row = rb + rt * 32 + r, col = cs * 32 + c;
+            if (row < jb && col < ncolA) A[(size_t)(j0 + jb + col) * n + j0 + row] = ts[c][r];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
     }
   }
 }
