@@ -10,26 +10,30 @@
 //   (a) bse_pivot:  P = A_JJ^-1 by Gauss-Jordan on the NB x NB diagonal block,
 //                   held in registers (one column per thread and a slice of its
 //                   rows), pivot rows and columns broadcast through LDS, stored
-//                   transposed (k-major); bse_multcopy copies the multipliers
-//                   A_IJ k-major (MT[k][i] = A[i][J0 + k]); k-major operands
-//                   make the matrix-core operand loads of (b) and (c) contiguous;
+//                   transposed (k-major);
 //   (b) bse_panel:  pivot rows R_JK = P A_JK for every column right of the
 //                   panel in A and every column of B (in place);
 //   (c) bse_update: A_IK -= A_IJ R_JK, B_I -= A_IJ R_JB for the rows I below
 //                   the panel, a rank-NB update; each wave owns a 64 x 64
 //                   (complex64) or 32 x 32 (complex128) tile, reads both
 //                   operands straight from L1/L2 (no LDS), and forms each
-//                   complex product from three real matrix products;
-// leaves in A the block unit upper triangular factor U (the scaled pivot
-// rows) and in B the right-hand sides Y of U F = Y. The back substitution then
-// runs over the panels from the last one down: B_I -= U_IJ B_J for the rows I
-// above panel J, with the same update kernel (multipliers copied by
-// bse_multcopy). This is (4/3) n^3 complex multiply-adds per block, the work of
-// an LU factorisation and two n-column triangular solves; full Gauss-Jordan,
-// which also clears U, would take 1.5 n^3. B then holds F, and bse_epilogue
-// applies the mixing. Steps (b) and (c) are complex products on the matrix
-// cores (v_mfma_f32_32x32x2f32 for complex64, v_mfma_f64_16x16x4f64 for
-// complex128).
+//                   complex product from three real matrix products.
+// The multipliers A_IJ are read k-major (MT[k][i] = A[i][J0 + k]), which makes
+// the matrix-core operand loads of (b) and (c) contiguous: the update of panel
+// J - 1 writes those of panel J transposed into MT (two buffers, alternating),
+// and bse_multcopy copies them for the first panel (formed from Gamma) and a
+// ragged last one. The sweep leaves in A the block unit upper triangular
+// factor U (the scaled pivot rows) and in B the right-hand sides Y of
+// U F = Y. The back substitution then runs over the panels from the last one
+// down: B_I -= U_IJ B_J for the rows I above panel J, with the same update
+// kernel; (b) also writes the A part of the pivot rows transposed below the
+// diagonal block (where the multipliers of that panel are dead), which gives
+// the back substitution U k-major with no copy step. This is (4/3) n^3 complex
+// multiply-adds per block, the work of an LU factorisation and two n-column
+// triangular solves; full Gauss-Jordan, which also clears U, would take
+// 1.5 n^3. B then holds F, and bse_epilogue applies the mixing. Steps (b) and
+// (c) are complex products on the matrix cores (v_mfma_f32_32x32x2f32 for
+// complex64, v_mfma_f64_16x16x4f64 for complex128).
 //
 // No row exchanges: A is the identity minus the small-norm kernel s Gamma X,
 // and every leading principal block of it stays invertible while the BSE is
@@ -393,7 +397,8 @@ struct BseCtx {
   C* phi;                // [Nq][n][n]
   C* A;                  // [Nq][n][n]
   C* B;                  // [Nq][n][n]
-  C* MT;                 // [Nq][NB][n]    multipliers of the current panel, k-major
+  C* MT;                 // [2][Nq][NB][n] multipliers, k-major (panel J in buffer J % 2; the
+                         //                kernels take the buffer of their panel)
   C* PI;                 // [Nq][NB][NB]   inverse P of the current diagonal block, transposed:
                          //                PI[k][r] = P[r][k] (k-major, like MT)
   double* pst;           // [Nq][kPst]  min |pivot|, max |pivot|, non-finite seen, re-solved,
