@@ -337,23 +337,33 @@ def batch_study(tol: float = 1e-6, max_iter: int = 150):
             "converged": sum(int(r["converged"]) for r in recs), "by_nv": by_nv}
 
 
-def warmstart_study(tol: float = 1e-6, max_iter: int = 400):
-    """Learned warm start on the momentum-independent problem (semicircle bath,
-    D = 2, half filling, Nv = 16, alpha = 0.5): converged kernel functions of
-    a 12 x 12 grid U in [0.5, 1.5] x beta in [2, 5] (complex128, to 1e-8)
-    train a 2 -> 3 x 512 -> (K1, K2, Sigma) perceptron on the GPU; 24 seeded held-out
-    (U, beta) are then solved to tol from the bare vertex and from the vertex
-    rebuilt from the predicted kernels with the predicted self-energy (and,
-    for comparison, with the bare self-energy), in complex128."""
+def warmstart_study(tol: float = 1e-6, max_iter: int = 400, lattice: bool = False):
+    """Learned warm start. Local problem (default): semicircle bath, D = 2, half
+    filling, Nv = 16, alpha = 0.5, a 12 x 12 training grid U in [0.5, 1.5] x
+    beta in [2, 5]. Lattice: the 4x4 lattice, t = 1, t' = 0, half filling,
+    Nv = 16 (BSE dimension 256, 240 transfers), a 12 x 12 grid U in [1, 2] x
+    beta in [2, 3.5] (the region where the bare-vertex start converges; at
+    U = 2, beta = 4 it diverges). Converged kernel functions and self-energy
+    (complex128, to 1e-8) train a 2 -> 3 x 512 -> (K1, K2, Sigma) perceptron on
+    the GPU; 24 seeded held-out (U, beta) are then solved to tol from the bare
+    vertex and from the vertex rebuilt from the predicted kernels with the
+    predicted self-energy (and, for comparison, with the bare self-energy), in
+    complex128."""
     import numpy as np
     import torch
     from paper_1510_03330_amd import warmstart as W
-    from paper_1510_03330_amd.ops import Solver
     from workloads import config
 
-    base = config("c1", Nv=16, beta=2.0, D=2.0, alpha=0.5)
-    grid = [base.replace(U=float(u), beta=float(b)) for u in np.linspace(0.5, 1.5, 12)
-            for b in np.linspace(2.0, 5.0, 12)]
+    if lattice:
+        base = config("c2", U=1.5, beta=3.0)
+        u_lo, u_hi, b_lo, b_hi = 1.0, 2.0, 2.0, 3.5
+        workload = "4x4 lattice, t=1, t'=0, half filling, Nv=16, alpha=0.5"
+    else:
+        base = config("c1", Nv=16, beta=2.0, D=2.0, alpha=0.5)
+        u_lo, u_hi, b_lo, b_hi = 0.5, 1.5, 2.0, 5.0
+        workload = "local model, semicircle bath D=2, half filling, Nv=16, alpha=0.5"
+    grid = [base.replace(U=float(u), beta=float(b)) for u in np.linspace(u_lo, u_hi, 12)
+            for b in np.linspace(b_lo, b_hi, 12)]
     print("[warmstart] training data", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ps, k1s, k2s, sigs, dropped = [], [], [], [], 0
@@ -368,11 +378,16 @@ def warmstart_study(tol: float = 1e-6, max_iter: int = 400):
     pred = W.KernelPredictor(base, hidden=(512, 512, 512), seed=0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = pred.fit(ps, k1s, k2s, sigs, steps=3000, batch=64, lr=1e-3)
+    hist = pred.fit(ps, k1s, k2s, sigs, steps=3000, batch=64, lr=1e-3,
+                    progress=lambda it, loss: print(f"[warmstart] step {it} loss {loss:.3g}", file=sys.stderr,
+                                                    flush=True))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    del k1s, k2s, sigs
     rng = np.random.default_rng(10000)
-    held = [base.replace(U=float(rng.uniform(0.55, 1.45)), beta=float(rng.uniform(2.1, 4.9))) for _ in range(24)]
+    du, db = 0.05 * (u_hi - u_lo), 0.033 * (b_hi - b_lo)
+    held = [base.replace(U=float(rng.uniform(u_lo + du, u_hi - du)), beta=float(rng.uniform(b_lo + db, b_hi - db)))
+            for _ in range(24)]
     print("[warmstart] held-out solves", file=sys.stderr, flush=True)
     rows = []
     for p in held:
@@ -386,8 +401,10 @@ def warmstart_study(tol: float = 1e-6, max_iter: int = 400):
     it_p = np.array([r["warm_phi"]["iterations"] for r in rows])
     s_b = sum(r["bare"]["sec"] for r in rows)
     s_w = sum(r["warm"]["sec"] for r in rows)
-    return {"mode": "warmstart", "workload": "local model, semicircle bath D=2, half filling, Nv=16, alpha=0.5",
+    return {"mode": "warmstart", "workload": workload,
             "network": "2 -> 512 -> 512 -> 512 -> %d (K1, K2, Sigma; tanh, bf16 weights, FP32 accumulate)" % pred.nout,
+            "parameters": pred.mlp.count,
+            "train_grid": {"U": [u_lo, u_hi], "beta": [b_lo, b_hi], "points": len(grid)},
             "train_samples": len(ps), "train_dropped_not_converged": dropped, "data_sec": round(t_data, 2),
             "train_steps": 3000, "train_sec": round(t_train, 2), "loss_first_last": [hist[0][1], hist[-1][1]],
             "held_out": len(rows), "tol": tol,
@@ -489,6 +506,8 @@ def main():
                     help="run only the kernel-level / regulation / U-range study (one JSON line)")
     ap.add_argument("--batch", action="store_true",
                     help="run only the 64-instance batched-solver study (one JSON line)")
+    ap.add_argument("--warmstart-lattice", action="store_true",
+                    help="run only the learned warm-start study on the 4x4 lattice (one JSON line)")
     ap.add_argument("--warmstart", action="store_true",
                     help="run only the learned warm-start study (one JSON line)")
     ap.add_argument("--no-ttc", action="store_true",
@@ -511,6 +530,9 @@ def main():
         return
     if args.warmstart:
         print(json.dumps(warmstart_study()))
+        return
+    if args.warmstart_lattice:
+        print(json.dumps(warmstart_study(lattice=True)))
         return
     from workloads import config
     p = config(args.workload)

@@ -226,9 +226,10 @@ pq_status phi_from_kernels(const pq_params* p, const void* k1, const void* k2, v
  * mlp_param_count entries, and params_bf16, the same array rounded to bf16
  * (to nearest even; the products use the bf16 weights, biases, activations and
  * accumulation are FP32). acts: device floats, batch * (w_1 + ... + w_L), the
- * outputs of every layer, the network output last. Used for the learned warm
- * start, model parameters -> kernel functions (an addition to the paper's
- * method, which starts from the bare vertex). */
+ * outputs of every layer, the network output last. 1 <= n_layers <= 16 and
+ * 1 <= widths <= 1048560 (ERR_ARG otherwise). Used for the learned warm start,
+ * model parameters -> kernel functions (an addition to the paper's method,
+ * which starts from the bare vertex). */
 pq_status mlp_param_count(const int32_t* widths, int32_t n_layers, size_t* count);
 pq_status mlp_forward(const int32_t* widths, int32_t n_layers, const void* params_bf16, const float* params,
                       const float* x, float* acts, int32_t batch, pq_stream stream);

@@ -204,10 +204,14 @@ pq_status sigma_mix(const pq_params* p, const void* sigma_new, void* sigma_io, d
 }
 
 // ------------------------------------------------------ learned warm start
+// widths up to 65535 GEMM tiles of 16 (the weight-gradient product puts the
+// output width on the grid's second dimension)
+constexpr int32_t kMlpMaxWidth = 65535 * 16;
+
 static bool mlp_widths_ok(const int32_t* w, int32_t nl) {
   if (!w || nl < 1 || nl > 16) return false;
   for (int l = 0; l <= nl; ++l)
-    if (w[l] < 1 || w[l] > 65536) return false;
+    if (w[l] < 1 || w[l] > kMlpMaxWidth) return false;
   return true;
 }
 

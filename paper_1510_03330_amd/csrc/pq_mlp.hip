@@ -70,23 +70,39 @@ __global__ __launch_bounds__(256) void colsum_kernel(int B, int O, const float* 
   db[o] = s;
 }
 
-// d = 2 (y - t) / count and loss = mean (y - t)^2 (one workgroup, fixed order)
-__global__ __launch_bounds__(256) void mse_kernel(size_t count, const float* y, const float* t, float* d,
-                                                  float* loss) {
-  __shared__ float red[256];
-  float s = 0.f;
-  for (size_t i = threadIdx.x; i < count; i += blockDim.x) {
-    const float e = y[i] - t[i];
-    d[i] = 2.f * e / (float)count;
-    s += e * e;
-  }
-  red[threadIdx.x] = s;
+// d = 2 (y - t) / count and loss = mean (y - t)^2, in two passes with a fixed
+// summation order (deterministic): each workgroup of the first pass sums a
+// fixed grid-stride subset into part[blockIdx.x], the second (one workgroup)
+// sums the parts.
+__device__ inline float block_sum256(float v, float* red) {
+  red[threadIdx.x] = v;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *loss = red[0] / (float)count;
+  return red[0];
+}
+
+__global__ __launch_bounds__(256) void mse_partial_kernel(size_t count, const float* y, const float* t, float* d,
+                                                          float* part) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const float e = y[i] - t[i];
+    d[i] = 2.f * e / (float)count;
+    s += e * e;
+  }
+  const float b = block_sum256(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(256) void mse_final_kernel(int nparts, const float* part, size_t count, float* loss) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+  const float b = block_sum256(s, red);
+  if (threadIdx.x == 0) *loss = b / (float)count;
 }
 
 __global__ __launch_bounds__(256) void adam_kernel(size_t count, float* p, __bf16* pb, float* m, float* v,
@@ -162,7 +178,11 @@ hipError_t launch_mlp_backward(const int32_t* w, int nl, const void* pb, const f
   float* d = scratch;
   float* dn = scratch + (size_t)B * maxw;
   const size_t nout = (size_t)B * w[nl];
-  hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(256), 0, s, nout, acts + aoff[nl - 1], target, d, loss);
+  // the partial sums of the loss live in dn, which the layer loop below
+  // writes only after the final pass has read them
+  const int nparts = (int)std::min<size_t>({(size_t)1024, (nout + 255) / 256, (size_t)B * maxw});
+  hipLaunchKernelGGL(mse_partial_kernel, dim3(nparts), dim3(256), 0, s, nout, acts + aoff[nl - 1], target, d, dn);
+  hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, s, nparts, (const float*)dn, nout, loss);
   for (int l = nl - 1; l >= 0; --l) {
     const int in = w[l], out = w[l + 1];
     const float* hin = l == 0 ? x : acts + aoff[l - 1];

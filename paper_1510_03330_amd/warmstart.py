@@ -74,8 +74,9 @@ class MLP:
                                   float(lr), float(beta1), float(beta2), float(eps), self.step_count, _stream()))
 
     def train(self, X: torch.Tensor, Y: torch.Tensor, steps: int, batch: int = 64, lr: float = 1e-3,
-              seed: int = 0, lr_final: float = 1e-5):
-        """Minibatch Adam on (X, Y); cosine decay of the learning rate."""
+              seed: int = 0, lr_final: float = 1e-5, progress=None):
+        """Minibatch Adam on (X, Y); cosine decay of the learning rate;
+        progress(step, loss) is called every 500 steps if given."""
         rng = np.random.default_rng(seed)
         n = X.shape[0]
         hist = []
@@ -88,6 +89,8 @@ class MLP:
             self.adam(a)
             if it % 100 == 0 or it == steps - 1:
                 hist.append((it, float(self.loss.item())))
+                if progress is not None and it % 500 == 0:
+                    progress(it, hist[-1][1])
         return hist
 
 
@@ -118,14 +121,14 @@ class KernelPredictor:
         return torch.cat([torch.view_as_real(k1).reshape(-1), torch.view_as_real(k2).reshape(-1),
                           torch.view_as_real(sig).reshape(-1)])
 
-    def fit(self, params, k1s, k2s, sigs, steps=3000, batch=64, lr=1e-3):
+    def fit(self, params, k1s, k2s, sigs, steps=3000, batch=64, lr=1e-3, progress=None):
         x = self._x(params)
         y = torch.stack([self._flat(a, b, c) for a, b, c in zip(k1s, k2s, sigs)]).to(torch.float64)
         self.x_mean, self.x_std = x.mean(0), x.std(0).clamp_min(1e-6)
         self.y_mean, self.y_std = y.mean(0), y.std(0).clamp_min(1e-12)
         X = self._scale_x(x)
         Y = ((y - self.y_mean) / self.y_std).to(torch.float32)
-        return self.mlp.train(X, Y, steps, batch, lr)
+        return self.mlp.train(X, Y, steps, batch, lr, progress=progress)
 
     def predict(self, p):
         X = self._scale_x(self._x([p]))

@@ -149,3 +149,22 @@ def test_precision_storage_pairs():
     assert lib.pq_dims_from_params(ctypes.byref(bad), ctypes.byref(d)) == N.PQ_ERR_ARG
     with pytest.raises(ValueError):
         N.make_params(p, "fp16")
+
+
+def test_mlp_widths_are_checked_on_the_host():
+    """mlp_param_count accepts 1..16 layers of widths 1..1048560 (65535 GEMM
+    tiles of 16) and counts W and b of every layer; anything else is ERR_ARG."""
+    lib = N.load()
+    cnt = ctypes.c_size_t()
+
+    def count(widths):
+        arr = (ctypes.c_int32 * len(widths))(*widths)
+        return lib.mlp_param_count(arr, len(widths) - 1, ctypes.byref(cnt))
+
+    assert count([2, 512, 512, 512, 494464]) == N.PQ_OK
+    assert cnt.value == (2 * 512 + 512) + 2 * (512 * 512 + 512) + (512 * 494464 + 494464)
+    assert count([3, 1048560]) == N.PQ_OK and cnt.value == 3 * 1048560 + 1048560
+    assert count([3, 1048561]) == N.PQ_ERR_ARG
+    assert count([0, 4]) == N.PQ_ERR_ARG
+    assert count([4]) == N.PQ_ERR_ARG                       # no layer
+    assert count([1] * 18) == N.PQ_ERR_ARG                  # 17 layers
