@@ -253,14 +253,22 @@ BSE_TOL = {"fp64": 1e-11, "fp32": 2e-4, "bf16x3": 2e-3}
 PRODUCT_EPS = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16x3": 3 * 2.0 ** -18}
 
 
+_BSE_CASES = {
+    "bse_ragged": ("small_4x4", dict(Nv=10)),    # n = 160: 2.5 panels of 64, 1.25 of 128
+    "bse_odd": ("tiny_local", dict(Nv=150)),     # n = 150: panels 64 + 64 + 22 and 128 + 22, no 32-row multiple
+}
+
+
+def _bse_config(name):
+    base, over = _BSE_CASES.get(name, (name, {}))
+    return config(base, **over)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("name", ["tiny_2x2", "tiny_2x2_hf", "small_2x4", "small_4x4", "bse_ragged"])
+@pytest.mark.parametrize("name", ["tiny_2x2", "tiny_2x2_hf", "small_2x4", "small_4x4", "bse_ragged", "bse_odd"])
 def test_bse_solve(prec, name):
     _print_case("bse", prec, name)
-    if name == "bse_ragged":
-        p = config("small_4x4", Nv=10)       # n = 160: 2.5 panels of 64, 1.25 of 128
-    else:
-        p = config(name)
+    p = _bse_config(name)
     g, gam, xph, xpp = _bse_inputs(p, 101)
     if prec != "fp64":
         gam = gam.astype(np.complex64).astype(np.complex128)
@@ -340,14 +348,14 @@ def test_bse_deep_panels_sampled_blocks(prec, nv):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("name", ["bse_ragged", "c2"])
+@pytest.mark.parametrize("name", ["bse_ragged", "bse_odd", "c2"])
 def test_bse_repeat_is_bitwise_identical(prec, name):
     """Solving the same blocks again with the same workspace gives the same
     bits: no step reads a value another workgroup, or a wave of the same
     workgroup, is still writing (the pivot-row step overwrites its input rows
     in place; with several waves per column strip they all read first)."""
     _print_case("bse repeat", prec, name)
-    p = config("small_4x4", Nv=10) if name == "bse_ragged" else config(name)
+    p = _bse_config(name)
     g, gam, xph, xpp = _bse_inputs(p, 303)
     st = _ops().Stage(p, prec)
     ws = torch.empty(st.bse_workspace_bytes(), dtype=torch.uint8, device=DEV)
