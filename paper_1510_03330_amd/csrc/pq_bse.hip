@@ -819,6 +819,20 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
   }
 }
 
+// Mixing of the solved vertex: Phi <- alpha (F - Gamma) + (1 - alpha) Phi.
+template <typename T>
+__device__ inline typename cplx_of<T>::type mix_phi(typename cplx_of<T>::type f, typename cplx_of<T>::type g,
+                                                    typename cplx_of<T>::type o, T al, T be, bool mix) {
+  typename cplx_of<T>::type v;
+  v.x = f.x - g.x;
+  v.y = f.y - g.y;
+  if (mix) {
+    v.x = al * v.x + be * o.x;
+    v.y = al * v.y + be * o.y;
+  }
+  return v;
+}
+
 // ----------------------------------------------------------------- update
 // C[i][col] -= sum_k MT[k][i] R[k][col] for the rows row_lo <= i < row_hi and
 // the combined columns col_lo <= col < ncols: the forward step takes the rows
@@ -829,6 +843,9 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
 // transposed into mtn[col][i], the next panel's MT, instead of into A (where
 // nothing reads them: the next pivot-row step writes U there); the next
 // panel's diagonal block (rows row_lo .. row_lo + ntc) is stored in A as usual.
+// In the back substitution the rows mix_lo .. row_hi (the panel above, whose F
+// is final after this launch) are also mixed into Phi as they are stored (the
+// epilogue's formula; B keeps F, the next launch's operand).
 // Tile shape and pipelining of the update: wave tile UWM x UWN, workgroup of
 // 2 x 2 waves, operand prefetch PF k-steps ahead; FULL = the panel is NB wide
 // (every panel but a ragged last one), so the panel rows need no clamping.
@@ -907,7 +924,7 @@ template <typename T, int NB, class CF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CF::WPE)))
 void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int col_lo,
                        const typename cplx_of<T>::type* mt0, size_t mt_bs, typename cplx_of<T>::type* mtn,
-                       int ntc) {
+                       int ntc, int mix_lo) {
   using C = typename cplx_of<T>::type;
   static_assert(!CF::BF3 || sizeof(T) == 4, "BF16x3 products take complex64 operands");
   using M = typename std::conditional<CF::BF3, MmaBF3, Mma<T>>::type;
@@ -933,7 +950,7 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
   // the loads carry no branches and are issued ahead of the matrix-core work.
   // Lanes of rows or columns that are not stored read finite data that never
   // reaches an output; panel rows k >= jb (ragged last panel) multiply the
-  // rows of MT that the panel step wrote as zeros.
+  // rows of MT that the multiplier copy wrote as zeros.
   C* cb[USC];
   bool cok[USC];
 #pragma unroll
@@ -995,6 +1012,23 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
     __builtin_amdgcn_sched_barrier(0);     // keep the prefetch ahead of this step's MFMAs
     acc.mac(ca, cbv);
   }
+  if (i0 >= mix_lo) {      // wave-uniform (mix_lo is a multiple of the workgroup tile height)
+    const int ncolA = n - j0 - jb;                 // B column = combined column - ncolA
+    const C* G = a.gamma + (size_t)blk * n * n;
+    C* P = a.phi + (size_t)blk * n * n;
+    const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
+    const bool mix = a.alpha != 1.0;
+    acc.store_c([&](int r, int c, C v) {
+      const int i = i0 + r;
+      const int y = c / M::TN;
+      if (cok[y] && i < row_hi) {
+        st_c<CF::NT>(&cb[y][(size_t)i * n], v);
+        const size_t e = (size_t)i * n + (c0 + c - ncolA);
+        P[e] = mix_phi<T>(v, ld_c<true>(&G[e]), mix ? ld_c<true>(&P[e]) : cz<C>(), al, be, mix);
+      }
+    });
+    return;
+  }
   C* MN = mtn + (size_t)blk * NB * n;
   acc.store_c([&](int r, int c, C v) {
     const int i = i0 + r;
@@ -1013,7 +1047,8 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
 // (forward step: the next panel's multipliers)
 template <typename T, int NB, class CF>
 void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int row_hi, int col_lo, bool ut,
-                   typename cplx_of<T>::type* mt, typename cplx_of<T>::type* mtn, int ntc, hipStream_t s) {
+                   typename cplx_of<T>::type* mt, typename cplx_of<T>::type* mtn, int ntc, hipStream_t s,
+                   int mix_lo = -1) {
   const auto* mt0 = ut ? a.A + (size_t)j0 * n : mt;
   const size_t mt_bs = ut ? (size_t)n * n : (size_t)NB * n;
   const int jb = std::min(NB, n - j0);
@@ -1021,46 +1056,45 @@ void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int ro
   const int nrb = (row_hi - row_lo + CF::WGM - 1) / CF::WGM;
   const int ncb = (ncols - col_lo + CF::WGN - 1) / CF::WGN;
   hipLaunchKernelGGL((bse_update_kernel<T, NB, CF>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb, row_lo,
-                     row_hi, col_lo, mt0, mt_bs, mtn ? mtn : mt, mtn ? ntc : 0);
+                     row_hi, col_lo, mt0, mt_bs, mtn ? mtn : mt, mtn ? ntc : 0, mix_lo < 0 ? n : mix_lo);
 }
 
 // --------------------------------------------------------------- epilogue
-// B holds F after the last panel: Phi <- alpha (F - Gamma) + (1 - alpha) Phi,
-// and the per-block pivot statistics.
+// Phi <- alpha (F - Gamma) + (1 - alpha) Phi for the rows whose F is final
+// when the back substitution is done with them: the back substitution mixes
+// the rows of every panel but the last as it stores them (update kernel,
+// mix_lo); this pass takes the rows row0 .. n (the last panel's, final after
+// its pivot-row step).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a) {
+__global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a, int row0) {
   using C = typename cplx_of<T>::type;
   const int blk = blockIdx.y, n = a.n;
   const size_t nn = (size_t)n * n;
   if (inactive(a, blk)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.stats) {
-    const double* ps = a.pst + (size_t)blk * kPst;
-    pq_bse_block_stats st;
-    const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
-    st.min_pivot = (float)ratio;
-    st.growth = (float)ps[4];
-    st.flags = (ps[2] > 0.0 ? 2 : 0) | ((ratio < a.weak_ratio || ps[4] > a.kappa_max) ? 1 : 0) |
-               (ps[3] > 0.0 ? 4 : 0);
-    st.reserved = 0;
-    a.stats[blk] = st;
-  }
   const C* F = a.B + (size_t)blk * nn;
   const C* G = a.gamma + (size_t)blk * nn;
   C* P = a.phi + (size_t)blk * nn;
   const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
   const bool mix = a.alpha != 1.0;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn; idx += (size_t)gridDim.x * blockDim.x) {
-    const C f = F[idx], g = G[idx];
-    C v;
-    v.x = f.x - g.x;
-    v.y = f.y - g.y;
-    if (mix) {
-      const C o = P[idx];
-      v.x = al * v.x + be * o.x;
-      v.y = al * v.y + be * o.y;
-    }
-    P[idx] = v;
-  }
+  for (size_t idx = (size_t)row0 * n + (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn;
+       idx += (size_t)gridDim.x * blockDim.x)
+    P[idx] = mix_phi<T>(F[idx], G[idx], mix ? P[idx] : cz<C>(), al, be, mix);
+}
+
+// Per-block pivot statistics (after the FP64 re-solve has marked its blocks).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void bse_stats_kernel(BseCtx<T> a) {
+  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= a.Nq || inactive(a, blk) || !a.stats) return;
+  const double* ps = a.pst + (size_t)blk * kPst;
+  pq_bse_block_stats st;
+  const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
+  st.min_pivot = (float)ratio;
+  st.growth = (float)ps[4];
+  st.flags = (ps[2] > 0.0 ? 2 : 0) | ((ratio < a.weak_ratio || ps[4] > a.kappa_max) ? 1 : 0) |
+             (ps[3] > 0.0 ? 4 : 0);
+  st.reserved = 0;
+  a.stats[blk] = st;
 }
 
 template <typename T>
@@ -1074,7 +1108,7 @@ constexpr int kRefineSlots = 8;
 struct BseLayout {
   size_t A, B, MT, PI, pst;
   // complex64 path only: FP64 re-solve of flagged blocks
-  size_t list, g64, x64, p64, ws64;
+  size_t list, g64, x64, p64, phis, ws64;
   size_t total;
 };
 
@@ -1098,6 +1132,7 @@ BseLayout bse_layout(const Dims& d) {
     L.g64 = take(sizeof(double2) * nn * kRefineSlots);
     L.x64 = take(sizeof(double2) * (size_t)d.n * kRefineSlots);
     L.p64 = take(sizeof(double2) * nn * kRefineSlots);
+    L.phis = take(sizeof(float2) * nn * kRefineSlots);
     L.ws64 = take(bse_layout<double>(r).total);
   }
   L.total = off;
@@ -1136,8 +1171,9 @@ __global__ __launch_bounds__(kThreads) void refine_list_kernel(const double* pst
   }
 }
 
-__global__ __launch_bounds__(kThreads) void refine_gather_kernel(const float2* gamma, const double2* chi0, int n,
-                                                                  const int* list, double2* g64, double2* x64) {
+__global__ __launch_bounds__(kThreads) void refine_gather_kernel(const float2* gamma, const double2* chi0,
+                                                                  const float2* phi, int n, const int* list,
+                                                                  double2* g64, double2* x64, float2* phis) {
   const int slot = blockIdx.y;
   if (slot >= list[kRefineSlots]) return;
   const int b = list[slot];
@@ -1145,20 +1181,30 @@ __global__ __launch_bounds__(kThreads) void refine_gather_kernel(const float2* g
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
     const float2 v = gamma[(size_t)b * nn + i];
     g64[(size_t)slot * nn + i] = mk((double)v.x, (double)v.y);
+    phis[(size_t)slot * nn + i] = phi[(size_t)b * nn + i];     // Phi before this solve (for the mixing)
   }
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < n; i += blockDim.x) x64[(size_t)slot * n + i] = chi0[(size_t)b * n + i];
 }
 
-__global__ __launch_bounds__(kThreads) void refine_scatter_kernel(const double2* p64, const double2* g64, int n,
-                                                                   const int* list, float2* B, double* pst) {
+// Phi of a re-solved block <- alpha (F - Gamma)_64 + (1 - alpha) Phi_saved,
+// replacing what the complex64 back substitution mixed into it.
+__global__ __launch_bounds__(kThreads) void refine_scatter_kernel(const double2* p64, const float2* phis, int n,
+                                                                   const int* list, double alpha, float2* phi,
+                                                                   double* pst) {
   const int slot = blockIdx.y;
   if (slot >= list[kRefineSlots]) return;
   const int b = list[slot];
   const size_t nn = (size_t)n * n;
+  const bool mix = alpha != 1.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
-    const double2 f = cadd(p64[(size_t)slot * nn + i], g64[(size_t)slot * nn + i]);
-    B[(size_t)b * nn + i] = mkf((float)f.x, (float)f.y);
+    double2 v = p64[(size_t)slot * nn + i];
+    if (mix) {
+      const float2 o = phis[(size_t)slot * nn + i];
+      v.x = alpha * v.x + (1.0 - alpha) * (double)o.x;
+      v.y = alpha * v.y + (1.0 - alpha) * (double)o.y;
+    }
+    phi[(size_t)b * nn + i] = mkf((float)v.x, (float)v.y);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) pst[(size_t)b * kPst + 3] = 1.0;
 }
@@ -1212,7 +1258,6 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     }
   };
   if (tm) tm->update_flops = 0.0;
-  const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)n * n + kThreads - 1) / kThreads);
   // Multipliers: two buffers, panel J in buffer J % 2. The multiplier copy
   // runs for the first panel (formed from Gamma) and a ragged last panel; every
   // other panel's multipliers come from the previous forward update (rows
@@ -1256,43 +1301,58 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
       if (tm) tm->update_flops += 8.0 * (double)(n - lo) * ncols * jb * d.Nq;
     }
   }
+  // complex64 path: the blocks the pivot monitor flagged (the monitor is
+  // complete after the forward sweep) are listed and gathered for the FP64
+  // re-solve now, with their Phi, which the back substitution's mixing
+  // overwrites (none flagged: empty launches)
+  int* list = nullptr;
+  double2 *g64 = nullptr, *x64 = nullptr, *p64 = nullptr;
+  float2* phis = nullptr;
+  const unsigned gx = (unsigned)std::min<size_t>(256, ((size_t)n * n + kThreads - 1) / kThreads);
+  if constexpr (sizeof(T) == 4) {
+    list = (int*)(w + L.list);
+    g64 = (double2*)(w + L.g64);
+    x64 = (double2*)(w + L.x64);
+    p64 = (double2*)(w + L.p64);
+    phis = (float2*)(w + L.phis);
+    hipLaunchKernelGGL(refine_list_kernel, dim3(1), dim3(kThreads), 0, s, a.pst, d.Nq, weak, kappa_max, list);
+    hipLaunchKernelGGL(refine_gather_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, (const float2*)gamma,
+                       chi0, (const float2*)phi_io, n, list, g64, x64, phis);
+  }
   // Back substitution: the rows of panel J of B hold F once every later panel
   // has been subtracted from them, so going from the last panel down, the
   // rows above panel J take B_I -= U_IJ F_J, with U_IJ read k-major from A
   // below the diagonal blocks (full panels) or from the multiplier copy of a
-  // ragged last panel.
+  // ragged last panel. The rows of panel J - 1 are final after the launch of
+  // panel J, which also mixes them into Phi.
   for (int j0 = last; j0 > 0; j0 -= NB) {
     const int jb = std::min(NB, n - j0);
     pre(3);
     if (jb == NB)
-      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s);
+      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s,
+                                                  j0 - NB);
     else
       launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, false, mtb[(j0 / NB) & 1],
-                                                   nullptr, 0, s);
+                                                   nullptr, 0, s, j0 - NB);
     post();
     if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
   }
+  // the last panel's rows, final since its pivot-row step
+  pre(4);
+  const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)(n - last) * n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a, last);
+  post();
   if constexpr (sizeof(T) == 4) {
-    // FP64 re-solve of the blocks the pivot monitor flagged (none: empty launches)
-    int* list = (int*)(w + L.list);
-    double2* g64 = (double2*)(w + L.g64);
-    double2* x64 = (double2*)(w + L.x64);
-    double2* p64 = (double2*)(w + L.p64);
     Dims r = d;
     r.Nq = kRefineSlots;
-    const unsigned gx = (unsigned)std::min<size_t>(256, ((size_t)n * n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(refine_list_kernel, dim3(1), dim3(kThreads), 0, s, a.pst, d.Nq, weak, kappa_max, list);
-    hipLaunchKernelGGL(refine_gather_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, (const float2*)gamma,
-                       chi0, n, list, g64, x64);
     hipError_t e = run_bse<double>(r, channel, 1.0, 1e-10f, 1e12, g64, x64, p64, nullptr, w + L.ws64, s, nullptr,
                                    list + kRefineSlots);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(refine_scatter_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, p64, g64, n, list,
-                       (float2*)a.B, a.pst);
+    hipLaunchKernelGGL(refine_scatter_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, (const double2*)p64,
+                       (const float2*)phis, n, list, alpha, (float2*)phi_io, a.pst);
   }
-  pre(4);
-  hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a);
-  post();
+  if (stats)
+    hipLaunchKernelGGL((bse_stats_kernel<T>), dim3((d.Nq + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
