@@ -31,9 +31,12 @@
 // the back substitution U k-major with no copy step. This is (4/3) n^3 complex
 // multiply-adds per block, the work of an LU factorisation and two n-column
 // triangular solves; full Gauss-Jordan, which also clears U, would take
-// 1.5 n^3. B then holds F, and bse_epilogue applies the mixing. Steps (b) and
-// (c) are complex products on the matrix cores (v_mfma_f32_32x32x2f32 for
-// complex64, v_mfma_f64_16x16x4f64 for complex128).
+// 1.5 n^3. B then holds F. The mixing Phi <- alpha (F - Gamma) + (1 - alpha)
+// Phi is done by each back-substitution launch for the rows it finishes (the
+// panel above), and by bse_epilogue for the last panel's rows (BF16x3
+// products: by bse_epilogue for every row). Steps (b) and (c) are complex
+// products on the matrix cores (v_mfma_f32_32x32x2f32 for complex64,
+// v_mfma_f64_16x16x4f64 for complex128).
 //
 // No row exchanges: A is the identity minus the small-norm kernel s Gamma X,
 // and every leading principal block of it stays invertible while the BSE is
@@ -1012,7 +1015,9 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
     __builtin_amdgcn_sched_barrier(0);     // keep the prefetch ahead of this step's MFMAs
     acc.mac(ca, cbv);
   }
-  if (i0 >= mix_lo) {      // wave-uniform (mix_lo is a multiple of the workgroup tile height)
+  // wave-uniform (mix_lo is a multiple of the workgroup tile height); the
+  // BF16x3 form never mixes here (the driver keeps its separate pass)
+  if (!CF::BF3 && i0 >= mix_lo) {
     const int ncolA = n - j0 - jb;                 // B column = combined column - ncolA
     const C* G = a.gamma + (size_t)blk * n * n;
     C* P = a.phi + (size_t)blk * n * n;
@@ -1060,11 +1065,11 @@ void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int ro
 }
 
 // --------------------------------------------------------------- epilogue
-// Phi <- alpha (F - Gamma) + (1 - alpha) Phi for the rows whose F is final
-// when the back substitution is done with them: the back substitution mixes
-// the rows of every panel but the last as it stores them (update kernel,
-// mix_lo); this pass takes the rows row0 .. n (the last panel's, final after
-// its pivot-row step).
+// Phi <- alpha (F - Gamma) + (1 - alpha) Phi for the rows row0 .. n: the back
+// substitution mixes the rows of every panel but the last as it stores them
+// (update kernel, mix_lo), so this pass takes the last panel's rows (final
+// after its pivot-row step), or every row where the back substitution does
+// not mix (BF16x3 products).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a, int row0) {
   using C = typename cplx_of<T>::type;
@@ -1143,10 +1148,11 @@ BseLayout bse_layout(const Dims& d) {
 // Blocks of a complex64 elimination whose pivot monitor reports a weak pivot
 // ratio or a non-finite pivot are solved again in FP64 from Gamma: a single
 // workgroup lists them (list[0..kRefineSlots), count in list[kRefineSlots],
-// total flagged in list[kRefineSlots + 1]), the blocks are gathered into
-// complex128 slots, the complex128 elimination runs on the slots (slots past
-// the count exit at once), and F = Phi64 + Gamma64 replaces B of the block
-// before the mixing epilogue.
+// total flagged in list[kRefineSlots + 1]) once the forward sweep has met
+// every pivot, the blocks are gathered into complex128 slots together with
+// their Phi before the mixing, the complex128 elimination runs on the slots
+// (slots past the count exit at once), and the block's Phi is mixed again from
+// the FP64 solution and the saved Phi, replacing the complex64 result.
 constexpr int kMaxBlocks = 4096;     // Nq < n <= 4096
 
 __global__ __launch_bounds__(kThreads) void refine_list_kernel(const double* pst, int Nq, float weak,
@@ -1324,23 +1330,29 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   // rows above panel J take B_I -= U_IJ F_J, with U_IJ read k-major from A
   // below the diagonal blocks (full panels) or from the multiplier copy of a
   // ragged last panel. The rows of panel J - 1 are final after the launch of
-  // panel J, which also mixes them into Phi.
+  // panel J, which also mixes them into Phi (not with the BF16x3 products: that
+  // update runs at one wave per SIMD with no registers to spare, and the loads
+  // of the mixing cost it more than the separate pass).
+  constexpr bool kFuseMix = !BF3;
   for (int j0 = last; j0 > 0; j0 -= NB) {
     const int jb = std::min(NB, n - j0);
+    const int mix_lo = kFuseMix ? j0 - NB : -1;
     pre(3);
     if (jb == NB)
       launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s,
-                                                  j0 - NB);
+                                                  mix_lo);
     else
       launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, false, mtb[(j0 / NB) & 1],
-                                                   nullptr, 0, s, j0 - NB);
+                                                   nullptr, 0, s, mix_lo);
     post();
     if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
   }
-  // the last panel's rows, final since its pivot-row step
+  // the rows not mixed yet: the last panel's (final since its pivot-row step),
+  // or all of them
+  const int row0 = kFuseMix ? last : 0;
   pre(4);
-  const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)(n - last) * n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a, last);
+  const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)(n - row0) * n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a, row0);
   post();
   if constexpr (sizeof(T) == 4) {
     Dims r = d;
