@@ -483,6 +483,67 @@ def test_bse_mixing_epilogue():
     assert relerr(H(io), ref) < 1e-11
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_bse_mixing_across_panels(prec):
+    """Phi <- alpha (F - Gamma) + (1 - alpha) Phi with several panels (n = 150:
+    the back substitution mixes the rows of every panel but the last as it
+    finishes them, a separate pass the last panel's rows; BF16x3 mixes every
+    row in that pass), all four channels, against the oracle."""
+    _print_case("bse-mix panels", prec)
+    p = _bse_config("bse_odd")
+    g, gam, xph, xpp = _bse_inputs(p, 17)
+    if prec != "fp64":
+        gam = gam.astype(np.complex64).astype(np.complex128)
+    old = random_phi(g.Nq, g.n, seed=19, scale=0.2)
+    if prec != "fp64":
+        old = old.astype(np.complex64).astype(np.complex128)
+    new = P.bse(g, gam, xph, xpp)
+    st = _ops().Stage(p, prec)
+    ws = torch.empty(st.bse_workspace_bytes(), dtype=torch.uint8, device=DEV)
+    for r in range(4):
+        X = xph if r < 2 else xpp
+        io = T(old[r], st.vdtype)
+        st.bse_solve(r, T(gam[r], st.vdtype), T(X), io, alpha=0.3, ws=ws)
+        ref = 0.3 * new[r] + 0.7 * old[r]
+        err = relerr(H(io).astype(np.complex128), ref)
+        assert err < BSE_TOL[prec], (r, err)
+
+
+def test_bse_flagged_blocks_mixed_from_saved_phi():
+    """The FP64 re-solve of flagged blocks with mixing (alpha = 0.4) and
+    several panels (n = 160): the re-solved blocks are mixed from the FP64
+    solution and the vertex saved before the complex64 back substitution
+    mixed it, so they match the oracle's alpha F64 + (1 - alpha) Phi_old to
+    complex64 storage accuracy; well-conditioned blocks keep the FP32 bound."""
+    _print_case("bse refine mix")
+    p = _bse_config("bse_ragged")
+    g, gam, xph, xpp = _bse_inputs(p, 404)
+    r = 1
+    sign = P.BSE_SIGN[r]
+    blocks = [2, 40, 77]
+    gam_r = _near_instability(gam[r], xph, sign, blocks)
+    old = random_phi(g.Nq, g.n, seed=405, scale=0.2)[r].astype(np.complex64).astype(np.complex128)
+    st = _ops().Stage(p, "fp32")
+    ws = torch.empty(st.bse_workspace_bytes(), dtype=torch.uint8, device=DEV)
+    stats = torch.empty((g.Nq, 4), dtype=torch.int32, device=DEV)
+    io = T(old, torch.complex64)
+    st.bse_solve(r, T(gam_r, torch.complex64), T(xph), io, alpha=0.4, stats=stats, ws=ws)
+    got = H(io).astype(np.complex128)
+    flags = H(stats)[:, 2]
+    refined = [q for q in range(g.Nq) if flags[q] & 4]
+    # the monitor's thresholds are heuristic: not every near-singular block
+    # need trip them, but only those can, and some do here
+    assert refined and set(refined) <= set(blocks), (blocks, refined)
+    for q in refined:
+        ref = 0.4 * P.bse_block(gam_r[q], xph[q], sign) + 0.6 * old[q]
+        err = relerr(got[q], ref)
+        assert err < 1e-6, (q, err)
+    for q in (0, 1, g.Nq - 1):
+        if q not in refined:
+            ref = 0.4 * P.bse_block(gam_r[q], xph[q], sign) + 0.6 * old[q]
+            assert relerr(got[q], ref) < 2e-4, q
+
+
 def test_sigma_mix_and_norm():
     p = config("tiny_2x2")
     g = _grid(p)
