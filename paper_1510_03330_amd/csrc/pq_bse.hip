@@ -33,8 +33,8 @@
 // triangular solves; full Gauss-Jordan, which also clears U, would take
 // 1.5 n^3. B then holds F. The mixing Phi <- alpha (F - Gamma) + (1 - alpha)
 // Phi is done by each back-substitution launch for the rows it finishes (the
-// panel above), and by bse_epilogue for the last panel's rows (BF16x3
-// products: by bse_epilogue for every row). Steps (b) and (c) are complex
+// panel above), and by the last panel's pivot-row step for its own rows
+// (BF16x3 products: by bse_epilogue for every row). Steps (b) and (c) are complex
 // products on the matrix cores (v_mfma_f32_32x32x2f32 for complex64,
 // v_mfma_f64_16x16x4f64 for complex128).
 //
@@ -654,6 +654,20 @@ __global__ __launch_bounds__(kThreads) void bse_multcopy_kernel(BseCtx<T> a, int
   copy_multipliers<T, NB>(a, blockIdx.y, j0, blockIdx.x * 32, X);
 }
 
+// Mixing of the solved vertex: Phi <- alpha (F - Gamma) + (1 - alpha) Phi.
+template <typename T>
+__device__ inline typename cplx_of<T>::type mix_phi(typename cplx_of<T>::type f, typename cplx_of<T>::type g,
+                                                    typename cplx_of<T>::type o, T al, T be, bool mix) {
+  typename cplx_of<T>::type v;
+  v.x = f.x - g.x;
+  v.y = f.y - g.y;
+  if (mix) {
+    v.x = al * v.x + be * o.x;
+    v.y = al * v.y + be * o.y;
+  }
+  return v;
+}
+
 // ------------------------------------------------------------------ panel
 // One 32-column strip per wave: R = P A_J,strip for RW rows of the panel at
 // once (RW / 32 accumulator tiles in the three-product form; NB / RW waves per
@@ -709,7 +723,7 @@ template <typename T, int NB> constexpr int panel_rows_per_wave() { return sizeo
 
 template <typename T, int NB, bool FIRST, int RW = NB, int PFB = 2>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
-void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
+void bse_panel_kernel(BseCtx<T> a, int j0, int nwb, int mix) {
   using C = typename cplx_of<T>::type;
   using M = Mma<T>;
   using WT = WTile<T>;
@@ -797,7 +811,15 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
       for (int rt = 0; rt < NRT; ++rt) {
         acc[rt].store_prod([&](int r, int c, C v) {
           const int row = rb + rt * 32 + r, col = cs * 32 + c;
-          if (row < jb && col < ncols) colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
+          if (row < jb && col < ncols) {
+            colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
+            // the last panel: its B rows are final F, mixed into Phi here
+            if (mix && col >= ncolA) {
+              const size_t e = (size_t)blk * n * n + (size_t)(j0 + row) * n + (col - ncolA);
+              const bool m = a.alpha != 1.0;
+              a.phi[e] = mix_phi<T>(v, a.gamma[e], m ? a.phi[e] : cz<C>(), (T)a.alpha, (T)(1.0 - a.alpha), m);
+            }
+          }
           if (tr) ts[c][r] = v;
         });
         if (tr) {
@@ -820,20 +842,6 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb) {
       }
     }
   }
-}
-
-// Mixing of the solved vertex: Phi <- alpha (F - Gamma) + (1 - alpha) Phi.
-template <typename T>
-__device__ inline typename cplx_of<T>::type mix_phi(typename cplx_of<T>::type f, typename cplx_of<T>::type g,
-                                                    typename cplx_of<T>::type o, T al, T be, bool mix) {
-  typename cplx_of<T>::type v;
-  v.x = f.x - g.x;
-  v.y = f.y - g.y;
-  if (mix) {
-    v.x = al * v.x + be * o.x;
-    v.y = al * v.y + be * o.y;
-  }
-  return v;
 }
 
 // ----------------------------------------------------------------- update
@@ -1065,11 +1073,9 @@ void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int ro
 }
 
 // --------------------------------------------------------------- epilogue
-// Phi <- alpha (F - Gamma) + (1 - alpha) Phi for the rows row0 .. n: the back
-// substitution mixes the rows of every panel but the last as it stores them
-// (update kernel, mix_lo), so this pass takes the last panel's rows (final
-// after its pivot-row step), or every row where the back substitution does
-// not mix (BF16x3 products).
+// Phi <- alpha (F - Gamma) + (1 - alpha) Phi for the rows row0 .. n, where
+// the kernels that finish the rows do not mix them (BF16x3 products: every
+// row; otherwise the back substitution and the last pivot-row step mix).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a, int row0) {
   using C = typename cplx_of<T>::type;
@@ -1271,6 +1277,31 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   // entries above it, stored in A below the diagonal blocks).
   C* mtb[2] = {a.MT, a.MT + (size_t)NB * n * d.Nq};
   const int last = (a.nJ - 1) * NB;
+  // The mixing is fused into the kernels that finish rows of F: the
+  // back-substitution launch of panel J for the rows of panel J - 1, the last
+  // panel's pivot-row step for its own rows (not with the BF16x3 products:
+  // that update runs at one wave per SIMD with no registers to spare, and the
+  // loads of the mixing cost it more than a separate pass over every row).
+  constexpr bool kFuseMix = !BF3;
+  // complex64 path: the blocks the pivot monitor flagged (complete once the
+  // last pivot is met) are listed and gathered for the FP64 re-solve before
+  // any row is mixed, with their Phi (none flagged: empty launches)
+  int* list = nullptr;
+  double2 *g64 = nullptr, *x64 = nullptr, *p64 = nullptr;
+  float2* phis = nullptr;
+  const unsigned gx = (unsigned)std::min<size_t>(256, ((size_t)n * n + kThreads - 1) / kThreads);
+  auto refine_gather = [&]() {
+    if constexpr (sizeof(T) == 4) {
+      list = (int*)(w + L.list);
+      g64 = (double2*)(w + L.g64);
+      x64 = (double2*)(w + L.x64);
+      p64 = (double2*)(w + L.p64);
+      phis = (float2*)(w + L.phis);
+      hipLaunchKernelGGL(refine_list_kernel, dim3(1), dim3(kThreads), 0, s, a.pst, d.Nq, weak, kappa_max, list);
+      hipLaunchKernelGGL(refine_gather_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, (const float2*)gamma,
+                         chi0, (const float2*)phi_io, n, list, g64, x64, phis);
+    }
+  };
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int jb = std::min(NB, n - j0);
     const int ncols = (n - j0 - jb) + n;
@@ -1283,13 +1314,15 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
       hipLaunchKernelGGL((bse_multcopy_kernel<T, NB>), dim3((n + 31) / 32, d.Nq), dim3(kThreads), 0, s, am, j0);
     }
     post();
+    if (j0 == last) refine_gather();
     constexpr int RW = panel_rows_per_wave<T, NB>();
     const int nwb = ((ncols + 31) / 32 * (NB / RW) + kWaves - 1) / kWaves;
+    const int mix = kFuseMix && j0 == last ? 1 : 0;
     pre(2);
     if (j0 == 0)
-      hipLaunchKernelGGL((bse_panel_kernel<T, NB, true, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
+      hipLaunchKernelGGL((bse_panel_kernel<T, NB, true, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb, mix);
     else
-      hipLaunchKernelGGL((bse_panel_kernel<T, NB, false, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb);
+      hipLaunchKernelGGL((bse_panel_kernel<T, NB, false, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb, mix);
     post();
     // forward step: the rows below the panel (none below the last one); the
     // full panels before the last are the only ones with rows below
@@ -1307,33 +1340,12 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
       if (tm) tm->update_flops += 8.0 * (double)(n - lo) * ncols * jb * d.Nq;
     }
   }
-  // complex64 path: the blocks the pivot monitor flagged (the monitor is
-  // complete after the forward sweep) are listed and gathered for the FP64
-  // re-solve now, with their Phi, which the back substitution's mixing
-  // overwrites (none flagged: empty launches)
-  int* list = nullptr;
-  double2 *g64 = nullptr, *x64 = nullptr, *p64 = nullptr;
-  float2* phis = nullptr;
-  const unsigned gx = (unsigned)std::min<size_t>(256, ((size_t)n * n + kThreads - 1) / kThreads);
-  if constexpr (sizeof(T) == 4) {
-    list = (int*)(w + L.list);
-    g64 = (double2*)(w + L.g64);
-    x64 = (double2*)(w + L.x64);
-    p64 = (double2*)(w + L.p64);
-    phis = (float2*)(w + L.phis);
-    hipLaunchKernelGGL(refine_list_kernel, dim3(1), dim3(kThreads), 0, s, a.pst, d.Nq, weak, kappa_max, list);
-    hipLaunchKernelGGL(refine_gather_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, (const float2*)gamma,
-                       chi0, (const float2*)phi_io, n, list, g64, x64, phis);
-  }
   // Back substitution: the rows of panel J of B hold F once every later panel
   // has been subtracted from them, so going from the last panel down, the
   // rows above panel J take B_I -= U_IJ F_J, with U_IJ read k-major from A
   // below the diagonal blocks (full panels) or from the multiplier copy of a
   // ragged last panel. The rows of panel J - 1 are final after the launch of
-  // panel J, which also mixes them into Phi (not with the BF16x3 products: that
-  // update runs at one wave per SIMD with no registers to spare, and the loads
-  // of the mixing cost it more than the separate pass).
-  constexpr bool kFuseMix = !BF3;
+  // panel J, which also mixes them into Phi.
   for (int j0 = last; j0 > 0; j0 -= NB) {
     const int jb = std::min(NB, n - j0);
     const int mix_lo = kFuseMix ? j0 - NB : -1;
@@ -1347,13 +1359,12 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     post();
     if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
   }
-  // the rows not mixed yet: the last panel's (final since its pivot-row step),
-  // or all of them
-  const int row0 = kFuseMix ? last : 0;
-  pre(4);
-  const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)(n - row0) * n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a, row0);
-  post();
+  if (!kFuseMix) {            // every row in a separate pass
+    pre(4);
+    const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)n * n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a, 0);
+    post();
+  }
   if constexpr (sizeof(T) == 4) {
     Dims r = d;
     r.Nq = kRefineSlots;
