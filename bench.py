@@ -493,6 +493,110 @@ def cpu_baseline(p):
                 stage_seconds={k: round(v, 3) for k, v in parts.items()})
 
 
+def _oracle_iteration_by_stage(p, g, st, tag):
+    """One oracle iteration (the steps of oracle.parquet.iterate, called one by
+    one) with the seconds of each step; a progress line after each."""
+    from oracle import parquet as P
+    t = {}
+
+    def step(name, f):
+        t0 = time.perf_counter()
+        out = f()
+        t[name] = round(time.perf_counter() - t0, 3)
+        print(f"[oracle] {tag} {name} {t[name]:.1f} s", file=sys.stderr, flush=True)
+        return out
+
+    mu = step("filling", lambda: P.find_mu(p, g, st.sigma))
+    G = step("dyson", lambda: P.dyson(p, g, st.sigma, mu))
+    xph, xpp = step("bubbles", lambda: P.bubbles(p, g, G))
+    K1, K2 = step("kernels", lambda: P.kernel_functions(g, st.phi, p.kernel_level, p.edge_rule))
+    gamma = step("remap", lambda: P.remap(g, st.phi, K1, K2, P.pa_lambda(p.U)))
+    F = P.full_vertex(gamma, st.phi)
+    step("sigma", lambda: P.sigma_sde(p, g, G, F, K1, K2, mu))
+    step("bse", lambda: P.bse(g, gamma, xph, xpp))
+    return t
+
+
+def oracle_timing():
+    """The FP64 oracle timed on this host beside the GPU (the configurations of
+    the oracle-timing plan): the local problem (Nk = 1, Nv = 32, semicircle,
+    U = 1, beta = 5, tol 1e-8) end to end on all cores and on one core, the
+    4x4 lattice (Nv = 16, U = 2, beta = 4) per iteration on all cores and on
+    one core; the GPU complex128 (and complex64) solver on the same inputs."""
+    import numpy as np
+    import torch
+    from oracle import parquet as P
+    from paper_1510_03330_amd.ops import Solver
+    from workloads import config
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threadpool_limits = None
+        cores = os.cpu_count() or 1
+    out = {"mode": "oracle_timing", "host_threads": int(cores)}
+
+    # local problem, end to end
+    p1 = config("c1")
+    res = {}
+    for label, limit in (("all_cores", None), ("one_core", 1)):
+        ctx = threadpool_limits(limit) if (limit and threadpool_limits) else None
+        t0 = time.perf_counter()
+        if ctx is not None:
+            with ctx:
+                st = P.solve(p1, max_iter=400)
+        else:
+            st = P.solve(p1, max_iter=400)
+        res[label] = dict(sec=round(time.perf_counter() - t0, 2), iterations=int(st.iteration),
+                          dsigma=float(st.last_dsigma), threads=1 if limit else int(cores))
+        print(f"[oracle] c1 {label}: {res[label]}", file=sys.stderr, flush=True)
+        sig_oracle = st.sigma
+    torch.cuda.synchronize()
+    s = Solver(p1, "fp64", device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, conv, _ = s.iterate(400, p1.tol)
+    torch.cuda.synchronize()
+    gsec = time.perf_counter() - t0
+    sig_gpu = s.get("sigma").cpu().numpy()
+    s.close()
+    res["gpu_fp64"] = dict(sec=round(gsec, 3), iterations=int(done), converged=bool(conv))
+    res["converged_sigma_gpu_vs_oracle"] = {
+        "max_abs_diff": float(np.max(np.abs(sig_gpu - sig_oracle))),
+        "max_rel_diff": float(np.max(np.abs(sig_gpu - sig_oracle)) / np.max(np.abs(sig_oracle)))}
+    res["workload"] = "local model, semicircle bath D=2, U=1, beta=5, half filling, Nv=32, tol 1e-8"
+    out["c1"] = res
+
+    # 4x4 lattice, one iteration from the bare-vertex start
+    p2 = config("c2")
+    g2 = P.Grid(p2.Lx, p2.Ly, p2.Nv, p2.f_ext)
+    res = {"workload": "4x4 lattice, t=1, t'=0, U=2, beta=4, half filling, Nv=16 (240 blocks of n=256); "
+                       "the bare-vertex start diverges at these parameters (the magnetic block at (pi,pi) "
+                       "is near-singular), so the comparison is per iteration"}
+    for label, limit in (("all_cores", None), ("one_core", 1)):
+        st = P.init_state(p2, g2)
+        ctx = threadpool_limits(limit) if (limit and threadpool_limits) else None
+        t0 = time.perf_counter()
+        if ctx is not None:
+            with ctx:
+                stages = _oracle_iteration_by_stage(p2, g2, st, "c2 " + label)
+        else:
+            stages = _oracle_iteration_by_stage(p2, g2, st, "c2 " + label)
+        res["oracle_" + label] = dict(sec_per_iteration=round(time.perf_counter() - t0, 2), stages=stages,
+                                      threads=1 if limit else int(cores))
+    for prec in ("fp64", "fp32"):
+        s = Solver(p2, prec, device="cuda:0")
+        s.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(5)
+        torch.cuda.synchronize()
+        res["gpu_%s_ms_per_iteration" % prec] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+        s.close()
+    out["c2"] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -506,6 +610,9 @@ def main():
                     help="run only the kernel-level / regulation / U-range study (one JSON line)")
     ap.add_argument("--batch", action="store_true",
                     help="run only the 64-instance batched-solver study (one JSON line)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the FP64 oracle on this host beside the GPU (local problem end to end, "
+                         "4x4 lattice per iteration; one JSON line)")
     ap.add_argument("--warmstart-lattice", action="store_true",
                     help="run only the learned warm-start study on the 4x4 lattice (one JSON line)")
     ap.add_argument("--warmstart", action="store_true",
@@ -533,6 +640,9 @@ def main():
         return
     if args.warmstart_lattice:
         print(json.dumps(warmstart_study(lattice=True)))
+        return
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()))
         return
     from workloads import config
     p = config(args.workload)
