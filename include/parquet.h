@@ -272,8 +272,11 @@ typedef struct {
   double mu;               /* mu~ used by the last iteration                    */
   double ms_total;         /* wall time of the last iteration (device events)   */
   double ms_stage[8];      /* dyson, bubbles+kernels, -, remap, sigma, bse (4 channels), mix, - */
-  /* BSE of the density channel, per kernel kind (init, pivot, panel, update,
-   * epilogue): summed device time of its launches and the number of launches */
+  /* BSE of the density channel, per kernel kind (init, pivot and multiplier
+   * copy, pivot rows, update, separate mixing pass): summed device time of its
+   * launches and the number of launches. The update includes the back
+   * substitution and the mixing fused into it; the separate mixing pass runs
+   * only with BF16x3 products (otherwise 0 launches). */
   double ms_bse_kernel[5];
   int32_t n_bse_launch[5];
   int32_t reserved;
