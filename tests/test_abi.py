@@ -68,18 +68,6 @@ def test_dims_from_params(name):
     assert d.vertex_elems == d.Nq * d.n * d.n
 
 
-def test_quadrature_node_count_matches_the_oracle_definition():
-    import math
-    import numpy as np
-    from oracle import parquet as P
-    for name in ("c1", "c3", "tiny_2x2"):
-        p = config(name)
-        d = N.dims(N.make_params(p, "fp64"))
-        g = P.Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
-        tau, _ = P.tau_grid(p, g, 0.0)
-        assert d.ntau == len(tau)
-
-
 @pytest.mark.parametrize("bad", [dict(Nv=7), dict(Nv=0), dict(f_ext=0), dict(kernel_level=3),
                                  dict(alpha=0.0), dict(alpha=1.5), dict(beta=-1.0), dict(Lx=9, Ly=9),
                                  dict(edge_rule=2), dict(mu_mode=4)])

@@ -254,3 +254,27 @@ def test_box_correction_vanishes_when_kernels_are_exact():
     sb = P.sigma_box(p, g, G, F, K1, K2)
     assert np.max(np.abs(sb)) < 1e-14
     assert np.max(np.abs(P.sigma_tilde2(p, g, G, K1, K2))) > 1e-4
+
+
+def test_semicircle_pole_sum_is_converged():
+    """The pole representation of the semicircle no longer changes with the
+    number of poles: G0 at every box frequency and Sigma~_1 of the local
+    problem agree for 200 and 320 poles (and the pole sum equals the closed
+    form of G0)."""
+    p = config("c1")
+    g = P.Grid(1, 1, p.Nv, p.f_ext)
+    nu = g.nu(g.fext(), p.beta)
+    g0 = P.g0_semicircle(nu, p.D)
+    for M in (200, 320):
+        e, c = P.semicircle_poles(p.D, M)
+        gp = (c[None, :] / (1j * nu[:, None] - e[None, :])).sum(axis=1)
+        assert np.max(np.abs(gp - g0)) < 1e-14
+    G = P.dyson(p, g, np.zeros((g.Nve, 1), complex), 0.0)
+    a = P.sigma_tilde1(p, g, G, 0.0)
+    orig = P.semicircle_poles
+    try:
+        P.semicircle_poles = lambda D, M=320: orig(D, 320)
+        b = P.sigma_tilde1(p, g, G, 0.0)
+    finally:
+        P.semicircle_poles = orig
+    assert np.max(np.abs(a - b)) < 1e-14 * np.max(np.abs(a))

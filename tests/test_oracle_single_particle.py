@@ -150,3 +150,27 @@ def test_pp_bubble_finite_transfer_matches_direct_pairs():
             ref_ph = T / g.Nk * Gof(odd_k, K) * Gof(odd_k + even_q, g.kadd(K, Q))
             assert abs(xpp[qi, ki] - ref_pp) < 1e-15
             assert abs(xph[qi, ki] - ref_ph) < 1e-15
+
+
+@pytest.mark.parametrize("t,tp", [(1.0, -0.2), (1.3, -0.37), (0.7, 0.25)])
+def test_dispersion_at_high_symmetry_points(t, tp):
+    """epsilon_K at the high-symmetry points of the square lattice, values that
+    follow from cos 0 = 1, cos pi = -1, cos pi/2 = 0 alone:
+    (0,0): -4t - 4t';  (pi,pi): 4t - 4t';  (pi,0) and (0,pi): 4t';
+    (pi/2,0) and (0,pi/2): -2t;  (pi/2,pi/2): 0. A 4x4 grid (K = kx Ly + ky,
+    k = 2 pi kx / Lx) and a 2x4 grid, which also fixes the orientation of the
+    momentum index."""
+    g = P.Grid(4, 4, 2, 1)
+    eps = P.dispersion(g, t, tp)
+    K = lambda kx, ky: kx * 4 + ky
+    expect = {K(0, 0): -4 * t - 4 * tp, K(2, 2): 4 * t - 4 * tp, K(2, 0): 4 * tp, K(0, 2): 4 * tp,
+              K(1, 0): -2 * t, K(0, 1): -2 * t, K(3, 0): -2 * t, K(1, 1): 0.0, K(1, 2): 2 * t}
+    for k, v in expect.items():
+        assert abs(eps[k] - v) < 1e-14, (k, eps[k], v)
+    g2 = P.Grid(2, 4, 2, 1)
+    e2 = P.dispersion(g2, t, tp)
+    # kx in {0, pi}, ky in {0, pi/2, pi, 3pi/2}: K = kx_index * 4 + ky_index
+    assert abs(e2[1] - (-2 * t)) < 1e-14          # (0, pi/2)
+    assert abs(e2[4] - 4 * tp) < 1e-14            # (pi, 0)
+    assert abs(e2[6] - (4 * t - 4 * tp)) < 1e-14  # (pi, pi)
+    assert abs(e2[5] - 2 * t) < 1e-14             # (pi, pi/2)
