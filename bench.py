@@ -66,8 +66,8 @@ def run_gpu(p, precision, steps, warmup):
     torch.cuda.synchronize()
     bse_ms = []
     stage = [0.0] * 8
-    kern_ms = [0.0] * 5
-    kern_n = [0] * 5
+    kern_ms = [0.0] * 6
+    kern_n = [0] * 6
     upd_flops = 0.0
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -75,7 +75,7 @@ def run_gpu(p, precision, steps, warmup):
         bse_ms.append(st.ms_stage[5])
         for i in range(8):
             stage[i] += st.ms_stage[i] / steps
-        for i in range(5):
+        for i in range(6):
             kern_ms[i] += st.ms_bse_kernel[i]
             kern_n[i] += st.n_bse_launch[i]
         upd_flops += st.update_flops
@@ -684,7 +684,8 @@ def main():
             "bse_solve_lu_equivalent_tflops": round(bse_alg, 2),
             "bse_solve_ms_per_channel": round(bse_channel_ms, 2),
             "bse_kernel_ms_per_channel": {k: round(r32["kern_ms"][i] / args.steps, 2) for k, i in
-                                          (("pivot", 1), ("pivot_rows", 2), ("update", 3), ("epilogue", 4))}}
+                                          (("pivot", 1), ("pivot_rows", 2), ("update", 3), ("epilogue", 4),
+                                           ("error_estimate_and_fp64_resolve", 5))}}
 
     # remap: algorithmic bytes (read the 4 Phi arrays, write the 4 Gamma arrays
     # once) over its stage time, against the HBM peak and against a plain copy

@@ -62,8 +62,11 @@ typedef enum {
   PQ_ERR_ARG = 1,          /* invalid argument, nothing enqueued            */
   PQ_ERR_HIP = 2,          /* a HIP runtime call failed                      */
   PQ_ERR_NOMEM = 3,        /* workspace too small                            */
-  PQ_ERR_SINGULAR = 4,     /* a BSE block lost its pivots (see bse stats)    */
-  PQ_ERR_NOT_CONVERGED = 5,
+  PQ_ERR_SINGULAR = 4,     /* context API: a BSE block of the last iteration
+                              is unresolved (stats bit 3: no finite FP64
+                              solution, or flagged beyond the re-solve slots) */
+  PQ_ERR_NOT_CONVERGED = 5,/* context API: n_iter iterations done, tol > 0
+                              not reached (the state is valid; call again)   */
   PQ_ERR_NONFINITE = 6     /* NaN/Inf in Sigma                               */
 } pq_status;
 
@@ -92,12 +95,18 @@ typedef struct {
   int32_t mu_mode;         /* 0 fixed mu~ = mu_fixed, 1 bisection on filling */
   int32_t storage;         /* pq_storage of the vertex arrays                */
   int32_t precision;       /* pq_precision of the BSE                        */
-  int32_t reserved;
+  int32_t resolve_slots;   /* complex64 BSE: at most this many flagged blocks
+                              per channel are re-solved in FP64 (0: as many
+                              as a re-solve budget of 2.5 GiB holds, at
+                              least 8, at most Nq)                           */
   double U, beta, t, tp;   /* interaction, inverse temperature, hoppings     */
   double filling;          /* total density n for mu_mode = 1                */
   double D;                /* semicircle half-bandwidth (local mode)         */
   double mu_fixed;
   double alpha;            /* linear mixing of Sigma and Phi, (0, 1]         */
+  double bse_tol;          /* complex64 BSE: a block whose estimated relative
+                              error exceeds this is re-solved in FP64
+                              (0 selects 1e-5)                                */
 } pq_params;
 
 /* Sizes derived from pq_params (filled by pq_dims_from_params). */
@@ -150,10 +159,12 @@ pq_status kernel_extract(const pq_params* p, const void* phi, void* k1, void* k2
  * Lambda_r(m; n, n') (results section: full parquet / parquet DGA take a
  * local Lambda, extended outside the box by U, -U, 2U, 0), index
  * [r][m + Nv/2 - 1][n + Nv/2][n' + Nv/2], used in place of lambda at every
- * momentum. phi, gamma_out: [4][Nq][n][n] storage precision, must not alias. */
+ * momentum. phi, gamma_out: [4][Nq][n][n] storage precision, must not alias.
+ * f_out (nullable, same layout, must alias neither): the full vertex
+ * F_r = Gamma_r + Phi_r (Eq. PA_F_G), which is Eq. PA_F. */
 pq_status channel_remap(const pq_params* p, const double lambda[4], const void* lambda_box,
                         const void* phi, const void* k1, const void* k2, void* gamma_out,
-                        pq_stream stream);
+                        void* f_out, pq_stream stream);
 
 /* Workspace bytes for sigma_sde. */
 pq_status sigma_sde_workspace(const pq_params* p, size_t* bytes);
@@ -182,12 +193,22 @@ typedef struct {
   float min_pivot;       /* smallest |pivot| / largest |pivot| of the block  */
   float growth;          /* largest |entry| of the inverted diagonal blocks
                             (a lower bound of |A^-1| for the last block)     */
-  int32_t flags;         /* bit 0: weak (pivot ratio below 1e-3, or growth
-                            above 1e3, on the complex64 path; 1e-10 / 1e12
-                            on the complex128 path), bit 1: non-finite,
-                            bit 2: re-solved in FP64 (complex64 path, at most
-                            8 flagged blocks per call, in q order)          */
-  int32_t reserved;
+  int32_t flags;         /* bit 0: flagged; complex64 paths: for the FP64
+                            re-solve (weak pivots: ratio below 1e-3 or growth
+                            above 1e3; a non-finite pivot; or an error
+                            estimate above the tolerance), complex128 path:
+                            weak pivots (ratio below 1e-10 or growth above
+                            1e12, a warning only);
+                            bit 1: non-finite values in the elimination;
+                            bit 2: re-solved in FP64 (complex64 paths);
+                            bit 3: unresolved -- flagged but not re-solved
+                            (no re-solve slot left, or the FP64 re-solve was
+                            not finite), or non-finite on the complex128
+                            path; the block's Phi is not trusted;
+                            bit 4: error estimate above the tolerance        */
+  float err_est;         /* complex64 paths: estimated relative error of the
+                            complex64 solution F (before any re-solve; +inf
+                            if non-finite); 0 on the complex128 path         */
 } pq_bse_block_stats;
 
 /* Bethe-Salpeter equation of one channel (Eq. PA_F_Phi) for every transfer q:
@@ -195,12 +216,23 @@ typedef struct {
  *   X = X_ph for d, m and X_pp for s, t,
  *   phi_io <- alpha (F - Gamma_r) + (1 - alpha) phi_io   (alpha = 1: plain output).
  * Elimination without row exchanges (A is the identity minus a small-norm
- * kernel); the pivot monitor flags weak blocks in stats (nullable). On the
- * complex64/FP32 path up to 8 flagged blocks per call (in q order) are solved
- * again in FP64 from the same Gamma before the mixing (stats bit 2); the
- * workspace includes the room for that.
+ * kernel); the pivot monitor flags weak blocks in stats (nullable).
+ * Error control of the complex64 paths (FP32, BF16x3): after the solve, the
+ * relative error of every block's complex64 F is estimated in FP64 from two
+ * fixed pseudo-random probe vectors v: the residual r = A (F v) - Gamma v and,
+ * since A^-1 = 1 + s F X, the error estimate |r + s F (X r)| / |F v| (a cheap
+ * upper bound (1 + |F X|_F) |r| / |F v| first, the refined one only where the
+ * bound exceeds the tolerance). Blocks with weak pivots, a non-finite value or
+ * an estimate above params.bse_tol (default 1e-5) are solved again in FP64
+ * from the same Gamma and their Phi is replaced by the mixing of the FP64 F;
+ * at most resolve_slots blocks per call (in q order, weak-pivot blocks first),
+ * the others keep the complex64 result and stats bit 3. The workspace
+ * includes the room for the re-solve. Errors of the enqueued kernels cannot
+ * be returned by this enqueue-only call: check stats (bit 3) or use the
+ * context API, which returns PQ_ERR_SINGULAR for them.
  * gamma: [Nq][n][n] (one channel), chi0: [Nq][n] c128, phi_io: [Nq][n][n],
- * both in storage precision; ws: bse_workspace bytes. */
+ * both in storage precision; stats: [Nq] pq_bse_block_stats (device,
+ * nullable); ws: bse_workspace bytes. */
 pq_status bse_solve(const pq_params* p, int32_t channel, int32_t precision,
                     const void* gamma, const void* chi0, void* phi_io, double alpha,
                     void* stats, void* ws, size_t ws_bytes, pq_stream stream);
@@ -260,27 +292,34 @@ typedef enum {
   PQ_FIELD_MU = 6,     /* 1 double                 */
   PQ_FIELD_XPH = 7,    /* [Nq][n] c128             */
   PQ_FIELD_XPP = 8,    /* [Nq][n] c128             */
-  PQ_FIELD_LAMBDA = 9  /* [4][Nv-1][Nv][Nv] c128: local Lambda on the box (channel_remap's
+  PQ_FIELD_LAMBDA = 9, /* [4][Nv-1][Nv][Nv] c128: local Lambda on the box (channel_remap's
                           lambda_box); (U, -U, 2U, 0) after init; setting it makes the
                           context iterate with it (full parquet / parquet DGA input) */
+  PQ_FIELD_F = 10      /* [4][Nq][n][n] storage, get only: the full vertex of the
+                          current state, F_r = Gamma_r[Phi] + Phi_r (Eq. PA_F_G), with
+                          the kernel functions and Gamma recomputed from the current
+                          Phi (this refreshes the K1, K2 and GAMMA fields) */
 } pq_field;
 
 typedef struct {
   int32_t iteration;       /* iterations done since init                       */
-  int32_t flagged_blocks;  /* BSE blocks flagged by the pivot monitor (last it) */
+  int32_t flagged_blocks;  /* BSE blocks flagged (stats bit 0) in the last iteration */
   double dsigma;           /* max |Sigma_new - Sigma_old| of the last iteration */
   double mu;               /* mu~ used by the last iteration                    */
   double ms_total;         /* wall time of the last iteration (device events)   */
   double ms_stage[8];      /* dyson, bubbles+kernels, -, remap, sigma, bse (4 channels), mix, - */
   /* BSE of the density channel, per kernel kind (init, pivot and multiplier
-   * copy, pivot rows, update, separate mixing pass): summed device time of its
-   * launches and the number of launches. The update includes the back
-   * substitution and the mixing fused into it; the separate mixing pass runs
-   * only with BF16x3 products (otherwise 0 launches). */
-  double ms_bse_kernel[5];
-  int32_t n_bse_launch[5];
-  int32_t reserved;
+   * copy, pivot rows, update, separate mixing pass, error estimate and FP64
+   * re-solve): summed device time of its launches and the number of
+   * launches. The update includes the back substitution and the mixing fused
+   * into it; the separate mixing pass runs only with BF16x3 products
+   * (otherwise 0 launches); the last kind runs on the complex64 paths. */
+  double ms_bse_kernel[6];
+  int32_t n_bse_launch[6];
+  int32_t resolved_blocks;   /* blocks re-solved in FP64 (stats bit 2), last iteration */
+  int32_t unresolved_blocks; /* unresolved blocks (stats bit 3), last iteration        */
   double update_flops;     /* matrix-core flops of those update launches (8 per complex MAC) */
+  double max_err_est;      /* largest BSE error estimate of the last iteration (complex64) */
 } pq_iter_stats;
 
 /* Device bytes parquet_init needs in its workspace. */
@@ -293,7 +332,12 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
 
 /* Run up to n_iter iterations (Dyson -> bubbles -> kernels -> remap -> SDE ->
  * BSE -> mixing); stops early once max|Sigma_new - Sigma_old| < tol (tol <= 0:
- * never). Synchronises once per iteration for the norm. stats: host, nullable. */
+ * never). Synchronises once per iteration for the norm and a summary of the
+ * BSE block flags. stats: host, nullable. Returns PQ_OK (converged, or tol <= 0
+ * and n_iter done), PQ_ERR_NOT_CONVERGED (tol > 0 not reached in n_iter),
+ * PQ_ERR_NONFINITE (the new self-energy is not finite) or PQ_ERR_SINGULAR (a
+ * BSE block is unresolved); the last two stop after the iteration that met
+ * them, whose results are kept (*iters_done counts it). */
 pq_status parquet_iterate(pq_ctx* ctx, int32_t n_iter, double tol, pq_iter_stats* stats,
                           int32_t* iters_done, int32_t* converged);
 
@@ -304,8 +348,11 @@ pq_status parquet_iterate(pq_ctx* ctx, int32_t n_iter, double tol, pq_iter_stats
  * setting changed. Every round replays the graphs of the contexts that are
  * still active, each on its own stream, then reads each norm (one
  * synchronisation per context per round) and retires the converged ones
- * (max|Sigma_new - Sigma_old| < tol, tol <= 0: never) and those with a
- * non-finite self-energy (status PQ_ERR_NONFINITE, the others continue).
+ * (max|Sigma_new - Sigma_old| < tol, tol <= 0: never), those with a
+ * non-finite self-energy and those with an unresolved BSE block (the others
+ * continue). Returns the most severe outcome over the contexts:
+ * PQ_ERR_NONFINITE, then PQ_ERR_SINGULAR, then PQ_ERR_NOT_CONVERGED (tol > 0
+ * and a context still active after n_iter rounds), else PQ_OK.
  * ctxs: count contexts with distinct, created (non-null) streams;
  * iters_done, converged: host arrays of count entries, nullable. Not for
  * contexts another thread uses at the same time. */

@@ -59,6 +59,8 @@ bool make_dims(const pq_params* p, Dims* d) {
   if (!(p->beta > 0.0) || !isfinite(p->U) || !isfinite(p->beta)) { set_error("beta must be > 0 and U finite"); return false; }
   if (!(p->alpha > 0.0 && p->alpha <= 1.0)) { set_error("alpha must be in (0, 1]"); return false; }
   if (p->Lx * p->Ly == 1 && !(p->D > 0.0)) { set_error("local mode needs D > 0"); return false; }
+  if (p->resolve_slots < 0) { set_error("resolve_slots must be >= 0"); return false; }
+  if (!(p->bse_tol >= 0.0 && p->bse_tol <= 1.0)) { set_error("bse_tol must be in [0, 1]"); return false; }
   Dims x;
   x.Lx = p->Lx; x.Ly = p->Ly; x.Nk = p->Lx * p->Ly; x.Nv = p->Nv; x.NW = p->Nv - 1;
   x.f = p->f_ext; x.Nve = p->f_ext * p->Nv; x.NWe = x.Nve - 1; x.NG = 2 * x.Nve;
@@ -133,13 +135,17 @@ pq_status kernel_extract(const pq_params* p, const void* phi, void* k1, void* k2
 }
 
 pq_status channel_remap(const pq_params* p, const double lambda[4], const void* lambda_box, const void* phi,
-                        const void* k1, const void* k2, void* gamma_out, pq_stream stream) {
+                        const void* k1, const void* k2, void* gamma_out, void* f_out, pq_stream stream) {
   Dims d;
   if (!make_dims(p, &d)) return PQ_ERR_ARG;
   PQ_CHECK_ARG(lambda && phi && k1 && k2 && gamma_out, "null pointer");
   PQ_CHECK_ARG(phi != gamma_out, "phi and gamma_out must not alias");
-  return enq(launch_remap(*p, d, lambda, (const double2*)lambda_box, phi, (const double2*)k1,
-                          (const double2*)k2, gamma_out, (hipStream_t)stream), "channel_remap");
+  PQ_CHECK_ARG(f_out != phi && f_out != gamma_out, "f_out must alias neither phi nor gamma_out");
+  hipError_t e = launch_remap(*p, d, lambda, (const double2*)lambda_box, phi, (const double2*)k1,
+                              (const double2*)k2, gamma_out, (hipStream_t)stream);
+  if (e == hipSuccess && f_out)
+    e = launch_vertex_sum(gamma_out, phi, f_out, p->storage, 4 * (size_t)d.Nq * d.n * d.n, (hipStream_t)stream);
+  return enq(e, "channel_remap");
 }
 
 pq_status sigma_sde_workspace(const pq_params* p, size_t* bytes) {
@@ -301,7 +307,7 @@ CtxLayout ctx_layout(const pq_params& p, const Dims& d) {
   L.sigma_new = take(sizeof(double2) * d.Nve * nk);
   L.g = take(sizeof(double2) * d.NG * nk);
   L.mu = take(sizeof(double));
-  L.dnorm = take(sizeof(double));
+  L.dnorm = take(5 * sizeof(double));      // the norm, then the BSE summary (bse_summary)
   L.xph = take(sizeof(double2) * (size_t)d.Nq * d.n);
   L.xpp = take(sizeof(double2) * (size_t)d.Nq * d.n);
   L.k1 = take(sizeof(double2) * 4 * (size_t)d.Nq);
@@ -325,7 +331,8 @@ size_t field_bytes(const pq_ctx* c, int f) {
     case PQ_FIELD_SIGMA: return sizeof(double2) * d.Nve * (size_t)d.Nk;
     case PQ_FIELD_G: return sizeof(double2) * d.NG * (size_t)d.Nk;
     case PQ_FIELD_PHI:
-    case PQ_FIELD_GAMMA: return elem_bytes(c->p) * (size_t)d.Nq * d.n * d.n * 4;
+    case PQ_FIELD_GAMMA:
+    case PQ_FIELD_F: return elem_bytes(c->p) * (size_t)d.Nq * d.n * d.n * 4;
     case PQ_FIELD_K1: return sizeof(double2) * 4 * (size_t)d.Nq;
     case PQ_FIELD_K2: return sizeof(double2) * 4 * (size_t)d.Nq * d.n;
     case PQ_FIELD_MU: return sizeof(double);
@@ -387,6 +394,7 @@ hipError_t enqueue_iteration(pq_ctx* c, bool record, BseTiming* tm, const char**
                    c->bstats + (size_t)r * d.Nq, c->bse_ws, c->s, r == 0 ? tm : nullptr);
     if (e != hipSuccess) { *where = "bse"; return e; }
   }
+  if ((e = launch_bse_summary(c->bstats, 4 * d.Nq, c->dnorm + 1, c->s)) != hipSuccess) { *where = "bse summary"; return e; }
   rec(5);
   if ((e = launch_mix(d, c->sigma_new, c->sigma, p.alpha, c->dnorm, c->s)) != hipSuccess) { *where = "mix"; return e; }
   rec(6);
@@ -472,7 +480,6 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
                           int32_t* iters_done, int32_t* converged) {
   PQ_CHECK_ARG(c, "null context");
   PQ_CHECK_ARG(n_iter >= 0, "n_iter must be >= 0");
-  const Dims& d = c->d;
   int done = 0, conv = 0;
   pq_status st = PQ_OK;
   for (int it = 0; it < n_iter; ++it) {
@@ -486,10 +493,11 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
     const char* where = nullptr;
     if ((e = enqueue_iteration(c, c->have_events, timing ? &tm : nullptr, &where)) != hipSuccess)
       return hip_fail(e, where);
-    double dn = 0.0, mu = 0.0;
-    if ((e = hipMemcpyAsync(&dn, c->dnorm, sizeof(double), hipMemcpyDeviceToHost, c->s)) != hipSuccess) return hip_fail(e, "norm copy");
+    double res[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, mu = 0.0;      // norm, flagged, re-solved, unresolved, max estimate
+    if ((e = hipMemcpyAsync(res, c->dnorm, sizeof(res), hipMemcpyDeviceToHost, c->s)) != hipSuccess) return hip_fail(e, "norm copy");
     if ((e = hipMemcpyAsync(&mu, c->mu, sizeof(double), hipMemcpyDeviceToHost, c->s)) != hipSuccess) return hip_fail(e, "mu copy");
     if ((e = hipStreamSynchronize(c->s)) != hipSuccess) return hip_fail(e, "iteration");
+    const double dn = res[0];
     c->iteration++;
     done++;
     if (stats) {
@@ -497,6 +505,10 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
       stats->iteration = c->iteration;
       stats->dsigma = dn;
       stats->mu = mu;
+      stats->flagged_blocks = (int32_t)res[1];
+      stats->resolved_blocks = (int32_t)res[2];
+      stats->unresolved_blocks = (int32_t)res[3];
+      stats->max_err_est = res[4];
       if (c->have_events) {
         float ms;
         hipEventElapsedTime(&ms, c->ev[0], c->ev[6]); stats->ms_total = ms;
@@ -516,24 +528,26 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
         }
         stats->update_flops = tm.update_flops;
       }
-      const size_t nb = 4 * (size_t)d.Nq;
-      pq_bse_block_stats* hs = new (std::nothrow) pq_bse_block_stats[nb];
-      if (hs && hipMemcpy(hs, c->bstats, nb * sizeof(pq_bse_block_stats), hipMemcpyDeviceToHost) == hipSuccess) {
-        int flagged = 0;
-        for (size_t i = 0; i < nb; ++i) flagged += hs[i].flags != 0;
-        stats->flagged_blocks = flagged;
-      }
-      delete[] hs;
     }
     if (!(dn == dn)) {
       set_error("non-finite self-energy at iteration %d", c->iteration);
       st = PQ_ERR_NONFINITE;
       break;
     }
+    if (res[3] > 0.0) {
+      set_error("%d BSE blocks unresolved at iteration %d (no finite FP64 re-solve, or more flagged blocks than "
+                "re-solve slots)", (int)res[3], c->iteration);
+      st = PQ_ERR_SINGULAR;
+      break;
+    }
     if (tol > 0.0 && dn < tol) {
       conv = 1;
       break;
     }
+  }
+  if (st == PQ_OK && tol > 0.0 && !conv && n_iter > 0) {
+    set_error("not converged to %g in %d iterations", tol, done);
+    st = PQ_ERR_NOT_CONVERGED;
   }
   if (iters_done) *iters_done = done;
   if (converged) *converged = conv;
@@ -577,8 +591,8 @@ pq_status parquet_iterate_batch(pq_ctx* const* ctxs, int32_t count, int32_t n_it
     if (converged) converged[i] = 0;
   }
   std::vector<char> active(count, 1);
-  std::vector<double> dn(count, 0.0);
-  pq_status st = PQ_OK;
+  std::vector<double> res(5 * (size_t)count, 0.0);
+  bool nonfinite = false, singular = false;
   for (int it = 0; it < n_iter; ++it) {
     bool any = false;
     for (int i = 0; i < count; ++i) {
@@ -591,22 +605,36 @@ pq_status parquet_iterate_batch(pq_ctx* const* ctxs, int32_t count, int32_t n_it
     for (int i = 0; i < count; ++i) {
       if (!active[i]) continue;
       pq_ctx* c = ctxs[i];
-      hipError_t e = hipMemcpyAsync(&dn[i], c->dnorm, sizeof(double), hipMemcpyDeviceToHost, c->s);
+      double* r = &res[5 * (size_t)i];
+      hipError_t e = hipMemcpyAsync(r, c->dnorm, 5 * sizeof(double), hipMemcpyDeviceToHost, c->s);
       if (e == hipSuccess) e = hipStreamSynchronize(c->s);
       if (e != hipSuccess) return hip_fail(e, "batch iteration");
       c->iteration++;
       if (iters_done) iters_done[i]++;
-      if (!(dn[i] == dn[i])) {
+      if (!(r[0] == r[0])) {
         set_error("non-finite self-energy in context %d at iteration %d", i, c->iteration);
-        st = PQ_ERR_NONFINITE;
+        nonfinite = true;
         active[i] = 0;
-      } else if (tol > 0.0 && dn[i] < tol) {
+      } else if (r[3] > 0.0) {
+        if (!nonfinite) set_error("context %d: %d BSE blocks unresolved at iteration %d", i, (int)r[3], c->iteration);
+        singular = true;
+        active[i] = 0;
+      } else if (tol > 0.0 && r[0] < tol) {
         if (converged) converged[i] = 1;
         active[i] = 0;
       }
     }
   }
-  return st;
+  if (nonfinite) return PQ_ERR_NONFINITE;
+  if (singular) return PQ_ERR_SINGULAR;
+  if (tol > 0.0 && n_iter > 0) {
+    for (int i = 0; i < count; ++i)
+      if (active[i]) {
+        set_error("context %d not converged to %g in %d rounds", i, tol, n_iter);
+        return PQ_ERR_NOT_CONVERGED;
+      }
+  }
+  return PQ_OK;
 }
 
 pq_status parquet_field_bytes(pq_ctx* c, int32_t field, size_t* bytes) {
@@ -621,6 +649,19 @@ pq_status parquet_get(pq_ctx* c, int32_t field, void* dev_dst, size_t bytes) {
   PQ_CHECK_ARG(c && dev_dst, "null pointer");
   size_t b = field_bytes(c, field);
   PQ_CHECK_ARG(b > 0 && bytes == b, "field %d needs %zu bytes, got %zu", field, b, bytes);
+  if (field == PQ_FIELD_F) {
+    // F = Gamma[Phi] + Phi of the current state: kernels and Gamma from the current Phi
+    PQ_CHECK_ARG(dev_dst != c->phi && dev_dst != c->gamma, "destination aliases the context state");
+    const pq_params& p = c->p;
+    const double lam[4] = {p.U, -p.U, 2.0 * p.U, 0.0};
+    hipError_t e = launch_kernel_extract(p, c->d, c->phi, c->k1, c->k2, c->s);
+    if (e == hipSuccess)
+      e = launch_remap(p, c->d, lam, c->has_lam ? c->lam : nullptr, c->phi, c->k1, c->k2, c->gamma, c->s);
+    if (e == hipSuccess)
+      e = launch_vertex_sum(c->gamma, c->phi, dev_dst, p.storage, 4 * (size_t)c->d.Nq * c->d.n * c->d.n, c->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+    return e == hipSuccess ? PQ_OK : hip_fail(e, "parquet_get (F)");
+  }
   hipError_t e = hipMemcpyAsync(dev_dst, field_ptr(c, field), b, hipMemcpyDeviceToDevice, c->s);
   if (e == hipSuccess) e = hipStreamSynchronize(c->s);
   return e == hipSuccess ? PQ_OK : hip_fail(e, "parquet_get");
@@ -628,6 +669,7 @@ pq_status parquet_get(pq_ctx* c, int32_t field, void* dev_dst, size_t bytes) {
 
 pq_status parquet_set(pq_ctx* c, int32_t field, const void* dev_src, size_t bytes) {
   PQ_CHECK_ARG(c && dev_src, "null pointer");
+  PQ_CHECK_ARG(field != PQ_FIELD_F, "the full vertex F is derived from Phi and cannot be set");
   size_t b = field_bytes(c, field);
   PQ_CHECK_ARG(b > 0 && bytes == b, "field %d needs %zu bytes, got %zu", field, b, bytes);
   hipError_t e = hipMemcpyAsync(field_ptr(c, field), dev_src, b, hipMemcpyDeviceToDevice, c->s);

@@ -56,7 +56,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kPst = 8;        // per-block pivot-monitor doubles
+constexpr int kPst = 12;       // per-block monitor doubles (BseCtx::pst)
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
@@ -404,8 +404,11 @@ struct BseCtx {
                          //                kernels take the buffer of their panel)
   C* PI;                 // [Nq][NB][NB]   inverse P of the current diagonal block, transposed:
                          //                PI[k][r] = P[r][k] (k-major, like MT)
-  double* pst;           // [Nq][kPst]  min |pivot|, max |pivot|, non-finite seen, re-solved,
-                         //             max |entry| of the diagonal-block inverses
+  double* pst;           // [Nq][kPst]  [0] min |pivot|, [1] max |pivot|, [2] non-finite seen,
+                         //             [3] re-solved in FP64, [4] largest |entry| of the
+                         //             diagonal-block inverses, [5] error estimate,
+                         //             [6] estimate above tol (2: refined estimate pending),
+                         //             [7] unresolved, [8], [9] |F v_p|^2 of the two probes
   double kappa_max;      // flag a block whose diagonal-block inverses exceed this
   pq_bse_block_stats* stats;
   const int* active;     // nullable: only blocks < *active are solved (re-solve slots)
@@ -1092,7 +1095,8 @@ __global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a, int
     P[idx] = mix_phi<T>(F[idx], G[idx], mix ? P[idx] : cz<C>(), al, be, mix);
 }
 
-// Per-block pivot statistics (after the FP64 re-solve has marked its blocks).
+// Per-block statistics (after the error estimate and the FP64 re-solve have
+// marked their blocks).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void bse_stats_kernel(BseCtx<T> a) {
   const int blk = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1100,31 +1104,390 @@ __global__ __launch_bounds__(kThreads) void bse_stats_kernel(BseCtx<T> a) {
   const double* ps = a.pst + (size_t)blk * kPst;
   pq_bse_block_stats st;
   const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
+  const bool weak = ratio < a.weak_ratio || ps[4] > a.kappa_max;
+  const bool nonfin = ps[2] > 0.0;
   st.min_pivot = (float)ratio;
   st.growth = (float)ps[4];
-  st.flags = (ps[2] > 0.0 ? 2 : 0) | ((ratio < a.weak_ratio || ps[4] > a.kappa_max) ? 1 : 0) |
-             (ps[3] > 0.0 ? 4 : 0);
-  st.reserved = 0;
+  if constexpr (sizeof(T) == 4) {
+    const bool probe = ps[6] > 0.0;
+    const bool nonfin_est = !(ps[5] <= DBL_MAX);
+    st.flags = ((weak || nonfin || probe) ? 1 : 0) | ((nonfin || nonfin_est) ? 2 : 0) | (ps[3] > 0.0 ? 4 : 0) |
+               (ps[7] > 0.0 ? 8 : 0) | (probe ? 16 : 0);
+    st.err_est = (float)ps[5];
+  } else {
+    // complex128: weak pivots are only reported; a non-finite block has no
+    // more precise path to fall back on
+    st.flags = (weak ? 1 : 0) | (nonfin ? 2 | 8 : 0);
+    st.err_est = 0.f;
+  }
   a.stats[blk] = st;
 }
 
 template <typename T>
 constexpr int panel_width() { return sizeof(T) == 4 ? 128 : 64; }
 
-// At most kRefineSlots blocks per channel and iteration are re-solved in FP64
-// on the complex64 path; further flagged blocks keep their FP32 solution (and
-// their flags).
-constexpr int kRefineSlots = 8;
+// ------------------------------------------------------------ error estimate
+// After the complex64 solve, B holds F^ = F + E. With A = 1 - s Gamma diag(X)
+// and F = A^-1 Gamma, the inverse is A^-1 = 1 + s F diag(X). For a probe v:
+//   y = F^ v,   r = A y - Gamma v = y - s Gamma (X y) - Gamma v,
+// and E v = A^-1 (A F^ - Gamma) v = A^-1 r = r + s F (X r) ~ r + s F^ (X r).
+// Two estimates of the relative error |E v| / |F v| per block (max over two
+// probes), every sum in FP64 from the stored complex64 F^ and Gamma:
+//   est  = (1 + |F^ diag(X)|_F) |r| / |y|    an upper bound (|A^-1| <= 1 + |F X|_F),
+//                                           two passes: F^ (y), Gamma (Gamma v, Gamma X y);
+//   est2 = |r + s F^ (X r)| / |y|           one more pass over F^, only for the
+//                                           blocks whose bound exceeds the tolerance.
+// A block is flagged for the FP64 re-solve when est2 (or a non-finite value)
+// exceeds the tolerance. The probes have entries (+-1 +- i)/sqrt(2) from an
+// integer hash of (column, probe), so that they are fixed and reproducible.
+constexpr int kProbeRows = 4;      // rows per wave, loaded together
+constexpr double kDefaultBseTol = 1e-5;
+
+__device__ inline double2 probe_vec(int j, int p) {
+  unsigned x = (unsigned)j * 2u + (unsigned)p + 0x9E3779B9u;
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  const double h = 0.70710678118654752440;
+  return mk((x & 1u) ? -h : h, (x & 2u) ? -h : h);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline void cfma(double2& acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+
+// y_p = F^ v_p and the row sums of |F^_ij X_j|^2. One wave per kProbeRows rows,
+// lanes across the columns (coalesced rows), grid (ceil(n / (4 kProbeRows)), Nq).
+__global__ __launch_bounds__(kThreads) void probe_y_kernel(const float2* F, const double2* chi0, int n,
+                                                          const int* active, double2* y, double* nfx) {
+  const int blk = blockIdx.y, lane = threadIdx.x & 63;
+  if (active && blk >= *active) return;
+  const int i0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * kProbeRows;
+  if (i0 >= n) return;
+  const float2* Fb = F + (size_t)blk * n * n;
+  const double2* X = chi0 + (size_t)blk * n;
+  double2 a0[kProbeRows], a1[kProbeRows];
+  double sq[kProbeRows];
+#pragma unroll
+  for (int r = 0; r < kProbeRows; ++r) {
+    a0[r] = mk(0.0, 0.0);
+    a1[r] = mk(0.0, 0.0);
+    sq[r] = 0.0;
+  }
+  for (int j = lane; j < n; j += 64) {
+    const double2 v0 = probe_vec(j, 0), v1 = probe_vec(j, 1);
+    const double2 x = X[j];
+    const double x2 = x.x * x.x + x.y * x.y;
+    float2 f[kProbeRows];
+#pragma unroll
+    for (int r = 0; r < kProbeRows; ++r) f[r] = Fb[(size_t)min(i0 + r, n - 1) * n + j];
+#pragma unroll
+    for (int r = 0; r < kProbeRows; ++r) {
+      const double2 fd = to_d(f[r]);
+      cfma(a0[r], fd, v0);
+      cfma(a1[r], fd, v1);
+      sq[r] = fma(fd.x * fd.x + fd.y * fd.y, x2, sq[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kProbeRows; ++r) {
+    const double2 s0 = mk(wave_sum(a0[r].x), wave_sum(a0[r].y));
+    const double2 s1 = mk(wave_sum(a1[r].x), wave_sum(a1[r].y));
+    const double q = wave_sum(sq[r]);
+    if (lane == 0 && i0 + r < n) {
+      y[((size_t)blk * 2 + 0) * n + i0 + r] = s0;
+      y[((size_t)blk * 2 + 1) * n + i0 + r] = s1;
+      nfx[(size_t)blk * n + i0 + r] = q;
+    }
+  }
+}
+
+// r_p = y_p - s Gamma (X y_p) - Gamma v_p, one pass over Gamma (same grid).
+__global__ __launch_bounds__(kThreads) void probe_r_kernel(const float2* G, const double2* chi0, const double2* y,
+                                                          int n, double sign, const int* active, double2* r) {
+  const int blk = blockIdx.y, lane = threadIdx.x & 63;
+  if (active && blk >= *active) return;
+  const int i0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * kProbeRows;
+  if (i0 >= n) return;
+  const float2* Gb = G + (size_t)blk * n * n;
+  const double2* X = chi0 + (size_t)blk * n;
+  const double2* y0 = y + (size_t)blk * 2 * n;
+  const double2* y1 = y0 + n;
+  double2 g0[kProbeRows], g1[kProbeRows], h0[kProbeRows], h1[kProbeRows];
+#pragma unroll
+  for (int k = 0; k < kProbeRows; ++k) g0[k] = g1[k] = h0[k] = h1[k] = mk(0.0, 0.0);
+  for (int j = lane; j < n; j += 64) {
+    const double2 v0 = probe_vec(j, 0), v1 = probe_vec(j, 1);
+    const double2 x = X[j];
+    const double2 z0 = cmul(x, y0[j]), z1 = cmul(x, y1[j]);
+    float2 g[kProbeRows];
+#pragma unroll
+    for (int k = 0; k < kProbeRows; ++k) g[k] = Gb[(size_t)min(i0 + k, n - 1) * n + j];
+#pragma unroll
+    for (int k = 0; k < kProbeRows; ++k) {
+      const double2 gd = to_d(g[k]);
+      cfma(g0[k], gd, v0);
+      cfma(g1[k], gd, v1);
+      cfma(h0[k], gd, z0);
+      cfma(h1[k], gd, z1);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kProbeRows; ++k) {
+    const double2 sg0 = mk(wave_sum(g0[k].x), wave_sum(g0[k].y));
+    const double2 sg1 = mk(wave_sum(g1[k].x), wave_sum(g1[k].y));
+    const double2 sh0 = mk(wave_sum(h0[k].x), wave_sum(h0[k].y));
+    const double2 sh1 = mk(wave_sum(h1[k].x), wave_sum(h1[k].y));
+    const int i = i0 + k;
+    if (lane == 0 && i < n) {
+      const double2 a = y0[i], b = y1[i];
+      r[((size_t)blk * 2 + 0) * n + i] = mk(a.x - sign * sh0.x - sg0.x, a.y - sign * sh0.y - sg0.y);
+      r[((size_t)blk * 2 + 1) * n + i] = mk(b.x - sign * sh1.x - sg1.x, b.y - sign * sh1.y - sg1.y);
+    }
+  }
+}
+
+__device__ inline double safe_ratio(double num2, double den2) {
+  if (num2 == 0.0) return 0.0;
+  return sqrt(num2 / den2);     // den2 = 0 with num2 > 0: +inf (flagged)
+}
+
+// Per block (one workgroup): the bound est; blocks above tol with a finite
+// bound get the refined estimate (pst[6] = 2), non-finite ones are flagged.
+__global__ __launch_bounds__(kThreads) void probe_est_kernel(const double2* y, const double2* r, const double* nfx,
+                                                            int n, double tol, const int* active, double* pst) {
+  __shared__ double red[kThreads];
+  const int blk = blockIdx.x;
+  if (active && blk >= *active) return;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    s[0] += cabs2(y[((size_t)blk * 2 + 0) * n + i]);
+    s[1] += cabs2(y[((size_t)blk * 2 + 1) * n + i]);
+    s[2] += cabs2(r[((size_t)blk * 2 + 0) * n + i]);
+    s[3] += cabs2(r[((size_t)blk * 2 + 1) * n + i]);
+    s[4] += nfx[(size_t)blk * n + i];
+  }
+  for (int k = 0; k < 5; ++k) s[k] = block_sum(s[k], red);
+  if (threadIdx.x == 0) {
+    double* ps = pst + (size_t)blk * kPst;
+    double est = (1.0 + sqrt(s[4])) * fmax(safe_ratio(s[2], s[0]), safe_ratio(s[3], s[1]));
+    const bool fin = est <= DBL_MAX;          // false for NaN and +inf
+    if (!fin) est = INFINITY;
+    ps[5] = est;
+    ps[6] = est > tol ? (fin ? 2.0 : 1.0) : 0.0;
+    ps[8] = s[0];
+    ps[9] = s[1];
+  }
+}
+
+// c_p = r_p + s F^ (X r_p) for the blocks marked pst[6] = 2; writes |c_p|^2 per row.
+__global__ __launch_bounds__(kThreads) void probe_c_kernel(const float2* F, const double2* chi0, const double2* r,
+                                                          int n, double sign, const int* active, const double* pst,
+                                                          double* cq) {
+  const int blk = blockIdx.y, lane = threadIdx.x & 63;
+  if (active && blk >= *active) return;
+  if (pst[(size_t)blk * kPst + 6] != 2.0) return;
+  const int i0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * kProbeRows;
+  if (i0 >= n) return;
+  const float2* Fb = F + (size_t)blk * n * n;
+  const double2* X = chi0 + (size_t)blk * n;
+  const double2* r0 = r + (size_t)blk * 2 * n;
+  const double2* r1 = r0 + n;
+  double2 c0[kProbeRows], c1[kProbeRows];
+#pragma unroll
+  for (int k = 0; k < kProbeRows; ++k) c0[k] = c1[k] = mk(0.0, 0.0);
+  for (int j = lane; j < n; j += 64) {
+    const double2 x = X[j];
+    const double2 z0 = cmul(x, r0[j]), z1 = cmul(x, r1[j]);
+    float2 f[kProbeRows];
+#pragma unroll
+    for (int k = 0; k < kProbeRows; ++k) f[k] = Fb[(size_t)min(i0 + k, n - 1) * n + j];
+#pragma unroll
+    for (int k = 0; k < kProbeRows; ++k) {
+      const double2 fd = to_d(f[k]);
+      cfma(c0[k], fd, z0);
+      cfma(c1[k], fd, z1);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kProbeRows; ++k) {
+    const double2 s0 = mk(wave_sum(c0[k].x), wave_sum(c0[k].y));
+    const double2 s1 = mk(wave_sum(c1[k].x), wave_sum(c1[k].y));
+    const int i = i0 + k;
+    if (lane == 0 && i < n) {
+      const double2 a = r0[i], b = r1[i];
+      const double2 e0 = mk(a.x + sign * s0.x, a.y + sign * s0.y);
+      const double2 e1 = mk(b.x + sign * s1.x, b.y + sign * s1.y);
+      cq[((size_t)blk * n + i) * 2 + 0] = cabs2(e0);
+      cq[((size_t)blk * n + i) * 2 + 1] = cabs2(e1);
+    }
+  }
+}
+
+// Per block: the refined estimate replaces the bound and decides the flag.
+__global__ __launch_bounds__(kThreads) void probe_flag_kernel(const double* cq, int n, double tol, const int* active,
+                                                             double* pst) {
+  __shared__ double red[kThreads];
+  const int blk = blockIdx.x;
+  if (active && blk >= *active) return;
+  double* ps = pst + (size_t)blk * kPst;
+  if (ps[6] != 2.0) return;                   // uniform over the workgroup
+  double c0 = 0.0, c1 = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    c0 += cq[((size_t)blk * n + i) * 2 + 0];
+    c1 += cq[((size_t)blk * n + i) * 2 + 1];
+  }
+  c0 = block_sum(c0, red);
+  c1 = block_sum(c1, red);
+  if (threadIdx.x == 0) {
+    double est = fmax(safe_ratio(c0, ps[8]), safe_ratio(c1, ps[9]));
+    if (!(est <= DBL_MAX)) est = INFINITY;
+    ps[5] = est;
+    ps[6] = est > tol ? 1.0 : 0.0;
+  }
+}
+
+// ------------------------------------------------------ FP64 re-solve
+// Flagged blocks of a complex64 elimination are solved again in FP64 from
+// Gamma, in S slots (list[0 .. S): block of each slot; list[S]: slots in use;
+// list[S + 1]: slots of the first list). Two lists, both in q order:
+//  - before any row is mixed (once the forward sweep has met every pivot):
+//    the blocks with weak or non-finite pivots; their Phi is saved, and the
+//    re-solved block is mixed from the FP64 F and the saved Phi;
+//  - after the error estimate: the other blocks it flags; their Phi already
+//    holds alpha (F^ - Gamma) + (1 - alpha) Phi_old, so the FP64 F enters as
+//    Phi + alpha (F_64 - F^) (no saved copy needed; F^ is still in B).
+// Flagged blocks beyond the slots keep the complex64 result and pst[7] = 1.
+constexpr int kMaxBlocks = 4096;     // Nq < n <= 4096
+
+__device__ inline bool pivot_flagged(const double* ps, float weak, double kappa_max) {
+  const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
+  return ps[2] > 0.0 || ratio < weak || ps[4] > kappa_max;
+}
+
+__global__ __launch_bounds__(kThreads) void refine_list_kernel(double* pst, int Nq, float weak, double kappa_max,
+                                                              int S, int late, int* list) {
+  __shared__ unsigned char flag[kMaxBlocks];
+  for (int b = threadIdx.x; b < Nq; b += blockDim.x) {
+    const double* ps = pst + (size_t)b * kPst;
+    const bool piv = pivot_flagged(ps, weak, kappa_max);
+    flag[b] = late ? (!piv && ps[6] == 1.0) : piv;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {           // ordered compaction from LDS
+    int c = late ? list[S] : 0;
+    for (int b = 0; b < Nq; ++b) {
+      if (!late) {
+        pst[(size_t)b * kPst + 3] = 0.0;
+        pst[(size_t)b * kPst + 7] = 0.0;
+      }
+      if (flag[b]) {
+        if (c < S) list[c++] = b;
+        else pst[(size_t)b * kPst + 7] = 1.0;
+      }
+    }
+    list[S] = c;
+    if (!late) list[S + 1] = c;
+  }
+}
+
+// Gamma and X of the slots [lo, hi) into the complex128 slots (early list: also Phi).
+__global__ __launch_bounds__(kThreads) void refine_gather_kernel(const float2* gamma, const double2* chi0,
+                                                                  const float2* phi, int n, const int* list, int S,
+                                                                  int late, double2* g64, double2* x64, float2* phis) {
+  const int slot = blockIdx.y;
+  const int lo = late ? list[S + 1] : 0, hi = list[S];
+  if (slot < lo || slot >= hi) return;
+  const int b = list[slot];
+  const size_t nn = (size_t)n * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 v = gamma[(size_t)b * nn + i];
+    g64[(size_t)slot * nn + i] = mk((double)v.x, (double)v.y);
+    if (!late) phis[(size_t)slot * nn + i] = phi[(size_t)b * nn + i];   // Phi before this solve
+  }
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x64[(size_t)slot * n + i] = chi0[(size_t)b * n + i];
+}
+
+// Phi of a re-solved block from the FP64 solution p64 = F_64 - Gamma:
+//   first list:  alpha p64 + (1 - alpha) Phi_saved,
+//   second list: Phi + alpha (p64 + Gamma - F^).
+// A slot whose FP64 elimination met a non-finite pivot, or (second list) whose
+// complex64 F^ is not finite, is left as it is and marked unresolved.
+__global__ __launch_bounds__(kThreads) void refine_scatter_kernel(const double2* p64, const float2* phis,
+                                                                   const double* pst64, const float2* gamma,
+                                                                   const float2* fhat, int n, const int* list, int S,
+                                                                   double alpha, float2* phi, double* pst) {
+  const int slot = blockIdx.y;
+  if (slot >= list[S]) return;
+  const int b = list[slot];
+  const bool early = slot < list[S + 1];
+  double* ps = pst + (size_t)b * kPst;
+  const bool ok = !(pst64[(size_t)slot * kPst + 2] > 0.0) && (early || ps[5] <= DBL_MAX);
+  if (!ok) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ps[7] = 1.0;
+    return;
+  }
+  const size_t nn = (size_t)n * n;
+  const bool mix = alpha != 1.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
+    double2 v = p64[(size_t)slot * nn + i];
+    if (early) {
+      if (mix) {
+        const float2 o = phis[(size_t)slot * nn + i];
+        v.x = alpha * v.x + (1.0 - alpha) * (double)o.x;
+        v.y = alpha * v.y + (1.0 - alpha) * (double)o.y;
+      }
+    } else {
+      const double2 cur = to_d(phi[(size_t)b * nn + i]);
+      const double2 g = to_d(gamma[(size_t)b * nn + i]);
+      const double2 f = to_d(fhat[(size_t)b * nn + i]);
+      v.x = cur.x + alpha * (v.x + g.x - f.x);
+      v.y = cur.y + alpha * (v.y + g.y - f.y);
+    }
+    phi[(size_t)b * nn + i] = mkf((float)v.x, (float)v.y);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ps[3] = 1.0;
+}
+
+// Re-solve slots per channel: as many as kResolveBudget bytes hold (at least
+// 8, at most Nq), or the caller's limit.
+constexpr double kResolveBudget = 2.5 * 1024.0 * 1024.0 * 1024.0;
 
 struct BseLayout {
   size_t A, B, MT, PI, pst;
-  // complex64 path only: FP64 re-solve of flagged blocks
+  // complex64 path only: error estimate and FP64 re-solve of flagged blocks
+  size_t py, pr, pnfx, pcq;
   size_t list, g64, x64, p64, phis, ws64;
+  int slots;
   size_t total;
 };
 
 template <typename T>
-BseLayout bse_layout(const Dims& d) {
+BseLayout bse_layout(const Dims& d, int slots_req = 0);
+
+inline int resolve_slots(const Dims& d, int req) {
+  const double nn = (double)d.n * d.n;
+  // per slot: Gamma and F in complex128, saved Phi in complex64, and the
+  // complex128 elimination's A, B and panels
+  const double per = nn * (16.0 + 16.0 + 8.0 + 32.0) + 2.0 * 64 * d.n * 16.0 + 64.0 * 64 * 16.0 + 4096.0;
+  int s = (int)std::min<double>(1e6, kResolveBudget / per);
+  s = std::max(s, 8);
+  if (req > 0) s = req;
+  return std::min(s, d.Nq);
+}
+
+template <typename T>
+BseLayout bse_layout(const Dims& d, int slots_req) {
   using C = typename cplx_of<T>::type;
   constexpr int NB = panel_width<T>();
   const size_t nn = (size_t)d.n * d.n;
@@ -1137,105 +1500,40 @@ BseLayout bse_layout(const Dims& d) {
   L.PI = take(sizeof(C) * (size_t)NB * NB * d.Nq);
   L.pst = take(sizeof(double) * kPst * (size_t)d.Nq);
   if constexpr (sizeof(T) == 4) {
+    const int S = resolve_slots(d, slots_req);
+    L.slots = S;
+    L.py = take(sizeof(double2) * 2 * (size_t)d.n * d.Nq);
+    L.pr = take(sizeof(double2) * 2 * (size_t)d.n * d.Nq);
+    L.pnfx = take(sizeof(double) * (size_t)d.n * d.Nq);
+    L.pcq = take(sizeof(double) * 2 * (size_t)d.n * d.Nq);
     Dims r = d;
-    r.Nq = kRefineSlots;
-    L.list = take(sizeof(int) * (kRefineSlots + 2));
-    L.g64 = take(sizeof(double2) * nn * kRefineSlots);
-    L.x64 = take(sizeof(double2) * (size_t)d.n * kRefineSlots);
-    L.p64 = take(sizeof(double2) * nn * kRefineSlots);
-    L.phis = take(sizeof(float2) * nn * kRefineSlots);
+    r.Nq = S;
+    L.list = take(sizeof(int) * (S + 2));
+    L.g64 = take(sizeof(double2) * nn * S);
+    L.x64 = take(sizeof(double2) * (size_t)d.n * S);
+    L.p64 = take(sizeof(double2) * nn * S);
+    L.phis = take(sizeof(float2) * nn * S);
     L.ws64 = take(bse_layout<double>(r).total);
   }
   L.total = off;
   return L;
 }
 
-// ------------------------------------------------------ FP64 re-solve
-// Blocks of a complex64 elimination whose pivot monitor reports a weak pivot
-// ratio or a non-finite pivot are solved again in FP64 from Gamma: a single
-// workgroup lists them (list[0..kRefineSlots), count in list[kRefineSlots],
-// total flagged in list[kRefineSlots + 1]) once the forward sweep has met
-// every pivot, the blocks are gathered into complex128 slots together with
-// their Phi before the mixing, the complex128 elimination runs on the slots
-// (slots past the count exit at once), and the block's Phi is mixed again from
-// the FP64 solution and the saved Phi, replacing the complex64 result.
-constexpr int kMaxBlocks = 4096;     // Nq < n <= 4096
-
-__global__ __launch_bounds__(kThreads) void refine_list_kernel(const double* pst, int Nq, float weak,
-                                                                double kappa_max, int* list) {
-  __shared__ unsigned char flag[kMaxBlocks];
-  for (int b = threadIdx.x; b < Nq; b += blockDim.x) {
-    const double* ps = pst + (size_t)b * kPst;
-    const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
-    flag[b] = (ps[2] > 0.0 || ratio < weak || ps[4] > kappa_max) ? 1 : 0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {           // ordered compaction from LDS
-    int c = 0, tot = 0;
-    for (int b = 0; b < Nq; ++b) {
-      if (flag[b]) {
-        if (c < kRefineSlots) list[c++] = b;
-        ++tot;
-      }
-    }
-    list[kRefineSlots] = c;
-    list[kRefineSlots + 1] = tot;
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void refine_gather_kernel(const float2* gamma, const double2* chi0,
-                                                                  const float2* phi, int n, const int* list,
-                                                                  double2* g64, double2* x64, float2* phis) {
-  const int slot = blockIdx.y;
-  if (slot >= list[kRefineSlots]) return;
-  const int b = list[slot];
-  const size_t nn = (size_t)n * n;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
-    const float2 v = gamma[(size_t)b * nn + i];
-    g64[(size_t)slot * nn + i] = mk((double)v.x, (double)v.y);
-    phis[(size_t)slot * nn + i] = phi[(size_t)b * nn + i];     // Phi before this solve (for the mixing)
-  }
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < n; i += blockDim.x) x64[(size_t)slot * n + i] = chi0[(size_t)b * n + i];
-}
-
-// Phi of a re-solved block <- alpha (F - Gamma)_64 + (1 - alpha) Phi_saved,
-// replacing what the complex64 back substitution mixed into it.
-__global__ __launch_bounds__(kThreads) void refine_scatter_kernel(const double2* p64, const float2* phis, int n,
-                                                                   const int* list, double alpha, float2* phi,
-                                                                   double* pst) {
-  const int slot = blockIdx.y;
-  if (slot >= list[kRefineSlots]) return;
-  const int b = list[slot];
-  const size_t nn = (size_t)n * n;
-  const bool mix = alpha != 1.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
-    double2 v = p64[(size_t)slot * nn + i];
-    if (mix) {
-      const float2 o = phis[(size_t)slot * nn + i];
-      v.x = alpha * v.x + (1.0 - alpha) * (double)o.x;
-      v.y = alpha * v.y + (1.0 - alpha) * (double)o.y;
-    }
-    phi[(size_t)b * nn + i] = mkf((float)v.x, (float)v.y);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) pst[(size_t)b * kPst + 3] = 1.0;
-}
-
 }  // namespace
 
 size_t bse_ws_bytes(const pq_params& p, const Dims& d, int precision) {
-  (void)p;
-  return precision == PQ_PREC_FP64 ? bse_layout<double>(d).total : bse_layout<float>(d).total;
+  return precision == PQ_PREC_FP64 ? bse_layout<double>(d).total : bse_layout<float>(d, p.resolve_slots).total;
 }
 
 template <typename T, bool BF3 = false>
-static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, double kappa_max, const void* gamma,
-                          const double2* chi0, void* phi_io, pq_bse_block_stats* stats, void* ws,
-                          hipStream_t s, BseTiming* tm, const int* active = nullptr) {
+static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, double kappa_max, double err_tol,
+                          int slots_req, const void* gamma, const double2* chi0, void* phi_io,
+                          pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm,
+                          const int* active = nullptr) {
   using C = typename cplx_of<T>::type;
   constexpr int NB = panel_width<T>();
   static const double kSign[4] = {1.0, 1.0, -1.0, 1.0};
-  const BseLayout L = bse_layout<T>(d);
+  const BseLayout L = bse_layout<T>(d, slots_req);
   char* w = (char*)ws;
   BseCtx<T> a;
   a.n = d.n;
@@ -1256,7 +1554,8 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   a.stats = stats;
   a.active = active;
   const int n = d.n;
-  // event timing around each launch (kind: 0 init, 1 pivot, 2 panel, 3 update, 4 epilogue)
+  // event timing around each launch (kind: 0 init, 1 pivot, 2 panel, 3 update,
+  // 4 epilogue, 5 error estimate and FP64 re-solve)
   auto pre = [&](int kind) {
     if (tm && tm->used < tm->cap) {
       tm->kind[tm->used] = kind;
@@ -1283,23 +1582,27 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   // that update runs at one wave per SIMD with no registers to spare, and the
   // loads of the mixing cost it more than a separate pass over every row).
   constexpr bool kFuseMix = !BF3;
-  // complex64 path: the blocks the pivot monitor flagged (complete once the
-  // last pivot is met) are listed and gathered for the FP64 re-solve before
-  // any row is mixed, with their Phi (none flagged: empty launches)
+  // complex64 path: the blocks with weak or non-finite pivots (all known once
+  // the last pivot is met) are listed and gathered for the FP64 re-solve
+  // before any row is mixed, with their Phi (none flagged: empty launches)
+  const int S = L.slots;
   int* list = nullptr;
   double2 *g64 = nullptr, *x64 = nullptr, *p64 = nullptr;
   float2* phis = nullptr;
   const unsigned gx = (unsigned)std::min<size_t>(256, ((size_t)n * n + kThreads - 1) / kThreads);
-  auto refine_gather = [&]() {
+  if constexpr (sizeof(T) == 4) {
+    list = (int*)(w + L.list);
+    g64 = (double2*)(w + L.g64);
+    x64 = (double2*)(w + L.x64);
+    p64 = (double2*)(w + L.p64);
+    phis = (float2*)(w + L.phis);
+  }
+  auto refine_gather = [&](int late) {
     if constexpr (sizeof(T) == 4) {
-      list = (int*)(w + L.list);
-      g64 = (double2*)(w + L.g64);
-      x64 = (double2*)(w + L.x64);
-      p64 = (double2*)(w + L.p64);
-      phis = (float2*)(w + L.phis);
-      hipLaunchKernelGGL(refine_list_kernel, dim3(1), dim3(kThreads), 0, s, a.pst, d.Nq, weak, kappa_max, list);
-      hipLaunchKernelGGL(refine_gather_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, (const float2*)gamma,
-                         chi0, (const float2*)phi_io, n, list, g64, x64, phis);
+      hipLaunchKernelGGL(refine_list_kernel, dim3(1), dim3(kThreads), 0, s, a.pst, d.Nq, weak, kappa_max, S, late,
+                         list);
+      hipLaunchKernelGGL(refine_gather_kernel, dim3(gx, S), dim3(kThreads), 0, s, (const float2*)gamma, chi0,
+                         (const float2*)phi_io, n, list, S, late, g64, x64, phis);
     }
   };
   for (int j0 = 0; j0 < n; j0 += NB) {
@@ -1314,7 +1617,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
       hipLaunchKernelGGL((bse_multcopy_kernel<T, NB>), dim3((n + 31) / 32, d.Nq), dim3(kThreads), 0, s, am, j0);
     }
     post();
-    if (j0 == last) refine_gather();
+    if (j0 == last) refine_gather(0);
     constexpr int RW = panel_rows_per_wave<T, NB>();
     const int nwb = ((ncols + 31) / 32 * (NB / RW) + kWaves - 1) / kWaves;
     const int mix = kFuseMix && j0 == last ? 1 : 0;
@@ -1366,16 +1669,70 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     post();
   }
   if constexpr (sizeof(T) == 4) {
+    // error estimate of every block (B holds the complex64 F), then the FP64
+    // re-solve of the flagged blocks
+    pre(5);
+    const double sg = kSign[channel];
+    const unsigned rx = (unsigned)((n + kWaves * kProbeRows - 1) / (kWaves * kProbeRows));
+    double2* py = (double2*)(w + L.py);
+    double2* pr = (double2*)(w + L.pr);
+    double* pnfx = (double*)(w + L.pnfx);
+    double* pcq = (double*)(w + L.pcq);
+    const float2* fh = (const float2*)a.B;
+    hipLaunchKernelGGL(probe_y_kernel, dim3(rx, d.Nq), dim3(kThreads), 0, s, fh, chi0, n, active, py, pnfx);
+    hipLaunchKernelGGL(probe_r_kernel, dim3(rx, d.Nq), dim3(kThreads), 0, s, (const float2*)gamma, chi0,
+                       (const double2*)py, n, sg, active, pr);
+    hipLaunchKernelGGL(probe_est_kernel, dim3(d.Nq), dim3(kThreads), 0, s, (const double2*)py, (const double2*)pr,
+                       (const double*)pnfx, n, err_tol, active, a.pst);
+    hipLaunchKernelGGL(probe_c_kernel, dim3(rx, d.Nq), dim3(kThreads), 0, s, fh, chi0, (const double2*)pr, n, sg,
+                       active, (const double*)a.pst, pcq);
+    hipLaunchKernelGGL(probe_flag_kernel, dim3(d.Nq), dim3(kThreads), 0, s, (const double*)pcq, n, err_tol, active,
+                       a.pst);
+    refine_gather(1);
     Dims r = d;
-    r.Nq = kRefineSlots;
-    hipError_t e = run_bse<double>(r, channel, 1.0, 1e-10f, 1e12, g64, x64, p64, nullptr, w + L.ws64, s, nullptr,
-                                   list + kRefineSlots);
+    r.Nq = S;
+    const BseLayout L64 = bse_layout<double>(r);
+    hipError_t e = run_bse<double>(r, channel, 1.0, 1e-10f, 1e12, 0.0, 0, g64, x64, p64, nullptr, w + L.ws64, s,
+                                   nullptr, list + S);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(refine_scatter_kernel, dim3(gx, kRefineSlots), dim3(kThreads), 0, s, (const double2*)p64,
-                       (const float2*)phis, n, list, alpha, (float2*)phi_io, a.pst);
+    hipLaunchKernelGGL(refine_scatter_kernel, dim3(gx, S), dim3(kThreads), 0, s, (const double2*)p64,
+                       (const float2*)phis, (const double*)(w + L.ws64 + L64.pst), (const float2*)gamma, fh, n,
+                       list, S, alpha, (float2*)phi_io, a.pst);
+    post();
   }
   if (stats)
     hipLaunchKernelGGL((bse_stats_kernel<T>), dim3((d.Nq + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+namespace {
+// Counts over the block stats of one iteration (one workgroup, fixed-order sums).
+__global__ __launch_bounds__(kThreads) void bse_summary_kernel(const pq_bse_block_stats* st, int nb, double* out) {
+  __shared__ double red[kThreads];
+  double f = 0.0, r = 0.0, u = 0.0, m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    const int fl = st[i].flags;
+    f += (fl & 1) ? 1.0 : 0.0;
+    r += (fl & 4) ? 1.0 : 0.0;
+    u += (fl & 8) ? 1.0 : 0.0;
+    const double e = st[i].err_est;
+    m = fmax(m, e <= DBL_MAX ? e : INFINITY);
+  }
+  f = block_sum(f, red);
+  r = block_sum(r, red);
+  u = block_sum(u, red);
+  m = block_max(m, red);
+  if (threadIdx.x == 0) {
+    out[0] = f;
+    out[1] = r;
+    out[2] = u;
+    out[3] = m;
+  }
+}
+}  // namespace
+
+hipError_t launch_bse_summary(const pq_bse_block_stats* stats, int nb, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(bse_summary_kernel, dim3(1), dim3(kThreads), 0, s, stats, nb, out);
   return hipGetLastError();
 }
 
@@ -1384,14 +1741,17 @@ hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precis
                       pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm) {
   if (precision == PQ_PREC_FP64) {
     if (p.storage != PQ_STORE_C128) return hipErrorInvalidValue;
-    return run_bse<double>(d, channel, alpha, 1e-10f, 1e12, gamma, chi0, phi_io, stats, ws, s, tm);
+    return run_bse<double>(d, channel, alpha, 1e-10f, 1e12, 0.0, 0, gamma, chi0, phi_io, stats, ws, s, tm);
   }
   if (p.storage != PQ_STORE_C64) return hipErrorInvalidValue;
   // complex64: a block is re-solved in FP64 when its pivot ratio drops below
-  // 1e-3 or a diagonal-block inverse exceeds 1e3 (FP32 error ~ 1e3 eps32 n^1/2)
+  // 1e-3, a diagonal-block inverse exceeds 1e3, a pivot is not finite, or its
+  // error estimate exceeds bse_tol (default 1e-5)
+  const double tol = p.bse_tol > 0.0 ? p.bse_tol : kDefaultBseTol;
   if (precision == PQ_PREC_BF16X3)
-    return run_bse<float, true>(d, channel, alpha, 1e-3f, 1e3, gamma, chi0, phi_io, stats, ws, s, tm);
-  return run_bse<float>(d, channel, alpha, 1e-3f, 1e3, gamma, chi0, phi_io, stats, ws, s, tm);
+    return run_bse<float, true>(d, channel, alpha, 1e-3f, 1e3, tol, p.resolve_slots, gamma, chi0, phi_io, stats, ws,
+                                s, tm);
+  return run_bse<float>(d, channel, alpha, 1e-3f, 1e3, tol, p.resolve_slots, gamma, chi0, phi_io, stats, ws, s, tm);
 }
 
 }  // namespace pq

@@ -40,6 +40,8 @@ hipError_t launch_kernel_extract(const pq_params& p, const Dims& d, const void* 
 hipError_t launch_remap(const pq_params& p, const Dims& d, const double lam[4], const double2* lam_box,
                         const void* phi, const double2* k1, const double2* k2, void* gamma, hipStream_t s);
 hipError_t launch_lambda_fill(const Dims& d, double U, double2* lam_box, hipStream_t s);
+// f = a + b elementwise over count complex elements of the given storage
+hipError_t launch_vertex_sum(const void* a, const void* b, void* f, int storage, size_t count, hipStream_t s);
 // learned warm start (pq_mlp.hip)
 size_t mlp_count(const int32_t* widths, int n_layers);
 hipError_t launch_mlp_forward(const int32_t* widths, int n_layers, const void* params_bf16, const float* params,
@@ -61,7 +63,7 @@ hipError_t launch_sigma1(const pq_params& p, const Dims& d, const double2* g, co
                          double2* sigma_out, void* ws, hipStream_t s);
 size_t bse_ws_bytes(const pq_params& p, const Dims& d, int precision);
 // Optional device-event timing of the BSE launches, by kernel kind
-// (0 init, 1 pivot, 2 panel, 3 update, 4 epilogue).
+// (0 init, 1 pivot, 2 panel, 3 update, 4 epilogue, 5 error estimate and FP64 re-solve).
 struct BseTiming {
   hipEvent_t* ev;     // 2 * cap events
   int cap, used;
@@ -71,5 +73,8 @@ struct BseTiming {
 hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precision,
                       const void* gamma, const double2* chi0, void* phi_io, double alpha,
                       pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm = nullptr);
+// summary of nb block stats into out[0..3]: flagged, re-solved and unresolved
+// block counts, largest error estimate (+inf for a non-finite one)
+hipError_t launch_bse_summary(const pq_bse_block_stats* stats, int nb, double* out, hipStream_t s);
 
 }  // namespace pq

@@ -170,7 +170,31 @@ __global__ __launch_bounds__(kThreads) void convert_kernel(const S* src, D* dst,
   }
 }
 
+// F = Gamma + Phi over a vertex array (Eq. PA_F_G)
+template <typename C>
+__global__ __launch_bounds__(kThreads) void vertex_sum_kernel(const C* a, const C* b, C* f, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const C x = a[i], y = b[i];
+    C z;
+    z.x = x.x + y.x;
+    z.y = x.y + y.y;
+    f[i] = z;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_vertex_sum(const void* a, const void* b, void* f, int storage, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>(16384, (count + kThreads - 1) / kThreads);
+  if (storage == PQ_STORE_C64)
+    hipLaunchKernelGGL((vertex_sum_kernel<float2>), dim3(blocks), dim3(kThreads), 0, s, (const float2*)a,
+                       (const float2*)b, (float2*)f, count);
+  else
+    hipLaunchKernelGGL((vertex_sum_kernel<double2>), dim3(blocks), dim3(kThreads), 0, s, (const double2*)a,
+                       (const double2*)b, (double2*)f, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_convert(const void* src, int src_storage, void* dst, int dst_storage, size_t count,
                           hipStream_t s) {

@@ -20,7 +20,9 @@ PQ_STORE_C128, PQ_STORE_C64 = 0, 1
 PQ_PREC_FP64, PQ_PREC_FP32, PQ_PREC_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": PQ_PREC_FP64, "fp32": PQ_PREC_FP32, "bf16x3": PQ_PREC_BF16X3}
 FIELDS = {"sigma": 0, "g": 1, "phi": 2, "gamma": 3, "k1": 4, "k2": 5, "mu": 6, "xph": 7, "xpp": 8,
-          "lambda": 9}
+          "lambda": 9, "f": 10}
+# pq_bse_block_stats.flags bits
+BSE_FLAGGED, BSE_NONFINITE, BSE_RESOLVED, BSE_UNRESOLVED, BSE_ESTIMATE = 1, 2, 4, 8, 16
 
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_SINGULAR",
                 5: "ERR_NOT_CONVERGED", 6: "ERR_NONFINITE"}
@@ -39,9 +41,10 @@ class PqParams(ctypes.Structure):
     _fields_ = [
         ("Lx", c_int32), ("Ly", c_int32), ("Nv", c_int32), ("f_ext", c_int32),
         ("kernel_level", c_int32), ("edge_rule", c_int32), ("mu_mode", c_int32),
-        ("storage", c_int32), ("precision", c_int32), ("reserved", c_int32),
+        ("storage", c_int32), ("precision", c_int32), ("resolve_slots", c_int32),
         ("U", c_double), ("beta", c_double), ("t", c_double), ("tp", c_double),
         ("filling", c_double), ("D", c_double), ("mu_fixed", c_double), ("alpha", c_double),
+        ("bse_tol", c_double),
     ]
 
 
@@ -56,14 +59,15 @@ class PqDims(ctypes.Structure):
 class PqIterStats(ctypes.Structure):
     _fields_ = [
         ("iteration", c_int32), ("flagged_blocks", c_int32), ("dsigma", c_double), ("mu", c_double),
-        ("ms_total", c_double), ("ms_stage", c_double * 8), ("ms_bse_kernel", c_double * 5),
-        ("n_bse_launch", c_int32 * 5), ("reserved", c_int32), ("update_flops", c_double),
+        ("ms_total", c_double), ("ms_stage", c_double * 8), ("ms_bse_kernel", c_double * 6),
+        ("n_bse_launch", c_int32 * 6), ("resolved_blocks", c_int32), ("unresolved_blocks", c_int32),
+        ("update_flops", c_double), ("max_err_est", c_double),
     ]
 
 
 class PqBseBlockStats(ctypes.Structure):
     _fields_ = [("min_pivot", ctypes.c_float), ("growth", ctypes.c_float), ("flags", c_int32),
-                ("reserved", c_int32)]
+                ("err_est", ctypes.c_float)]
 
 
 class ParquetError(RuntimeError):
@@ -93,7 +97,8 @@ def load() -> ctypes.CDLL:
         "dyson_update": [P, c_void_p, c_void_p, c_void_p, c_void_p],
         "bubble_build": [P, c_void_p, c_void_p, c_void_p, c_void_p],
         "kernel_extract": [P, c_void_p, c_void_p, c_void_p, c_void_p],
-        "channel_remap": [P, POINTER(c_double), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+        "channel_remap": [P, POINTER(c_double), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                          c_void_p],
         "sigma_sde_workspace": [P, POINTER(c_size_t)],
         "sigma_sde": [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                       c_size_t, c_void_p],
@@ -137,8 +142,9 @@ def check(status: int):
         raise ParquetError(status, msg)
 
 
-def make_params(p, precision: str = "fp64") -> PqParams:
-    """pq_params from any object with the ModelParams attributes."""
+def make_params(p, precision: str = "fp64", resolve_slots: int = 0, bse_tol: float = 0.0) -> PqParams:
+    """pq_params from any object with the ModelParams attributes (resolve_slots
+    and bse_tol: 0 selects the library defaults)."""
     if precision not in PRECISIONS:
         raise ValueError(f"precision {precision!r} not available ({', '.join(PRECISIONS)})")
     out = PqParams()
@@ -151,6 +157,8 @@ def make_params(p, precision: str = "fp64") -> PqParams:
     out.precision = PRECISIONS[precision]
     out.U, out.beta, out.t, out.tp = float(p.U), float(p.beta), float(p.t), float(p.tp)
     out.filling, out.D, out.mu_fixed, out.alpha = float(p.filling), float(p.D), float(p.mu_fixed), float(p.alpha)
+    out.resolve_slots = int(resolve_slots)
+    out.bse_tol = float(bse_tol)
     return out
 
 

@@ -34,11 +34,11 @@ def _ptr(t: torch.Tensor, dtype, shape: Sequence[int], name: str) -> ctypes.c_vo
 class Stage:
     """Shapes and dtypes of one parameter set, plus the stateless stage calls."""
 
-    def __init__(self, p, precision: str = "fp64"):
+    def __init__(self, p, precision: str = "fp64", resolve_slots: int = 0, bse_tol: float = 0.0):
         N.load()
         self.model = p
         self.precision = precision
-        self.pp = N.make_params(p, precision)
+        self.pp = N.make_params(p, precision, resolve_slots, bse_tol)
         self.d = N.dims(self.pp)
         self.vdtype = torch.complex128 if precision == "fp64" else torch.complex64
         d = self.d
@@ -70,14 +70,16 @@ class Stage:
                                         _ptr(k1, torch.complex128, self.k1_shape, "k1"),
                                         _ptr(k2, torch.complex128, self.k2_shape, "k2"), _stream(stream)))
 
-    def channel_remap(self, lam, phi, k1, k2, gamma_out, lam_box=None, stream=None):
-        """lam: 4 scalars; lam_box (optional): [4][Nv-1][Nv][Nv] complex128 local Lambda."""
+    def channel_remap(self, lam, phi, k1, k2, gamma_out, lam_box=None, f_out=None, stream=None):
+        """lam: 4 scalars; lam_box (optional): [4][Nv-1][Nv][Nv] complex128 local Lambda;
+        f_out (optional): the full vertex Gamma + Phi."""
         arr = (ctypes.c_double * 4)(*[float(v) for v in lam])
         lb = ctypes.c_void_p(0) if lam_box is None else _ptr(lam_box, torch.complex128, self.lam_shape, "lam_box")
+        fo = ctypes.c_void_p(0) if f_out is None else _ptr(f_out, self.vdtype, self.vshape, "f_out")
         N.check(N.load().channel_remap(self._pp(), arr, lb, _ptr(phi, self.vdtype, self.vshape, "phi"),
                                        _ptr(k1, torch.complex128, self.k1_shape, "k1"),
                                        _ptr(k2, torch.complex128, self.k2_shape, "k2"),
-                                       _ptr(gamma_out, self.vdtype, self.vshape, "gamma_out"),
+                                       _ptr(gamma_out, self.vdtype, self.vshape, "gamma_out"), fo,
                                        _stream(stream)))
 
     def sigma_workspace_bytes(self) -> int:
@@ -130,8 +132,9 @@ class Stage:
 class Solver:
     """A parquet context on one device: workspace owned by a torch uint8 tensor."""
 
-    def __init__(self, p, precision: str = "fp64", device: str = "cuda:0", stream=None):
-        self.stage = Stage(p, precision)
+    def __init__(self, p, precision: str = "fp64", device: str = "cuda:0", stream=None, resolve_slots: int = 0,
+                 bse_tol: float = 0.0):
+        self.stage = Stage(p, precision, resolve_slots, bse_tol)
         self.device = torch.device(device)
         self.stream = stream
         lib = N.load()
@@ -158,12 +161,21 @@ class Solver:
         return self.stage.d
 
     def iterate(self, n: int = 1, tol: float = 0.0):
+        """Up to n iterations, stopping once the change of Sigma is below tol
+        (tol <= 0: never). Returns (iterations done, converged, stats of the
+        last iteration); not reaching tol is no error (converged is False).
+        Raises ParquetError for a non-finite self-energy or an unresolved BSE
+        block (the iterations done are kept in the context)."""
         st = N.PqIterStats()
         done = ctypes.c_int32()
         conv = ctypes.c_int32()
-        N.check(N.load().parquet_iterate(self.ctx, int(n), float(tol), ctypes.byref(st),
-                                         ctypes.byref(done), ctypes.byref(conv)))
+        status = N.load().parquet_iterate(self.ctx, int(n), float(tol), ctypes.byref(st),
+                                          ctypes.byref(done), ctypes.byref(conv))
         self.last_stats = st
+        self.last_status = status
+        self.last_done = int(done.value)
+        if status != N.PQ_ERR_NOT_CONVERGED:
+            N.check(status)
         return int(done.value), bool(conv.value), st
 
     def _field_shape_dtype(self, name):
@@ -174,6 +186,7 @@ class Solver:
             "k1": (s.k1_shape, torch.complex128), "k2": (s.k2_shape, torch.complex128),
             "mu": ((1,), torch.float64), "xph": (s.x_shape, torch.complex128),
             "xpp": (s.x_shape, torch.complex128), "lambda": (s.lam_shape, torch.complex128),
+            "f": (s.vshape, s.vdtype),
         }[name]
 
     def get(self, name: str) -> torch.Tensor:
@@ -249,7 +262,7 @@ def iterate_batch(solvers, n_iter: int, tol: float = 0.0):
     done = (ctypes.c_int32 * n)()
     conv = (ctypes.c_int32 * n)()
     st = N.load().parquet_iterate_batch(arr, n, int(n_iter), float(tol), done, conv)
-    if st not in (N.PQ_OK, N.PQ_ERR_NONFINITE):
+    if st not in (N.PQ_OK, N.PQ_ERR_NONFINITE, N.PQ_ERR_SINGULAR, N.PQ_ERR_NOT_CONVERGED):
         N.check(st)
     return [int(x) for x in done], [bool(x) for x in conv]
 

@@ -91,7 +91,7 @@ def test_null_pointers_are_rejected_before_enqueue():
     pp = N.make_params(config("tiny_2x2"), "fp64")
     lib = N.load()
     assert lib.bubble_build(ctypes.byref(pp), None, None, None, None) == N.PQ_ERR_ARG
-    assert lib.channel_remap(ctypes.byref(pp), None, None, None, None, None, None, None) == N.PQ_ERR_ARG
+    assert lib.channel_remap(ctypes.byref(pp), None, None, None, None, None, None, None, None) == N.PQ_ERR_ARG
     assert lib.parquet_iterate(None, 1, 0.0, None, None, None) == N.PQ_ERR_ARG
     # workspace too small is reported, not enqueued
     fake = ctypes.c_void_p(0x1000)

@@ -111,7 +111,7 @@ def _phi_on_device(u, v, dtype):
     return phi
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
 def test_full_size_iteration_sampled(ref, prec):
     print("CASE full-size iteration", prec, flush=True)
     from paper_1510_03330_amd.ops import Solver
@@ -129,12 +129,19 @@ def test_full_size_iteration_sampled(ref, prec):
     torch.cuda.empty_cache()
     done, _, stats = s.iterate(1)
     assert done == 1
-    assert stats.flagged_blocks == 0
+    print(f"   flagged {stats.flagged_blocks}, re-solved {stats.resolved_blocks}, "
+          f"largest error estimate {stats.max_err_est:.3g}", flush=True)
+    assert stats.unresolved_blocks == 0
+    if fp64:
+        assert stats.flagged_blocks == 0
+    else:
+        assert stats.max_err_est <= 1e-5 or stats.resolved_blocks == stats.flagged_blocks
 
+    bf3 = prec == "bf16x3"
     tol_sp = 1e-11 if fp64 else 1e-9        # single-particle stages run in FP64 on both paths
     tol_v = 1e-11 if fp64 else 2e-6         # vertex sums of <= 9 terms
-    tol_bse = 1e-9 if fp64 else 5e-4
-    tol_sig = 1e-9 if fp64 else 1e-4         # vertex part of Sigma alone
+    tol_bse = 1e-9 if fp64 else (5e-3 if bf3 else 5e-4)
+    tol_sig = 1e-9 if fp64 else (1e-3 if bf3 else 1e-4)   # vertex part of Sigma alone
 
     assert abs(H(s.get("mu"))[0] - ref["mu"]) < tol_sp
     assert relerr(H(s.get("g")), ref["G"]) < tol_sp
@@ -170,7 +177,7 @@ def test_full_size_iteration_sampled(ref, prec):
                 worst = max(worst, float(torch.amax(torch.abs(res)) / scale))
                 del gm, F, res
         print("max relative BSE residual over all blocks:", worst, flush=True)
-        assert worst < 1e-4
+        assert worst < (1e-3 if bf3 else 1e-4)
         del phi_new
     del gamma
     torch.cuda.empty_cache()
@@ -183,7 +190,7 @@ def test_full_size_iteration_sampled(ref, prec):
 
     sig = H(s.get("sigma"))
     got = np.array([sig[g.eidx(n), K] for (n, K) in ref["sigma_pts"]])
-    assert relerr(got, ref["sigma_base"] + ref["sigma_vertex"]) < (1e-11 if fp64 else 1e-6)
+    assert relerr(got, ref["sigma_base"] + ref["sigma_vertex"]) < (1e-11 if fp64 else (1e-5 if bf3 else 1e-6))
     assert relerr(got - ref["sigma_base"], ref["sigma_vertex"]) < tol_sig
     s.close()
     del phi_old

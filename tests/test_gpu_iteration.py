@@ -189,3 +189,149 @@ def test_reinit_restarts_from_the_bare_vertex(prec):
         assert np.array_equal(H(a.get(f)), H(b.get(f))), f
     a.close()
     b.close()
+
+
+# ----------------------------------------------------------- failure statuses
+def _status_of(fn):
+    from paper_1510_03330_amd.native import ParquetError
+    try:
+        fn()
+    except ParquetError as e:
+        return e.status
+    return 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_nan_sigma_set_through_the_context_is_reported(prec):
+    """A NaN put into Sigma through parquet_set reaches G, the bubbles and the
+    new self-energy; parquet_iterate stops after that one iteration with
+    PQ_ERR_NONFINITE (the iteration is counted), and the context stays usable:
+    setting a finite state again iterates normally."""
+    from paper_1510_03330_amd.native import PQ_ERR_NONFINITE
+    print("CASE nan sigma", prec, flush=True)
+    p = config("tiny_2x2")
+    s = _solver(p, prec)
+    good = s.get("sigma")
+    bad = good.clone()
+    bad[3, 1] = complex(float("nan"), 0.0)
+    s.set("sigma", bad)
+    assert _status_of(lambda: s.iterate(5, 1e-8)) == PQ_ERR_NONFINITE
+    assert s.last_done == 1 and s.last_stats.iteration == 1
+    assert not np.isfinite(H(s.get("sigma"))).all()
+    s.set("sigma", good)
+    s.set("phi", torch.zeros_like(s.get("phi")))
+    done, conv, st = s.iterate(2)
+    assert done == 2 and np.isfinite(st.dsigma)
+    s.close()
+
+
+def test_single_iteration_with_zero_tolerance_and_not_converged():
+    """n_iter = 1 with tol = 0: one iteration, PQ_OK, not converged. With a
+    tolerance that one iteration cannot reach: PQ_ERR_NOT_CONVERGED from the C
+    ABI (the Python wrapper returns converged = False and keeps the status)."""
+    import ctypes
+    from paper_1510_03330_amd import native as N
+    p = config("tiny_2x2")
+    s = _solver(p, "fp64")
+    done, conv, st = s.iterate(1, 0.0)
+    assert (done, conv, s.last_status) == (1, False, N.PQ_OK)
+    done, conv, st = s.iterate(1, 1e-14)
+    assert (done, conv, s.last_status) == (1, False, N.PQ_ERR_NOT_CONVERGED)
+    d, c = ctypes.c_int32(), ctypes.c_int32()
+    assert N.load().parquet_iterate(s.ctx, 2, 1e-14, None, ctypes.byref(d), ctypes.byref(c)) == N.PQ_ERR_NOT_CONVERGED
+    assert (d.value, c.value) == (2, 0)
+    assert N.load().parquet_iterate(s.ctx, 0, 1e-14, None, ctypes.byref(d), ctypes.byref(c)) == N.PQ_OK
+    assert d.value == 0
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_unresolved_blocks_make_the_iteration_singular(prec):
+    """An error tolerance no complex64 solution can meet (1e-12) flags every
+    block with a nonzero vertex; with two FP64 re-solve slots per channel the
+    others stay unresolved and parquet_iterate returns PQ_ERR_SINGULAR after
+    the iteration, with the counts in the iteration stats. With the default
+    slots every flagged block is re-solved and the iteration is OK, and its
+    results match the FP64 path to complex64 storage accuracy."""
+    from paper_1510_03330_amd.native import PQ_ERR_SINGULAR
+    from paper_1510_03330_amd.ops import Solver
+    print("CASE singular", prec, flush=True)
+    p = config("tiny_2x2")
+    s = Solver(p, prec, resolve_slots=2, bse_tol=1e-12)
+    assert _status_of(lambda: s.iterate(3)) == PQ_ERR_SINGULAR
+    st = s.last_stats
+    assert s.last_done == 1 and st.unresolved_blocks > 0 and st.flagged_blocks > 8
+    assert 6 <= st.resolved_blocks <= 8                  # two slots per channel (t: Gamma = 0 at first)
+    s.close()
+    s = Solver(p, prec, bse_tol=1e-12)
+    ref = _solver(p, "fp64")
+    for _ in range(2):
+        done, conv, st = s.iterate(1)
+        ref.iterate(1)
+        assert done == 1 and st.unresolved_blocks == 0 and st.resolved_blocks == st.flagged_blocks > 8
+    assert relerr(H(s.get("phi")).astype(np.complex128), H(ref.get("phi"))) < 1e-6
+    s.close()
+    ref.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_vertex_field(prec):
+    """PQ_FIELD_F: F = Gamma[Phi] + Phi of the current state (Eq. PA_F_G) after
+    two iterations, against the oracle's remap of that Phi plus Phi; the
+    stateless channel_remap gives the same F through its f_out argument."""
+    print("CASE full vertex", prec, flush=True)
+    p = config("small_2x4")
+    g = P.Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
+    s = _solver(p, prec)
+    s.iterate(2)
+    phi = H(s.get("phi")).astype(np.complex128)
+    K1, K2 = P.kernel_functions(g, phi, p.kernel_level, p.edge_rule)
+    ref = P.full_vertex(P.remap(g, phi, K1, K2, P.pa_lambda(p.U)), phi)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    F = s.get("f")
+    assert relerr(H(F).astype(np.complex128), ref) < tol
+    st = s.stage
+    gam = torch.empty_like(F)
+    f2 = torch.empty_like(F)
+    st.channel_remap(P.pa_lambda(p.U), s.get("phi"), s.get("k1"), s.get("k2"), gam, f_out=f2)
+    assert torch.equal(f2, F)
+    s.close()
+
+
+# ------------------------------------------------------ 4x4 lattice, Nv = 16
+@pytest.fixture(scope="module")
+def c2_two_iterations():
+    """The oracle's first two iterations on the 4x4 lattice (U = 2, beta = 4,
+    Nv = 16: 240 blocks of n = 256 per channel) from the bare-vertex start."""
+    print("CASE c2 oracle", flush=True)
+    p = config("c2")
+    g = P.Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
+    st = P.init_state(p, g)
+    out = [st]
+    for _ in range(2):
+        st = P.iterate(p, st, g)
+        out.append(st)
+    return p, g, out
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-5), ("bf16x3", 2e-4)])
+def test_c2_two_iterations_match_oracle(c2_two_iterations, prec, tol):
+    """Whole-iteration parity at the 4x4, Nv = 16 size (n = 256, 240 blocks):
+    Sigma and Phi after each of two iterations from the bare-vertex start.
+    FP64: rounding order only. Complex64 paths: complex64 storage of Phi and
+    Gamma (6e-8), the BSE error below its estimate tolerance (1e-5) times the
+    blocks' amplification into Sigma."""
+    print("CASE c2 two iterations", prec, flush=True)
+    p, g, states = c2_two_iterations
+    s = _solver(p, prec)
+    assert relerr(H(s.get("sigma")), states[0].sigma) < 1e-12
+    for it in (1, 2):
+        done, conv, stats = s.iterate(1)
+        assert done == 1 and stats.unresolved_blocks == 0
+        es = relerr(H(s.get("sigma")), states[it].sigma)
+        ep = relerr(H(s.get("phi")).astype(np.complex128), states[it].phi)
+        print(f"   iteration {it}: sigma {es:.3g}, phi {ep:.3g}, flagged {stats.flagged_blocks}, "
+              f"max estimate {stats.max_err_est:.3g}", flush=True)
+        assert es < tol and ep < 10 * tol, (it, es, ep)
+    s.close()
