@@ -105,8 +105,8 @@ typedef struct {
   double mu_fixed;
   double alpha;            /* linear mixing of Sigma and Phi, (0, 1]         */
   double bse_tol;          /* complex64 BSE: a block whose estimated relative
-                              error exceeds this is re-solved in FP64
-                              (0 selects 1e-5)                                */
+                              error |F - F_exact|_F / |F|_F exceeds this is
+                              re-solved in FP64 (0 selects 2e-5)             */
 } pq_params;
 
 /* Sizes derived from pq_params (filled by pq_dims_from_params). */
@@ -218,18 +218,21 @@ typedef struct {
  * Elimination without row exchanges (A is the identity minus a small-norm
  * kernel); the pivot monitor flags weak blocks in stats (nullable).
  * Error control of the complex64 paths (FP32, BF16x3): after the solve, the
- * relative error of every block's complex64 F is estimated in FP64 from two
- * fixed pseudo-random probe vectors v: the residual r = A (F v) - Gamma v and,
- * since A^-1 = 1 + s F X, the error estimate |r + s F (X r)| / |F v| (a cheap
- * upper bound (1 + |F X|_F) |r| / |F v| first, the refined one only where the
- * bound exceeds the tolerance). Blocks with weak pivots, a non-finite value or
- * an estimate above params.bse_tol (default 1e-5) are solved again in FP64
- * from the same Gamma and their Phi is replaced by the mixing of the FP64 F;
- * at most resolve_slots blocks per call (in q order, weak-pivot blocks first),
- * the others keep the complex64 result and stats bit 3. The workspace
- * includes the room for the re-solve. Errors of the enqueued kernels cannot
- * be returned by this enqueue-only call: check stats (bit 3) or use the
- * context API, which returns PQ_ERR_SINGULAR for them.
+ * relative error |F^ - F|_F / |F|_F of every block's complex64 solution F^ is
+ * estimated in FP64 from the residual R = A F^ - Gamma and A^-1 = 1 + s F X
+ * (which follows from F = A^-1 Gamma): a screen for every block, with R
+ * sampled through two fixed pseudo-random probe vectors on a sample of 128
+ * rows and columns (all for n <= 256) and the expected amplification
+ * |A^-1|_F / n^1/2 from tr(F X) and |F X|_F, and, where the screen exceeds
+ * half the tolerance or |A^-1|_F / n^1/2 exceeds 2, the error E v = A^-1 R v
+ * of eight probe vectors itself (max over the probes). Blocks with weak
+ * pivots, a non-finite value or an estimate above params.bse_tol (default
+ * 2e-5) are solved again in FP64 from the same Gamma and their Phi takes the
+ * mixing of the FP64 F; at most resolve_slots blocks per call (in q order,
+ * weak-pivot blocks first), the others keep the complex64 result and stats
+ * bit 3. The workspace includes the room for the re-solve. Errors of the
+ * enqueued kernels cannot be returned by this enqueue-only call: check stats
+ * (bit 3) or use the context API, which returns PQ_ERR_SINGULAR for them.
  * gamma: [Nq][n][n] (one channel), chi0: [Nq][n] c128, phi_io: [Nq][n][n],
  * both in storage precision; stats: [Nq] pq_bse_block_stats (device,
  * nullable); ws: bse_workspace bytes. */

@@ -412,7 +412,24 @@ struct BseCtx {
   double kappa_max;      // flag a block whose diagonal-block inverses exceed this
   pq_bse_block_stats* stats;
   const int* active;     // nullable: only blocks < *active are solved (re-solve slots)
+  float2* pfx;           // complex64 paths: [Nq][ceil(n/64)][ceil(n/32)] sums of |F_ij X_j|^2 and
+                         // |F_ij|^2 over the 64-row x 32-column tiles of F, written by the
+                         // kernels that mix the rows (each tile by exactly one wave)
 };
+
+// Sums over one wave's elements of a 64 x 32 tile of F (x: |F_ij X_j|^2,
+// y: |F_ij|^2), stored by lane 0 in the tile's slot (complex64 paths: the
+// norms of the error estimate).
+__device__ inline void put_fx(float2* pfx, int n, int blk, int rowblk, int colsub, float2 v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  const int nr = (n + 63) / 64, nc = (n + 31) / 32;
+  if ((threadIdx.x & 63) == 0 && rowblk < nr && colsub < nc) pfx[((size_t)blk * nr + rowblk) * nc + colsub] = v;
+}
+__device__ inline float abs2f(double2 x) { return (float)(x.x * x.x + x.y * x.y); }
 
 template <typename T>
 __device__ inline bool inactive(const BseCtx<T>& a, int blk) { return a.active && blk >= *a.active; }
@@ -810,17 +827,31 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb, int mix) {
       const int ncolA = n - j0 - jb;
       const bool tr = cs * 32 < ncolA;            // wave-uniform: the strip has A columns
       C (*ts)[33] = tr_s[wave];
+      // the last panel's rows of B are final F: mixed into Phi here, and on the
+      // complex64 paths |F_ij X_j|^2 summed per 64-row block (ncolA = 0 there,
+      // so the strip is one 32-column tile of F)
+      const bool mixes = mix && cs * 32 >= ncolA;
+      float xw = 0.f;
+      float2 fx[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+      if (sizeof(T) == 4 && mixes) {
+        const int bc = min(cs * 32 + lane % 32, ncols - 1) - ncolA;
+        xw = abs2f(a.chi0[(size_t)blk * n + bc]);
+      }
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt) {
         acc[rt].store_prod([&](int r, int c, C v) {
           const int row = rb + rt * 32 + r, col = cs * 32 + c;
           if (row < jb && col < ncols) {
             colptr(A, B, n, j0, jb, col)[(size_t)(j0 + row) * n] = v;
-            // the last panel: its B rows are final F, mixed into Phi here
-            if (mix && col >= ncolA) {
+            if (mixes) {
               const size_t e = (size_t)blk * n * n + (size_t)(j0 + row) * n + (col - ncolA);
               const bool m = a.alpha != 1.0;
               a.phi[e] = mix_phi<T>(v, a.gamma[e], m ? a.phi[e] : cz<C>(), (T)a.alpha, (T)(1.0 - a.alpha), m);
+              if constexpr (sizeof(T) == 4) {
+                const float f2 = (float)v.x * v.x + (float)v.y * v.y;
+                fx[(rb + rt * 32) / 64 % 2].x += f2 * xw;
+                fx[(rb + rt * 32) / 64 % 2].y += f2;
+              }
             }
           }
           if (tr) ts[c][r] = v;
@@ -841,6 +872,13 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb, int mix) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
+      if constexpr (sizeof(T) == 4) {
+        if (mixes && a.pfx) {
+          // rows j0 + rb .. + RW: one or two 64-row blocks (j0 is a multiple of 128)
+          put_fx(a.pfx, n, blk, (j0 + rb) / 64, cs - ncolA / 32, fx[0]);
+          if (RW > 64) put_fx(a.pfx, n, blk, (j0 + rb) / 64 + 1, cs - ncolA / 32, fx[1]);
         }
       }
     }
@@ -1034,6 +1072,17 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
     C* P = a.phi + (size_t)blk * n * n;
     const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
     const bool mix = a.alpha != 1.0;
+    // complex64: |F_ij X_j|^2 of the finished rows, per 32-column tile of the
+    // wave's 64 x 64 tile (c0 - ncolA is a multiple of 64, i0 of 64)
+    float xw[USC];
+    float2 fx[USC];
+#pragma unroll
+    for (int y = 0; y < USC; ++y) {
+      fx[y] = make_float2(0.f, 0.f);
+      xw[y] = 0.f;
+      if constexpr (sizeof(T) == 4)
+        xw[y] = cok[y] ? abs2f(a.chi0[(size_t)blk * n + c0 + y * M::TN + M::b_col(lane) - ncolA]) : 0.f;
+    }
     acc.store_c([&](int r, int c, C v) {
       const int i = i0 + r;
       const int y = c / M::TN;
@@ -1041,8 +1090,19 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
         st_c<CF::NT>(&cb[y][(size_t)i * n], v);
         const size_t e = (size_t)i * n + (c0 + c - ncolA);
         P[e] = mix_phi<T>(v, ld_c<true>(&G[e]), mix ? ld_c<true>(&P[e]) : cz<C>(), al, be, mix);
+        if constexpr (sizeof(T) == 4) {
+          const float f2 = (float)v.x * v.x + (float)v.y * v.y;
+          fx[y].x += f2 * xw[y];
+          fx[y].y += f2;
+        }
       }
     });
+    if constexpr (sizeof(T) == 4) {
+      if (a.pfx) {
+#pragma unroll
+        for (int y = 0; y < USC; ++y) put_fx(a.pfx, n, blk, i0 / 64, (c0 - ncolA) / 32 + y, fx[y]);
+      }
+    }
     return;
   }
   C* MN = mtn + (size_t)blk * NB * n;
@@ -1076,23 +1136,42 @@ void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int ro
 }
 
 // --------------------------------------------------------------- epilogue
-// Phi <- alpha (F - Gamma) + (1 - alpha) Phi for the rows row0 .. n, where
-// the kernels that finish the rows do not mix them (BF16x3 products: every
-// row; otherwise the back substitution and the last pivot-row step mix).
+// Phi <- alpha (F - Gamma) + (1 - alpha) Phi for every row, where the kernels
+// that finish the rows do not mix them (BF16x3 products). One wave per 64-row
+// x 32-column tile of F (lane l: column l % 32, rows l / 32 + 2 k), which also
+// sums |F_ij X_j|^2 over the tile for the error estimate.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a, int row0) {
+__global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a) {
   using C = typename cplx_of<T>::type;
-  const int blk = blockIdx.y, n = a.n;
-  const size_t nn = (size_t)n * n;
+  const int blk = blockIdx.y, n = a.n, lane = threadIdx.x & 63;
   if (inactive(a, blk)) return;
+  const int nr = (n + 63) / 64, nc = (n + 31) / 32;
+  const int tile = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (tile >= nr * nc) return;
+  const int rowblk = tile / nc, colsub = tile - (tile / nc) * nc;
+  const int col = colsub * 32 + (lane & 31);
+  const size_t nn = (size_t)n * n;
   const C* F = a.B + (size_t)blk * nn;
   const C* G = a.gamma + (size_t)blk * nn;
   C* P = a.phi + (size_t)blk * nn;
   const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
   const bool mix = a.alpha != 1.0;
-  for (size_t idx = (size_t)row0 * n + (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn;
-       idx += (size_t)gridDim.x * blockDim.x)
-    P[idx] = mix_phi<T>(F[idx], G[idx], mix ? P[idx] : cz<C>(), al, be, mix);
+  const float xw = col < n ? abs2f(a.chi0[(size_t)blk * n + col]) : 0.f;
+  float2 fx = make_float2(0.f, 0.f);
+  for (int k = 0; k < 32; ++k) {
+    const int row = rowblk * 64 + (lane >> 5) + 2 * k;
+    if (row < n && col < n) {
+      const size_t idx = (size_t)row * n + col;
+      const C f = F[idx];
+      P[idx] = mix_phi<T>(f, G[idx], mix ? P[idx] : cz<C>(), al, be, mix);
+      const float f2 = (float)f.x * f.x + (float)f.y * f.y;
+      fx.x += f2 * xw;
+      fx.y += f2;
+    }
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (a.pfx) put_fx(a.pfx, n, blk, rowblk, colsub, fx);
+  }
 }
 
 // Per-block statistics (after the error estimate and the FP64 re-solve have
@@ -1128,23 +1207,46 @@ constexpr int panel_width() { return sizeof(T) == 4 ? 128 : 64; }
 
 // ------------------------------------------------------------ error estimate
 // After the complex64 solve, B holds F^ = F + E. With A = 1 - s Gamma diag(X)
-// and F = A^-1 Gamma, the inverse is A^-1 = 1 + s F diag(X). For a probe v:
-//   y = F^ v,   r = A y - Gamma v = y - s Gamma (X y) - Gamma v,
-// and E v = A^-1 (A F^ - Gamma) v = A^-1 r = r + s F (X r) ~ r + s F^ (X r).
-// Two estimates of the relative error |E v| / |F v| per block (max over two
-// probes), every sum in FP64 from the stored complex64 F^ and Gamma:
-//   est  = (1 + |F^ diag(X)|_F) |r| / |y|    an upper bound (|A^-1| <= 1 + |F X|_F),
-//                                           two passes: F^ (y), Gamma (Gamma v, Gamma X y);
-//   est2 = |r + s F^ (X r)| / |y|           one more pass over F^, only for the
-//                                           blocks whose bound exceeds the tolerance.
-// A block is flagged for the FP64 re-solve when est2 (or a non-finite value)
-// exceeds the tolerance. The probes have entries (+-1 +- i)/sqrt(2) from an
-// integer hash of (column, probe), so that they are fixed and reproducible.
+// and F = A^-1 Gamma, the inverse is A^-1 = 1 + s F diag(X), and
+//   E = A^-1 R,   R = A F^ - Gamma   (the residual of the stored solution).
+// The quantity estimated per block is the relative error |E|_F / |F|_F.
+// R comes from rounding (the elimination's backward error and the complex64
+// storage of F^): it is small, not amplified and without a preferred
+// direction, so
+//   |E|_F^2 = sum_k |u_k^H R|^2 / sigma_k^2 ~ |R|_F^2 |A^-1|_F^2 / n,
+//   |A^-1|_F^2 = n + 2 s Re tr(F X) + |F X|_F^2,
+// and |R|_F is sampled through two probe vectors v_p (entries (+-1 +- i)/sqrt(2)
+// on a column sample S, from an integer hash of (column, probe); zero elsewhere):
+//   y = F^ v,   r = A y - Gamma v = y - s Gamma (X y) - Gamma v = R v,
+// evaluated in FP64 on the rows of the same sample, |R|_F^2 ~ (n/|S|)^2 |r_S|^2.
+// |F^ X|_F and |F^|_F come from the kernels that mixed the rows (tile sums),
+// tr(F^ X) from the diagonal: no full pass over F^ or Gamma.
+//   screen: est = (|A^-1|_F / n^1/2) (n / |S|) |r_S| / |F^|_F   (max over the probes)
+// Where the screen exceeds tol / 2, or |A^-1|_F / n^1/2 exceeds 2 (near the
+// instability the residual leans towards the amplified direction, and the
+// isotropic screen can be low by a few times), the error of the probes
+// themselves is evaluated (one pass over Gamma for r on every row, one over F^):
+//   E v = A^-1 r = r + s F (X r) ~ r + s F^ (X r),
+//   refined: est2 = max_p |E v_p| / |F^|_F  (8 probes on every column, |v_p|^2 = n,
+//            so |E v_p|^2 averages |E|_F^2),
+// and decides the flag (est2 > tol); otherwise the screen stands.
+// S: every index for n <= 256, else two contiguous chunks of 64 at n/4 and 3n/4.
 constexpr int kProbeRows = 4;      // rows per wave, loaded together
-constexpr double kDefaultBseTol = 1e-5;
+constexpr double kDefaultBseTol = 2e-5;
+constexpr double kScreen = 2.0;    // margin of the sampled screen
+constexpr double kAmp2 = 4.0;      // |A^-1|_F^2 / n above which the probes are evaluated exactly
+
+__device__ inline int probe_ns(int n) { return n <= 256 ? n : 128; }
+__device__ inline int probe_chunk(int n, int c) { return ((c == 0 ? n / 4 : (3 * n) / 4) - 32) & ~15; }
+__device__ inline int probe_at(int n, int s) { return n <= 256 ? s : probe_chunk(n, s >> 6) + (s & 63); }
+__device__ inline bool probe_in(int n, int j) {
+  if (n <= 256) return true;
+  const int a = probe_chunk(n, 0), b = probe_chunk(n, 1);
+  return (j >= a && j < a + 64) || (j >= b && j < b + 64);
+}
 
 __device__ inline double2 probe_vec(int j, int p) {
-  unsigned x = (unsigned)j * 2u + (unsigned)p + 0x9E3779B9u;
+  unsigned x = (unsigned)j * 8u + (unsigned)p + 0x9E3779B9u;
   x ^= x >> 16;
   x *= 0x7feb352du;
   x ^= x >> 15;
@@ -1165,95 +1267,112 @@ __device__ inline void cfma(double2& acc, double2 a, double2 b) {
   acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
 }
 
-// y_p = F^ v_p and the row sums of |F^_ij X_j|^2. One wave per kProbeRows rows,
-// lanes across the columns (coalesced rows), grid (ceil(n / (4 kProbeRows)), Nq).
-__global__ __launch_bounds__(kThreads) void probe_y_kernel(const float2* F, const double2* chi0, int n,
-                                                          const int* active, double2* y, double* nfx) {
+// Probe sets: the screen takes kNpScreen probes on the column sample of every
+// block; the refined estimate kNpRefine probes on every column of the marked
+// blocks (max over the probes: near the instability E is nearly of rank one,
+// and one probe's |E v| / |E|_F fluctuates like an exponential variable).
+constexpr int kNpScreen = 2, kNpRefine = 8;
+
+template <bool REFINE> __device__ inline bool probe_col(int n, int j) { return REFINE || probe_in(n, j); }
+
+// y_p = F^ v_p on every row. Screen: the sampled columns of every block;
+// refined: every column of the blocks with pst[6] = 2. One wave per RPW rows,
+// lanes across the columns; grid (ceil(n / (4 RPW)), Nq).
+template <int NP, int RPW, bool REFINE>
+__global__ __launch_bounds__(kThreads) void probe_y_kernel(const float2* F, int n, const double* pst, double2* y) {
   const int blk = blockIdx.y, lane = threadIdx.x & 63;
-  if (active && blk >= *active) return;
-  const int i0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * kProbeRows;
+  if (REFINE && pst[(size_t)blk * kPst + 6] != 2.0) return;
+  const int i0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * RPW;
   if (i0 >= n) return;
   const float2* Fb = F + (size_t)blk * n * n;
-  const double2* X = chi0 + (size_t)blk * n;
-  double2 a0[kProbeRows], a1[kProbeRows];
-  double sq[kProbeRows];
+  const int ns = REFINE ? n : probe_ns(n);
+  double2 acc[RPW][NP];
 #pragma unroll
-  for (int r = 0; r < kProbeRows; ++r) {
-    a0[r] = mk(0.0, 0.0);
-    a1[r] = mk(0.0, 0.0);
-    sq[r] = 0.0;
-  }
-  for (int j = lane; j < n; j += 64) {
-    const double2 v0 = probe_vec(j, 0), v1 = probe_vec(j, 1);
-    const double2 x = X[j];
-    const double x2 = x.x * x.x + x.y * x.y;
-    float2 f[kProbeRows];
+  for (int r = 0; r < RPW; ++r)
 #pragma unroll
-    for (int r = 0; r < kProbeRows; ++r) f[r] = Fb[(size_t)min(i0 + r, n - 1) * n + j];
+    for (int p = 0; p < NP; ++p) acc[r][p] = mk(0.0, 0.0);
+  for (int s = lane; s < ns; s += 64) {
+    const int j = REFINE ? s : probe_at(n, s);
+    double2 v[NP];
 #pragma unroll
-    for (int r = 0; r < kProbeRows; ++r) {
+    for (int p = 0; p < NP; ++p) v[p] = probe_vec(j, p);
+    float2 f[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) f[r] = Fb[(size_t)min(i0 + r, n - 1) * n + j];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
       const double2 fd = to_d(f[r]);
-      cfma(a0[r], fd, v0);
-      cfma(a1[r], fd, v1);
-      sq[r] = fma(fd.x * fd.x + fd.y * fd.y, x2, sq[r]);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) cfma(acc[r][p], fd, v[p]);
     }
   }
 #pragma unroll
-  for (int r = 0; r < kProbeRows; ++r) {
-    const double2 s0 = mk(wave_sum(a0[r].x), wave_sum(a0[r].y));
-    const double2 s1 = mk(wave_sum(a1[r].x), wave_sum(a1[r].y));
-    const double q = wave_sum(sq[r]);
-    if (lane == 0 && i0 + r < n) {
-      y[((size_t)blk * 2 + 0) * n + i0 + r] = s0;
-      y[((size_t)blk * 2 + 1) * n + i0 + r] = s1;
-      nfx[(size_t)blk * n + i0 + r] = q;
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const double2 sm = mk(wave_sum(acc[r][p].x), wave_sum(acc[r][p].y));
+      if (lane == 0 && i0 + r < n) y[((size_t)blk * NP + p) * n + i0 + r] = sm;
     }
-  }
 }
 
-// r_p = y_p - s Gamma (X y_p) - Gamma v_p, one pass over Gamma (same grid).
+// r_p = y_p - s Gamma (X y_p) - Gamma v_p. Screen: on the rows of the sample
+// (grid.x over the sample); refined: on every row of the marked blocks.
+template <int NP, int RPW, bool REFINE>
 __global__ __launch_bounds__(kThreads) void probe_r_kernel(const float2* G, const double2* chi0, const double2* y,
-                                                          int n, double sign, const int* active, double2* r) {
+                                                          int n, double sign, const double* pst, double2* r) {
   const int blk = blockIdx.y, lane = threadIdx.x & 63;
-  if (active && blk >= *active) return;
-  const int i0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * kProbeRows;
-  if (i0 >= n) return;
+  if (REFINE && pst[(size_t)blk * kPst + 6] != 2.0) return;
+  const int nrows = REFINE ? n : probe_ns(n);
+  const int s0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * RPW;
+  if (s0 >= nrows) return;
+  int rows[RPW];
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int sk = min(s0 + k, nrows - 1);
+    rows[k] = REFINE ? sk : probe_at(n, sk);
+  }
   const float2* Gb = G + (size_t)blk * n * n;
   const double2* X = chi0 + (size_t)blk * n;
-  const double2* y0 = y + (size_t)blk * 2 * n;
-  const double2* y1 = y0 + n;
-  double2 g0[kProbeRows], g1[kProbeRows], h0[kProbeRows], h1[kProbeRows];
+  const double2* yb = y + (size_t)blk * NP * n;
+  double2 g[RPW][NP], h[RPW][NP];
 #pragma unroll
-  for (int k = 0; k < kProbeRows; ++k) g0[k] = g1[k] = h0[k] = h1[k] = mk(0.0, 0.0);
+  for (int k = 0; k < RPW; ++k)
+#pragma unroll
+    for (int p = 0; p < NP; ++p) g[k][p] = h[k][p] = mk(0.0, 0.0);
   for (int j = lane; j < n; j += 64) {
-    const double2 v0 = probe_vec(j, 0), v1 = probe_vec(j, 1);
+    const bool in = probe_col<REFINE>(n, j);
     const double2 x = X[j];
-    const double2 z0 = cmul(x, y0[j]), z1 = cmul(x, y1[j]);
-    float2 g[kProbeRows];
+    double2 v[NP], z[NP];
 #pragma unroll
-    for (int k = 0; k < kProbeRows; ++k) g[k] = Gb[(size_t)min(i0 + k, n - 1) * n + j];
+    for (int p = 0; p < NP; ++p) {
+      v[p] = in ? probe_vec(j, p) : mk(0.0, 0.0);
+      z[p] = cmul(x, yb[(size_t)p * n + j]);
+    }
+    float2 gv[RPW];
 #pragma unroll
-    for (int k = 0; k < kProbeRows; ++k) {
-      const double2 gd = to_d(g[k]);
-      cfma(g0[k], gd, v0);
-      cfma(g1[k], gd, v1);
-      cfma(h0[k], gd, z0);
-      cfma(h1[k], gd, z1);
+    for (int k = 0; k < RPW; ++k) gv[k] = Gb[(size_t)rows[k] * n + j];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const double2 gd = to_d(gv[k]);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        cfma(g[k][p], gd, v[p]);
+        cfma(h[k][p], gd, z[p]);
+      }
     }
   }
 #pragma unroll
-  for (int k = 0; k < kProbeRows; ++k) {
-    const double2 sg0 = mk(wave_sum(g0[k].x), wave_sum(g0[k].y));
-    const double2 sg1 = mk(wave_sum(g1[k].x), wave_sum(g1[k].y));
-    const double2 sh0 = mk(wave_sum(h0[k].x), wave_sum(h0[k].y));
-    const double2 sh1 = mk(wave_sum(h1[k].x), wave_sum(h1[k].y));
-    const int i = i0 + k;
-    if (lane == 0 && i < n) {
-      const double2 a = y0[i], b = y1[i];
-      r[((size_t)blk * 2 + 0) * n + i] = mk(a.x - sign * sh0.x - sg0.x, a.y - sign * sh0.y - sg0.y);
-      r[((size_t)blk * 2 + 1) * n + i] = mk(b.x - sign * sh1.x - sg1.x, b.y - sign * sh1.y - sg1.y);
+  for (int k = 0; k < RPW; ++k)
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const double2 sg = mk(wave_sum(g[k][p].x), wave_sum(g[k][p].y));
+      const double2 sh = mk(wave_sum(h[k][p].x), wave_sum(h[k][p].y));
+      const int i = rows[k];
+      if (lane == 0 && s0 + k < nrows) {
+        const double2 a = yb[(size_t)p * n + i];
+        r[((size_t)blk * NP + p) * n + i] = mk(a.x - sign * sh.x - sg.x, a.y - sign * sh.y - sg.y);
+      }
     }
-  }
 }
 
 __device__ inline double safe_ratio(double num2, double den2) {
@@ -1261,95 +1380,95 @@ __device__ inline double safe_ratio(double num2, double den2) {
   return sqrt(num2 / den2);     // den2 = 0 with num2 > 0: +inf (flagged)
 }
 
-// Per block (one workgroup): the bound est; blocks above tol with a finite
-// bound get the refined estimate (pst[6] = 2), non-finite ones are flagged.
-__global__ __launch_bounds__(kThreads) void probe_est_kernel(const double2* y, const double2* r, const double* nfx,
-                                                            int n, double tol, const int* active, double* pst) {
+// Per block (one workgroup): the screen. Above tol / kScreen, or with |A^-1|_F
+// amplifying, with a finite value: refined estimate pending (pst[6] = 2);
+// non-finite: flagged (1).
+__global__ __launch_bounds__(kThreads) void probe_est_kernel(const double2* r, const float2* pfx, const float2* F,
+                                                            const double2* chi0, int n, double sign, double tol,
+                                                            double* pst) {
   __shared__ double red[kThreads];
   const int blk = blockIdx.x;
-  if (active && blk >= *active) return;
-  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int ns = probe_ns(n);
+  const int nt = ((n + 63) / 64) * ((n + 31) / 32);
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // |r_0|^2, |r_1|^2, |F X|^2, |F|^2, Re tr(F X)
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const int i = probe_at(n, q);
+    s[0] += cabs2(r[((size_t)blk * kNpScreen + 0) * n + i]);
+    s[1] += cabs2(r[((size_t)blk * kNpScreen + 1) * n + i]);
+  }
+  for (int q = threadIdx.x; q < nt; q += blockDim.x) {
+    const float2 v = pfx[(size_t)blk * nt + q];
+    s[2] += (double)v.x;
+    s[3] += (double)v.y;
+  }
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    s[0] += cabs2(y[((size_t)blk * 2 + 0) * n + i]);
-    s[1] += cabs2(y[((size_t)blk * 2 + 1) * n + i]);
-    s[2] += cabs2(r[((size_t)blk * 2 + 0) * n + i]);
-    s[3] += cabs2(r[((size_t)blk * 2 + 1) * n + i]);
-    s[4] += nfx[(size_t)blk * n + i];
+    const double2 f = to_d(F[(size_t)blk * n * n + (size_t)i * n + i]), x = chi0[(size_t)blk * n + i];
+    s[4] += f.x * x.x - f.y * x.y;
   }
   for (int k = 0; k < 5; ++k) s[k] = block_sum(s[k], red);
   if (threadIdx.x == 0) {
     double* ps = pst + (size_t)blk * kPst;
-    double est = (1.0 + sqrt(s[4])) * fmax(safe_ratio(s[2], s[0]), safe_ratio(s[3], s[1]));
+    const double samp = (double)n / ns;
+    const double amp2 = fmax(0.0, 1.0 + (2.0 * sign * s[4] + s[2]) / n);     // |A^-1|_F^2 / n
+    double est = sqrt(amp2) * samp * sqrt(fmax(s[0], s[1])) / sqrt(s[3]);
+    if (s[0] == 0.0 && s[1] == 0.0) est = s[3] == s[3] ? 0.0 : INFINITY;     // F = 0 exactly
     const bool fin = est <= DBL_MAX;          // false for NaN and +inf
     if (!fin) est = INFINITY;
     ps[5] = est;
-    ps[6] = est > tol ? (fin ? 2.0 : 1.0) : 0.0;
-    ps[8] = s[0];
-    ps[9] = s[1];
+    // the refined estimate also wherever A^-1 amplifies (|A^-1|_F / n^1/2 > 2):
+    // there the rounding residual need not be isotropic (near the instability
+    // it leans towards the amplified direction)
+    ps[6] = !fin ? 1.0 : ((est > tol / kScreen || amp2 > kAmp2) ? 2.0 : 0.0);
+    ps[8] = s[3];
   }
 }
 
-// c_p = r_p + s F^ (X r_p) for the blocks marked pst[6] = 2; writes |c_p|^2 per row.
+// c_p = r_p + s F^ (X r_p) = E v_p for the marked blocks; writes |c_p|^2 per row.
+template <int NP>
 __global__ __launch_bounds__(kThreads) void probe_c_kernel(const float2* F, const double2* chi0, const double2* r,
-                                                          int n, double sign, const int* active, const double* pst,
-                                                          double* cq) {
+                                                          int n, double sign, const double* pst, double* cq) {
   const int blk = blockIdx.y, lane = threadIdx.x & 63;
-  if (active && blk >= *active) return;
   if (pst[(size_t)blk * kPst + 6] != 2.0) return;
-  const int i0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * kProbeRows;
-  if (i0 >= n) return;
-  const float2* Fb = F + (size_t)blk * n * n;
+  const int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const float2* Fb = F + (size_t)blk * n * n + (size_t)i * n;
   const double2* X = chi0 + (size_t)blk * n;
-  const double2* r0 = r + (size_t)blk * 2 * n;
-  const double2* r1 = r0 + n;
-  double2 c0[kProbeRows], c1[kProbeRows];
+  const double2* rb = r + (size_t)blk * NP * n;
+  double2 c[NP];
 #pragma unroll
-  for (int k = 0; k < kProbeRows; ++k) c0[k] = c1[k] = mk(0.0, 0.0);
+  for (int p = 0; p < NP; ++p) c[p] = mk(0.0, 0.0);
   for (int j = lane; j < n; j += 64) {
     const double2 x = X[j];
-    const double2 z0 = cmul(x, r0[j]), z1 = cmul(x, r1[j]);
-    float2 f[kProbeRows];
+    const double2 fd = to_d(Fb[j]);
 #pragma unroll
-    for (int k = 0; k < kProbeRows; ++k) f[k] = Fb[(size_t)min(i0 + k, n - 1) * n + j];
-#pragma unroll
-    for (int k = 0; k < kProbeRows; ++k) {
-      const double2 fd = to_d(f[k]);
-      cfma(c0[k], fd, z0);
-      cfma(c1[k], fd, z1);
-    }
+    for (int p = 0; p < NP; ++p) cfma(c[p], fd, cmul(x, rb[(size_t)p * n + j]));
   }
 #pragma unroll
-  for (int k = 0; k < kProbeRows; ++k) {
-    const double2 s0 = mk(wave_sum(c0[k].x), wave_sum(c0[k].y));
-    const double2 s1 = mk(wave_sum(c1[k].x), wave_sum(c1[k].y));
-    const int i = i0 + k;
-    if (lane == 0 && i < n) {
-      const double2 a = r0[i], b = r1[i];
-      const double2 e0 = mk(a.x + sign * s0.x, a.y + sign * s0.y);
-      const double2 e1 = mk(b.x + sign * s1.x, b.y + sign * s1.y);
-      cq[((size_t)blk * n + i) * 2 + 0] = cabs2(e0);
-      cq[((size_t)blk * n + i) * 2 + 1] = cabs2(e1);
+  for (int p = 0; p < NP; ++p) {
+    const double2 sm = mk(wave_sum(c[p].x), wave_sum(c[p].y));
+    if (lane == 0) {
+      const double2 a = rb[(size_t)p * n + i];
+      cq[((size_t)blk * n + i) * NP + p] = cabs2(mk(a.x + sign * sm.x, a.y + sign * sm.y));
     }
   }
 }
 
-// Per block: the refined estimate replaces the bound and decides the flag.
-__global__ __launch_bounds__(kThreads) void probe_flag_kernel(const double* cq, int n, double tol, const int* active,
-                                                             double* pst) {
+// Per block: the refined estimate (max over the probes of (n |E v_p|^2)^1/2 /
+// (|v_p| |F^|_F), |v_p|^2 = n) replaces the screen and decides the flag.
+template <int NP>
+__global__ __launch_bounds__(kThreads) void probe_flag_kernel(const double* cq, int n, double tol, double* pst) {
   __shared__ double red[kThreads];
   const int blk = blockIdx.x;
-  if (active && blk >= *active) return;
   double* ps = pst + (size_t)blk * kPst;
   if (ps[6] != 2.0) return;                   // uniform over the workgroup
-  double c0 = 0.0, c1 = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    c0 += cq[((size_t)blk * n + i) * 2 + 0];
-    c1 += cq[((size_t)blk * n + i) * 2 + 1];
+  double mx = 0.0;
+  for (int p = 0; p < NP; ++p) {
+    double c = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) c += cq[((size_t)blk * n + i) * NP + p];
+    mx = fmax(mx, block_sum(c, red));
   }
-  c0 = block_sum(c0, red);
-  c1 = block_sum(c1, red);
   if (threadIdx.x == 0) {
-    double est = fmax(safe_ratio(c0, ps[8]), safe_ratio(c1, ps[9]));
+    double est = safe_ratio(mx, ps[8]);
     if (!(est <= DBL_MAX)) est = INFINITY;
     ps[5] = est;
     ps[6] = est > tol ? 1.0 : 0.0;
@@ -1378,18 +1497,18 @@ __global__ __launch_bounds__(kThreads) void refine_list_kernel(double* pst, int 
                                                               int S, int late, int* list) {
   __shared__ unsigned char flag[kMaxBlocks];
   for (int b = threadIdx.x; b < Nq; b += blockDim.x) {
-    const double* ps = pst + (size_t)b * kPst;
+    double* ps = pst + (size_t)b * kPst;
     const bool piv = pivot_flagged(ps, weak, kappa_max);
     flag[b] = late ? (!piv && ps[6] == 1.0) : piv;
+    if (!late) {
+      ps[3] = 0.0;
+      ps[7] = 0.0;
+    }
   }
-  __syncthreads();
+  __syncthreads();                  // (also orders the resets before the overflow marks below)
   if (threadIdx.x == 0) {           // ordered compaction from LDS
     int c = late ? list[S] : 0;
     for (int b = 0; b < Nq; ++b) {
-      if (!late) {
-        pst[(size_t)b * kPst + 3] = 0.0;
-        pst[(size_t)b * kPst + 7] = 0.0;
-      }
       if (flag[b]) {
         if (c < S) list[c++] = b;
         else pst[(size_t)b * kPst + 7] = 1.0;
@@ -1466,7 +1585,7 @@ constexpr double kResolveBudget = 2.5 * 1024.0 * 1024.0 * 1024.0;
 struct BseLayout {
   size_t A, B, MT, PI, pst;
   // complex64 path only: error estimate and FP64 re-solve of flagged blocks
-  size_t py, pr, pnfx, pcq;
+  size_t py, pr, pfx, pcq;
   size_t list, g64, x64, p64, phis, ws64;
   int slots;
   size_t total;
@@ -1502,10 +1621,10 @@ BseLayout bse_layout(const Dims& d, int slots_req) {
   if constexpr (sizeof(T) == 4) {
     const int S = resolve_slots(d, slots_req);
     L.slots = S;
-    L.py = take(sizeof(double2) * 2 * (size_t)d.n * d.Nq);
-    L.pr = take(sizeof(double2) * 2 * (size_t)d.n * d.Nq);
-    L.pnfx = take(sizeof(double) * (size_t)d.n * d.Nq);
-    L.pcq = take(sizeof(double) * 2 * (size_t)d.n * d.Nq);
+    L.py = take(sizeof(double2) * kNpRefine * (size_t)d.n * d.Nq);
+    L.pr = take(sizeof(double2) * kNpRefine * (size_t)d.n * d.Nq);
+    L.pfx = take(sizeof(float2) * (size_t)((d.n + 63) / 64) * ((d.n + 31) / 32) * d.Nq);
+    L.pcq = take(sizeof(double) * kNpRefine * (size_t)d.n * d.Nq);
     Dims r = d;
     r.Nq = S;
     L.list = take(sizeof(int) * (S + 2));
@@ -1553,6 +1672,8 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   a.pst = (double*)(w + L.pst);
   a.stats = stats;
   a.active = active;
+  a.pfx = nullptr;
+  if constexpr (sizeof(T) == 4) a.pfx = (float2*)(w + L.pfx);
   const int n = d.n;
   // event timing around each launch (kind: 0 init, 1 pivot, 2 panel, 3 update,
   // 4 epilogue, 5 error estimate and FP64 re-solve)
@@ -1664,8 +1785,9 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   }
   if (!kFuseMix) {            // every row in a separate pass
     pre(4);
-    const unsigned ew_x = (unsigned)std::min<size_t>(1024, ((size_t)n * n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3(ew_x, d.Nq), dim3(kThreads), 0, s, a, 0);
+    const unsigned ntile = (unsigned)(((n + 63) / 64) * ((n + 31) / 32));
+    hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3((ntile + kWaves - 1) / kWaves, d.Nq), dim3(kThreads), 0, s,
+                       a);
     post();
   }
   if constexpr (sizeof(T) == 4) {
@@ -1673,21 +1795,33 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     // re-solve of the flagged blocks
     pre(5);
     const double sg = kSign[channel];
-    const unsigned rx = (unsigned)((n + kWaves * kProbeRows - 1) / (kWaves * kProbeRows));
+    const unsigned rows_scr = kWaves * 4, rows_ref = kWaves;
+    const unsigned rx_all = (unsigned)((n + rows_scr - 1) / rows_scr);
+    const int ns = n <= 256 ? n : 128;
+    const unsigned rx_s = (unsigned)((ns + rows_scr - 1) / rows_scr);
+    const unsigned rx_ref = (unsigned)((n + rows_ref - 1) / rows_ref);
     double2* py = (double2*)(w + L.py);
     double2* pr = (double2*)(w + L.pr);
-    double* pnfx = (double*)(w + L.pnfx);
     double* pcq = (double*)(w + L.pcq);
     const float2* fh = (const float2*)a.B;
-    hipLaunchKernelGGL(probe_y_kernel, dim3(rx, d.Nq), dim3(kThreads), 0, s, fh, chi0, n, active, py, pnfx);
-    hipLaunchKernelGGL(probe_r_kernel, dim3(rx, d.Nq), dim3(kThreads), 0, s, (const float2*)gamma, chi0,
-                       (const double2*)py, n, sg, active, pr);
-    hipLaunchKernelGGL(probe_est_kernel, dim3(d.Nq), dim3(kThreads), 0, s, (const double2*)py, (const double2*)pr,
-                       (const double*)pnfx, n, err_tol, active, a.pst);
-    hipLaunchKernelGGL(probe_c_kernel, dim3(rx, d.Nq), dim3(kThreads), 0, s, fh, chi0, (const double2*)pr, n, sg,
-                       active, (const double*)a.pst, pcq);
-    hipLaunchKernelGGL(probe_flag_kernel, dim3(d.Nq), dim3(kThreads), 0, s, (const double*)pcq, n, err_tol, active,
-                       a.pst);
+    const float2* gm = (const float2*)gamma;
+    const double* cpst = a.pst;
+    // screen (every block)
+    hipLaunchKernelGGL((probe_y_kernel<kNpScreen, 4, false>), dim3(rx_all, d.Nq), dim3(kThreads), 0, s, fh, n, cpst,
+                       py);
+    hipLaunchKernelGGL((probe_r_kernel<kNpScreen, 4, false>), dim3(rx_s, d.Nq), dim3(kThreads), 0, s, gm, chi0,
+                       (const double2*)py, n, sg, cpst, pr);
+    hipLaunchKernelGGL(probe_est_kernel, dim3(d.Nq), dim3(kThreads), 0, s, (const double2*)pr,
+                       (const float2*)a.pfx, fh, chi0, n, sg, err_tol, a.pst);
+    // refined estimate (the marked blocks only; the others exit at once)
+    hipLaunchKernelGGL((probe_y_kernel<kNpRefine, 1, true>), dim3(rx_ref, d.Nq), dim3(kThreads), 0, s, fh, n, cpst,
+                       py);
+    hipLaunchKernelGGL((probe_r_kernel<kNpRefine, 1, true>), dim3(rx_ref, d.Nq), dim3(kThreads), 0, s, gm, chi0,
+                       (const double2*)py, n, sg, cpst, pr);
+    hipLaunchKernelGGL((probe_c_kernel<kNpRefine>), dim3(rx_ref, d.Nq), dim3(kThreads), 0, s, fh, chi0,
+                       (const double2*)pr, n, sg, cpst, pcq);
+    hipLaunchKernelGGL((probe_flag_kernel<kNpRefine>), dim3(d.Nq), dim3(kThreads), 0, s, (const double*)pcq, n,
+                       err_tol, a.pst);
     refine_gather(1);
     Dims r = d;
     r.Nq = S;

@@ -389,10 +389,10 @@ def c2_bse():
 
 # Stated bound of the complex64 paths: a block either keeps its complex64
 # solution, whose relative error (Frobenius norm of F) is then below the
-# tolerance (default 1e-5; factor 2 for the spread of a two-probe estimate),
+# tolerance (default 2e-5; factor 2 for the spread of the estimate),
 # or carries the FP64 re-solve flag and matches the FP64 solution to complex64
 # storage accuracy.
-BSE_TOL_DEFAULT = 1e-5
+BSE_TOL_DEFAULT = 2e-5
 
 
 def _fro_rel(a, b):
