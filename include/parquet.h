@@ -185,6 +185,20 @@ pq_status sigma_sde(const pq_params* p, const void* phi, const void* k1,
                     const void* k2, const void* lambda_box, const void* g, const void* mu,
                     void* sigma_out, void* ws, size_t ws_bytes, pq_stream stream);
 
+/* sigma_sde without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same computation, its scratch taken from a
+ * static device array of 64 MiB that each GPU holds from the library's load
+ * until the process ends. No device memory is allocated or freed. Parameter
+ * sets whose sigma_sde_workspace exceeds 64 MiB return PQ_ERR_NOMEM before
+ * anything is enqueued (the 8x8, Nv = 16, f = 2 box needs 6.9 MB). Every call
+ * on one GPU shares that GPU's scratch: calls that overlap on one GPU (other
+ * streams, other threads) race; calls on one stream are ordered. The stream
+ * must belong to the current device. Arguments as sigma_sde. */
+pq_status sigma_sde_no_alloc(const pq_params* p, const void* phi, const void* k1, const void* k2,
+                             const void* lambda_box, const void* g, const void* mu, void* sigma_out,
+                             pq_stream stream);
+
 /* Workspace bytes for bse_solve on one channel. */
 pq_status bse_workspace(const pq_params* p, size_t* bytes);
 

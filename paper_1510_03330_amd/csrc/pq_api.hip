@@ -171,6 +171,26 @@ pq_status sigma_sde(const pq_params* p, const void* phi, const void* k1, const v
              "sigma_sde");
 }
 
+pq_status sigma_sde_no_alloc(const pq_params* p, const void* phi, const void* k1, const void* k2,
+                             const void* lambda_box, const void* g, const void* mu, void* sigma_out,
+                             pq_stream stream) {
+  Dims d;
+  if (!make_dims(p, &d)) return PQ_ERR_ARG;
+  PQ_CHECK_ARG(phi && k1 && k2 && g && mu && sigma_out, "null pointer");
+  const size_t need = sigma_ws_bytes(d);
+  if (need > kStaticScratchBytes) {
+    set_error("sigma_sde_no_alloc needs %zu bytes of scratch; the static scratch holds %zu", need,
+              kStaticScratchBytes);
+    return PQ_ERR_NOMEM;
+  }
+  void* ws = nullptr;
+  hipError_t e = static_scratch(&ws);
+  if (e != hipSuccess) return hip_fail(e, "sigma_sde_no_alloc (scratch address)");
+  return enq(launch_sigma(*p, d, phi, (const double2*)k1, (const double2*)k2, (const double2*)lambda_box,
+                          (const double2*)g, (const double*)mu, (double2*)sigma_out, ws, (hipStream_t)stream),
+             "sigma_sde_no_alloc");
+}
+
 pq_status bse_workspace(const pq_params* p, size_t* bytes) {
   Dims d;
   if (!make_dims(p, &d)) return PQ_ERR_ARG;

@@ -55,6 +55,10 @@ hipError_t launch_mlp_to_bf16(const float* params, void* params_bf16, size_t cou
 hipError_t launch_phi_from_kernels(const pq_params& p, const Dims& d, const double2* k1, const double2* k2,
                                    void* phi, hipStream_t s);
 size_t sigma_ws_bytes(const Dims& d);
+// Device address of the static scratch of sigma_sde_no_alloc on the current
+// device (looked up once per device, then cached).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+hipError_t static_scratch(void** out);
 hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, const double2* k1,
                         const double2* k2, const double2* lam_box, const double2* g, const double* mu,
                         double2* sigma_out, void* ws, hipStream_t s);

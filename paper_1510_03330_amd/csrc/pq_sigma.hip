@@ -20,6 +20,8 @@
 // gathers), and the kernel part only needs contiguous rows of K2.
 #include <math.h>
 
+#include <mutex>
+
 #include "pq_internal.h"
 
 namespace pq {
@@ -547,6 +549,36 @@ hipError_t run_sigma1(const pq_params& p, const Dims& d, const double2* g, const
 }  // namespace
 
 size_t sigma_ws_bytes(const Dims& d) { return ws_layout(d).total; }
+
+// ------------------------------------------------------ static scratch
+// Workspace of sigma_sde_no_alloc: a file-scope device array, one copy per
+// device that loads the library, held until the process ends. Host code never
+// uses the array's name as an address (on the host it is a stand-in symbol):
+// the device address is looked up once per device with hipGetSymbolAddress,
+// with that device current, and kept.
+namespace {
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_sigma1(const pq_params& p, const Dims& d, const double2* g, const double* mu,
                          double2* sigma_out, void* ws, hipStream_t s) {

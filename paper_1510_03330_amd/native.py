@@ -34,6 +34,7 @@ EXPORTS = [
     "parquet_query_workspace", "parquet_init", "parquet_iterate", "parquet_get", "parquet_set",
     "parquet_field_bytes", "parquet_copy_state", "parquet_iterate_batch", "parquet_destroy",
     "phi_from_kernels", "mlp_param_count", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_to_bf16",
+    "sigma_sde_no_alloc",
 ]
 
 
@@ -102,6 +103,8 @@ def load() -> ctypes.CDLL:
         "sigma_sde_workspace": [P, POINTER(c_size_t)],
         "sigma_sde": [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                       c_size_t, c_void_p],
+        "sigma_sde_no_alloc": [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_void_p],
         "bse_workspace": [P, POINTER(c_size_t)],
         "bse_solve": [P, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
                       c_void_p, c_size_t, c_void_p],

@@ -101,6 +101,17 @@ class Stage:
                                    _ptr(ws, torch.uint8, (ws.numel(),), "ws"), ctypes.c_size_t(ws.numel()),
                                    _stream(stream)))
 
+    def sigma_sde_no_alloc(self, phi, k1, k2, g, mu, sigma_out, lam_box=None, stream=None):
+        """sigma_sde with its scratch in the library's static device array (no workspace)."""
+        lb = ctypes.c_void_p(0) if lam_box is None else _ptr(lam_box, torch.complex128, self.lam_shape, "lam_box")
+        N.check(N.load().sigma_sde_no_alloc(self._pp(), _ptr(phi, self.vdtype, self.vshape, "phi"),
+                                            _ptr(k1, torch.complex128, self.k1_shape, "k1"),
+                                            _ptr(k2, torch.complex128, self.k2_shape, "k2"), lb,
+                                            _ptr(g, torch.complex128, self.g_shape, "g"),
+                                            _ptr(mu, torch.float64, (1,), "mu"),
+                                            _ptr(sigma_out, torch.complex128, self.sigma_shape, "sigma_out"),
+                                            _stream(stream)))
+
     def bse_workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
         N.check(N.load().bse_workspace(self._pp(), ctypes.byref(b)))

@@ -156,3 +156,22 @@ def test_mlp_widths_are_checked_on_the_host():
     assert count([0, 4]) == N.PQ_ERR_ARG
     assert count([4]) == N.PQ_ERR_ARG                       # no layer
     assert count([1] * 18) == N.PQ_ERR_ARG                  # 17 layers
+
+
+def test_no_alloc_entry_point_rejects_boxes_beyond_its_scratch():
+    """sigma_sde_no_alloc checks the scratch its parameters need against the
+    64 MiB static array before touching the device: an 8x8 lattice with
+    Nv = 64 and f = 4 needs more and gets PQ_ERR_NOMEM; null pointers give
+    PQ_ERR_ARG."""
+    lib = N.load()
+    big = N.make_params(config("c3", Nv=64, f_ext=4), "fp32")
+    ws = ctypes.c_size_t()
+    N.check(lib.sigma_sde_workspace(ctypes.byref(big), ctypes.byref(ws)))
+    assert ws.value > 64 << 20
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.sigma_sde_no_alloc(ctypes.byref(big), fake, fake, fake, None, fake, fake, fake, None) == N.PQ_ERR_NOMEM
+    assert b"static scratch" in lib.parquet_last_error()
+    small = N.make_params(config("c3"), "fp32")
+    N.check(lib.sigma_sde_workspace(ctypes.byref(small), ctypes.byref(ws)))
+    assert ws.value < 64 << 20
+    assert lib.sigma_sde_no_alloc(ctypes.byref(small), None, fake, fake, None, fake, fake, fake, None) == N.PQ_ERR_ARG
