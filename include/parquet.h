@@ -65,8 +65,9 @@ typedef enum {
   PQ_ERR_SINGULAR = 4,     /* context API: a BSE block of the last iteration
                               is unresolved (stats bit 3: no finite FP64
                               solution, or flagged beyond the re-solve slots) */
-  PQ_ERR_NOT_CONVERGED = 5,/* context API: n_iter iterations done, tol > 0
-                              not reached (the state is valid; call again)   */
+  PQ_ERR_NOT_CONVERGED = 5,/* context API: n_iter iterations done, the
+                              convergence test (tol != 0) not met (the state
+                              is valid; call again)                          */
   PQ_ERR_NONFINITE = 6     /* NaN/Inf in Sigma                               */
 } pq_status;
 
@@ -348,10 +349,20 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
                        pq_ctx** out);
 
 /* Run up to n_iter iterations (Dyson -> bubbles -> kernels -> remap -> SDE ->
- * BSE -> mixing); stops early once max|Sigma_new - Sigma_old| < tol (tol <= 0:
- * never). Synchronises once per iteration for the norm and a summary of the
- * BSE block flags. stats: host, nullable. Returns PQ_OK (converged, or tol <= 0
- * and n_iter done), PQ_ERR_NOT_CONVERGED (tol > 0 not reached in n_iter),
+ * BSE -> mixing), stopping early on the convergence test of tol:
+ *   tol > 0: the change max|Sigma_new - Sigma_old| is below tol;
+ *   tol < 0: the estimated distance of the mixed Sigma to the fixed point is
+ *            below |tol| max|Sigma|, i.e. alpha dmax / (1 - rho) < |tol|
+ *            max|Sigma| with dmax the largest change of the last six
+ *            iterations and rho the contraction per iteration, the geometric
+ *            mean of the last six ratios of successive changes (seven
+ *            iterations of this state needed, rho < 0.98; the history
+ *            restarts after parquet_set of SIGMA or PHI and goes along
+ *            with parquet_copy_state);
+ *   tol = 0: never (exactly n_iter iterations).
+ * Synchronises once per iteration for the norm and a summary of the BSE block
+ * flags. stats: host, nullable. Returns PQ_OK (converged, or tol = 0 and n_iter
+ * done), PQ_ERR_NOT_CONVERGED (tol != 0 not reached in n_iter),
  * PQ_ERR_NONFINITE (the new self-energy is not finite) or PQ_ERR_SINGULAR (a
  * BSE block is unresolved); the last two stop after the iteration that met
  * them, whose results are kept (*iters_done counts it). */
@@ -365,10 +376,10 @@ pq_status parquet_iterate(pq_ctx* ctx, int32_t n_iter, double tol, pq_iter_stats
  * setting changed. Every round replays the graphs of the contexts that are
  * still active, each on its own stream, then reads each norm (one
  * synchronisation per context per round) and retires the converged ones
- * (max|Sigma_new - Sigma_old| < tol, tol <= 0: never), those with a
+ * (the test of parquet_iterate with tol), those with a
  * non-finite self-energy and those with an unresolved BSE block (the others
  * continue). Returns the most severe outcome over the contexts:
- * PQ_ERR_NONFINITE, then PQ_ERR_SINGULAR, then PQ_ERR_NOT_CONVERGED (tol > 0
+ * PQ_ERR_NONFINITE, then PQ_ERR_SINGULAR, then PQ_ERR_NOT_CONVERGED (tol != 0
  * and a context still active after n_iter rounds), else PQ_OK.
  * ctxs: count contexts with distinct, created (non-null) streams;
  * iters_done, converged: host arrays of count entries, nullable. Not for

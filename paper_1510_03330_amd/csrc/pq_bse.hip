@@ -412,24 +412,19 @@ struct BseCtx {
   double kappa_max;      // flag a block whose diagonal-block inverses exceed this
   pq_bse_block_stats* stats;
   const int* active;     // nullable: only blocks < *active are solved (re-solve slots)
-  float2* pfx;           // complex64 paths: [Nq][ceil(n/64)][ceil(n/32)] sums of |F_ij X_j|^2 and
-                         // |F_ij|^2 over the 64-row x 32-column tiles of F, written by the
-                         // kernels that mix the rows (each tile by exactly one wave)
+  float* pcs;            // complex64 paths: [Nq][ceil(n/64)][n] column sums of |F_ij|^2 over
+                         // the 64-row blocks of F, written by the kernels that mix the rows
 };
 
-// Sums over one wave's elements of a 64 x 32 tile of F (x: |F_ij X_j|^2,
-// y: |F_ij|^2), stored by lane 0 in the tile's slot (complex64 paths: the
-// norms of the error estimate).
-__device__ inline void put_fx(float2* pfx, int n, int blk, int rowblk, int colsub, float2 v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o, 64);
-    v.y += __shfl_xor(v.y, o, 64);
-  }
-  const int nr = (n + 63) / 64, nc = (n + 31) / 32;
-  if ((threadIdx.x & 63) == 0 && rowblk < nr && colsub < nc) pfx[((size_t)blk * nr + rowblk) * nc + colsub] = v;
+// Column sums of |F_ij|^2 over one 64-row block: the two lanes l and l + 32 of
+// a 32-column tile hold different rows of column l % 32 in the matrix-core
+// layouts used here, so they are combined and lanes 0 .. 31 store
+// (complex64 paths: the norms of the error estimate).
+__device__ inline void put_cs(float* pcs, int n, int blk, int rowblk, int col, float v) {
+  v += __shfl_xor(v, 32, 64);
+  const int nr = (n + 63) / 64;
+  if ((threadIdx.x & 63) < 32 && rowblk < nr && col < n) pcs[((size_t)blk * nr + rowblk) * n + col] = v;
 }
-__device__ inline float abs2f(double2 x) { return (float)(x.x * x.x + x.y * x.y); }
 
 template <typename T>
 __device__ inline bool inactive(const BseCtx<T>& a, int blk) { return a.active && blk >= *a.active; }
@@ -831,12 +826,7 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb, int mix) {
       // complex64 paths |F_ij X_j|^2 summed per 64-row block (ncolA = 0 there,
       // so the strip is one 32-column tile of F)
       const bool mixes = mix && cs * 32 >= ncolA;
-      float xw = 0.f;
-      float2 fx[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-      if (sizeof(T) == 4 && mixes) {
-        const int bc = min(cs * 32 + lane % 32, ncols - 1) - ncolA;
-        xw = abs2f(a.chi0[(size_t)blk * n + bc]);
-      }
+      float fs[2] = {0.f, 0.f};      // |F_ij|^2 of this lane's column, per 64-row block
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt) {
         acc[rt].store_prod([&](int r, int c, C v) {
@@ -847,11 +837,7 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb, int mix) {
               const size_t e = (size_t)blk * n * n + (size_t)(j0 + row) * n + (col - ncolA);
               const bool m = a.alpha != 1.0;
               a.phi[e] = mix_phi<T>(v, a.gamma[e], m ? a.phi[e] : cz<C>(), (T)a.alpha, (T)(1.0 - a.alpha), m);
-              if constexpr (sizeof(T) == 4) {
-                const float f2 = (float)v.x * v.x + (float)v.y * v.y;
-                fx[(rb + rt * 32) / 64 % 2].x += f2 * xw;
-                fx[(rb + rt * 32) / 64 % 2].y += f2;
-              }
+              if constexpr (sizeof(T) == 4) fs[(rb + rt * 32) / 64 % 2] += (float)v.x * v.x + (float)v.y * v.y;
             }
           }
           if (tr) ts[c][r] = v;
@@ -875,10 +861,12 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb, int mix) {
         }
       }
       if constexpr (sizeof(T) == 4) {
-        if (mixes && a.pfx) {
-          // rows j0 + rb .. + RW: one or two 64-row blocks (j0 is a multiple of 128)
-          put_fx(a.pfx, n, blk, (j0 + rb) / 64, cs - ncolA / 32, fx[0]);
-          if (RW > 64) put_fx(a.pfx, n, blk, (j0 + rb) / 64 + 1, cs - ncolA / 32, fx[1]);
+        if (mixes && a.pcs) {
+          // rows j0 + rb .. + RW: one or two 64-row blocks (j0 is a multiple of 128);
+          // lane l holds column l % 32 of the strip
+          const int col = cs * 32 + lane % 32 - ncolA;
+          put_cs(a.pcs, n, blk, (j0 + rb) / 64, col, fs[0]);
+          if (RW > 64) put_cs(a.pcs, n, blk, (j0 + rb) / 64 + 1, col, fs[1]);
         }
       }
     }
@@ -1072,17 +1060,12 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
     C* P = a.phi + (size_t)blk * n * n;
     const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
     const bool mix = a.alpha != 1.0;
-    // complex64: |F_ij X_j|^2 of the finished rows, per 32-column tile of the
-    // wave's 64 x 64 tile (c0 - ncolA is a multiple of 64, i0 of 64)
-    float xw[USC];
-    float2 fx[USC];
+    // complex64: |F_ij|^2 of the finished rows summed per lane (each lane holds
+    // one column of each 32-column tile y of the wave's 64 x 64 tile; i0 is a
+    // multiple of 64)
+    float cs[USC];
 #pragma unroll
-    for (int y = 0; y < USC; ++y) {
-      fx[y] = make_float2(0.f, 0.f);
-      xw[y] = 0.f;
-      if constexpr (sizeof(T) == 4)
-        xw[y] = cok[y] ? abs2f(a.chi0[(size_t)blk * n + c0 + y * M::TN + M::b_col(lane) - ncolA]) : 0.f;
-    }
+    for (int y = 0; y < USC; ++y) cs[y] = 0.f;
     acc.store_c([&](int r, int c, C v) {
       const int i = i0 + r;
       const int y = c / M::TN;
@@ -1090,17 +1073,13 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
         st_c<CF::NT>(&cb[y][(size_t)i * n], v);
         const size_t e = (size_t)i * n + (c0 + c - ncolA);
         P[e] = mix_phi<T>(v, ld_c<true>(&G[e]), mix ? ld_c<true>(&P[e]) : cz<C>(), al, be, mix);
-        if constexpr (sizeof(T) == 4) {
-          const float f2 = (float)v.x * v.x + (float)v.y * v.y;
-          fx[y].x += f2 * xw[y];
-          fx[y].y += f2;
-        }
+        if constexpr (sizeof(T) == 4) cs[y] += (float)v.x * v.x + (float)v.y * v.y;
       }
     });
     if constexpr (sizeof(T) == 4) {
-      if (a.pfx) {
+      if (a.pcs) {
 #pragma unroll
-        for (int y = 0; y < USC; ++y) put_fx(a.pfx, n, blk, i0 / 64, (c0 - ncolA) / 32 + y, fx[y]);
+        for (int y = 0; y < USC; ++y) put_cs(a.pcs, n, blk, i0 / 64, c0 + y * M::TN + M::b_col(lane) - ncolA, cs[y]);
       }
     }
     return;
@@ -1139,7 +1118,7 @@ void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int ro
 // Phi <- alpha (F - Gamma) + (1 - alpha) Phi for every row, where the kernels
 // that finish the rows do not mix them (BF16x3 products). One wave per 64-row
 // x 32-column tile of F (lane l: column l % 32, rows l / 32 + 2 k), which also
-// sums |F_ij X_j|^2 over the tile for the error estimate.
+// sums |F_ij|^2 over the tile's columns for the error estimate.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a) {
   using C = typename cplx_of<T>::type;
@@ -1156,21 +1135,18 @@ __global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a) {
   C* P = a.phi + (size_t)blk * nn;
   const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
   const bool mix = a.alpha != 1.0;
-  const float xw = col < n ? abs2f(a.chi0[(size_t)blk * n + col]) : 0.f;
-  float2 fx = make_float2(0.f, 0.f);
+  float fs = 0.f;
   for (int k = 0; k < 32; ++k) {
     const int row = rowblk * 64 + (lane >> 5) + 2 * k;
     if (row < n && col < n) {
       const size_t idx = (size_t)row * n + col;
       const C f = F[idx];
       P[idx] = mix_phi<T>(f, G[idx], mix ? P[idx] : cz<C>(), al, be, mix);
-      const float f2 = (float)f.x * f.x + (float)f.y * f.y;
-      fx.x += f2 * xw;
-      fx.y += f2;
+      fs += (float)f.x * f.x + (float)f.y * f.y;
     }
   }
   if constexpr (sizeof(T) == 4) {
-    if (a.pfx) put_fx(a.pfx, n, blk, rowblk, colsub, fx);
+    if (a.pcs) put_cs(a.pcs, n, blk, rowblk, col, fs);
   }
 }
 
@@ -1219,7 +1195,7 @@ constexpr int panel_width() { return sizeof(T) == 4 ? 128 : 64; }
 // on a column sample S, from an integer hash of (column, probe); zero elsewhere):
 //   y = F^ v,   r = A y - Gamma v = y - s Gamma (X y) - Gamma v = R v,
 // evaluated in FP64 on the rows of the same sample, |R|_F^2 ~ (n/|S|)^2 |r_S|^2.
-// |F^ X|_F and |F^|_F come from the kernels that mixed the rows (tile sums),
+// |F^ X|_F and |F^|_F come from the kernels that mixed the rows (column sums),
 // tr(F^ X) from the diagonal: no full pass over F^ or Gamma.
 //   screen: est = (|A^-1|_F / n^1/2) (n / |S|) |r_S| / |F^|_F   (max over the probes)
 // Where the screen exceeds tol / 2, or |A^-1|_F / n^1/2 exceeds 2 (near the
@@ -1383,23 +1359,24 @@ __device__ inline double safe_ratio(double num2, double den2) {
 // Per block (one workgroup): the screen. Above tol / kScreen, or with |A^-1|_F
 // amplifying, with a finite value: refined estimate pending (pst[6] = 2);
 // non-finite: flagged (1).
-__global__ __launch_bounds__(kThreads) void probe_est_kernel(const double2* r, const float2* pfx, const float2* F,
+__global__ __launch_bounds__(kThreads) void probe_est_kernel(const double2* r, const float* pcs, const float2* F,
                                                             const double2* chi0, int n, double sign, double tol,
                                                             double* pst) {
   __shared__ double red[kThreads];
   const int blk = blockIdx.x;
   const int ns = probe_ns(n);
-  const int nt = ((n + 63) / 64) * ((n + 31) / 32);
+  const int nr = (n + 63) / 64;
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};    // |r_0|^2, |r_1|^2, |F X|^2, |F|^2, Re tr(F X)
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
     const int i = probe_at(n, q);
     s[0] += cabs2(r[((size_t)blk * kNpScreen + 0) * n + i]);
     s[1] += cabs2(r[((size_t)blk * kNpScreen + 1) * n + i]);
   }
-  for (int q = threadIdx.x; q < nt; q += blockDim.x) {
-    const float2 v = pfx[(size_t)blk * nt + q];
-    s[2] += (double)v.x;
-    s[3] += (double)v.y;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double c = 0.0;
+    for (int rb = 0; rb < nr; ++rb) c += (double)pcs[((size_t)blk * nr + rb) * n + j];
+    s[2] += c * cabs2(chi0[(size_t)blk * n + j]);
+    s[3] += c;
   }
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double2 f = to_d(F[(size_t)blk * n * n + (size_t)i * n + i]), x = chi0[(size_t)blk * n + i];
@@ -1585,7 +1562,7 @@ constexpr double kResolveBudget = 2.5 * 1024.0 * 1024.0 * 1024.0;
 struct BseLayout {
   size_t A, B, MT, PI, pst;
   // complex64 path only: error estimate and FP64 re-solve of flagged blocks
-  size_t py, pr, pfx, pcq;
+  size_t py, pr, pcs, pcq;
   size_t list, g64, x64, p64, phis, ws64;
   int slots;
   size_t total;
@@ -1623,7 +1600,7 @@ BseLayout bse_layout(const Dims& d, int slots_req) {
     L.slots = S;
     L.py = take(sizeof(double2) * kNpRefine * (size_t)d.n * d.Nq);
     L.pr = take(sizeof(double2) * kNpRefine * (size_t)d.n * d.Nq);
-    L.pfx = take(sizeof(float2) * (size_t)((d.n + 63) / 64) * ((d.n + 31) / 32) * d.Nq);
+    L.pcs = take(sizeof(float) * (size_t)((d.n + 63) / 64) * d.n * d.Nq);
     L.pcq = take(sizeof(double) * kNpRefine * (size_t)d.n * d.Nq);
     Dims r = d;
     r.Nq = S;
@@ -1672,8 +1649,8 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   a.pst = (double*)(w + L.pst);
   a.stats = stats;
   a.active = active;
-  a.pfx = nullptr;
-  if constexpr (sizeof(T) == 4) a.pfx = (float2*)(w + L.pfx);
+  a.pcs = nullptr;
+  if constexpr (sizeof(T) == 4) a.pcs = (float*)(w + L.pcs);
   const int n = d.n;
   // event timing around each launch (kind: 0 init, 1 pivot, 2 panel, 3 update,
   // 4 epilogue, 5 error estimate and FP64 re-solve)
@@ -1812,7 +1789,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     hipLaunchKernelGGL((probe_r_kernel<kNpScreen, 4, false>), dim3(rx_s, d.Nq), dim3(kThreads), 0, s, gm, chi0,
                        (const double2*)py, n, sg, cpst, pr);
     hipLaunchKernelGGL(probe_est_kernel, dim3(d.Nq), dim3(kThreads), 0, s, (const double2*)pr,
-                       (const float2*)a.pfx, fh, chi0, n, sg, err_tol, a.pst);
+                       (const float*)a.pcs, fh, chi0, n, sg, err_tol, a.pst);
     // refined estimate (the marked blocks only; the others exit at once)
     hipLaunchKernelGGL((probe_y_kernel<kNpRefine, 1, true>), dim3(rx_ref, d.Nq), dim3(kThreads), 0, s, fh, n, cpst,
                        py);

@@ -29,8 +29,9 @@ hipError_t launch_dyson(const pq_params& p, const Dims& d, const double2* sigma,
                         double* mu_out, hipStream_t s);
 hipError_t launch_bubbles(const pq_params& p, const Dims& d, const double2* g, double2* xph,
                           double2* xpp, hipStream_t s);
+// smax (nullable): max |sigma_io| after the mixing
 hipError_t launch_mix(const Dims& d, const double2* snew, double2* sio, double alpha,
-                      double* dnorm, hipStream_t s);
+                      double* dnorm, hipStream_t s, double* smax = nullptr);
 // dst[i] = src[i] between complex64 / complex128 storages (count complex elements)
 hipError_t launch_convert(const void* src, int src_storage, void* dst, int dst_storage, size_t count,
                           hipStream_t s);

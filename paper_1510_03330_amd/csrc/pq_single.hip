@@ -142,20 +142,26 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs a) {
 }
 
 __global__ __launch_bounds__(kThreads) void mix_kernel(int count, const double2* snew, double2* sio,
-                                                       double alpha, double* dnorm) {
+                                                       double alpha, double* dnorm, double* smax) {
   __shared__ double red[kThreads];
-  double mx = 0.0, bad = 0.0;
+  double mx = 0.0, bad = 0.0, sm = 0.0;
   for (int i = threadIdx.x; i < count; i += blockDim.x) {
     double2 a = snew[i], b = sio[i];
     double dr = a.x - b.x, di = a.y - b.y;
     double dd = hypot(dr, di);
     if (!isfinite(a.x) || !isfinite(a.y)) bad = 1.0;
     mx = fmax(mx, dd);
-    sio[i] = mk(alpha * a.x + (1.0 - alpha) * b.x, alpha * a.y + (1.0 - alpha) * b.y);
+    const double2 c = mk(alpha * a.x + (1.0 - alpha) * b.x, alpha * a.y + (1.0 - alpha) * b.y);
+    sio[i] = c;
+    sm = fmax(sm, hypot(c.x, c.y));
   }
   mx = block_max(mx, red);
   bad = block_max(bad, red);
-  if (threadIdx.x == 0) *dnorm = bad > 0.0 ? __builtin_nan("") : mx;
+  sm = block_max(sm, red);
+  if (threadIdx.x == 0) {
+    *dnorm = bad > 0.0 ? __builtin_nan("") : mx;
+    if (smax) *smax = sm;
+  }
 }
 
 // storage conversion of a vertex array (complex64 <-> complex128, or a copy)
@@ -234,8 +240,8 @@ hipError_t launch_bubbles(const pq_params& p, const Dims& d, const double2* g, d
 }
 
 hipError_t launch_mix(const Dims& d, const double2* snew, double2* sio, double alpha,
-                      double* dnorm, hipStream_t s) {
-  hipLaunchKernelGGL(mix_kernel, dim3(1), dim3(kThreads), 0, s, d.Nve * d.Nk, snew, sio, alpha, dnorm);
+                      double* dnorm, hipStream_t s, double* smax) {
+  hipLaunchKernelGGL(mix_kernel, dim3(1), dim3(kThreads), 0, s, d.Nve * d.Nk, snew, sio, alpha, dnorm, smax);
   return hipGetLastError();
 }
 

@@ -172,8 +172,10 @@ class Solver:
         return self.stage.d
 
     def iterate(self, n: int = 1, tol: float = 0.0):
-        """Up to n iterations, stopping once the change of Sigma is below tol
-        (tol <= 0: never). Returns (iterations done, converged, stats of the
+        """Up to n iterations, stopping on the convergence test of tol (tol > 0:
+        the change of Sigma below tol; tol < 0: the estimated distance to the
+        fixed point below |tol| max|Sigma|; tol = 0: never; see parquet_iterate).
+        Returns (iterations done, converged, stats of the
         last iteration); not reaching tol is no error (converged is False).
         Raises ParquetError for a non-finite self-energy or an unresolved BSE
         block (the iterations done are kept in the context)."""
@@ -373,14 +375,15 @@ class BatchRunner:
         return out, time.perf_counter() - t_all
 
 
-def converge_mixed(p, tol: float = 1e-6, switch_tol: float = 1e-5, max_iter: int = 200,
+def converge_mixed(p, tol: float = -1e-6, switch_tol: float = -2e-5, max_iter: int = 200,
                    device: str = "cuda:0", low: str = "fp32", solvers=None):
     """Iterate the complex64 path (precision ``low``: "fp32" or "bf16x3") from
-    the bare-vertex start until max|Sigma_new - Sigma| < switch_tol, then
-    continue on the complex128/FP64 path from that state until the change is
-    below tol. Returns the FP64 solver and a dict with the iteration counts of
-    both phases (the first under the key iterations_fp32). ``solvers``: an
-    already allocated (low, fp64) pair of the same box, re-initialised here
+    the bare-vertex start until the convergence test of switch_tol is met, then
+    continue on the complex128/FP64 path from that state until the test of tol
+    is met (tests as in parquet_iterate: negative values are relative distances
+    to the fixed point). Returns the FP64 solver and a dict with the iteration
+    counts of both phases (the first under the key iterations_fp32). ``solvers``:
+    an already allocated (low, fp64) pair of the same box, re-initialised here
     (the low one is closed at the switch)."""
     if low not in ("fp32", "bf16x3"):
         raise ValueError(f"low precision {low!r} must be fp32 or bf16x3")
@@ -402,4 +405,3 @@ def converge_mixed(p, tol: float = 1e-6, switch_tol: float = 1e-5, max_iter: int
     info = dict(iterations_fp32=done32, iterations_fp64=done64, converged=bool(conv64),
                 dsigma=st64.dsigma if done64 else st32.dsigma)
     return s64, info
-

@@ -165,7 +165,7 @@ def test_c1_mixed_precision_converges_to_fp64_solution(c1_oracle):
     from paper_1510_03330_amd.ops import converge_mixed
     print("CASE c1 mixed precision", flush=True)
     p, ref = c1_oracle
-    s, info = converge_mixed(p, tol=p.tol, switch_tol=1e-5, max_iter=200)
+    s, info = converge_mixed(p, tol=p.tol, switch_tol=1e-5, max_iter=200)     # absolute changes
     assert info["converged"] and info["iterations_fp32"] > 0 and info["iterations_fp64"] > 0
     assert relerr(H(s.get("sigma")), ref.sigma) < 1e-8
     assert relerr(H(s.get("phi")), ref.phi) < 1e-7
@@ -335,4 +335,28 @@ def test_c2_two_iterations_match_oracle(c2_two_iterations, prec, tol):
         print(f"   iteration {it}: sigma {es:.3g}, phi {ep:.3g}, flagged {stats.flagged_blocks}, "
               f"max estimate {stats.max_err_est:.3g}", flush=True)
         assert es < tol and ep < 10 * tol, (it, es, ep)
+    s.close()
+
+
+@pytest.mark.parametrize("rel", [1e-6, 1e-8])
+def test_relative_stopping_rule_reaches_the_fixed_point(rel):
+    """parquet_iterate with tol = -rel stops once alpha dsigma / (1 - rho) is
+    below rel max|Sigma| (rho the measured contraction): the result is within
+    rel of the fixed point (the oracle's solution of the local problem
+    converged to a change below 1e-13), and it stops earlier for the looser
+    target. The contraction estimate needs seven iterations of the same state,
+    so a call with n_iter = 6 cannot converge."""
+    print("CASE relative stop", rel, flush=True)
+    p = config("c1")
+    ref = P.solve(p, max_iter=300, tol=1e-13)
+    s = _solver(p, "fp64")
+    done, conv, _ = s.iterate(6, -1.0)
+    assert done == 6 and not conv
+    s.reinit()
+    done, conv, st = s.iterate(300, -rel)
+    assert conv, st.dsigma
+    err = relerr(H(s.get("sigma")), ref.sigma)
+    print(f"   {done} iterations, distance {err:.3g}", flush=True)
+    assert err < rel
+    assert err > 1e-3 * rel          # it stopped near the target, not far beyond
     s.close()
