@@ -39,20 +39,21 @@ def bse_flops_per_launch(d) -> float:
     return d.Nq * (32.0 / 3.0) * float(d.n) ** 3
 
 
-def measured_traffic():
+def measured_counters():
     """HBM bytes per launch of the BSE update kernel (FETCH_SIZE + WRITE_SIZE,
-    each scaled by what it reads for a plain device copy) from the committed
-    counter runs, or None when the kernel source has changed since."""
+    each scaled by what it reads for a plain device copy) and its matrix-core
+    utilisation (MfmaUtil) from the committed counter runs, or None when the
+    kernel source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "bse_traffic_8x8_nv16_c64.json")
     try:
         rec = json.load(open(path))
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     except (OSError, ValueError, KeyError):
-        return None
+        return None, None
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
-        return None
-    return rec["hbm_bytes_per_dispatch"]
+        return None, None
+    return rec["hbm_bytes_per_dispatch"], rec.get("mfma_util_pct")
 
 
 def run_gpu(p, precision, steps, warmup):
@@ -680,8 +681,12 @@ def main():
     achieved = upd_flops / (upd_ms * 1e-3) / 1e12
     bse_channel_ms = sum(r32["bse_ms"]) / len(r32["bse_ms"]) / 4.0
     bse_alg = bse_flops_per_launch(d) / (bse_channel_ms * 1e-3) / 1e12
+    traffic, mfma_util = measured_counters()
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(),
+            "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": traffic,
+            "achieved_counts": "algorithmic-equivalent: 8 flops per complex multiply-add; the kernel forms each "
+                               "product from three real matrix products (6 flops)",
+            "mfma_util": (round(mfma_util / 100.0, 4) if mfma_util is not None else None),
             "kernel": "bse_update_kernel<float,128> (one launch = one rank-128 update of %d blocks, n=%d: "
                       "the rows below a panel in the forward sweep or the rows above it in the back "
                       "substitution)" % (d.Nq, d.n),
