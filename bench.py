@@ -236,11 +236,13 @@ def kernel_study(max_iter: int = 600, tol: float = 1e-8, chunk: int = 10):
     paper's convergence claims for its local validation problem: the
     momentum-independent model (Nk = 1, fixed semicircle bath of half-bandwidth
     D = 2, half filling, beta = 2), complex128 path, bare-vertex start, linear
-    mixing alpha. For kernel level 0 (truncation), 1 (K1) and 2 (K1 + K2) and
-    regulation box f_ext = 1 (the box itself) or 2: whether the iteration
-    reaches max|dSigma| < tol, or after how many iterations it diverges
-    (max|dSigma| > 1e2 or non-finite), for U = 2 .. 4; and the box convergence
-    of Sigma(i nu_0) in Nv at U = 2."""
+    mixing alpha. For kernel level 0 (truncation), 1 (K1) and 2 (K1 + K2),
+    regulation box f_ext = 1 (the box itself) or 2, and without the regulation
+    (the plain box sum of Eq. PA_Sigma): whether the iteration reaches
+    max|dSigma| < tol, or after how many iterations it diverges (max|dSigma| >
+    1e2 or non-finite), for U = 2 .. 4; the box convergence of Sigma(i nu_0) in
+    Nv at U = 2; and the self-energy tail nu Im Sigma against -U^2/4 at the
+    local problem's U = 1, beta = 5."""
     import math as _m
     from paper_1510_03330_amd.native import ParquetError
     from paper_1510_03330_amd.ops import Solver
@@ -277,16 +279,42 @@ def kernel_study(max_iter: int = 600, tol: float = 1e-8, chunk: int = 10):
 
     out = {"study": "kernel level / regulation box / U range, local model with a semicircle bath (D=2), "
                     "beta=2, half filling, complex128",
-           "max_iter": max_iter, "tol": tol, "u_range": [], "box_convergence": []}
-    for alpha in (0.3, 0.1):
-        for level, f_ext in ((0, 2), (1, 2), (2, 2), (2, 1)):
-            for U in (2.0, 2.5, 3.0, 3.5, 4.0):
-                print(f"[study] alpha {alpha} level {level} f_ext {f_ext} U {U}", file=sys.stderr, flush=True)
-                out["u_range"].append(solve(alpha=alpha, kernel_level=level, f_ext=f_ext, U=U, Nv=32))
+           "max_iter": max_iter, "tol": tol, "u_range": [], "box_convergence": [], "tail": []}
+    # the self-energy tail: nu Im Sigma(i nu) -> -U^2 n_s (1 - n_s) = -U^2 / 4 at half filling, at the
+    # local problem's parameters (U = 1, beta = 5, Nv = 32), for every kernel level with and without
+    # the regulation (regulated: Sigma on the extended box f = 2; plain: the box only)
+    tail_base = config("c1").replace(tol=1e-10)
     for level in (0, 1, 2):
+        for reg, f_ext in ((1, 2), (0, 1)):
+            print(f"[study] tail level {level} regulation {reg}", file=sys.stderr, flush=True)
+            p = tail_base.replace(kernel_level=level, regulation=reg, f_ext=f_ext)
+            s = Solver(p, "fp64", device="cuda:0")
+            done, conv, st = s.iterate(400, p.tol)
+            sig = s.get("sigma").cpu().numpy()[:, 0]
+            s.close()
+            ne = sig.shape[0]
+            nus = [(2 * (i - ne // 2) + 1) * _m.pi / p.beta for i in range(ne)]
+            c_exact = -p.U ** 2 / 4.0
+            box_edge = ne // 2 + p.Nv // 2 - 1               # the last box frequency
+            rec = {"kernel_level": level, "regulation": reg, "f_ext": f_ext, "converged": bool(conv),
+                   "iterations": done, "exact": c_exact,
+                   "nu_im_sigma": {round(nus[i], 3): round(float(nus[i] * sig[i].imag), 5)
+                                   for i in range(ne // 2, ne) if (i - ne // 2) % 4 == 3 or i == ne - 1},
+                   "box_edge_rel_error": round(float(nus[box_edge] * sig[box_edge].imag / c_exact - 1.0), 5),
+                   "last_rel_error": round(float(nus[-1] * sig[-1].imag / c_exact - 1.0), 5)}
+            out["tail"].append(rec)
+    for alpha in (0.3, 0.1):
+        for level, f_ext, reg in ((0, 2, 1), (1, 2, 1), (2, 2, 1), (2, 1, 1), (2, 1, 0), (0, 1, 0)):
+            for U in (2.0, 2.5, 3.0, 3.5, 4.0):
+                print(f"[study] alpha {alpha} level {level} f_ext {f_ext} regulation {reg} U {U}", file=sys.stderr,
+                      flush=True)
+                out["u_range"].append(solve(alpha=alpha, kernel_level=level, f_ext=f_ext, regulation=reg, U=U,
+                                            Nv=32))
+    for level, f_ext, reg in ((0, 2, 1), (1, 2, 1), (2, 2, 1), (2, 1, 0)):
         for Nv in (8, 16, 24, 32, 48, 64):
-            print(f"[study] box level {level} Nv {Nv}", file=sys.stderr, flush=True)
-            out["box_convergence"].append(solve(alpha=0.3, kernel_level=level, f_ext=2, U=2.0, Nv=Nv))
+            print(f"[study] box level {level} regulation {reg} Nv {Nv}", file=sys.stderr, flush=True)
+            out["box_convergence"].append(solve(alpha=0.3, kernel_level=level, f_ext=f_ext, regulation=reg,
+                                                U=2.0, Nv=Nv))
     return out
 
 

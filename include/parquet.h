@@ -100,6 +100,13 @@ typedef struct {
                               per channel are re-solved in FP64 (0: as many
                               as a re-solve budget of 2.5 GiB holds, at
                               least 8, at most Nq)                           */
+  int32_t regulation;      /* 1: the Schwinger-Dyson equation with the high-
+                              frequency regulation (Sigma~_1 + Sigma~_2 + the
+                              box part of F - F~); 0: Eq. PA_Sigma plainly
+                              summed over the box with the full F, Sigma on
+                              the box only (requires f_ext = 1; the ablation
+                              the regulation is measured against)           */
+  int32_t reserved;        /* 0                                              */
   double U, beta, t, tp;   /* interaction, inverse temperature, hoppings     */
   double filling;          /* total density n for mu_mode = 1                */
   double D;                /* semicircle half-bandwidth (local mode)         */
@@ -181,7 +188,11 @@ pq_status sigma_sde_workspace(const pq_params* p, size_t* bytes);
  * (U, -U, 2U, 0) is part of F - F~ and adds to Sigma_box (F~ keeps the
  * parquet-approximation values); g: [NG][Nk]; mu: device double from
  * dyson_update; sigma_out: [Nve][Nk] c128. ws: device workspace of
- * sigma_sde_workspace bytes. */
+ * sigma_sde_workspace bytes.
+ * With params.regulation = 0 (f_ext = 1): Eq. PA_Sigma summed plainly over
+ * the box with the full F, computed as the same pieces on the box with
+ * Sigma~_1 replaced by the second-order diagram truncated to the box
+ * (the plain box sum of F splits exactly that way). */
 pq_status sigma_sde(const pq_params* p, const void* phi, const void* k1,
                     const void* k2, const void* lambda_box, const void* g, const void* mu,
                     void* sigma_out, void* ws, size_t ws_bytes, pq_stream stream);
@@ -344,7 +355,8 @@ typedef struct {
 pq_status parquet_query_workspace(const pq_params* p, size_t* bytes);
 
 /* Bind a context to caller workspace and stream, and set the bare-vertex start:
- * Phi_r = 0, Sigma_0 = Sigma~_1[G_0] (second-order diagram of the Sigma = 0 G). */
+ * Phi_r = 0, Sigma_0 = Sigma~_1[G_0] (second-order diagram of the Sigma = 0 G;
+ * without the regulation its box truncation). */
 pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream stream,
                        pq_ctx** out);
 

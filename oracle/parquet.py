@@ -692,8 +692,65 @@ def sigma_box(p, grid: Grid, G, F, K1, K2, k_list=None):
     return out if k_list is not None else out.reshape(grid.Nv, grid.Nk)
 
 
+def second_order_box(p, grid: Grid, G):
+    """The second-order diagram with both internal sums truncated to the box,
+    -(U^2 T^2 / 2N^2) sum_{k' in box, q in box} [G(k+q)G(k'+q)G(k') + G(q-k')G(q-k)G(k')]
+    (Eq. PA_Sigma at F = Lambda = (U, -U, 2U, 0) without regulation), for k in
+    the box, [Nv][Nk]."""
+    T = 1.0 / p.beta
+    N = grid.Nk
+    n2, K2m, m, Q = _box_pairs(grid)
+    out = np.empty((grid.Nv, grid.Nk), dtype=np.complex128)
+    for i, n in enumerate(grid.fbox()):
+        for K in range(grid.Nk):
+            wph, wpp = _sde_weights(grid, G, n, K, n2, K2m, m, Q)
+            out[i, K] = -p.U**2 * T**2 / (2 * N**2) * np.sum(wph + wpp)
+    return out
+
+
+def sigma_plain(p, grid: Grid, G, F):
+    """Eq. PA_Sigma evaluated plainly on the box, without the high-frequency
+    regulation (the ablation the regulation subsection argues against):
+    -(U T^2 / 4N^2) sum_{k', q in box} [G(k+q)G(k'+q)G(k') (F_d - F_m)
+                                       + G(q-k')G(q-k)G(k') (F_s + F_t)]
+    for k in the box, with the full vertex F = Gamma + Phi of the box. Nothing is
+    known of Sigma outside the box, so the regulation box must be the box
+    itself (f = 1). Returns [Nv][Nk]."""
+    assert grid.f == 1, "without regulation Sigma lives on the box (f_ext = 1)"
+    T = 1.0 / p.beta
+    N = grid.Nk
+    out = np.empty((grid.Nv, grid.Nk), dtype=np.complex128)
+    for i, n in enumerate(grid.fbox()):
+        for K in range(grid.Nk):
+            ki = grid.kidx(n, K)
+            acc = 0.0
+            for qi in range(grid.Nq):
+                jm, Qm = divmod(qi, grid.Nk)
+                m = jm - (grid.Nv // 2 - 1)
+                for kpi in range(grid.n):
+                    i2, K2m = divmod(kpi, grid.Nk)
+                    n2 = i2 - grid.Nv // 2
+                    g_kq = G[grid.gidx(n + m), grid.kadd(K, Qm)]
+                    g_kpq = G[grid.gidx(n2 + m), grid.kadd(K2m, Qm)]
+                    g_kp = G[grid.gidx(n2), K2m]
+                    g_qmkp = G[grid.gidx(m - n2 - 1), grid.ksub(Qm, K2m)]
+                    g_qmk = G[grid.gidx(m - n - 1), grid.ksub(Qm, K)]
+                    fdm = F[CH_D][qi, ki, kpi] - F[CH_M][qi, ki, kpi]
+                    fst = F[CH_S][qi, ki, kpi] + F[CH_T][qi, ki, kpi]
+                    acc += g_kq * g_kpq * g_kp * fdm + g_qmkp * g_qmk * g_kp * fst
+            out[i, K] = -p.U * T**2 / (4 * N**2) * acc
+    return out
+
+
+def regulation_of(p) -> int:
+    return int(getattr(p, "regulation", 1))
+
+
 def sigma_sde(p, grid: Grid, G, F, K1, K2, mu: float = 0.0):
-    """Sigma_new(k) = Sigma~_1 + Sigma~_2 + [k in box] Sigma_box on the extended box."""
+    """Sigma_new(k) = Sigma~_1 + Sigma~_2 + [k in box] Sigma_box on the extended
+    box (high-frequency regulation); without regulation the plain box sum."""
+    if regulation_of(p) == 0:
+        return sigma_plain(p, grid, G, F)
     s = sigma_tilde1(p, grid, G, mu) + sigma_tilde2(p, grid, G, K1, K2)
     lo = grid.eidx(-grid.Nv // 2)
     s[lo:lo + grid.Nv] += sigma_box(p, grid, G, F, K1, K2)
@@ -714,12 +771,13 @@ class State:
 
 def init_state(p, grid: Optional[Grid] = None) -> State:
     """Bare-vertex start: Phi_r = 0 and Sigma_0 = Sigma~_1[G_0] (reading), where
-    G_0 is the Dyson G with Sigma = 0 (mu~ from the filling)."""
+    G_0 is the Dyson G with Sigma = 0 (mu~ from the filling); without the
+    regulation the box-truncated second-order diagram of G_0."""
     grid = grid or Grid(p.Lx, p.Ly, p.Nv, p.f_ext)
     zero = np.zeros((grid.Nve, grid.Nk), dtype=np.complex128)
     mu0 = find_mu(p, grid, zero)
     G0 = dyson(p, grid, zero, mu0)
-    sigma0 = sigma_tilde1(p, grid, G0, mu0)
+    sigma0 = second_order_box(p, grid, G0) if regulation_of(p) == 0 else sigma_tilde1(p, grid, G0, mu0)
     phi = np.zeros((4, grid.Nq, grid.n, grid.n), dtype=np.complex128)
     return State(sigma=sigma0, phi=phi, mu=mu0)
 

@@ -60,6 +60,11 @@ bool make_dims(const pq_params* p, Dims* d) {
   if (!(p->alpha > 0.0 && p->alpha <= 1.0)) { set_error("alpha must be in (0, 1]"); return false; }
   if (p->Lx * p->Ly == 1 && !(p->D > 0.0)) { set_error("local mode needs D > 0"); return false; }
   if (p->resolve_slots < 0) { set_error("resolve_slots must be >= 0"); return false; }
+  if (p->regulation != 0 && p->regulation != 1) { set_error("regulation must be 0 or 1"); return false; }
+  if (p->regulation == 0 && p->f_ext != 1) {
+    set_error("without the regulation Sigma lives on the box: f_ext must be 1");
+    return false;
+  }
   if (!(p->bse_tol >= 0.0 && p->bse_tol <= 1.0)) { set_error("bse_tol must be in [0, 1]"); return false; }
   Dims x;
   x.Lx = p->Lx; x.Ly = p->Ly; x.Nk = p->Lx * p->Ly; x.Nv = p->Nv; x.NW = p->Nv - 1;

@@ -504,8 +504,62 @@ __global__ void combine_kernel(CombineArgs a) {
   a.out[idx] = v;
 }
 
+// ------------------------------------ second order without the regulation
+// Eq. PA_Sigma at F = Lambda with both sums truncated to the box (the Sigma~_1
+// term of the plain, unregulated equation):
+//   -(U^2 T^2 / 2N^2) sum_{q in box} [G(k+q) S_ph(q) + G(q-k) S_pp(q)],
+//   S_ph(q) = sum_{k' in box} G(k'+q) G(k'),  S_pp(q) = sum_{k' in box} G(q-k') G(k').
+struct S2BoxArgs {
+  Dims d;
+  double cfac;             // -U^2 T^2 / (2 N^2)
+  const double2* g;
+  double2* sq;             // [Nq][2]  S_ph, S_pp
+  double2* out;            // [Nve][Nk]
+};
+
+// one wave per transfer q, lanes over k'
+__global__ __launch_bounds__(kThreads) void s2box_tables_kernel(S2BoxArgs a) {
+  const Dims& d = a.d;
+  const int qi = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (qi >= d.Nq) return;
+  const int jm = qi / d.Nk, Q = qi - jm * d.Nk, m = jm - (d.Nv / 2 - 1), hG = d.NG / 2;
+  double v[4] = {0, 0, 0, 0};
+  for (int kp = lane; kp < d.n; kp += 64) {
+    const int n2 = kp / d.Nk - d.Nv / 2, K2 = kp - (kp / d.Nk) * d.Nk;
+    const double2 gk = a.g[(size_t)(n2 + hG) * d.Nk + K2];
+    const double2 ph = cmul(a.g[(size_t)(n2 + m + hG) * d.Nk + kadd(K2, Q, d.Lx, d.Ly)], gk);
+    const double2 pp = cmul(a.g[(size_t)(m - n2 - 1 + hG) * d.Nk + ksub(Q, K2, d.Lx, d.Ly)], gk);
+    v[0] += ph.x; v[1] += ph.y; v[2] += pp.x; v[3] += pp.y;
+  }
+  for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+    a.sq[(size_t)qi * 2] = mk(v[0], v[1]);
+    a.sq[(size_t)qi * 2 + 1] = mk(v[2], v[3]);
+  }
+}
+
+// one workgroup per k (f = 1: the extended box is the box), threads over q
+__global__ __launch_bounds__(kThreads) void s2box_kernel(S2BoxArgs a) {
+  __shared__ double red[kThreads];
+  const Dims& d = a.d;
+  const int kid = blockIdx.x, e = kid / d.Nk, K = kid - e * d.Nk;
+  const int nk = e - d.Nve / 2, hG = d.NG / 2;
+  double tr = 0.0, ti = 0.0;
+  for (int qi = threadIdx.x; qi < d.Nq; qi += blockDim.x) {
+    const int jm = qi / d.Nk, Q = qi - jm * d.Nk, m = jm - (d.Nv / 2 - 1);
+    const double2 gkq = a.g[(size_t)(nk + m + hG) * d.Nk + kadd(K, Q, d.Lx, d.Ly)];
+    const double2 gqk = a.g[(size_t)(m - nk - 1 + hG) * d.Nk + ksub(Q, K, d.Lx, d.Ly)];
+    const double2 v = cadd(cmul(gkq, a.sq[(size_t)qi * 2]), cmul(gqk, a.sq[(size_t)qi * 2 + 1]));
+    tr += v.x;
+    ti += v.y;
+  }
+  tr = block_sum(tr, red);
+  ti = block_sum(ti, red);
+  if (threadIdx.x == 0) a.out[kid] = mk(a.cfac * tr, a.cfac * ti);
+}
+
 struct WsLayout {
-  size_t tau, wt, dg, gkt, grt, trn, s1, s2, tab, part, lb1, lb2, lpart, total;
+  size_t tau, wt, dg, gkt, grt, trn, s1, s2, tab, part, lb1, lb2, lpart, sq, total;
 };
 
 WsLayout ws_layout(const Dims& d) {
@@ -525,6 +579,7 @@ WsLayout ws_layout(const Dims& d) {
   L.lb1 = take(sizeof(double2) * (size_t)d.Nv * d.NW * d.Nk);
   L.lb2 = take(sizeof(double2) * (size_t)d.Nv * d.NW * d.Nk);
   L.lpart = take(sizeof(double2) * (size_t)d.n);
+  L.sq = take(sizeof(double2) * 2 * (size_t)d.Nq);
   L.total = off;
   return L;
 }
@@ -580,9 +635,23 @@ hipError_t static_scratch(void** out) {
   return hipSuccess;
 }
 
+// The second-order term: over all frequencies (Sigma~_1 of the regulation) or,
+// without the regulation, truncated to the box.
+static hipError_t run_second_order(const pq_params& p, const Dims& d, const double2* g, const double* mu,
+                                   double2* out, char* ws, hipStream_t s) {
+  if (p.regulation != 0) return run_sigma1(p, d, g, mu, out, ws, s);
+  const WsLayout L = ws_layout(d);
+  const double T = 1.0 / p.beta;
+  S2BoxArgs a{d, -p.U * p.U * T * T / (2.0 * d.Nk * (double)d.Nk), g, (double2*)(ws + L.sq), out};
+  const unsigned wpb = kThreads / 64;
+  hipLaunchKernelGGL(s2box_tables_kernel, dim3((d.Nq + wpb - 1) / wpb), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(s2box_kernel, dim3(d.Nve * d.Nk), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_sigma1(const pq_params& p, const Dims& d, const double2* g, const double* mu,
                          double2* sigma_out, void* ws, hipStream_t s) {
-  return run_sigma1(p, d, g, mu, sigma_out, (char*)ws, s);
+  return run_second_order(p, d, g, mu, sigma_out, (char*)ws, s);
 }
 
 hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, const double2* k1,
@@ -593,7 +662,7 @@ hipError_t launch_sigma(const pq_params& p, const Dims& d, const void* phi, cons
   double2* s1 = (double2*)(ws + L.s1);
   double2* s2 = (double2*)(ws + L.s2);
   double2* part = (double2*)(ws + L.part);
-  hipError_t e = run_sigma1(p, d, g, mu, s1, ws, s);
+  hipError_t e = run_second_order(p, d, g, mu, s1, ws, s);
   if (e != hipSuccess) return e;
   const int has_s2 = p.kernel_level > 0 ? 1 : 0;
   if (has_s2) {

@@ -43,7 +43,7 @@ class PqParams(ctypes.Structure):
         ("Lx", c_int32), ("Ly", c_int32), ("Nv", c_int32), ("f_ext", c_int32),
         ("kernel_level", c_int32), ("edge_rule", c_int32), ("mu_mode", c_int32),
         ("storage", c_int32), ("precision", c_int32), ("resolve_slots", c_int32),
-        ("U", c_double), ("beta", c_double), ("t", c_double), ("tp", c_double),
+        ("regulation", c_int32), ("reserved", c_int32), ("U", c_double), ("beta", c_double), ("t", c_double), ("tp", c_double),
         ("filling", c_double), ("D", c_double), ("mu_fixed", c_double), ("alpha", c_double),
         ("bse_tol", c_double),
     ]
@@ -161,6 +161,7 @@ def make_params(p, precision: str = "fp64", resolve_slots: int = 0, bse_tol: flo
     out.U, out.beta, out.t, out.tp = float(p.U), float(p.beta), float(p.t), float(p.tp)
     out.filling, out.D, out.mu_fixed, out.alpha = float(p.filling), float(p.D), float(p.mu_fixed), float(p.alpha)
     out.resolve_slots = int(resolve_slots)
+    out.regulation = int(getattr(p, "regulation", 1))
     out.bse_tol = float(bse_tol)
     return out
 

@@ -70,7 +70,8 @@ def test_dims_from_params(name):
 
 @pytest.mark.parametrize("bad", [dict(Nv=7), dict(Nv=0), dict(f_ext=0), dict(kernel_level=3),
                                  dict(alpha=0.0), dict(alpha=1.5), dict(beta=-1.0), dict(Lx=9, Ly=9),
-                                 dict(edge_rule=2), dict(mu_mode=4)])
+                                 dict(edge_rule=2), dict(mu_mode=4), dict(regulation=0), dict(regulation=2),
+                                 dict(regulation=0, f_ext=2)])
 def test_invalid_params_are_rejected_on_the_host(bad):
     p = config("tiny_2x2", **bad)
     pp = N.make_params(p, "fp64")

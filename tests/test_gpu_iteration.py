@@ -31,11 +31,15 @@ def relerr(a, b):
                                        ("tiny_2x2", dict(kernel_level=0, f_ext=1)),
                                        ("tiny_2x2", dict(kernel_level=1, f_ext=3)),
                                        ("tiny_local", dict(kernel_level=0, f_ext=1)),
-                                       ("tiny_local", dict(kernel_level=1, f_ext=2, U=3.0, beta=2.0))])
+                                       ("tiny_local", dict(kernel_level=1, f_ext=2, U=3.0, beta=2.0)),
+                                       ("tiny_2x2", dict(regulation=0, f_ext=1, kernel_level=0)),
+                                       ("tiny_2x2", dict(regulation=0, f_ext=1)),
+                                       ("small_2x4", dict(regulation=0, f_ext=1, kernel_level=1)),
+                                       ("tiny_local", dict(regulation=0, f_ext=1, kernel_level=2))])
 def test_first_iterations_match_oracle(name, over):
-    """Three whole iterations against the oracle, also at the kernel levels and
-    regulation boxes the ablation study runs (level 0 truncation, level 1,
-    f_ext 1..3)."""
+    """Three whole iterations against the oracle, also at the kernel levels,
+    regulation boxes and regulation settings the ablation study runs (level 0
+    truncation, level 1, f_ext 1..3, the plain unregulated box sum)."""
     print("CASE iterations", name, over, flush=True)
     p = config(name, **over)
     g = P.Grid(p.Lx, p.Ly, p.Nv, p.f_ext)

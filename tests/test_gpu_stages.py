@@ -214,6 +214,29 @@ def test_sigma_sde_box_lambda(prec, name, level):
     assert relerr(H(out0), ref) > 1e-6
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,level", [("tiny_2x2", 0), ("tiny_2x2", 2), ("small_2x4", 1), ("tiny_local", 2)])
+def test_sigma_sde_without_regulation(prec, name, level):
+    """regulation = 0: the plain box sum of F (Eq. PA_Sigma on the box) for a
+    random reducible vertex, against the oracle's direct loops."""
+    _print_case("sigma plain", prec, name, level)
+    p = config(name, f_ext=1, kernel_level=level, regulation=0)
+    g = _grid(p)
+    phi = random_phi(g.Nq, g.n, seed=61, scale=0.2)
+    if prec != "fp64":
+        phi = phi.astype(np.complex64).astype(np.complex128)
+    sig = random_sigma(g.Nve, g.Nk, seed=62, scale=0.1)
+    mu = P.find_mu(p, g, sig)
+    G = P.dyson(p, g, sig, mu)
+    K1, K2 = P.kernel_functions(g, phi, level)
+    F = P.remap(g, phi, K1, K2, P.pa_lambda(p.U)) + phi
+    ref = P.sigma_plain(p, g, G, F)
+    st = _ops().Stage(p, prec)
+    out = torch.empty(st.sigma_shape, dtype=torch.complex128, device=DEV)
+    st.sigma_sde(T(phi, st.vdtype), T(K1), T(K2), T(G), torch.tensor([mu], dtype=torch.float64, device=DEV), out)
+    assert relerr(H(out), ref) < (1e-12 if prec == "fp64" else 1e-6)
+
+
 def test_sigma_tilde1_alone_matches_oracle_lattice_and_local():
     # zero vertex: Sigma = Sigma~_1 exactly (the imaginary-time route)
     for name in ("tiny_2x2", "tiny_local", "c2"):

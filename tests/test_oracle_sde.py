@@ -278,3 +278,70 @@ def test_semicircle_pole_sum_is_converged():
     finally:
         P.semicircle_poles = orig
     assert np.max(np.abs(a - b)) < 1e-14 * np.max(np.abs(a))
+
+
+# ------------------------------------------------- without the regulation
+def test_plain_sde_of_the_bare_vertex_is_the_box_truncated_second_order():
+    """Without the regulation, F = Lambda (Phi = 0) gives the second-order
+    diagram with both sums truncated to the box; the explicit odd/even
+    Matsubara loops of _direct_second_order on the f = 1 grid (the box) are the
+    independent route. second_order_box (the bare-vertex start) is the same sum."""
+    for name in ("tiny_2x2", "tiny_local"):
+        p = config(name, f_ext=1, regulation=0)
+        g = P.Grid(p.Lx, p.Ly, p.Nv, 1)
+        G = P.dyson(p, g, rand_complex((g.Nve, g.Nk), 5, 0.1), 0.07)
+        phi = np.zeros((4, g.Nq, g.n, g.n), complex)
+        K1, K2 = P.kernel_functions(g, phi)
+        F = P.remap(g, phi, K1, K2, P.pa_lambda(p.U)) + phi
+        pts = [(int(n), K) for n in g.fbox() for K in range(g.Nk)]
+        direct = _direct_second_order(p, g, G, pts).reshape(g.Nv, g.Nk)
+        assert np.max(np.abs(P.sigma_plain(p, g, G, F) - direct)) < 1e-14 * np.max(np.abs(direct))
+        assert np.max(np.abs(P.second_order_box(p, g, G) - direct)) < 1e-14 * np.max(np.abs(direct))
+
+
+def test_plain_sde_third_order_is_the_box_ladder():
+    """Through the BSE -> remap -> SDE chain at kernel level 0, the plain box sum
+    minus its second-order part is the third-order ladder closed form on the box
+    domain (Richardson in U removes O(U^4))."""
+    base = config("tiny_2x2", Nv=4, f_ext=1, kernel_level=0, regulation=0)
+    g = P.Grid(base.Lx, base.Ly, base.Nv, 1)
+    G = P.dyson(base, g, rand_complex((g.Nve, g.Nk), 4, 0.1), 0.05)
+    pts = [(0, 0), (-1, 2), (1, 3), (-2, 1)]
+    idx = [(n + g.Nv // 2, K) for (n, K) in pts]
+
+    def delta(u):
+        p = base.replace(U=u)
+        xph, xpp = P.bubbles(p, g, G)
+        lam = P.pa_lambda(u)
+        gam0 = np.empty((4, g.Nq, g.n, g.n), complex)
+        for r in range(4):
+            gam0[r] = lam[r]
+        phi1 = P.bse(g, gam0, xph, xpp)
+        K1, K2 = P.kernel_functions(g, phi1, 0)
+        F = P.remap(g, phi1, K1, K2, lam) + phi1
+        d = P.sigma_plain(p, g, G, F) - P.second_order_box(p, g, G)
+        return np.array([d[i] for i in idx])
+
+    u = 1e-3
+    c3 = 2 * delta(u) / u**3 - delta(2 * u) / (8 * u**3)
+    closed = _third_order_closed_form(base.replace(U=1.0), g, G, pts, 0)
+    assert np.max(np.abs(c3 - closed)) < 1e-5 * np.max(np.abs(closed))
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_plain_sde_splits_into_the_regulated_pieces_on_the_box(level):
+    """With the regulation box equal to the box (f = 1), the plain box sum of F
+    splits exactly into the pieces of the regulated equation, the all-frequency
+    second order replaced by its box truncation:
+    sigma_plain = second_order_box + Sigma~_2 + Sigma_box(F - F~), for a random
+    reducible vertex at kernel levels 1 and 2 (out-of-box arguments read the
+    kernels)."""
+    p = config("tiny_2x2", f_ext=1, kernel_level=level)
+    g = P.Grid(p.Lx, p.Ly, p.Nv, 1)
+    G = P.dyson(p, g, rand_complex((g.Nve, g.Nk), 6, 0.1), 0.1)
+    phi = rand_complex((4, g.Nq, g.n, g.n), 13, 0.2)
+    K1, K2 = P.kernel_functions(g, phi, level)
+    F = P.remap(g, phi, K1, K2, P.pa_lambda(p.U)) + phi
+    plain = P.sigma_plain(p.replace(regulation=0), g, G, F)
+    parts = P.second_order_box(p, g, G) + P.sigma_tilde2(p, g, G, K1, K2) + P.sigma_box(p, g, G, F, K1, K2)
+    assert np.max(np.abs(plain - parts)) < 1e-13 * np.max(np.abs(plain))

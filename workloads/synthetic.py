@@ -37,6 +37,7 @@ class ModelParams:
     D: float = 2.0          # semicircle half-bandwidth (local mode, Nk = 1)
     f_ext: int = 2          # extension factor of the regulation box
     kernel_level: int = 2   # 0: truncation, 1: K1 only, 2: K1 + K2
+    regulation: int = 1     # 1: high-frequency regulation of the SDE; 0: plain box sum (needs f_ext = 1)
     edge_rule: int = 0      # 0: far edge per channel and sign of m; 1: lowest edge always
     mu_mode: int = 0        # 0: mu_tilde fixed to mu_fixed; 1: bisection on the filling
     mu_fixed: float = 0.0
