@@ -371,107 +371,154 @@ def batch_study(tol: float = 1e-6, max_iter: int = 150):
             "converged": sum(int(r["converged"]) for r in recs), "by_nv": by_nv}
 
 
-def warmstart_study(tol: float = 1e-6, max_iter: int = 400, lattice: bool = False):
-    """Learned warm start. Local problem (default): semicircle bath, D = 2, half
-    filling, Nv = 16, alpha = 0.5, a 12 x 12 training grid U in [0.5, 1.5] x
-    beta in [2, 5]. Lattice: the 4x4 lattice, t = 1, t' = 0, half filling,
-    Nv = 16 (BSE dimension 256, 240 transfers), a 12 x 12 grid U in [1, 2] x
-    beta in [2, 3.5] (the region where the bare-vertex start converges; at
-    U = 2, beta = 4 it diverges). Converged kernel functions and self-energy
-    (complex128, to 1e-8) train a 2 -> 3 x 512 -> (K1, K2, Sigma) perceptron on
-    the GPU; 24 seeded held-out (U, beta) are then solved to tol from the bare
-    vertex and from the vertex rebuilt from the predicted kernels with the
-    predicted self-energy (and, for comparison, with the bare self-energy), in
-    complex128."""
+WARMSTART_KINDS = {
+    # kind: (base config and overrides, sampling box, training seeds, held-out seeds, solver precision and
+    #        tolerance of the training solves, description)
+    "local": ("c1", dict(Nv=16, beta=2.0, D=2.0, alpha=0.5), {"U": (0.5, 1.5), "beta": (2.0, 5.0)},
+              range(0, 144), range(10000, 10024), ("fp64", 1e-8),
+              "local model, semicircle bath D=2, half filling, Nv=16, alpha=0.5"),
+    "4x4": ("c2", dict(U=1.5, beta=3.0), {"U": (1.0, 2.0), "beta": (2.0, 3.5), "filling": (0.85, 1.0),
+                                          "tp": (-0.2, 0.0)},
+            range(0, 144), range(10000, 10024), ("fp64", 1e-8),
+            "4x4 lattice, t=1, Nv=16 (BSE dimension 256), alpha=0.5"),
+    "8x8": ("c3", dict(), {"U": (1.6, 2.2), "beta": (4.0, 6.0), "filling": (0.85, 0.95), "tp": (-0.25, -0.15)},
+            range(0, 32), range(10000, 10004), ("fp32", -2e-5),
+            "8x8 lattice, t=1, Nv=16 (BSE dimension 1024, 960 transfers), kernel level 2, alpha=0.5"),
+}
+
+
+def warmstart_study(kind: str = "local", tol: float = -1e-6, max_iter: int = 400, n_train=None, n_held=None):
+    """Learned warm start. Seeded draws (PCG64(seed), seeds 0.. for training
+    and 10000.. held out) of the parameters in the sampling box of the kind;
+    converged kernel functions and self-energy of the training draws (draws
+    whose bare start does not converge are dropped) give the factorised head's
+    bases, and a (#inputs) -> 3 x 512 -> coordinates perceptron is trained on
+    the GPU (bf16 matrix-core products, FP32 accumulation). Each held-out draw
+    is solved to tol (negative: Sigma within |tol| relative of the fixed point)
+    from the bare vertex and from the predicted kernels and self-energy: in
+    complex128 for the local and 4x4 kinds, by the mixed schedule (complex64 /
+    FP32 to 2e-5, then complex128) for the 8x8 kind."""
     import numpy as np
     import torch
     from paper_1510_03330_amd import warmstart as W
-    from workloads import config
+    from paper_1510_03330_amd.ops import converge_mixed
+    from workloads import config, parameter_draws
 
-    if lattice:
-        base = config("c2", U=1.5, beta=3.0)
-        u_lo, u_hi, b_lo, b_hi = 1.0, 2.0, 2.0, 3.5
-        workload = "4x4 lattice, t=1, t'=0, half filling, Nv=16, alpha=0.5"
-    else:
-        base = config("c1", Nv=16, beta=2.0, D=2.0, alpha=0.5)
-        u_lo, u_hi, b_lo, b_hi = 0.5, 1.5, 2.0, 5.0
-        workload = "local model, semicircle bath D=2, half filling, Nv=16, alpha=0.5"
-    grid = [base.replace(U=float(u), beta=float(b)) for u in np.linspace(u_lo, u_hi, 12)
-            for b in np.linspace(b_lo, b_hi, 12)]
-    print("[warmstart] training data", file=sys.stderr, flush=True)
+    cfg, over, box, seeds_train, seeds_held, (tprec, ttol), workload = WARMSTART_KINDS[kind]
+    seeds_train = list(seeds_train)[:n_train] if n_train else list(seeds_train)
+    seeds_held = list(seeds_held)[:n_held] if n_held else list(seeds_held)
+    base = config(cfg, **over)
+    train = parameter_draws(base, box, seeds_train)
+    held = parameter_draws(base, box, seeds_held)
+    pred = W.KernelPredictor(base, box, max_samples=len(train), hidden=(512, 512, 512), seed=0)
+    print(f"[warmstart] {kind}: {len(train)} training solves ({tprec}, tol {ttol})", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    ps, k1s, k2s, sigs, dropped = [], [], [], [], 0
-    for p in grid:
-        conv, it, k1, k2, sig = W.converged_kernels(p, "fp64", tol=1e-8, max_iter=600)
+    dropped, it_train = 0, []
+    from paper_1510_03330_amd.ops import Solver, workspace_bytes
+    # one workspace for all training solves, sized for the largest need (the
+    # imaginary-time grid of the self-energy grows with beta)
+    s_train = Solver(base, tprec, ws_bytes=max(workspace_bytes(p, tprec) for p in train))
+    for k, p in enumerate(train):
+        conv, it, k1, k2, sig = W.converged_kernels(p, tprec, tol=ttol, max_iter=max_iter, solver=s_train)
         if conv:
-            ps.append(p), k1s.append(k1), k2s.append(k2), sigs.append(sig)
+            pred.add(p, k1, k2, sig)
+            it_train.append(it)
         else:
             dropped += 1
+        del k1, k2, sig
+        if kind == "8x8" or k % 24 == 23:
+            print(f"[warmstart] training solve {k + 1}/{len(train)}: converged {conv} in {it}", file=sys.stderr,
+                  flush=True)
     t_data = time.perf_counter() - t0
-    print(f"[warmstart] {len(ps)} samples; training", file=sys.stderr, flush=True)
-    pred = W.KernelPredictor(base, hidden=(512, 512, 512), seed=0)
+    del s_train
+    torch.cuda.empty_cache()
+    print(f"[warmstart] {len(pred.params)} samples; bases and training", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = pred.fit(ps, k1s, k2s, sigs, steps=3000, batch=64, lr=1e-3,
+    steps = 3000
+    hist = pred.fit(steps=steps, batch=64, lr=1e-3,
                     progress=lambda it, loss: print(f"[warmstart] step {it} loss {loss:.3g}", file=sys.stderr,
                                                     flush=True))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    del k1s, k2s, sigs
-    rng = np.random.default_rng(10000)
-    du, db = 0.05 * (u_hi - u_lo), 0.033 * (b_hi - b_lo)
-    held = [base.replace(U=float(rng.uniform(u_lo + du, u_hi - du)), beta=float(rng.uniform(b_lo + db, b_hi - db)))
-            for _ in range(24)]
+
+    # the 8x8 solves reuse one pair of workspaces (complex64 and complex128),
+    # allocated before the timed solves
+    pair = ((Solver(base, "fp32", ws_bytes=max(workspace_bytes(p, "fp32") for p in held)),
+             Solver(base, "fp64", ws_bytes=max(workspace_bytes(p, "fp64") for p in held)))
+            if kind == "8x8" else None)
+
+    def solve(p, warm):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if kind == "8x8":
+            s64, info = converge_mixed(p, tol=tol, max_iter=max_iter, warm=warm, solvers=pair)
+            sig = s64.get("sigma") if info["converged"] else None
+            kern = (s64.get("k1"), s64.get("k2"), sig) if info["converged"] else None
+            s64.close()
+            torch.cuda.synchronize()
+            return dict(iterations=info["iterations_fp32"] + info["iterations_fp64"],
+                        iterations_fp32=info["iterations_fp32"], converged=info["converged"],
+                        sec=time.perf_counter() - t, fallback=False, sigma=sig, kernels=kern)
+        return W.solve_timed(p, "fp64", tol, max_iter, warm=warm, keep=True)
+
+    # the best any predictor of K1, K2 and Sigma can do: the start rebuilt from
+    # the converged solution's own kernel functions (the part of Phi outside
+    # the kernel form is what the iteration still has to build)
+    n_exact = min(len(held), 8)
     print("[warmstart] held-out solves", file=sys.stderr, flush=True)
     rows = []
-    for p in held:
+    for hi, p in enumerate(held):
         k1, k2, sig = pred.predict(p)
-        warm = W.solve_timed(p, "fp64", tol, max_iter, warm=(k1, k2, sig))
-        warm_phi = W.solve_timed(p, "fp64", tol, max_iter, warm=(k1, k2))
-        bare = W.solve_timed(p, "fp64", tol, max_iter)
-        rows.append(dict(U=p.U, beta=p.beta, bare=bare, warm=warm, warm_phi=warm_phi))
-    it_b = np.array([r["bare"]["iterations"] for r in rows])
-    it_w = np.array([r["warm"]["iterations"] for r in rows])
-    it_p = np.array([r["warm_phi"]["iterations"] for r in rows])
-    s_b = sum(r["bare"]["sec"] for r in rows)
-    s_w = sum(r["warm"]["sec"] for r in rows)
-    return {"mode": "warmstart", "workload": workload,
-            "network": "2 -> 512 -> 512 -> 512 -> %d (K1, K2, Sigma; tanh, bf16 weights, FP32 accumulate)" % pred.nout,
-            "parameters": pred.mlp.count,
-            "train_grid": {"U": [u_lo, u_hi], "beta": [b_lo, b_hi], "points": len(grid)},
-            "train_samples": len(ps), "train_dropped_not_converged": dropped, "data_sec": round(t_data, 2),
-            "train_steps": 3000, "train_sec": round(t_train, 2), "loss_first_last": [hist[0][1], hist[-1][1]],
-            "held_out": len(rows), "tol": tol,
-            "iterations_bare_mean": float(it_b.mean()), "iterations_warm_mean": float(it_w.mean()),
-            "iterations_ratio_mean": float((it_w / it_b).mean()),
-            "iterations_warm_phi_only_mean": float(it_p.mean()),
+        warm = solve(p, (k1, k2, sig))
+        del k1, k2, sig
+        bare = solve(p, None)
+        dist = None
+        if warm["sigma"] is not None and bare["sigma"] is not None:
+            dist = float((warm["sigma"] - bare["sigma"]).abs().max() / bare["sigma"].abs().max())
+        exact = None
+        if hi < n_exact and bare["kernels"] is not None:
+            exact = solve(p, bare["kernels"])
+            exact.pop("sigma"), exact.pop("kernels")
+        for r in (warm, bare):
+            r.pop("sigma"), r.pop("kernels")
+        rows.append(dict(U=p.U, beta=p.beta, filling=p.filling, tp=p.tp, bare=bare, warm=warm,
+                         exact_kernels=exact, warm_vs_bare_rel=dist))
+        print(f"[warmstart] held-out U={p.U:.3f} beta={p.beta:.3f}: bare {bare['iterations']} it "
+              f"{bare['sec']:.2f} s, warm {warm['iterations']} it {warm['sec']:.2f} s"
+              + (f", from exact kernels {exact['iterations']} it" if exact else ""), file=sys.stderr, flush=True)
+    conv = [r for r in rows if r["bare"]["converged"]]
+    it_b = np.array([r["bare"]["iterations"] for r in conv], dtype=float)
+    it_w = np.array([r["warm"]["iterations"] for r in conv], dtype=float)
+    s_b = sum(r["bare"]["sec"] for r in conv)
+    s_w = sum(r["warm"]["sec"] for r in conv)
+    names = list(box)
+    return {"mode": "warmstart", "kind": kind, "workload": workload,
+            "network": "%d -> 512 -> 512 -> 512 -> %d coordinates (K1, K2, Sigma bases of %d rows each); tanh, "
+                       "bf16 matrix-core products, FP32 accumulate" % (len(names), 3 * pred.rows, pred.rows),
+            "inputs": {k: list(v) for k, v in box.items()}, "parameters": pred.mlp.count,
+            "field_lengths": pred.lens,
+            "train_seeds": [seeds_train[0], seeds_train[-1]], "held_out_seeds": [seeds_held[0], seeds_held[-1]],
+            "train_solver": {"precision": tprec, "tol": ttol, "iterations_mean": float(np.mean(it_train))},
+            "train_samples": len(pred.params), "train_dropped_not_converged": dropped,
+            "data_sec": round(t_data, 2), "train_steps": steps, "train_sec": round(t_train, 2),
+            "loss_first_last": [hist[0][1], hist[-1][1]],
+            "held_out": len(rows), "held_out_bare_converged": len(conv), "tol": tol,
+            "solve": "mixed complex64 -> complex128" if kind == "8x8" else "complex128",
+            "iterations_bare_mean": float(it_b.mean()) if len(conv) else None,
+            "iterations_warm_mean": float(it_w.mean()) if len(conv) else None,
+            "iterations_ratio_mean": float((it_w / it_b).mean()) if len(conv) else None,
             "sec_bare_total": round(s_b, 3), "sec_warm_total": round(s_w, 3),
-            "all_converged": bool(all(r["warm"]["converged"] and r["bare"]["converged"] for r in rows)),
+            "iterations_from_exact_kernels_mean": (float(np.mean([r["exact_kernels"]["iterations"] for r in conv
+                                                                   if r["exact_kernels"]]))
+                                                   if any(r["exact_kernels"] for r in conv) else None),
+            "iterations_bare_mean_same_points": (float(np.mean([r["bare"]["iterations"] for r in conv
+                                                                 if r["exact_kernels"]]))
+                                                 if any(r["exact_kernels"] for r in conv) else None),
+            "all_converged": bool(all(r["warm"]["converged"] for r in conv)),
             "fallbacks": int(sum(r["warm"]["fallback"] for r in rows)),
-            "cases": [{"U": round(r["U"], 4), "beta": round(r["beta"], 4), "bare": r["bare"]["iterations"],
-                       "warm": r["warm"]["iterations"]} for r in rows]}
-
-
-class _VirtualVertex:
-    """Deterministic pseudo-random stand-in for a [4][Nq][n][n] vertex too large
-    for host memory; supports the fancy indexing the oracle uses."""
-
-    def __init__(self, shape, r=None):
-        self.shape = shape
-        self.r = r
-
-    def __getitem__(self, key):
-        import numpy as np
-        if self.r is None:
-            if isinstance(key, tuple):
-                return _VirtualVertex(self.shape, int(key[0]))[key[1:]]
-            return _VirtualVertex(self.shape, int(key))
-        if isinstance(key, tuple) and len(key) == 3:
-            q, a, b = (np.asarray(k, dtype=np.int64) for k in key)
-            h = (q * 1000003 + a * 7919 + b * 104729 + self.r * 15485863) % 2147483647
-            return (np.sin(h * 1e-3) + 1j * np.cos(h * 1.7e-3)) * 0.05
-        raise TypeError("unsupported index")
-
+            "max_warm_vs_bare_rel": max((r["warm_vs_bare_rel"] or 0.0) for r in conv) if conv else None,
+            "rows": rows}
 
 def cpu_baseline(p):
     """Time the FP64 oracle on a bounded sample of one iteration and extrapolate."""
@@ -647,10 +694,10 @@ def main():
     ap.add_argument("--oracle-timing", action="store_true",
                     help="time the FP64 oracle on this host beside the GPU (local problem end to end, "
                          "4x4 lattice per iteration; one JSON line)")
-    ap.add_argument("--warmstart-lattice", action="store_true",
-                    help="run only the learned warm-start study on the 4x4 lattice (one JSON line)")
-    ap.add_argument("--warmstart", action="store_true",
-                    help="run only the learned warm-start study (one JSON line)")
+    ap.add_argument("--warmstart", choices=sorted(WARMSTART_KINDS), default=None,
+                    help="run only the learned warm-start study of that kind (one JSON line)")
+    ap.add_argument("--warmstart-train", type=int, default=None, help="limit the training draws")
+    ap.add_argument("--warmstart-held", type=int, default=None, help="limit the held-out draws")
     ap.add_argument("--no-ttc", action="store_true",
                     help="skip the time-to-converged-Sigma (1e-6) runs of both paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -670,10 +717,8 @@ def main():
         print(json.dumps(batch_study()))
         return
     if args.warmstart:
-        print(json.dumps(warmstart_study()))
-        return
-    if args.warmstart_lattice:
-        print(json.dumps(warmstart_study(lattice=True)))
+        print(json.dumps(warmstart_study(args.warmstart, n_train=args.warmstart_train,
+                                         n_held=args.warmstart_held)))
         return
     if args.oracle_timing:
         print(json.dumps(oracle_timing()))

@@ -285,10 +285,13 @@ pq_status phi_from_kernels(const pq_params* p, const void* k1, const void* k2, v
  * [batch][w_L] (widths: n_layers + 1 host ints). Parameters: params (float)
  * packed layer by layer as [W_l (w_{l+1} x w_l, row-major), b_l (w_{l+1})],
  * mlp_param_count entries, and params_bf16, the same array rounded to bf16
- * (to nearest even; the products use the bf16 weights, biases, activations and
- * accumulation are FP32). acts: device floats, batch * (w_1 + ... + w_L), the
- * outputs of every layer, the network output last. 1 <= n_layers <= 16 and
- * 1 <= widths <= 1048560 (ERR_ARG otherwise). Used for the learned warm start,
+ * (to nearest even). The products run on the bf16 matrix cores with FP32
+ * accumulation: weights as their bf16 copy, FP32 activations and gradients as
+ * two bf16 terms (hi + lo, about 2^-16 relative), so the result is that of
+ * FP32 operands with bf16 weights; biases and activations are FP32. acts:
+ * device floats, batch * (w_1 + ... + w_L), the outputs of every layer, the
+ * network output last. 1 <= n_layers <= 16, 1 <= widths <= 4194240 and
+ * 1 <= batch <= 4194240 (ERR_ARG otherwise). Used for the learned warm start,
  * model parameters -> kernel functions (an addition to the paper's method,
  * which starts from the bare vertex). */
 pq_status mlp_param_count(const int32_t* widths, int32_t n_layers, size_t* count);
@@ -306,6 +309,23 @@ pq_status mlp_backward(const int32_t* widths, int32_t n_layers, const void* para
 pq_status mlp_adam(float* params, void* params_bf16, float* m, float* v, const float* grad, size_t count,
                    float lr, float beta1, float beta2, float eps, int32_t step, pq_stream stream);
 pq_status mlp_to_bf16(const float* params, void* params_bf16, size_t count, pq_stream stream);
+/* Factorised output head of the warm-start network. mlp_basis takes rows
+ * training outputs y [rows][len] (device floats, overwritten) and leaves in y
+ * an orthonormal basis q_0 .. q_{rows-1} of their centred span (classical
+ * Gram-Schmidt with one re-orthogonalisation pass, FP64 dot products; a row
+ * with no new direction, its residual below 1e-6 of its centred norm, becomes
+ * zero), in mean [len] their mean, in coef [rows][ld_coef] (ld_coef >= rows)
+ * the coordinates of sample i, y_i = mean + scale sum_j coef[i][j] q_j
+ * (zero for j > i), divided by scale [1 float] = their root mean square. The
+ * network then predicts the rows coordinates; mlp_expand rebuilds out [len]
+ * (device doubles) = mean + scale sum_j coef[j] q_j from one predicted
+ * coordinate vector coef [rows] (device floats). ws: mlp_basis_workspace
+ * bytes of device memory. 1 <= rows <= 4096, len >= 1. */
+pq_status mlp_basis_workspace(int32_t rows, size_t* bytes);
+pq_status mlp_basis(float* y, int32_t rows, size_t len, float* mean, float* coef, int32_t ld_coef, float* scale,
+                    void* ws, pq_stream stream);
+pq_status mlp_expand(const float* q, int32_t rows, size_t len, const float* mean, const float* coef,
+                     const float* scale, double* out, pq_stream stream);
 
 /* ------------------------------------------------------------ context API */
 
@@ -406,6 +426,14 @@ pq_status parquet_set(pq_ctx* ctx, int32_t field, const void* dev_src, size_t by
 
 /* Byte size of a field for this context. */
 pq_status parquet_field_bytes(pq_ctx* ctx, int32_t field, size_t* bytes);
+
+/* Warm start of a context: Phi is rebuilt on the whole box from kernel values
+ * k1 [4][Nq] and k2 [4][Nq][n] (complex128, device) in the second-level kernel
+ * form of Sec. "Two-level kernel approximations" (as phi_from_kernels), in
+ * place in the context's storage, and Sigma is taken from sigma [Nve][Nk]
+ * (complex128, device) unless it is null. The history of changes used by the
+ * relative convergence test restarts. Synchronous on the context's stream. */
+pq_status parquet_warm_start(pq_ctx* ctx, const void* k1, const void* k2, const void* sigma);
 
 /* Copy the iteration state of src into dst: Sigma, mu~, the reducible
  * vertices Phi_r (converted between complex64 and complex128 storage as the

@@ -235,9 +235,10 @@ pq_status sigma_mix(const pq_params* p, const void* sigma_new, void* sigma_io, d
 }
 
 // ------------------------------------------------------ learned warm start
-// widths up to 65535 GEMM tiles of 16 (the weight-gradient product puts the
-// output width on the grid's second dimension)
-constexpr int32_t kMlpMaxWidth = 65535 * 16;
+// widths and batch up to 65535 GEMM tiles of 64 (the products put the output
+// width and the batch on the grid's second dimension)
+constexpr int32_t kMlpMaxWidth = 65535 * 64;
+constexpr int32_t kMlpMaxBasisRows = 4096;
 
 static bool mlp_widths_ok(const int32_t* w, int32_t nl) {
   if (!w || nl < 1 || nl > 16) return false;
@@ -254,7 +255,7 @@ pq_status mlp_param_count(const int32_t* widths, int32_t n_layers, size_t* count
 
 pq_status mlp_forward(const int32_t* widths, int32_t n_layers, const void* params_bf16, const float* params,
                       const float* x, float* acts, int32_t batch, pq_stream stream) {
-  PQ_CHECK_ARG(mlp_widths_ok(widths, n_layers) && batch >= 1, "bad widths or batch");
+  PQ_CHECK_ARG(mlp_widths_ok(widths, n_layers) && batch >= 1 && batch <= kMlpMaxWidth, "bad widths or batch");
   PQ_CHECK_ARG(params_bf16 && params && x && acts, "null pointer");
   return enq(launch_mlp_forward(widths, n_layers, params_bf16, params, x, acts, batch, (hipStream_t)stream),
              "mlp_forward");
@@ -263,7 +264,7 @@ pq_status mlp_forward(const int32_t* widths, int32_t n_layers, const void* param
 pq_status mlp_backward(const int32_t* widths, int32_t n_layers, const void* params_bf16, const float* x,
                        const float* acts, const float* target, float* grad, float* loss, float* scratch,
                        int32_t batch, pq_stream stream) {
-  PQ_CHECK_ARG(mlp_widths_ok(widths, n_layers) && batch >= 1, "bad widths or batch");
+  PQ_CHECK_ARG(mlp_widths_ok(widths, n_layers) && batch >= 1 && batch <= kMlpMaxWidth, "bad widths or batch");
   PQ_CHECK_ARG(params_bf16 && x && acts && target && grad && loss && scratch, "null pointer");
   return enq(launch_mlp_backward(widths, n_layers, params_bf16, x, acts, target, grad, loss, scratch, batch,
                                  (hipStream_t)stream),
@@ -281,6 +282,26 @@ pq_status mlp_adam(float* params, void* params_bf16, float* m, float* v, const f
 pq_status mlp_to_bf16(const float* params, void* params_bf16, size_t count, pq_stream stream) {
   PQ_CHECK_ARG(params && params_bf16 && count > 0, "null pointer or empty");
   return enq(launch_mlp_to_bf16(params, params_bf16, count, (hipStream_t)stream), "mlp_to_bf16");
+}
+
+pq_status mlp_basis_workspace(int32_t rows, size_t* bytes) {
+  PQ_CHECK_ARG(rows >= 1 && rows <= kMlpMaxBasisRows && bytes, "bad row count or null output");
+  *bytes = mlp_basis_ws_bytes(rows);
+  return PQ_OK;
+}
+
+pq_status mlp_basis(float* y, int32_t rows, size_t len, float* mean, float* coef, int32_t ld_coef, float* scale,
+                    void* ws, pq_stream stream) {
+  PQ_CHECK_ARG(rows >= 1 && rows <= kMlpMaxBasisRows && len >= 1 && ld_coef >= rows, "bad sizes");
+  PQ_CHECK_ARG(y && mean && coef && scale && ws, "null pointer");
+  return enq(launch_mlp_basis(y, rows, len, mean, coef, ld_coef, scale, ws, (hipStream_t)stream), "mlp_basis");
+}
+
+pq_status mlp_expand(const float* q, int32_t rows, size_t len, const float* mean, const float* coef,
+                     const float* scale, double* out, pq_stream stream) {
+  PQ_CHECK_ARG(rows >= 1 && rows <= kMlpMaxBasisRows && len >= 1, "bad sizes");
+  PQ_CHECK_ARG(q && mean && coef && scale && out, "null pointer");
+  return enq(launch_mlp_expand(q, rows, len, mean, coef, scale, out, (hipStream_t)stream), "mlp_expand");
 }
 
 pq_status phi_from_kernels(const pq_params* p, const void* k1, const void* k2, void* phi_out, pq_stream stream) {
@@ -734,6 +755,16 @@ pq_status parquet_set(pq_ctx* c, int32_t field, const void* dev_src, size_t byte
   if (e == hipSuccess && field == PQ_FIELD_LAMBDA) c->has_lam = true;
   if (field == PQ_FIELD_SIGMA || field == PQ_FIELD_PHI) c->nhist = 0;     // a new state: no contraction history
   return e == hipSuccess ? PQ_OK : hip_fail(e, "parquet_set");
+}
+
+pq_status parquet_warm_start(pq_ctx* c, const void* k1, const void* k2, const void* sigma) {
+  PQ_CHECK_ARG(c && k1 && k2, "null pointer");
+  hipError_t e = launch_phi_from_kernels(c->p, c->d, (const double2*)k1, (const double2*)k2, c->phi, c->s);
+  if (e == hipSuccess && sigma)
+    e = hipMemcpyAsync(c->sigma, sigma, field_bytes(c, PQ_FIELD_SIGMA), hipMemcpyDeviceToDevice, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  c->nhist = 0;
+  return e == hipSuccess ? PQ_OK : hip_fail(e, "parquet_warm_start");
 }
 
 pq_status parquet_copy_state(pq_ctx* dst, pq_ctx* src) {

@@ -53,6 +53,11 @@ hipError_t launch_mlp_backward(const int32_t* widths, int n_layers, const void* 
 hipError_t launch_mlp_adam(float* params, void* params_bf16, float* m, float* v, const float* grad, size_t count,
                            float lr, float beta1, float beta2, float eps, int step, hipStream_t s);
 hipError_t launch_mlp_to_bf16(const float* params, void* params_bf16, size_t count, hipStream_t s);
+size_t mlp_basis_ws_bytes(int rows);
+hipError_t launch_mlp_basis(float* y, int rows, size_t len, float* mean, float* coef, int ld, float* scale, void* ws,
+                            hipStream_t s);
+hipError_t launch_mlp_expand(const float* q, int rows, size_t len, const float* mean, const float* coef,
+                             const float* scale, double* out, hipStream_t s);
 hipError_t launch_phi_from_kernels(const pq_params& p, const Dims& d, const double2* k1, const double2* k2,
                                    void* phi, hipStream_t s);
 size_t sigma_ws_bytes(const Dims& d);

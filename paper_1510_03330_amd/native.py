@@ -34,6 +34,7 @@ EXPORTS = [
     "parquet_query_workspace", "parquet_init", "parquet_iterate", "parquet_get", "parquet_set",
     "parquet_field_bytes", "parquet_copy_state", "parquet_iterate_batch", "parquet_destroy",
     "phi_from_kernels", "mlp_param_count", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_to_bf16",
+    "mlp_basis_workspace", "mlp_basis", "mlp_expand", "parquet_warm_start",
     "sigma_sde_no_alloc",
 ]
 
@@ -127,6 +128,10 @@ def load() -> ctypes.CDLL:
         "mlp_adam": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, ctypes.c_float, ctypes.c_float,
                      ctypes.c_float, ctypes.c_float, c_int32, c_void_p],
         "mlp_to_bf16": [c_void_p, c_void_p, c_size_t, c_void_p],
+        "mlp_basis_workspace": [c_int32, POINTER(c_size_t)],
+        "parquet_warm_start": [c_void_p, c_void_p, c_void_p, c_void_p],
+        "mlp_basis": [c_void_p, c_int32, c_size_t, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p],
+        "mlp_expand": [c_void_p, c_int32, c_size_t, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
         "parquet_destroy": [c_void_p],
     }
     for name, args in sig.items():

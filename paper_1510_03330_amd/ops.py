@@ -140,26 +140,45 @@ class Stage:
                                    _ptr(dnorm, torch.float64, (1,), "dnorm"), _stream(stream)))
 
 
+def workspace_bytes(p, precision: str = "fp64", resolve_slots: int = 0, bse_tol: float = 0.0) -> int:
+    """Device workspace a context of these parameters needs (parquet_query_workspace)."""
+    st = Stage(p, precision, resolve_slots, bse_tol)
+    b = ctypes.c_size_t()
+    N.check(N.load().parquet_query_workspace(st._pp(), ctypes.byref(b)))
+    return int(b.value)
+
+
 class Solver:
-    """A parquet context on one device: workspace owned by a torch uint8 tensor."""
+    """A parquet context on one device: workspace owned by a torch uint8 tensor
+    (at least ws_bytes, so that reinit can take parameters of a larger need)."""
 
     def __init__(self, p, precision: str = "fp64", device: str = "cuda:0", stream=None, resolve_slots: int = 0,
-                 bse_tol: float = 0.0):
+                 bse_tol: float = 0.0, ws_bytes: int = 0):
         self.stage = Stage(p, precision, resolve_slots, bse_tol)
+        self._stage_args = (precision, resolve_slots, bse_tol)
         self.device = torch.device(device)
         self.stream = stream
         lib = N.load()
         b = ctypes.c_size_t()
         N.check(lib.parquet_query_workspace(self.stage._pp(), ctypes.byref(b)))
-        self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+        self.ws = torch.empty(max(int(b.value), int(ws_bytes)), dtype=torch.uint8, device=self.device)
         if stream is not None:
             self.ws.record_stream(stream)      # the context's work runs on its own stream
         self.ctx = None
         self.reinit()
 
-    def reinit(self):
+    def reinit(self, p=None):
         """Start again from the bare-vertex state (a new context on the same
-        workspace: parquet_init, nothing allocated)."""
+        workspace: parquet_init, nothing allocated), with new model parameters
+        p if given (any whose workspace fits the one held)."""
+        if p is not None:
+            st = Stage(p, *self._stage_args)
+            b = ctypes.c_size_t()
+            N.check(N.load().parquet_query_workspace(st._pp(), ctypes.byref(b)))
+            if int(b.value) > self.ws.numel():
+                raise ValueError(f"parameters need a {int(b.value)}-byte workspace, "
+                                 f"this solver holds {self.ws.numel()}")
+            self.stage = st
         self.close()
         ctx = ctypes.c_void_p()
         N.check(N.load().parquet_init(self.stage._pp(), ctypes.c_void_p(self.ws.data_ptr()),
@@ -216,6 +235,14 @@ class Solver:
             raise ValueError(f"{name} must have shape {shape}")
         N.check(N.load().parquet_set(self.ctx, N.FIELDS[name], ctypes.c_void_p(v.data_ptr()),
                                      ctypes.c_size_t(v.numel() * v.element_size())))
+
+    def warm_start(self, k1: torch.Tensor, k2: torch.Tensor, sigma: torch.Tensor = None):
+        """Rebuild Phi in place from kernel values (complex128, K1 [4][Nq] and
+        K2 [4][Nq][n]) and, if given, take Sigma [Nve][Nk] (parquet_warm_start)."""
+        st = self.stage
+        sp = _ptr(sigma, torch.complex128, st.sigma_shape, "sigma") if sigma is not None else None
+        N.check(N.load().parquet_warm_start(self.ctx, _ptr(k1, torch.complex128, st.k1_shape, "k1"),
+                                            _ptr(k2, torch.complex128, st.k2_shape, "k2"), sp))
 
     def copy_state_from(self, other: "Solver"):
         """Take Sigma, mu~, Phi and the iteration count of another context of the
@@ -376,7 +403,7 @@ class BatchRunner:
 
 
 def converge_mixed(p, tol: float = -1e-6, switch_tol: float = -2e-5, max_iter: int = 200,
-                   device: str = "cuda:0", low: str = "fp32", solvers=None):
+                   device: str = "cuda:0", low: str = "fp32", solvers=None, warm=None):
     """Iterate the complex64 path (precision ``low``: "fp32" or "bf16x3") from
     the bare-vertex start until the convergence test of switch_tol is met, then
     continue on the complex128/FP64 path from that state until the test of tol
@@ -384,18 +411,21 @@ def converge_mixed(p, tol: float = -1e-6, switch_tol: float = -2e-5, max_iter: i
     to the fixed point). Returns the FP64 solver and a dict with the iteration
     counts of both phases (the first under the key iterations_fp32). ``solvers``:
     an already allocated (low, fp64) pair of the same box, re-initialised here
-    (the low one is closed at the switch)."""
+    (the low one is closed at the switch). warm: (K1, K2) or (K1, K2, Sigma)
+    to start from (Solver.warm_start) instead of the bare vertex."""
     if low not in ("fp32", "bf16x3"):
         raise ValueError(f"low precision {low!r} must be fp32 or bf16x3")
     if solvers is not None:
         s32, s64 = solvers
-        s32.reinit()
+        s32.reinit(p)
     else:
         s32 = Solver(p, low, device)
+    if warm is not None:
+        s32.warm_start(*warm)
     done32, conv32, st32 = s32.iterate(max_iter, switch_tol)
     torch.cuda.synchronize()
     if solvers is not None:
-        s64.reinit()
+        s64.reinit(p)
     else:
         s64 = Solver(p, "fp64", device)
     s64.copy_state_from(s32)

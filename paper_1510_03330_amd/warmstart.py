@@ -1,11 +1,17 @@
-"""Learned warm start: a small multilayer perceptron maps the model parameters
-(U, beta) of the momentum-independent problem to its converged kernel
-functions K1_r(q), K2_r(k; q); the reducible vertex is then rebuilt from them
-(phi_from_kernels, second-level kernel form) and the iteration starts there
-instead of at the bare vertex. Training, inference and the rebuild run in the
-library's kernels (mlp_forward / mlp_backward / mlp_adam); this module only
-moves tensors and keeps the loop. The bare start remains the fallback when
-the warm-started iteration fails."""
+"""Learned warm start: a small multilayer perceptron maps model parameters
+(for instance U, beta, the filling n and t') to the converged kernel functions
+K1_r(q), K2_r(k; q) and the self-energy of one box; the reducible vertex is
+then rebuilt from the kernel values (phi_from_kernels, second-level kernel
+form) and the iteration starts there instead of at the bare vertex.
+
+The output layer is factorised: per field (K1, K2, Sigma) the library builds
+an orthonormal basis of the centred training solutions (mlp_basis), the
+network predicts the coordinates in those bases, and mlp_expand rebuilds the
+fields. The head is then as wide as the training set, not as the box (K2 alone
+has 3.9M complex values on the 8x8, Nv = 16 box). Training, inference, the
+basis and the rebuild run in the library's kernels; this module moves tensors
+and keeps the loop. The bare start remains the fallback when the
+warm-started iteration fails."""
 from __future__ import annotations
 
 import ctypes
@@ -17,9 +23,11 @@ import torch
 from . import native as N
 from .ops import Solver, Stage, _ptr, _stream
 
+FIELDS = ("k1", "k2", "sigma")
 
-def _p(t):
-    return ctypes.c_void_p(t.data_ptr())
+
+def _p(t, offset_elems: int = 0):
+    return ctypes.c_void_p(t.data_ptr() + offset_elems * t.element_size())
 
 
 class MLP:
@@ -95,51 +103,77 @@ class MLP:
 
 
 class KernelPredictor:
-    """(U, beta) -> K1 [4][Nq], K2 [4][Nq][n] and the self-energy [Nve][Nk]
-    for one box, with input scaling and per-output standardisation fitted on
-    the training set."""
+    """Model parameters -> K1 [4][Nq], K2 [4][Nq][n] and the self-energy
+    [Nve][Nk] of one box (complex128).
 
-    def __init__(self, base, hidden=(512, 512, 512), device: str = "cuda:0", seed: int = 0):
+    inputs: {name of a ModelParams field: (low, high)}, the sampling box of
+    the parameters the network sees; each is mapped affinely to [-1, 1].
+    Training solutions are added one at a time (add); fit builds the bases and
+    trains the network on the coordinates."""
+
+    def __init__(self, base, inputs, max_samples: int, hidden=(512, 512, 512), device: str = "cuda:0",
+                 seed: int = 0):
         self.base = base
-        self.stage = Stage(base, "fp64")
-        d = self.stage.d
-        self.nk1 = 4 * d.Nq
-        self.nk2 = 4 * d.Nq * d.n
-        self.nsig = d.Nve * d.Nk
-        self.nout = 2 * (self.nk1 + self.nk2 + self.nsig)
-        self.mlp = MLP([2, *hidden, self.nout], device, seed)
+        self.inputs = dict(inputs)
+        self.hidden = tuple(hidden)
+        self.seed = seed
         self.device = torch.device(device)
+        st = Stage(base, "fp64")
+        self.shapes = {"k1": st.k1_shape, "k2": st.k2_shape, "sigma": st.sigma_shape}
+        self.lens = {f: 2 * int(np.prod(self.shapes[f])) for f in FIELDS}
+        self.cap = int(max_samples)
+        self.Y = {f: torch.empty((self.cap, self.lens[f]), dtype=torch.float32, device=self.device) for f in FIELDS}
+        self.params = []
+        self.mlp = None
 
     def _x(self, params):
-        return torch.tensor([[p.U, p.beta] for p in params], dtype=torch.float32, device=self.device)
+        rows = []
+        for p in params:
+            rows.append([2.0 * (getattr(p, k) - lo) / (hi - lo) - 1.0 for k, (lo, hi) in self.inputs.items()])
+        return torch.tensor(rows, dtype=torch.float32, device=self.device)
 
-    def _scale_x(self, x):
-        return (x - self.x_mean) / self.x_std
+    def add(self, p, k1, k2, sigma):
+        """One converged solution (complex tensors on the device) as a training row."""
+        i = len(self.params)
+        if i >= self.cap:
+            raise ValueError("training set is full")
+        for f, v in zip(FIELDS, (k1, k2, sigma)):
+            self.Y[f][i].copy_(torch.view_as_real(v.reshape(self.shapes[f]).to(torch.complex64)).reshape(-1))
+        self.params.append(p)
 
-    @staticmethod
-    def _flat(k1, k2, sig):
-        return torch.cat([torch.view_as_real(k1).reshape(-1), torch.view_as_real(k2).reshape(-1),
-                          torch.view_as_real(sig).reshape(-1)])
-
-    def fit(self, params, k1s, k2s, sigs, steps=3000, batch=64, lr=1e-3, progress=None):
-        x = self._x(params)
-        y = torch.stack([self._flat(a, b, c) for a, b, c in zip(k1s, k2s, sigs)]).to(torch.float64)
-        self.x_mean, self.x_std = x.mean(0), x.std(0).clamp_min(1e-6)
-        self.y_mean, self.y_std = y.mean(0), y.std(0).clamp_min(1e-12)
-        X = self._scale_x(x)
-        Y = ((y - self.y_mean) / self.y_std).to(torch.float32)
-        return self.mlp.train(X, Y, steps, batch, lr, progress=progress)
+    def fit(self, steps=3000, batch=64, lr=1e-3, progress=None):
+        rows = len(self.params)
+        if rows < 2:
+            raise ValueError("need at least two training solutions")
+        lib = N.load()
+        wsb = ctypes.c_size_t()
+        N.check(lib.mlp_basis_workspace(rows, ctypes.byref(wsb)))
+        ws = torch.empty(int(wsb.value), dtype=torch.uint8, device=self.device)
+        T = torch.empty((rows, 3 * rows), dtype=torch.float32, device=self.device)
+        self.Q, self.mean, self.scale = {}, {}, {}
+        for gi, f in enumerate(FIELDS):
+            Y = self.Y[f][:rows].contiguous() if rows < self.cap else self.Y[f]
+            self.mean[f] = torch.empty(self.lens[f], dtype=torch.float32, device=self.device)
+            self.scale[f] = torch.empty(1, dtype=torch.float32, device=self.device)
+            N.check(lib.mlp_basis(_p(Y), rows, self.lens[f], _p(self.mean[f]), _p(T, gi * rows), 3 * rows,
+                                  _p(self.scale[f]), _p(ws), _stream()))
+            self.Q[f] = Y
+        self.Y = None                                     # the bases replace the raw rows
+        self.rows = rows
+        self.mlp = MLP([len(self.inputs), *self.hidden, 3 * rows], self.device, self.seed)
+        X = self._x(self.params)
+        return self.mlp.train(X, T, steps, min(batch, rows), lr, seed=self.seed, progress=progress)
 
     def predict(self, p):
-        X = self._scale_x(self._x([p]))
-        _, out = self.mlp.forward(X)
-        y = out[0].to(torch.float64) * self.y_std + self.y_mean
-        d = self.stage.d
-        a, b = 2 * self.nk1, 2 * (self.nk1 + self.nk2)
-        k1 = torch.view_as_complex(y[:a].reshape(-1, 2).contiguous()).reshape(4, d.Nq)
-        k2 = torch.view_as_complex(y[a:b].reshape(-1, 2).contiguous()).reshape(4, d.Nq, d.n)
-        sig = torch.view_as_complex(y[b:].reshape(-1, 2).contiguous()).reshape(d.Nve, d.Nk)
-        return k1.contiguous(), k2.contiguous(), sig.contiguous()
+        _, out = self.mlp.forward(self._x([p]))
+        lib = N.load()
+        res = []
+        for gi, f in enumerate(FIELDS):
+            y = torch.empty(self.lens[f], dtype=torch.float64, device=self.device)
+            N.check(lib.mlp_expand(_p(self.Q[f]), self.rows, self.lens[f], _p(self.mean[f]),
+                                   _p(out, gi * self.rows), _p(self.scale[f]), _p(y), _stream()))
+            res.append(torch.view_as_complex(y.view(-1, 2)).reshape(self.shapes[f]))
+        return tuple(res)
 
 
 def phi_from_kernels(p, precision: str, k1: torch.Tensor, k2: torch.Tensor, phi_out: torch.Tensor):
@@ -149,10 +183,14 @@ def phi_from_kernels(p, precision: str, k1: torch.Tensor, k2: torch.Tensor, phi_
                                       _ptr(phi_out, st.vdtype, st.vshape, "phi_out"), _stream()))
 
 
-def converged_kernels(p, precision: str = "fp64", tol: float = 1e-8, max_iter: int = 400):
+def converged_kernels(p, precision: str = "fp64", tol: float = 1e-8, max_iter: int = 400, solver=None):
     """Solve from the bare start; returns (converged, iterations, K1, K2, Sigma)
-    of the last iteration (the kernel functions of the converged vertex)."""
-    s = Solver(p, precision)
+    of the last iteration (the kernel functions of the converged vertex).
+    solver: a Solver of the same box and precision to reuse (re-initialised
+    with p; its workspace is kept)."""
+    s = solver if solver is not None else Solver(p, precision)
+    if solver is not None:
+        s.reinit(p)
     try:
         done, conv, _ = s.iterate(max_iter, tol)
     except N.ParquetError:
@@ -163,32 +201,36 @@ def converged_kernels(p, precision: str = "fp64", tol: float = 1e-8, max_iter: i
     return conv, done, k1, k2, sig
 
 
-def solve_timed(p, precision, tol, max_iter, warm=None):
-    """Iterations and seconds to max|dSigma| < tol from the bare start, or from
-    the vertex rebuilt from predicted kernels (warm = (k1, k2) or (k1, k2,
-    sigma), the latter also starting the self-energy from the prediction); a
-    warm start that does not converge is retried from the bare start (counted
-    in both)."""
+def solve_timed(p, precision, tol, max_iter, warm=None, keep=False):
+    """Iterations and seconds to the convergence test of tol (see
+    Solver.iterate) from the bare start, or from the vertex rebuilt from
+    predicted kernels (warm = (k1, k2) or (k1, k2, sigma), the latter also
+    starting the self-energy from the prediction); a warm start that does not
+    converge is retried from the bare start (counted in both). keep: also
+    return the final self-energy (key sigma) and kernel functions (key
+    kernels: K1, K2, Sigma)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = Solver(p, precision)
     if warm is not None:
-        phi = torch.empty(s.stage.vshape, dtype=s.stage.vdtype, device=s.device)
-        phi_from_kernels(p, precision, warm[0], warm[1], phi)
-        s.set("phi", phi)
-        del phi
-        if len(warm) > 2:
-            s.set("sigma", warm[2])
+        s.warm_start(*warm)
     try:
         done, conv, _ = s.iterate(max_iter, tol)
     except N.ParquetError:
         done, conv = max_iter, False
+    sigma = s.get("sigma") if keep and conv else None
+    kernels = (s.get("k1"), s.get("k2"), sigma) if keep and conv else None
     s.close()
     fallback = False
     if warm is not None and not conv:
         fallback = True
-        b = solve_timed(p, precision, tol, max_iter)
+        b = solve_timed(p, precision, tol, max_iter, keep=keep)
         done += b["iterations"]
         conv = b["converged"]
+        sigma, kernels = b.get("sigma"), b.get("kernels")
     torch.cuda.synchronize()
-    return dict(iterations=done, converged=bool(conv), sec=time.perf_counter() - t0, fallback=fallback)
+    out = dict(iterations=done, converged=bool(conv), sec=time.perf_counter() - t0, fallback=fallback)
+    if keep:
+        out["sigma"] = sigma
+        out["kernels"] = kernels
+    return out

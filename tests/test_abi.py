@@ -141,8 +141,8 @@ def test_precision_storage_pairs():
 
 
 def test_mlp_widths_are_checked_on_the_host():
-    """mlp_param_count accepts 1..16 layers of widths 1..1048560 (65535 GEMM
-    tiles of 16) and counts W and b of every layer; anything else is ERR_ARG."""
+    """mlp_param_count accepts 1..16 layers of widths 1..4194240 (65535 GEMM
+    tiles of 64) and counts W and b of every layer; anything else is ERR_ARG."""
     lib = N.load()
     cnt = ctypes.c_size_t()
 
@@ -152,11 +152,30 @@ def test_mlp_widths_are_checked_on_the_host():
 
     assert count([2, 512, 512, 512, 494464]) == N.PQ_OK
     assert cnt.value == (2 * 512 + 512) + 2 * (512 * 512 + 512) + (512 * 494464 + 494464)
-    assert count([3, 1048560]) == N.PQ_OK and cnt.value == 3 * 1048560 + 1048560
-    assert count([3, 1048561]) == N.PQ_ERR_ARG
+    assert count([3, 4194240]) == N.PQ_OK and cnt.value == 3 * 4194240 + 4194240
+    assert count([3, 4194241]) == N.PQ_ERR_ARG
     assert count([0, 4]) == N.PQ_ERR_ARG
     assert count([4]) == N.PQ_ERR_ARG                       # no layer
     assert count([1] * 18) == N.PQ_ERR_ARG                  # 17 layers
+
+
+def test_mlp_basis_arguments_are_checked_on_the_host():
+    """The factorised head's calls check their sizes and pointers before
+    touching the device: rows in 1..4096, a coordinate stride of at least
+    rows, non-null buffers; the workspace grows with the row count."""
+    lib = N.load()
+    b1, b2 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.mlp_basis_workspace(8, ctypes.byref(b1)) == N.PQ_OK
+    assert lib.mlp_basis_workspace(64, ctypes.byref(b2)) == N.PQ_OK and b2.value > b1.value
+    assert lib.mlp_basis_workspace(0, ctypes.byref(b1)) == N.PQ_ERR_ARG
+    assert lib.mlp_basis_workspace(4097, ctypes.byref(b1)) == N.PQ_ERR_ARG
+    f = ctypes.c_void_p(0x1000)
+    assert lib.mlp_basis(f, 8, 100, f, f, 7, f, f, None) == N.PQ_ERR_ARG          # ld < rows
+    assert lib.mlp_basis(f, 8, 0, f, f, 8, f, f, None) == N.PQ_ERR_ARG            # empty rows
+    assert lib.mlp_basis(None, 8, 100, f, f, 8, f, f, None) == N.PQ_ERR_ARG
+    assert lib.mlp_expand(f, 0, 100, f, f, f, f, None) == N.PQ_ERR_ARG
+    assert lib.mlp_expand(f, 8, 100, f, None, f, f, None) == N.PQ_ERR_ARG
+    assert lib.parquet_warm_start(None, f, f, None) == N.PQ_ERR_ARG
 
 
 def test_no_alloc_entry_point_rejects_boxes_beyond_its_scratch():

@@ -15,4 +15,6 @@ from .synthetic import (  # noqa: F401
     random_sigma,
     lowrank_phi_factors,
     lambda_box_parts,
+    parameter_draws,
+    batch_draws,
 )

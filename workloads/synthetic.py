@@ -80,6 +80,37 @@ def config(name: str, **overrides) -> ModelParams:
     return p.replace(**overrides) if overrides else p
 
 
+def parameter_draws(base: ModelParams, box: Dict[str, tuple], seeds) -> list:
+    """One parameter set per seed: every field named in box drawn uniformly
+    from its (low, high) range by Generator(PCG64(seed)), in the order of box;
+    a drawn filling is reached by bisection on the chemical potential
+    (mu_mode = 1)."""
+    out = []
+    for s in seeds:
+        rng = np.random.Generator(np.random.PCG64(int(s)))
+        kw = {k: float(rng.uniform(lo, hi)) for k, (lo, hi) in box.items()}
+        if "filling" in kw:
+            kw["mu_mode"] = 1
+        out.append(base.replace(**kw))
+    return out
+
+
+def batch_draws(count: int = 64, seed: int = 4, nvs=(8, 16, 24, 32)) -> list:
+    """Independent 4x4-lattice instances (t = 1, t' = 0) drawn in sequence by
+    one Generator(PCG64(seed)): U uniform in [0.5, 3], beta uniform in [2, 8],
+    filling uniform in [0.8, 1] (bisection on the chemical potential), box
+    size Nv uniform over nvs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        U = float(rng.uniform(0.5, 3.0))
+        beta = float(rng.uniform(2.0, 8.0))
+        n = float(rng.uniform(0.8, 1.0))
+        nv = int(nvs[int(rng.integers(len(nvs)))])
+        out.append(ModelParams(Lx=4, Ly=4, Nv=nv, U=U, beta=beta, t=1.0, tp=0.0, filling=n, mu_mode=1))
+    return out
+
+
 def rand_complex(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     """Complex normal draws with Re, Im ~ N(0, scale^2 / 2) each (E|z|^2 = scale^2)."""
     rng = np.random.Generator(np.random.PCG64(seed))
