@@ -318,57 +318,83 @@ def kernel_study(max_iter: int = 600, tol: float = 1e-8, chunk: int = 10):
     return out
 
 
-def batch_study(tol: float = 1e-6, max_iter: int = 150):
-    """Many small instances on one GPU: 64 instances of the 4x4 lattice (t = 1,
-    t' = 0, half filling) with Nv in {8, 16, 24, 32} (n = 128..512) and
-    U in {1, 1.5, 2, 2.5} x beta in {2, 3, 4, 5}, complex64/FP32 path, each
-    iterated from the bare-vertex start to max|dSigma| < tol. Batched: graph
-    replay of many contexts at once (BatchRunner, width autotuned); serial:
-    the same instances one after another with parquet_iterate."""
+def batch_study(tol: float = -1e-6, max_iter: int = 150, diverge: float = 1e2, serial: bool = True):
+    """Many independent instances on one GPU: 64 seeded draws of the 4x4
+    lattice (t = 1, t' = 0; one PCG64(4) stream: U in [0.5, 3], beta in
+    [2, 8], filling in [0.8, 1] reached by bisection, Nv in {8, 16, 24, 32},
+    n = 128..512), complex64/FP32 path, each iterated from the bare vertex
+    until Sigma is within 1e-6 relative of its fixed point (tol < 0 rule),
+    its change exceeds 1e2 (diverged) or it fails, at most max_iter
+    iterations. Batched: the batched solver, one batch per box (one BSE launch
+    sequence per channel over every active (instance, q) block, one HIP graph
+    per round, update tile chosen by timing at set-up). Serial: the same
+    instances one after another in their own contexts, stopped at the same
+    iteration. Also the previous form, concurrent graph replay of contexts."""
     import torch
-    from paper_1510_03330_amd.ops import BatchRunner, Solver
-    from workloads import config
-
-    params = [config("c2", Nv=nv, U=u, beta=b) for nv in (8, 16, 24, 32) for u in (1.0, 1.5, 2.0, 2.5)
-              for b in (2.0, 3.0, 4.0, 5.0)]
-    runner = BatchRunner(params, precision="fp32", mem_budget=200e9, widths=(1, 2, 4, 8, 16, 32))
-    print("[batch] autotune", file=sys.stderr, flush=True)
-    width = runner.autotune()
-    print(f"[batch] width {width}: batched run", file=sys.stderr, flush=True)
-    recs, t_batch = runner.run(tol=tol, max_iter=max_iter)
-    iters = sum(r["iterations"] for r in recs)
-    print("[batch] serial run", file=sys.stderr, flush=True)
     from paper_1510_03330_amd.native import ParquetError
+    from paper_1510_03330_amd.ops import Solver, run_batched
+    from workloads import batch_draws
+
+    params = batch_draws(64, seed=4)
+    print("[batch] batched solver", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    serial_iters = 0
-    for p, r in zip(params, recs):          # the same iterations, one instance after another
-        s = Solver(p, "fp32", device="cuda:0")
-        try:
-            done, conv, _ = s.iterate(r["iterations"], tol)
-        except ParquetError:                # the instance diverged (non-finite Sigma)
-            done = r["iterations"]
-        serial_iters += done
-        s.close()
-        del s
+    recs, batches = run_batched(params, "fp32", tol=tol, max_iter=max_iter, diverge=diverge,
+                                progress=lambda key, r, left: print(f"[batch] box {key}: round {r}, {left} active",
+                                                                    file=sys.stderr, flush=True))
     torch.cuda.synchronize()
-    t_serial = time.perf_counter() - t0
-    torch.cuda.empty_cache()
+    t_batch = time.perf_counter() - t0
+    iters = sum(r["iterations"] for r in recs)
+    t_serial, serial_iters = None, 0
+    if serial:
+        print("[batch] serial run", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        serial_by_nv = {}
+        for k, (p, r) in enumerate(zip(params, recs)):      # the same iterations, one instance after another
+            torch.cuda.synchronize()
+            ti = time.perf_counter()
+            s = Solver(p, "fp32", device="cuda:0")
+            try:
+                done, conv, _ = s.iterate(r["iterations"], 0.0)
+            except ParquetError:                             # non-finite Sigma or an unresolved block
+                done = s.last_done
+            serial_iters += done
+            s.close()
+            del s
+            torch.cuda.synchronize()
+            serial_by_nv[p.Nv] = serial_by_nv.get(p.Nv, 0.0) + time.perf_counter() - ti
+            if k % 8 == 7:
+                print(f"[batch] serial {k + 1}/64", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t_serial = time.perf_counter() - t0
+        torch.cuda.empty_cache()
     by_nv = {}
     for p, r in zip(params, recs):
-        e = by_nv.setdefault(p.Nv, {"instances": 0, "converged": 0, "diverged": 0, "iterations": 0})
+        e = by_nv.setdefault(p.Nv, {"instances": 0, "converged": 0, "diverged": 0, "failed": 0, "iterations": 0})
         e["instances"] += 1
-        e["converged"] += int(r["converged"])
-        e["diverged"] += int(not r["finite"])
+        e["converged"] += int(r["state"] == "converged")
+        e["diverged"] += int(r["state"] == "diverged")
+        e["failed"] += int(r["state"] in ("nonfinite", "singular"))
         e["iterations"] += r["iterations"]
-    return {"mode": "batch", "workload": "64 instances, 4x4 lattice, Nv 8/16/24/32, U 1..2.5, beta 2..5, fp32",
-            "tol": tol, "max_iter": max_iter, "width": width,
-            "autotune_instance_iterations_per_s": {str(k): round(v, 2) for k, v in runner.tuning.items()},
-            "batched_sec": round(t_batch, 3), "batched_instance_iterations": iters,
-            "batched_instance_iterations_per_s": round(iters / t_batch, 2),
-            "serial_sec": round(t_serial, 3), "serial_instance_iterations": serial_iters,
-            "speedup_vs_serial": round(t_serial / t_batch, 3),
-            "converged": sum(int(r["converged"]) for r in recs), "by_nv": by_nv}
+    out = {"mode": "batch",
+           "workload": "64 seeded instances (PCG64(4)): 4x4 lattice, t'=0, U in [0.5,3], beta in [2,8], "
+                       "n in [0.8,1] by bisection, Nv in {8,16,24,32}; fp32",
+           "tol": tol, "max_iter": max_iter, "diverge": diverge,
+           "batched_sec": round(t_batch, 3), "batched_instance_iterations": iters,
+           "batched_instance_iterations_per_s": round(iters / t_batch, 2), "batches": batches,
+           "converged": sum(int(r["state"] == "converged") for r in recs), "by_nv": by_nv}
+    for b in batches:
+        e = by_nv[b["box"][2]]
+        e["batched_sec"] = round(e.get("batched_sec", 0.0) + b["setup_sec"] + b["run_sec"], 3)
+    if t_serial is not None:
+        for nv, sec in serial_by_nv.items():
+            by_nv[nv]["serial_sec"] = round(sec, 3)
+            by_nv[nv]["speedup_vs_serial"] = round(sec / by_nv[nv]["batched_sec"], 3)
+        out.update(serial_sec=round(t_serial, 3), serial_instance_iterations=serial_iters,
+                   serial_instance_iterations_per_s=round(serial_iters / t_serial, 2),
+                   speedup_vs_serial=round(t_serial / t_batch, 3))
+    return out
 
 
 WARMSTART_KINDS = {
@@ -679,6 +705,8 @@ def oracle_timing():
 
 
 def main():
+    import faulthandler
+    faulthandler.enable()               # a Python traceback if the process dies on a signal
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)

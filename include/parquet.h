@@ -106,7 +106,13 @@ typedef struct {
                               summed over the box with the full F, Sigma on
                               the box only (requires f_ext = 1; the ablation
                               the regulation is measured against)           */
-  int32_t reserved;        /* 0                                              */
+  int32_t bse_tile;        /* complex64/FP32 BSE update tile: 0 the 128 x 128
+                              workgroup tile (64 x 64 per wave), 1 the
+                              128 x 64 tile (64 x 32 per wave, more
+                              workgroups for small systems); the other
+                              precisions have one tile. Both run the same
+                              products in the same order and agree to FP32
+                              rounding; the batched solver picks by timing.  */
   double U, beta, t, tp;   /* interaction, inverse temperature, hoppings     */
   double filling;          /* total density n for mu_mode = 1                */
   double D;                /* semicircle half-bandwidth (local mode)         */
@@ -449,6 +455,57 @@ pq_status parquet_warm_start(pq_ctx* ctx, const void* k1, const void* k2, const 
 pq_status parquet_copy_state(pq_ctx* dst, pq_ctx* src);
 
 pq_status parquet_destroy(pq_ctx* ctx);
+
+/* ------------------------------------------------------------ batched solver
+ * Many independent instances of one box iterated together (an addition to
+ * the paper's method, which treats one instance at a time). The count
+ * instances ps[0 .. count) must agree in Lx, Ly, Nv, f_ext, storage,
+ * precision, alpha, bse_tol and resolve_slots (PQ_ERR_ARG otherwise); U, beta,
+ * t, t', the filling, mu_mode, the kernel level, the edge rule and the
+ * regulation may differ. No box Lambda (the scalars (U, -U, 2U, 0) of each
+ * instance). count * Nq <= 16384.
+ *
+ * The reducible vertices live in one arena [4][count][Nq][n][n], so the BSE of
+ * one channel (Eq. PA_F_Phi) is one launch sequence over every (instance, q)
+ * block; the other stages run instance after instance around it, and one
+ * round (an iteration of every active instance) is one HIP graph.
+ * Each instance keeps its own convergence history and test (tol as in
+ * parquet_iterate); an instance that converges, whose Sigma is not finite,
+ * whose BSE left a block unresolved, or whose change exceeds diverge (> 0) is
+ * retired and no longer iterated (its vertex slot is reused; Sigma, G, mu,
+ * K1 and K2 stay readable).
+ *
+ * parquet_batch_init starts every instance from the bare vertex; with
+ * autotune != 0 and FP32 precision it first times both update tiles
+ * (pq_params.bse_tile) of the batch's BSE on its own block count and keeps the
+ * faster (parquet_batch_tile reports the choice and the times, ms per launch
+ * sequence of one channel). ws: parquet_batch_query_workspace bytes, owned by
+ * the caller. stream: a created stream (not the null stream; the rounds are
+ * captured into graphs on it) that the batch uses until it is destroyed;
+ * every call is synchronous.
+ * parquet_batch_iterate runs up to n_iter rounds, stopping early when no
+ * instance is active (active_left: the number still active).
+ * parquet_batch_status fills, per instance, the iterations done, the state
+ * (pq_batch_state) and the last change of Sigma (arrays of count; each
+ * pointer may be null). parquet_batch_get copies one instance's field
+ * (PQ_FIELD_SIGMA, G, MU, K1, K2; PHI only while the instance is active) to
+ * device memory; bytes must equal the field size. */
+typedef struct pq_batch pq_batch;
+typedef enum {
+  PQ_BATCH_RUNNING = 0,
+  PQ_BATCH_CONVERGED = 1,
+  PQ_BATCH_DIVERGED = 2,   /* change of Sigma above the diverge bound        */
+  PQ_BATCH_NONFINITE = 3,  /* NaN/Inf in Sigma                               */
+  PQ_BATCH_SINGULAR = 4    /* a BSE block unresolved                         */
+} pq_batch_state;
+pq_status parquet_batch_query_workspace(const pq_params* ps, int32_t count, size_t* bytes);
+pq_status parquet_batch_init(const pq_params* ps, int32_t count, void* ws, size_t ws_bytes, pq_stream stream,
+                             int32_t autotune, pq_batch** out);
+pq_status parquet_batch_iterate(pq_batch* b, int32_t n_iter, double tol, double diverge, int32_t* active_left);
+pq_status parquet_batch_status(pq_batch* b, int32_t* iterations, int32_t* state, double* dsigma);
+pq_status parquet_batch_get(pq_batch* b, int32_t instance, int32_t field, void* dev_dst, size_t bytes);
+pq_status parquet_batch_tile(pq_batch* b, int32_t* tile, float* ms);
+pq_status parquet_batch_destroy(pq_batch* b);
 
 #ifdef __cplusplus
 }

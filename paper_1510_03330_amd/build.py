@@ -20,7 +20,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 OBJ_DIR = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(OUT_DIR, "libparquet.so")
 
-SOURCES = ["pq_api.hip", "pq_single.hip", "pq_sigma.hip", "pq_remap.hip", "pq_bse.hip", "pq_mlp.hip"]
+SOURCES = ["pq_api.hip", "pq_single.hip", "pq_sigma.hip", "pq_remap.hip", "pq_bse.hip", "pq_mlp.hip", "pq_batch.hip"]
 HEADERS = ["pq_device.h", "pq_internal.h"]
 
 ARCH = os.environ.get("PQ_OFFLOAD_ARCH", "gfx950")

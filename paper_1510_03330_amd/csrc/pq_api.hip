@@ -66,15 +66,32 @@ bool make_dims(const pq_params* p, Dims* d) {
     return false;
   }
   if (!(p->bse_tol >= 0.0 && p->bse_tol <= 1.0)) { set_error("bse_tol must be in [0, 1]"); return false; }
+  if (p->bse_tile != 0 && p->bse_tile != 1) { set_error("bse_tile must be 0 or 1"); return false; }
   Dims x;
   x.Lx = p->Lx; x.Ly = p->Ly; x.Nk = p->Lx * p->Ly; x.Nv = p->Nv; x.NW = p->Nv - 1;
   x.f = p->f_ext; x.Nve = p->f_ext * p->Nv; x.NWe = x.Nve - 1; x.NG = 2 * x.Nve;
   x.n = x.Nk * x.Nv; x.Nq = x.Nk * x.NW;
+  x.cs = (long long)x.Nq * x.n * x.n;
   if (x.n > 4096) { set_error("BSE dimension %d above 4096", x.n); return false; }
   const double E = x.Nk == 1 ? p->D : 2.0 * max_abs_eps(*p, x);
   x.ntau = 8 * x.f * x.Nv + 64 + 4 * (int)ceil(p->beta * E);
   *d = x;
   return true;
+}
+
+bool convergence_test(double* dhist, int* nhist, double alpha, double dn, double smax, double tol) {
+  constexpr int W = 6;
+  for (int k = W; k > 0; --k) dhist[k] = dhist[k - 1];
+  dhist[0] = dn;
+  *nhist = *nhist < W + 1 ? *nhist + 1 : W + 1;
+  if (tol > 0.0) return dn < tol;
+  if (tol == 0.0 || *nhist < W + 1) return false;
+  if (!(dhist[W] > 0.0) || !(dn > 0.0)) return dn == 0.0 && *nhist > W;
+  const double rho = pow(dn / dhist[W], 1.0 / W);
+  double dmax = 0.0;
+  for (int k = 0; k < W; ++k) dmax = fmax(dmax, dhist[k]);
+  if (!(rho < 0.98)) return false;
+  return alpha * dmax / (1.0 - rho) < -tol * smax;
 }
 
 pq_dims to_public(const Dims& d) {
@@ -463,18 +480,7 @@ hipError_t enqueue_iteration(pq_ctx* c, bool record, BseTiming* tm, const char**
 // stops within 0.42 of the target distance at targets 1e-4 .. 1e-9.
 // tol = 0: never.
 bool converged_now(pq_ctx* c, double dn, double smax, double tol) {
-  constexpr int W = 6;
-  for (int k = W; k > 0; --k) c->dhist[k] = c->dhist[k - 1];
-  c->dhist[0] = dn;
-  c->nhist = c->nhist < W + 1 ? c->nhist + 1 : W + 1;
-  if (tol > 0.0) return dn < tol;
-  if (tol == 0.0 || c->nhist < W + 1) return false;
-  if (!(c->dhist[W] > 0.0) || !(dn > 0.0)) return dn == 0.0 && c->nhist > W;
-  const double rho = pow(dn / c->dhist[W], 1.0 / W);
-  double dmax = 0.0;
-  for (int k = 0; k < W; ++k) dmax = fmax(dmax, c->dhist[k]);
-  if (!(rho < 0.98)) return false;
-  return c->p.alpha * dmax / (1.0 - rho) < -tol * smax;
+  return convergence_test(c->dhist, &c->nhist, c->p.alpha, dn, smax, tol);
 }
 
 }  // namespace

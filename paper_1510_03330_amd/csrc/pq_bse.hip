@@ -943,6 +943,10 @@ template <bool FULL>
 using UpdBF3 = UpdCfg<float, 64, 64, 1, 1, FULL, true, false, true, true>;
 template <typename T, bool FULL, bool BF3>
 using UpdSel = typename std::conditional<BF3, UpdBF3<FULL>, UpdDefault<T, FULL>>::type;
+// the narrow complex64 tile (bse_tile = 1): 64 x 32 per wave, three waves per
+// SIMD, twice the workgroups of the default for the same update
+template <bool FULL>
+using UpdNarrow = UpdCfg<float, 64, 32, 2, 3, FULL, true, false, true>;
 
 // The four-product form behind the same interface (acc = C, acc -= ab).
 template <typename T, int WM, int WN>
@@ -1463,7 +1467,7 @@ __global__ __launch_bounds__(kThreads) void probe_flag_kernel(const double* cq, 
 //    holds alpha (F^ - Gamma) + (1 - alpha) Phi_old, so the FP64 F enters as
 //    Phi + alpha (F_64 - F^) (no saved copy needed; F^ is still in B).
 // Flagged blocks beyond the slots keep the complex64 result and pst[7] = 1.
-constexpr int kMaxBlocks = 4096;     // Nq < n <= 4096
+constexpr int kMaxBlocks = kBseMaxBlocks;   // blocks of one launch sequence (a batch: K Nq)
 
 __device__ inline bool pivot_flagged(const double* ps, float weak, double kappa_max) {
   const double ratio = ps[1] > 0.0 ? ps[0] / ps[1] : 0.0;
@@ -1625,7 +1629,7 @@ template <typename T, bool BF3 = false>
 static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, double kappa_max, double err_tol,
                           int slots_req, const void* gamma, const double2* chi0, void* phi_io,
                           pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm,
-                          const int* active = nullptr) {
+                          const int* active = nullptr, int tile = 0) {
   using C = typename cplx_of<T>::type;
   constexpr int NB = panel_width<T>();
   static const double kSign[4] = {1.0, 1.0, -1.0, 1.0};
@@ -1733,10 +1737,22 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
       C* mt = mtb[pj & 1];
       C* mtn = mtb[(pj + 1) & 1];
       const int ntc = std::min(NB, n - lo);      // the next panel's columns
-      if (j0 == 0)
+      if constexpr (sizeof(T) == 4 && !BF3) {
+        if (tile == 1) {
+          if (j0 == 0)
+            launch_update<T, NB, UpdFirst<UpdNarrow<true>>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
+          else
+            launch_update<T, NB, UpdNarrow<true>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
+        } else if (j0 == 0) {
+          launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
+        } else {
+          launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
+        }
+      } else if (j0 == 0) {
         launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
-      else
+      } else {
         launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
+      }
       post();
       if (tm) tm->update_flops += 8.0 * (double)(n - lo) * ncols * jb * d.Nq;
     }
@@ -1751,7 +1767,9 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     const int jb = std::min(NB, n - j0);
     const int mix_lo = kFuseMix ? j0 - NB : -1;
     pre(3);
-    if (jb == NB)
+    if (jb == NB && sizeof(T) == 4 && !BF3 && tile == 1)
+      launch_update<T, NB, UpdNarrow<true>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s, mix_lo);
+    else if (jb == NB)
       launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s,
                                                   mix_lo);
     else
@@ -1818,10 +1836,13 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
 
 namespace {
 // Counts over the block stats of one iteration (one workgroup, fixed-order sums).
-__global__ __launch_bounds__(kThreads) void bse_summary_kernel(const pq_bse_block_stats* st, int nb, double* out) {
+// nchunks runs of nb stats, stride apart
+__global__ __launch_bounds__(kThreads) void bse_summary_kernel(const pq_bse_block_stats* st, int nb, int nchunks,
+                                                               size_t stride, double* out) {
   __shared__ double red[kThreads];
   double f = 0.0, r = 0.0, u = 0.0, m = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+  for (int t = threadIdx.x; t < nb * nchunks; t += blockDim.x) {
+    const size_t i = (size_t)(t / nb) * stride + (t % nb);
     const int fl = st[i].flags;
     f += (fl & 1) ? 1.0 : 0.0;
     r += (fl & 4) ? 1.0 : 0.0;
@@ -1842,8 +1863,9 @@ __global__ __launch_bounds__(kThreads) void bse_summary_kernel(const pq_bse_bloc
 }
 }  // namespace
 
-hipError_t launch_bse_summary(const pq_bse_block_stats* stats, int nb, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(bse_summary_kernel, dim3(1), dim3(kThreads), 0, s, stats, nb, out);
+hipError_t launch_bse_summary(const pq_bse_block_stats* stats, int nb, double* out, hipStream_t s, int nchunks,
+                              size_t stride) {
+  hipLaunchKernelGGL(bse_summary_kernel, dim3(1), dim3(kThreads), 0, s, stats, nb, nchunks, stride, out);
   return hipGetLastError();
 }
 
@@ -1857,12 +1879,13 @@ hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precis
   if (p.storage != PQ_STORE_C64) return hipErrorInvalidValue;
   // complex64: a block is re-solved in FP64 when its pivot ratio drops below
   // 1e-3, a diagonal-block inverse exceeds 1e3, a pivot is not finite, or its
-  // error estimate exceeds bse_tol (default 1e-5)
+  // error estimate exceeds bse_tol (default 2e-5)
   const double tol = p.bse_tol > 0.0 ? p.bse_tol : kDefaultBseTol;
   if (precision == PQ_PREC_BF16X3)
     return run_bse<float, true>(d, channel, alpha, 1e-3f, 1e3, tol, p.resolve_slots, gamma, chi0, phi_io, stats, ws,
                                 s, tm);
-  return run_bse<float>(d, channel, alpha, 1e-3f, 1e3, tol, p.resolve_slots, gamma, chi0, phi_io, stats, ws, s, tm);
+  return run_bse<float>(d, channel, alpha, 1e-3f, 1e3, tol, p.resolve_slots, gamma, chi0, phi_io, stats, ws, s, tm,
+                        nullptr, p.bse_tile);
 }
 
 }  // namespace pq

@@ -11,6 +11,10 @@ namespace pq {
 // ----------------------------------------------------------------- sizes
 struct Dims {
   int Lx, Ly, Nk, Nv, NW, f, Nve, NWe, NG, n, Nq, ntau;
+  // elements between the channel arrays of a vertex (Phi, Gamma): Nq n^2 for
+  // one instance's [4][Nq][n][n]; K Nq n^2 in a batch of K instances of one
+  // box, whose vertices are stored [4][K][Nq][n][n]
+  long long cs;
 };
 
 // ------------------------------------------------------------- complex

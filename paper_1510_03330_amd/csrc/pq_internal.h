@@ -15,6 +15,13 @@ pq_status hip_fail(hipError_t e, const char* what);
 bool make_dims(const pq_params* p, Dims* d);
 pq_dims to_public(const Dims& d);
 
+// Convergence test of one iteration with change dn (max |dSigma|) and max |Sigma|
+// smax, on the history dhist[7] / *nhist of the earlier changes (newest first,
+// updated here). tol > 0: dn < tol. tol < 0: the estimated distance to the
+// fixed point, alpha max(last six changes) / (1 - rho) with rho the geometric
+// mean of the last six ratios (< 0.98), below |tol| smax. tol = 0: never.
+bool convergence_test(double* dhist, int* nhist, double alpha, double dn, double smax, double tol);
+
 // largest |eps_K| of the lattice (0 in the local mode)
 double max_abs_eps(const pq_params& p, const Dims& d);
 
@@ -84,7 +91,11 @@ hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precis
                       const void* gamma, const double2* chi0, void* phi_io, double alpha,
                       pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm = nullptr);
 // summary of nb block stats into out[0..3]: flagged, re-solved and unresolved
-// block counts, largest error estimate (+inf for a non-finite one)
-hipError_t launch_bse_summary(const pq_bse_block_stats* stats, int nb, double* out, hipStream_t s);
+// block counts, largest error estimate (+inf for a non-finite one); with
+// nchunks > 1, over nchunks runs of nb stats, stride apart
+hipError_t launch_bse_summary(const pq_bse_block_stats* stats, int nb, double* out, hipStream_t s, int nchunks = 1,
+                              size_t stride = 0);
+// largest number of blocks one BSE launch sequence takes (the refine list)
+constexpr int kBseMaxBlocks = 16384;
 
 }  // namespace pq

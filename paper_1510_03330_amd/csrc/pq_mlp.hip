@@ -179,8 +179,9 @@ __global__ __launch_bounds__(256) void phi_from_kernels_kernel(Dims d, const dou
   const size_t n = d.n, total = 4 * (size_t)d.Nq * n * n;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
     const size_t kp = i % n, k = (i / n) % n, rq = i / (n * n);      // rq = r Nq + q
+    const size_t r = rq / d.Nq, q = rq - r * d.Nq;
     const double2 a = k1[rq], b = k2[rq * n + k], c = k2[rq * n + kp];
-    phi[i] = from_d<C>(mk(a.x + b.x + c.x, a.y + b.y + c.y));
+    phi[r * d.cs + (q * n + k) * n + kp] = from_d<C>(mk(a.x + b.x + c.x, a.y + b.y + c.y));
   }
 }
 

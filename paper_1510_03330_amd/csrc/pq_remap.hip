@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kThreads) void kernel_extract_kernel(KxArgs<C> a) {
   } else {
     e0 = m > 0 ? bot : top;
   }
-  const C* blk = a.phi + ((size_t)r * d.Nq + qi) * n * n;
+  const C* blk = a.phi + (size_t)r * d.cs + (size_t)qi * n * n;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int ei = 0; ei < ne; ++ei) {
     const int e = ei == 0 ? e0 : e1;
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kRemapThreads) void remap_kernel(RemapArgs<C> a) {
   const int kbi = lin / d.NW, jm = lin - (lin / d.NW) * d.NW;
   const int nk = kbi / Nk - d.Nv / 2, K = kbi - (kbi / Nk) * Nk;
   const int m = jm - (d.Nv / 2 - 1);
-  const size_t n = d.n, nn = (size_t)d.n * d.n, chan = (size_t)d.Nq * nn;
+  const size_t n = d.n, nn = (size_t)d.n * d.n, chan = (size_t)d.cs;
   const int t = threadIdx.x;
 
   // output element e = Q Nk + K' reads source (Qp, Kb):

@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kThreads) void sigmab_kernel(SBArgs<C> a) {
   const int hG = d.NG / 2;
   const int nkp = nk + mp;
   const bool Yb = in_fbox(nkp, d.Nv);
-  const size_t n = d.n, nn = (size_t)d.n * d.n, chan = (size_t)d.Nq * nn;
+  const size_t n = d.n, nn = (size_t)d.n * d.n, chan = (size_t)d.cs;
   double ar = 0.0, ai = 0.0;
   for (int P = 0; P < d.Nk; ++P) {
     const int qi = jm * d.Nk + P;

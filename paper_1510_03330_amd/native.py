@@ -35,6 +35,8 @@ EXPORTS = [
     "parquet_field_bytes", "parquet_copy_state", "parquet_iterate_batch", "parquet_destroy",
     "phi_from_kernels", "mlp_param_count", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_to_bf16",
     "mlp_basis_workspace", "mlp_basis", "mlp_expand", "parquet_warm_start",
+    "parquet_batch_query_workspace", "parquet_batch_init", "parquet_batch_iterate", "parquet_batch_status",
+    "parquet_batch_get", "parquet_batch_tile", "parquet_batch_destroy",
     "sigma_sde_no_alloc",
 ]
 
@@ -44,7 +46,7 @@ class PqParams(ctypes.Structure):
         ("Lx", c_int32), ("Ly", c_int32), ("Nv", c_int32), ("f_ext", c_int32),
         ("kernel_level", c_int32), ("edge_rule", c_int32), ("mu_mode", c_int32),
         ("storage", c_int32), ("precision", c_int32), ("resolve_slots", c_int32),
-        ("regulation", c_int32), ("reserved", c_int32), ("U", c_double), ("beta", c_double), ("t", c_double), ("tp", c_double),
+        ("regulation", c_int32), ("bse_tile", c_int32), ("U", c_double), ("beta", c_double), ("t", c_double), ("tp", c_double),
         ("filling", c_double), ("D", c_double), ("mu_fixed", c_double), ("alpha", c_double),
         ("bse_tol", c_double),
     ]
@@ -133,6 +135,13 @@ def load() -> ctypes.CDLL:
         "mlp_basis": [c_void_p, c_int32, c_size_t, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p],
         "mlp_expand": [c_void_p, c_int32, c_size_t, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
         "parquet_destroy": [c_void_p],
+        "parquet_batch_query_workspace": [P, c_int32, POINTER(c_size_t)],
+        "parquet_batch_init": [P, c_int32, c_void_p, c_size_t, c_void_p, c_int32, POINTER(c_void_p)],
+        "parquet_batch_iterate": [c_void_p, c_int32, c_double, c_double, POINTER(c_int32)],
+        "parquet_batch_status": [c_void_p, c_void_p, c_void_p, c_void_p],
+        "parquet_batch_get": [c_void_p, c_int32, c_int32, c_void_p, c_size_t],
+        "parquet_batch_tile": [c_void_p, POINTER(c_int32), c_void_p],
+        "parquet_batch_destroy": [c_void_p],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -144,15 +153,19 @@ def load() -> ctypes.CDLL:
     return lib
 
 
+BATCH_STATES = {0: "running", 1: "converged", 2: "diverged", 3: "nonfinite", 4: "singular"}
+
+
 def check(status: int):
     if status != PQ_OK:
         msg = load().parquet_last_error().decode(errors="replace")
         raise ParquetError(status, msg)
 
 
-def make_params(p, precision: str = "fp64", resolve_slots: int = 0, bse_tol: float = 0.0) -> PqParams:
+def make_params(p, precision: str = "fp64", resolve_slots: int = 0, bse_tol: float = 0.0,
+                bse_tile: int = 0) -> PqParams:
     """pq_params from any object with the ModelParams attributes (resolve_slots
-    and bse_tol: 0 selects the library defaults)."""
+    and bse_tol: 0 selects the library defaults; bse_tile: the FP32 update tile)."""
     if precision not in PRECISIONS:
         raise ValueError(f"precision {precision!r} not available ({', '.join(PRECISIONS)})")
     out = PqParams()
@@ -168,6 +181,7 @@ def make_params(p, precision: str = "fp64", resolve_slots: int = 0, bse_tol: flo
     out.resolve_slots = int(resolve_slots)
     out.regulation = int(getattr(p, "regulation", 1))
     out.bse_tol = float(bse_tol)
+    out.bse_tile = int(bse_tile)
     return out
 
 

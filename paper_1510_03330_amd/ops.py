@@ -34,11 +34,12 @@ def _ptr(t: torch.Tensor, dtype, shape: Sequence[int], name: str) -> ctypes.c_vo
 class Stage:
     """Shapes and dtypes of one parameter set, plus the stateless stage calls."""
 
-    def __init__(self, p, precision: str = "fp64", resolve_slots: int = 0, bse_tol: float = 0.0):
+    def __init__(self, p, precision: str = "fp64", resolve_slots: int = 0, bse_tol: float = 0.0,
+                 bse_tile: int = 0):
         N.load()
         self.model = p
         self.precision = precision
-        self.pp = N.make_params(p, precision, resolve_slots, bse_tol)
+        self.pp = N.make_params(p, precision, resolve_slots, bse_tol, bse_tile)
         self.d = N.dims(self.pp)
         self.vdtype = torch.complex128 if precision == "fp64" else torch.complex64
         d = self.d
@@ -305,6 +306,133 @@ def iterate_batch(solvers, n_iter: int, tol: float = 0.0):
     if st not in (N.PQ_OK, N.PQ_ERR_NONFINITE, N.PQ_ERR_SINGULAR, N.PQ_ERR_NOT_CONVERGED):
         N.check(st)
     return [int(x) for x in done], [bool(x) for x in conv]
+
+
+class Batch:
+    """Instances of one box iterated together (parquet_batch_*): one vertex
+    arena, one BSE launch sequence per channel over every active (instance, q)
+    block, one HIP graph per round; autotune times the two FP32 update tiles
+    on the batch's own block count at set-up."""
+
+    def __init__(self, params, precision: str = "fp32", device: str = "cuda:0", autotune: bool = True):
+        self.params = list(params)
+        self.precision = precision
+        self.device = torch.device(device)
+        K = len(self.params)
+        self.K = K
+        self._pp = (N.PqParams * K)(*[N.make_params(p, precision) for p in self.params])
+        lib = N.load()
+        b = ctypes.c_size_t()
+        N.check(lib.parquet_batch_query_workspace(self._pp, K, ctypes.byref(b)))
+        self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self.stream = new_stream(str(self.device))           # pooled: created once, reused
+        self.ws.record_stream(self.stream)
+        h = ctypes.c_void_p()
+        N.check(lib.parquet_batch_init(self._pp, K, ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_size_t(b.value),
+                                       ctypes.c_void_p(self.stream.cuda_stream), int(bool(autotune)),
+                                       ctypes.byref(h)))
+        self.h = h
+        self.stage = Stage(self.params[0], precision)
+
+    @staticmethod
+    def workspace_bytes(params, precision: str = "fp32") -> int:
+        K = len(params)
+        pp = (N.PqParams * K)(*[N.make_params(p, precision) for p in params])
+        b = ctypes.c_size_t()
+        N.check(N.load().parquet_batch_query_workspace(pp, K, ctypes.byref(b)))
+        return int(b.value)
+
+    def iterate(self, n: int, tol: float = -1e-6, diverge: float = 0.0) -> int:
+        """Up to n rounds; returns the number of instances still active."""
+        left = ctypes.c_int32()
+        N.check(N.load().parquet_batch_iterate(self.h, int(n), float(tol), float(diverge), ctypes.byref(left)))
+        return int(left.value)
+
+    def status(self):
+        """Per instance: (iterations, state name, last change of Sigma)."""
+        it = (ctypes.c_int32 * self.K)()
+        st = (ctypes.c_int32 * self.K)()
+        dn = (ctypes.c_double * self.K)()
+        N.check(N.load().parquet_batch_status(self.h, it, st, dn))
+        return [(int(it[i]), N.BATCH_STATES[int(st[i])], float(dn[i])) for i in range(self.K)]
+
+    def tile(self):
+        t = ctypes.c_int32()
+        ms = (ctypes.c_float * 2)()
+        N.check(N.load().parquet_batch_tile(self.h, ctypes.byref(t), ms))
+        return int(t.value), float(ms[0]), float(ms[1])
+
+    def get(self, i: int, name: str) -> torch.Tensor:
+        st = self.stage
+        shape, dtype = {"sigma": (st.sigma_shape, torch.complex128), "g": (st.g_shape, torch.complex128),
+                        "mu": ((1,), torch.float64), "k1": (st.k1_shape, torch.complex128),
+                        "k2": (st.k2_shape, torch.complex128), "phi": (st.vshape, st.vdtype)}[name]
+        out = torch.empty(shape, dtype=dtype, device=self.device)
+        N.check(N.load().parquet_batch_get(self.h, int(i), N.FIELDS[name], ctypes.c_void_p(out.data_ptr()),
+                                           ctypes.c_size_t(out.numel() * out.element_size())))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            N.load().parquet_batch_destroy(self.h)
+            self.h = None
+            release_stream(self.stream)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_batched(params, precision: str = "fp32", device: str = "cuda:0", tol: float = -1e-6,
+                max_iter: int = 150, diverge: float = 1e2, mem_budget: float = 200e9, autotune: bool = True,
+                keep_sigma: bool = False, progress=None):
+    """Solve many instances with the batched solver: grouped by box (lattice,
+    Nv, f_ext), each group split into batches whose workspace fits
+    mem_budget, the batches run one after another. Returns (per-instance
+    records in the order of params, per-batch records)."""
+    import time
+    groups = {}
+    for i, p in enumerate(params):
+        groups.setdefault((p.Lx, p.Ly, p.Nv, p.f_ext), []).append(i)
+    out = [None] * len(params)
+    batches = []
+    for key in sorted(groups):
+        idx = groups[key]
+        per = Batch.workspace_bytes([params[idx[0]]], precision)
+        nd = N.dims(N.make_params(params[idx[0]], precision))
+        cap = max(1, min(int(mem_budget // max(per, 1)), 16384 // nd.Nq))
+        for c0 in range(0, len(idx), cap):
+            chunk = idx[c0:c0 + cap]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b = Batch([params[i] for i in chunk], precision, device, autotune)
+            t1 = time.perf_counter()
+            rounds = 0
+            while rounds < max_iter:
+                left = b.iterate(min(10, max_iter - rounds), tol, diverge)
+                rounds += min(10, max_iter - rounds)
+                if progress is not None:
+                    progress(key, rounds, left)
+                if left == 0:
+                    break
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            tile = b.tile()
+            for j, (it, state, dn) in zip(chunk, b.status()):
+                rec = dict(iterations=it, state=state, converged=state == "converged", dsigma=dn)
+                if keep_sigma:
+                    rec["sigma"] = b.get(chunk.index(j), "sigma").cpu()
+                out[j] = rec
+            batches.append(dict(box=list(key), instances=len(chunk), setup_sec=round(t1 - t0, 3),
+                                run_sec=round(t2 - t1, 3), tile=tile[0], tile_ms=[round(tile[1], 3), round(tile[2], 3)],
+                                instance_iterations=sum(out[j]["iterations"] for j in chunk)))
+            b.close()
+            del b
+            torch.cuda.empty_cache()
+    return out, batches
 
 
 class BatchRunner:

@@ -195,3 +195,32 @@ def test_no_alloc_entry_point_rejects_boxes_beyond_its_scratch():
     N.check(lib.sigma_sde_workspace(ctypes.byref(small), ctypes.byref(ws)))
     assert ws.value < 64 << 20
     assert lib.sigma_sde_no_alloc(ctypes.byref(small), None, fake, fake, None, fake, fake, fake, None) == N.PQ_ERR_ARG
+
+
+def test_batch_arguments_are_checked_on_the_host():
+    """The batched solver's sizes are validated before anything touches the
+    device: instances of different boxes, precisions or mixing are refused,
+    as are batches above 16384 BSE blocks per channel; the workspace grows
+    with the instance count; bse_tile is 0 or 1."""
+    lib = N.load()
+
+    def query(ps, prec="fp32"):
+        arr = (N.PqParams * len(ps))(*[N.make_params(p, prec) for p in ps])
+        b = ctypes.c_size_t()
+        return lib.parquet_batch_query_workspace(arr, len(ps), ctypes.byref(b)), b.value
+
+    p = config("small_2x4")
+    st1, b1 = query([p])
+    st3, b3 = query([p, p.replace(U=2.0, beta=3.0, filling=0.95), p.replace(tp=-0.1, kernel_level=1)])
+    assert st1 == N.PQ_OK and st3 == N.PQ_OK and b3 > 2 * b1
+    assert query([p, p.replace(Nv=8)])[0] == N.PQ_ERR_ARG
+    assert query([p, p.replace(alpha=0.3)])[0] == N.PQ_ERR_ARG
+    big = config("c2", Nv=32)                           # Nq = 496: 34 instances exceed 16384 blocks
+    assert query([big] * 33)[0] == N.PQ_OK
+    assert query([big] * 34)[0] == N.PQ_ERR_ARG
+    assert b"16384" in lib.parquet_last_error()
+    assert lib.parquet_batch_query_workspace(None, 1, ctypes.byref(ctypes.c_size_t())) == N.PQ_ERR_ARG
+    bad = N.make_params(p, "fp32", bse_tile=2)
+    assert lib.pq_dims_from_params(ctypes.byref(bad), ctypes.byref(N.PqDims())) == N.PQ_ERR_ARG
+    assert lib.parquet_batch_iterate(None, 1, 0.0, 0.0, None) == N.PQ_ERR_ARG
+    assert lib.parquet_batch_destroy(None) == N.PQ_OK
