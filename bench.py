@@ -90,26 +90,41 @@ def run_gpu(p, precision, steps, warmup):
                 kern_ms=kern_ms, kern_n=kern_n, upd_flops=upd_flops)
 
 
-def hbm_copy_rate(gib: int = 4, reps: int = 5) -> float:
-    """GB/s (read + write) of a plain device-to-device tensor copy of `gib` GiB:
-    the practical ceiling of a kernel that reads and writes equal volumes."""
+def hbm_rates(gib: int = 4, reps: int = 10) -> dict:
+    """GB/s of the library's float4 reference streams (hbm_stream) over `gib`
+    GiB: copy (read + write counted), read only, write only, timed with HIP
+    events around `reps` launches on the current stream. The copy rate is the
+    practical ceiling of a kernel that reads and writes equal volumes."""
+    import ctypes
     import torch
-    a = torch.ones((gib << 30) // 4, dtype=torch.float32, device="cuda:0")
+    from paper_1510_03330_amd import native as N
+    nbytes = gib << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    nbytes = 2.0 * a.numel() * 4
+    out = {}
+    lib = N.load()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for mode, name, moved in ((0, "copy", 2 * nbytes), (1, "read", nbytes), (2, "write", nbytes)):
+        src = ctypes.c_void_p(a.data_ptr())
+        dst = ctypes.c_void_p(b.data_ptr())
+        N.check(lib.hbm_stream(mode, src, dst, nbytes, st))          # warm-up
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            N.check(lib.hbm_stream(mode, src, dst, nbytes, st))
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = round(moved / (ms * 1e-3) / 1e9, 1)
     del a, b
     torch.cuda.empty_cache()
-    return nbytes / (ms * 1e-3) / 1e9
+    return out
+
+
+def hbm_copy_rate(gib: int = 4, reps: int = 5) -> float:
+    """GB/s (read + write) of the library's float4 copy stream of `gib` GiB."""
+    return hbm_rates(gib, reps)["copy"]
 
 
 def time_to_converged(p, precision, rel, max_iter, tight_tol=None):
@@ -719,6 +734,8 @@ def main():
                     help="run only the kernel-level / regulation / U-range study (one JSON line)")
     ap.add_argument("--batch", action="store_true",
                     help="run only the 64-instance batched-solver study (one JSON line)")
+    ap.add_argument("--hbm", action="store_true",
+                    help="run only the HBM reference streams (copy, read, write; one JSON line)")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="time the FP64 oracle on this host beside the GPU (local problem end to end, "
                          "4x4 lattice per iteration; one JSON line)")
@@ -750,6 +767,11 @@ def main():
         return
     if args.oracle_timing:
         print(json.dumps(oracle_timing()))
+        return
+    if args.hbm:
+        print(json.dumps({"mode": "hbm", "unit": "GB/s (bytes moved: copy counts read + write)",
+                          "peak": PEAK_HBM,
+                          "by_size_gib": {str(g): hbm_rates(g, 10) for g in (1, 4, 16)}}))
         return
     from workloads import config
     p = config(args.workload)
@@ -800,14 +822,21 @@ def main():
 
     # remap: algorithmic bytes (read the 4 Phi arrays, write the 4 Gamma arrays
     # once) over its stage time, against the HBM peak and against a plain copy
-    copy_gbs = hbm_copy_rate()
+    rates = hbm_rates()
+    copy_gbs = rates["copy"]
     remap_ms = r32["stage_ms"][3]
     remap_bytes = 8.0 * d.Nq * float(d.n) ** 2 * 8
     remap_gbs = remap_bytes / (remap_ms * 1e-3) / 1e9
     remap_roof = {"bound": "hbm", "ms": round(remap_ms, 3), "algorithmic_bytes": remap_bytes,
                   "achieved": round(remap_gbs, 1), "peak": PEAK_HBM, "unit": "GB/s",
                   "frac": round(remap_gbs / PEAK_HBM, 4), "copy_ceiling": round(copy_gbs, 1),
-                  "frac_of_copy_ceiling": round(remap_gbs / copy_gbs, 4)}
+                  "frac_of_copy_ceiling": round(remap_gbs / copy_gbs, 4), "hbm_streams_gbs": rates}
+    # the Schwinger-Dyson stage: its box part reads the 4 Phi arrays once
+    sde_ms = r32["stage_ms"][4]
+    sde_bytes = 4.0 * d.Nq * float(d.n) ** 2 * 8
+    sde_roof = {"bound": "hbm", "ms": round(sde_ms, 3), "algorithmic_bytes": sde_bytes,
+                "achieved": round(sde_bytes / (sde_ms * 1e-3) / 1e9, 1), "read_ceiling": rates["read"],
+                "frac_of_read_ceiling": round(sde_bytes / (sde_ms * 1e-3) / 1e9 / rates["read"], 4)}
 
     out = {
         "metric": "parquet iterations/s + time-to-converged Σ (1e-6) vs FP64 GPU, 8x8 Nv=16",
@@ -834,6 +863,7 @@ def main():
                             ("mix", 6))} if r64 else None),
         "roofline": roof,
         "remap": remap_roof,
+        "sde": sde_roof,
         "bf16x3_iterations_per_s": round(ips3, 4) if ips3 else None,
         "bf16x3_update_avg_launch_ms": (round(r3["kern_ms"][3] / r3["kern_n"][3], 3) if r3 else None),
         "stage_ms_bf16x3": ({k: round(r3["stage_ms"][i], 3) for k, i in

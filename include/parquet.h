@@ -287,6 +287,14 @@ pq_status sigma_mix(const pq_params* p, const void* sigma_new, void* sigma_io,
 pq_status phi_from_kernels(const pq_params* p, const void* k1, const void* k2, void* phi_out,
                            pq_stream stream);
 
+/* Reference streams for the memory-bound stages (not part of the method):
+ * mode 0 copies bytes from src to dst, 1 reads bytes from src (dst receives
+ * one float per workgroup: at least 64 KiB), 2 writes bytes to dst; float4
+ * accesses over a grid of at most 16384 workgroups. bytes: a positive multiple
+ * of 16. Measures what a kernel with the same read and write volumes can
+ * reach on this device. */
+pq_status hbm_stream(int32_t mode, const void* src, void* dst, size_t bytes, pq_stream stream);
+
 /* A multilayer perceptron x [batch][w0] -> tanh hidden layers -> linear output
  * [batch][w_L] (widths: n_layers + 1 host ints). Parameters: params (float)
  * packed layer by layer as [W_l (w_{l+1} x w_l, row-major), b_l (w_{l+1})],

@@ -301,6 +301,14 @@ pq_status mlp_to_bf16(const float* params, void* params_bf16, size_t count, pq_s
   return enq(launch_mlp_to_bf16(params, params_bf16, count, (hipStream_t)stream), "mlp_to_bf16");
 }
 
+pq_status hbm_stream(int32_t mode, const void* src, void* dst, size_t bytes, pq_stream stream) {
+  PQ_CHECK_ARG(mode >= 0 && mode <= 2, "mode must be 0 (copy), 1 (read) or 2 (write)");
+  PQ_CHECK_ARG(bytes > 0 && bytes % 16 == 0, "bytes must be a positive multiple of 16");
+  PQ_CHECK_ARG(mode == 2 || src, "null source");
+  PQ_CHECK_ARG(dst, "null destination");
+  return enq(launch_hbm_stream(mode, src, dst, bytes, (hipStream_t)stream), "hbm_stream");
+}
+
 pq_status mlp_basis_workspace(int32_t rows, size_t* bytes) {
   PQ_CHECK_ARG(rows >= 1 && rows <= kMlpMaxBasisRows && bytes, "bad row count or null output");
   *bytes = mlp_basis_ws_bytes(rows);

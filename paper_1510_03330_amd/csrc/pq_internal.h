@@ -50,6 +50,10 @@ hipError_t launch_remap(const pq_params& p, const Dims& d, const double lam[4], 
 hipError_t launch_lambda_fill(const Dims& d, double U, double2* lam_box, hipStream_t s);
 // f = a + b elementwise over count complex elements of the given storage
 hipError_t launch_vertex_sum(const void* a, const void* b, void* f, int storage, size_t count, hipStream_t s);
+// HBM streaming probes: mode 0 copy src -> dst, 1 read src (dst receives one
+// float per workgroup, at most kHbmStreamBlocks), 2 write dst; bytes a multiple of 16
+constexpr unsigned kHbmStreamBlocks = 16384;
+hipError_t launch_hbm_stream(int mode, const void* src, void* dst, size_t bytes, hipStream_t s);
 // learned warm start (pq_mlp.hip)
 size_t mlp_count(const int32_t* widths, int n_layers);
 hipError_t launch_mlp_forward(const int32_t* widths, int n_layers, const void* params_bf16, const float* params,

@@ -129,6 +129,18 @@ template <typename C> __device__ inline C czero();
 template <> __device__ inline float2 czero<float2>() { return make_float2(0.f, 0.f); }
 template <> __device__ inline double2 czero<double2>() { return make_double2(0.0, 0.0); }
 
+// non-temporal store of one complex value (Gamma is not read again here)
+__device__ inline void st_stream(float2* p, float2 v) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, (v2*)p);
+}
+__device__ inline void st_stream(double2* p, double2 v) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, (v2*)p);
+}
+
 template <typename C, typename R>
 __device__ inline C axpy(C acc, R c, C v) {
   acc.x += c * v.x;
@@ -281,8 +293,8 @@ __global__ __launch_bounds__(kRemapThreads) void remap_kernel(RemapArgs<C> a) {
         if (e < Nk2) {
           const int Q = e / Nk, Kp = e - (e / Nk) * Nk;
           const size_t off = (size_t)(jm * Nk + Q) * nn + (size_t)kbi * n + (size_t)in2 * Nk + Kp;
-          o0[off] = acc0[i];
-          o1[off] = acc1[i];
+          st_stream(o0 + off, acc0[i]);                // written once, read by a later stage
+          st_stream(o1 + off, acc1[i]);
         }
       }
     }

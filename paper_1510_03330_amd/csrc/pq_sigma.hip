@@ -354,9 +354,39 @@ struct SBArgs {
   double2* partial;      // [n][NW]
 };
 
+// 16-byte streaming loads of E consecutive complex values (E = 2 complex64,
+// 1 complex128): Phi is read exactly once, so the loads bypass the caches'
+// retention (non-temporal), which lets the read stream run closer to the HBM
+// read rate.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <typename C> struct Row16;
+template <> struct Row16<float2> {
+  static constexpr int E = 2;
+  __device__ static void load(const float2* p, double2 (&o)[2]) {
+    const f4v v = __builtin_nontemporal_load((const f4v*)p);
+    o[0] = mk(v.x, v.y);
+    o[1] = mk(v.z, v.w);
+  }
+};
+template <> struct Row16<double2> {
+  static constexpr int E = 1;
+  __device__ static void load(const double2* p, double2 (&o)[1]) {
+    const d2v v = __builtin_nontemporal_load((const d2v*)p);
+    o[0] = mk(v.x, v.y);
+  }
+};
+
+// One workgroup per (k, m): the box part of Eq. PA_Sigma for row k of the
+// four channels at the bosonic index m, summed over Q and k'. Each thread
+// takes E consecutive k' per 16-byte load (n is even, rows start 16-byte
+// aligned). (Momentum tables in LDS instead of the index arithmetic measured
+// slower: the kernel is bound by its loads, not by the integer work.)
 template <typename C>
 __global__ __launch_bounds__(kThreads) void sigmab_kernel(SBArgs<C> a) {
   __shared__ double red[kThreads];
+  using L16 = Row16<C>;
+  constexpr int E = L16::E;
   const Dims& d = a.d;
   const int kbi = blockIdx.x / d.NW, jm = blockIdx.x - (blockIdx.x / d.NW) * d.NW;
   const int nk = kbi / d.Nk - d.Nv / 2, K = kbi - (kbi / d.Nk) * d.Nk;
@@ -365,31 +395,37 @@ __global__ __launch_bounds__(kThreads) void sigmab_kernel(SBArgs<C> a) {
   const int nkp = nk + mp;
   const bool Yb = in_fbox(nkp, d.Nv);
   const size_t n = d.n, nn = (size_t)d.n * d.n, chan = (size_t)d.cs;
+  const int ng = d.n / E;                          // load groups per row
   double ar = 0.0, ai = 0.0;
   for (int P = 0; P < d.Nk; ++P) {
     const int qi = jm * d.Nk + P;
     const double2 g_kp = a.g[(size_t)(nkp + hG) * d.Nk + kadd(K, P, d.Lx, d.Ly)];
     const double2 g_pk = a.g[(size_t)(mp - nk - 1 + hG) * d.Nk + ksub(P, K, d.Lx, d.Ly)];
     const C* row = a.phi + (size_t)qi * nn + (size_t)kbi * n;
-    for (int b = threadIdx.x; b < d.n; b += blockDim.x) {
-      const int nb = b / d.Nk - d.Nv / 2, B = b - (b / d.Nk) * d.Nk;
-      const int x1 = mp + nk + nb + 1, x2 = nb - nk, x3 = mp - nk - nb - 1;
-      const double c16 = 1.0 + ind(in_bbox(x1, d.Nv));
-      const double c25 = Yb ? ind(in_bbox(x2, d.Nv)) + ind(in_bbox(x1, d.Nv)) : 0.0;
-      const double c34 = 1.0 + ind(in_bbox(x3, d.Nv));
-      const double2 gb = a.g[(size_t)(nb + hG) * d.Nk + B];
-      const double2 gbp = a.g[(size_t)(nb + mp + hG) * d.Nk + kadd(B, P, d.Lx, d.Ly)];
-      const double2 gpb = a.g[(size_t)(mp - nb - 1 + hG) * d.Nk + ksub(P, B, d.Lx, d.Ly)];
-      const double2 A1 = cmul(cmul(g_kp, gbp), gb);
-      const double2 A3 = cmul(cmul(gpb, g_pk), gb);
-      const double2 pd = to_d(row[b]);
-      const double2 pm = to_d(row[chan + b]);
-      const double2 ps = to_d(row[2 * chan + b]);
-      const double2 pt = to_d(row[3 * chan + b]);
-      double2 t1 = csub(cscale(pd, c16), cscale(pm, c16 + 2.0 * c25));
-      double2 v = cadd(cmul(A1, t1), cmul(A3, cscale(cadd(ps, pt), c34)));
-      ar += v.x;
-      ai += v.y;
+    for (int gi = threadIdx.x; gi < ng; gi += blockDim.x) {
+      double2 pd[E], pm[E], ps[E], pt[E];
+      L16::load(row + (size_t)gi * E, pd);
+      L16::load(row + chan + (size_t)gi * E, pm);
+      L16::load(row + 2 * chan + (size_t)gi * E, ps);
+      L16::load(row + 3 * chan + (size_t)gi * E, pt);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int b = gi * E + e;
+        const int nb = b / d.Nk - d.Nv / 2, B = b - (b / d.Nk) * d.Nk;
+        const int x1 = mp + nk + nb + 1, x2 = nb - nk, x3 = mp - nk - nb - 1;
+        const double c16 = 1.0 + ind(in_bbox(x1, d.Nv));
+        const double c25 = Yb ? ind(in_bbox(x2, d.Nv)) + ind(in_bbox(x1, d.Nv)) : 0.0;
+        const double c34 = 1.0 + ind(in_bbox(x3, d.Nv));
+        const double2 gb = a.g[(size_t)(nb + hG) * d.Nk + B];
+        const double2 gbp = a.g[(size_t)(nb + mp + hG) * d.Nk + kadd(B, P, d.Lx, d.Ly)];
+        const double2 gpb = a.g[(size_t)(mp - nb - 1 + hG) * d.Nk + ksub(P, B, d.Lx, d.Ly)];
+        const double2 A1 = cmul(cmul(g_kp, gbp), gb);
+        const double2 A3 = cmul(cmul(gpb, g_pk), gb);
+        const double2 t1 = csub(cscale(pd[e], c16), cscale(pm[e], c16 + 2.0 * c25));
+        const double2 v = cadd(cmul(A1, t1), cmul(A3, cscale(cadd(ps[e], pt[e]), c34)));
+        ar += v.x;
+        ai += v.y;
+      }
     }
   }
   ar = block_sum(ar, red);

@@ -246,3 +246,76 @@ hipError_t launch_mix(const Dims& d, const double2* snew, double2* sio, double a
 }
 
 }  // namespace pq
+
+// ------------------------------------------------------ HBM streaming probes
+// Reference rates for the memory-bound stages: float4 grid-stride streams,
+// eight 16-byte accesses in flight per thread and iteration, non-temporal
+// loads (and stores for the copy), up to 16384 workgroups: the fastest of the
+// shapes tried on this device (unroll 4, 8, 16; 1024 to 16384 workgroups;
+// with and without the non-temporal hint).
+namespace pq {
+namespace {
+
+constexpr int kHbmUnroll = 8;
+typedef float hf4 __attribute__((ext_vector_type(4)));
+
+__device__ inline hf4 nt_ld(const hf4* p) { return __builtin_nontemporal_load(p); }
+
+__global__ __launch_bounds__(256) void hbm_copy_kernel(const hf4* __restrict__ src, hf4* __restrict__ dst,
+                                                       size_t count) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (kHbmUnroll - 1) * stride < count; i += kHbmUnroll * stride) {
+    hf4 v[kHbmUnroll];
+#pragma unroll
+    for (int u = 0; u < kHbmUnroll; ++u) v[u] = nt_ld(src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < kHbmUnroll; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+  }
+  for (; i < count; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void hbm_read_kernel(const hf4* __restrict__ src, size_t count,
+                                                       float* __restrict__ out) {
+  __shared__ float red[256];
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float acc = 0.f;
+  for (; i + (kHbmUnroll - 1) * stride < count; i += kHbmUnroll * stride) {
+    hf4 v[kHbmUnroll];
+#pragma unroll
+    for (int u = 0; u < kHbmUnroll; ++u) v[u] = nt_ld(src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < kHbmUnroll; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+  }
+  for (; i < count; i += stride) acc += (src[i].x + src[i].y) + (src[i].z + src[i].w);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void hbm_write_kernel(hf4* __restrict__ dst, size_t count, float value) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const hf4 v = {value, value, value, value};
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_hbm_stream(int mode, const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const size_t count = bytes / 16;
+  const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>(kHbmStreamBlocks, (count + 255) / 256));
+  if (mode == 0)
+    hipLaunchKernelGGL(hbm_copy_kernel, dim3(blocks), dim3(256), 0, s, (const hf4*)src, (hf4*)dst, count);
+  else if (mode == 1)
+    hipLaunchKernelGGL(hbm_read_kernel, dim3(blocks), dim3(256), 0, s, (const hf4*)src, count, (float*)dst);
+  else
+    hipLaunchKernelGGL(hbm_write_kernel, dim3(blocks), dim3(256), 0, s, (hf4*)dst, count, 1.0f);
+  return hipGetLastError();
+}
+
+}  // namespace pq

@@ -36,7 +36,7 @@ EXPORTS = [
     "phi_from_kernels", "mlp_param_count", "mlp_forward", "mlp_backward", "mlp_adam", "mlp_to_bf16",
     "mlp_basis_workspace", "mlp_basis", "mlp_expand", "parquet_warm_start",
     "parquet_batch_query_workspace", "parquet_batch_init", "parquet_batch_iterate", "parquet_batch_status",
-    "parquet_batch_get", "parquet_batch_tile", "parquet_batch_destroy",
+    "parquet_batch_get", "parquet_batch_tile", "parquet_batch_destroy", "hbm_stream",
     "sigma_sde_no_alloc",
 ]
 
@@ -142,6 +142,7 @@ def load() -> ctypes.CDLL:
         "parquet_batch_get": [c_void_p, c_int32, c_int32, c_void_p, c_size_t],
         "parquet_batch_tile": [c_void_p, POINTER(c_int32), c_void_p],
         "parquet_batch_destroy": [c_void_p],
+        "hbm_stream": [c_int32, c_void_p, c_void_p, c_size_t, c_void_p],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
