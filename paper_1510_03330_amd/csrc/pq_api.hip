@@ -359,6 +359,8 @@ struct pq_ctx {
   bool have_events;
   hipEvent_t bev[512];   // BSE launch timing of one channel
   bool have_bev;
+  BseAsync la;           // BSE look-ahead stream and events (uncaptured iterations only)
+  bool have_la;
   hipGraphExec_t graph;  // one whole iteration captured on s (parquet_iterate_batch)
   bool have_graph;
   bool graph_has_lam;    // the box Lambda setting the graph was captured with
@@ -436,7 +438,7 @@ void* field_ptr(pq_ctx* c, int f) {
 // kernels -> remap -> Schwinger-Dyson -> BSE (4 channels) -> mixing (writes
 // dnorm). Nothing here waits on the host, allocates or clears memory, so the
 // sequence can be captured into a graph (record = false, tm = nullptr).
-hipError_t enqueue_iteration(pq_ctx* c, bool record, BseTiming* tm, const char** where) {
+hipError_t enqueue_iteration(pq_ctx* c, bool record, BseTiming* tm, const char** where, bool lookahead = false) {
   const Dims& d = c->d;
   const pq_params& p = c->p;
   const double lam[4] = {p.U, -p.U, 2.0 * p.U, 0.0};
@@ -464,7 +466,8 @@ hipError_t enqueue_iteration(pq_ctx* c, bool record, BseTiming* tm, const char**
   for (int r = 0; r < 4; ++r) {
     const double2* x = r < 2 ? c->xph : c->xpp;
     e = launch_bse(p, d, r, p.precision, (char*)c->gamma + r * vstride, x, (char*)c->phi + r * vstride, p.alpha,
-                   c->bstats + (size_t)r * d.Nq, c->bse_ws, c->s, r == 0 ? tm : nullptr);
+                   c->bstats + (size_t)r * d.Nq, c->bse_ws, c->s, r == 0 ? tm : nullptr,
+                   lookahead && c->have_la ? &c->la : nullptr);
     if (e != hipSuccess) { *where = "bse"; return e; }
   }
   if ((e = launch_bse_summary(c->bstats, 4 * d.Nq, c->dnorm + 1, c->s)) != hipSuccess) { *where = "bse summary"; return e; }
@@ -548,6 +551,17 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
   c->have_bev = true;
   for (int i = 0; i < 512; ++i)
     if (hipEventCreate(&c->bev[i]) != hipSuccess) c->have_bev = false;
+  // look-ahead stream (default priority) and its two events
+  c->have_la = hipStreamCreateWithFlags(&c->la.side, hipStreamNonBlocking) == hipSuccess;
+  if (c->have_la && hipEventCreateWithFlags(&c->la.ready, hipEventDisableTiming) != hipSuccess) {
+    hipStreamDestroy(c->la.side);
+    c->have_la = false;
+  }
+  if (c->have_la && hipEventCreateWithFlags(&c->la.done, hipEventDisableTiming) != hipSuccess) {
+    hipEventDestroy(c->la.ready);
+    hipStreamDestroy(c->la.side);
+    c->have_la = false;
+  }
   hipError_t e;
   const size_t vb = field_bytes(c, PQ_FIELD_PHI);
   if ((e = hipMemsetAsync(c->phi, 0, vb, c->s)) != hipSuccess) goto fail;
@@ -563,6 +577,11 @@ fail:
     if (c->have_events) hipEventDestroy(c->ev[i]);
   for (int i = 0; i < 512; ++i)
     if (c->have_bev) hipEventDestroy(c->bev[i]);
+  if (c->have_la) {
+    hipEventDestroy(c->la.ready);
+    hipEventDestroy(c->la.done);
+    hipStreamDestroy(c->la.side);
+  }
   delete c;
   return hip_fail(e, "parquet_init");
 }
@@ -582,7 +601,7 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
     tm.update_flops = 0.0;
     const bool timing = stats && c->have_bev;
     const char* where = nullptr;
-    if ((e = enqueue_iteration(c, c->have_events, timing ? &tm : nullptr, &where)) != hipSuccess)
+    if ((e = enqueue_iteration(c, c->have_events, timing ? &tm : nullptr, &where, true)) != hipSuccess)
       return hip_fail(e, where);
     double res[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, mu = 0.0;  // norm, flagged, re-solved, unresolved,
                                                                  // max estimate, max |Sigma|
@@ -817,6 +836,12 @@ pq_status parquet_copy_state(pq_ctx* dst, pq_ctx* src) {
 
 pq_status parquet_destroy(pq_ctx* c) {
   if (!c) return PQ_OK;
+  if (c->have_la) {
+    hipStreamSynchronize(c->la.side);
+    hipEventDestroy(c->la.ready);
+    hipEventDestroy(c->la.done);
+    hipStreamDestroy(c->la.side);
+  }
   if (c->have_graph) hipGraphExecDestroy(c->graph);
   if (c->have_events)
     for (int i = 0; i < 8; ++i) hipEventDestroy(c->ev[i]);

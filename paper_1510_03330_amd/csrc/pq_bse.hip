@@ -882,7 +882,9 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb, int mix) {
 // panel) are final multipliers of that panel for the rows below it: those go
 // transposed into mtn[col][i], the next panel's MT, instead of into A (where
 // nothing reads them: the next pivot-row step writes U there); the next
-// panel's diagonal block (rows row_lo .. row_lo + ntc) is stored in A as usual.
+// panel's diagonal block (the rows below the panel up to mult_row, where the
+// multiplier rows start) is stored in A as usual. A forward step may be split
+// by rows (the next panel's rows first), mult_row staying the same.
 // In the back substitution the rows mix_lo .. row_hi (the panel above, whose F
 // is final after this launch) are also mixed into Phi as they are stored (the
 // epilogue's formula; B keeps F, the next launch's operand).
@@ -968,7 +970,7 @@ template <typename T, int NB, class CF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CF::WPE)))
 void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int col_lo,
                        const typename cplx_of<T>::type* mt0, size_t mt_bs, typename cplx_of<T>::type* mtn,
-                       int ntc, int mix_lo) {
+                       int ntc, int mix_lo, int mult_row) {
   using C = typename cplx_of<T>::type;
   static_assert(!CF::BF3 || sizeof(T) == 4, "BF16x3 products take complex64 operands");
   using M = typename std::conditional<CF::BF3, MmaBF3, Mma<T>>::type;
@@ -1092,7 +1094,7 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
   acc.store_c([&](int r, int c, C v) {
     const int i = i0 + r;
     const int y = c / M::TN;
-    const bool mult = c0 + c < ntc && i >= row_lo + ntc;
+    const bool mult = c0 + c < ntc && i >= mult_row;
     if (cok[y] && i < row_hi && !mult) st_c<CF::NT>(&cb[y][(size_t)i * n], v);
     if (mult && i < row_hi) MN[(size_t)(c0 + c) * n + i] = v;
   });
@@ -1107,7 +1109,7 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
 template <typename T, int NB, class CF>
 void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int row_hi, int col_lo, bool ut,
                    typename cplx_of<T>::type* mt, typename cplx_of<T>::type* mtn, int ntc, hipStream_t s,
-                   int mix_lo = -1) {
+                   int mix_lo = -1, int mult_row = -1) {
   const auto* mt0 = ut ? a.A + (size_t)j0 * n : mt;
   const size_t mt_bs = ut ? (size_t)n * n : (size_t)NB * n;
   const int jb = std::min(NB, n - j0);
@@ -1115,7 +1117,8 @@ void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int ro
   const int nrb = (row_hi - row_lo + CF::WGM - 1) / CF::WGM;
   const int ncb = (ncols - col_lo + CF::WGN - 1) / CF::WGN;
   hipLaunchKernelGGL((bse_update_kernel<T, NB, CF>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb, row_lo,
-                     row_hi, col_lo, mt0, mt_bs, mtn ? mtn : mt, mtn ? ntc : 0, mix_lo < 0 ? n : mix_lo);
+                     row_hi, col_lo, mt0, mt_bs, mtn ? mtn : mt, mtn ? ntc : 0, mix_lo < 0 ? n : mix_lo,
+                     mult_row < 0 ? row_lo + ntc : mult_row);
 }
 
 // --------------------------------------------------------------- epilogue
@@ -1629,7 +1632,7 @@ template <typename T, bool BF3 = false>
 static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, double kappa_max, double err_tol,
                           int slots_req, const void* gamma, const double2* chi0, void* phi_io,
                           pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm,
-                          const int* active = nullptr, int tile = 0) {
+                          const int* active = nullptr, int tile = 0, const BseAsync* la = nullptr) {
   using C = typename cplx_of<T>::type;
   constexpr int NB = panel_width<T>();
   static const double kSign[4] = {1.0, 1.0, -1.0, 1.0};
@@ -1658,15 +1661,15 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   const int n = d.n;
   // event timing around each launch (kind: 0 init, 1 pivot, 2 panel, 3 update,
   // 4 epilogue, 5 error estimate and FP64 re-solve)
-  auto pre = [&](int kind) {
+  auto pre = [&](int kind, hipStream_t st) {
     if (tm && tm->used < tm->cap) {
       tm->kind[tm->used] = kind;
-      hipEventRecord(tm->ev[2 * tm->used], s);
+      hipEventRecord(tm->ev[2 * tm->used], st);
     }
   };
-  auto post = [&]() {
+  auto post = [&](hipStream_t st) {
     if (tm && tm->used < tm->cap) {
-      hipEventRecord(tm->ev[2 * tm->used + 1], s);
+      hipEventRecord(tm->ev[2 * tm->used + 1], st);
       tm->used++;
     }
   };
@@ -1699,62 +1702,112 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     p64 = (double2*)(w + L.p64);
     phis = (float2*)(w + L.phis);
   }
-  auto refine_gather = [&](int late) {
+  auto refine_gather = [&](int late, hipStream_t st) {
     if constexpr (sizeof(T) == 4) {
-      hipLaunchKernelGGL(refine_list_kernel, dim3(1), dim3(kThreads), 0, s, a.pst, d.Nq, weak, kappa_max, S, late,
+      hipLaunchKernelGGL(refine_list_kernel, dim3(1), dim3(kThreads), 0, st, a.pst, d.Nq, weak, kappa_max, S, late,
                          list);
-      hipLaunchKernelGGL(refine_gather_kernel, dim3(gx, S), dim3(kThreads), 0, s, (const float2*)gamma, chi0,
+      hipLaunchKernelGGL(refine_gather_kernel, dim3(gx, S), dim3(kThreads), 0, st, (const float2*)gamma, chi0,
                          (const float2*)phi_io, n, list, S, late, g64, x64, phis);
     }
   };
-  for (int j0 = 0; j0 < n; j0 += NB) {
+  // the diagonal-block inversion (and, for the first panel and a ragged last
+  // one, the multiplier copy) of the panel at j0, then its pivot-row step
+  auto pivot_step = [&](int j0, hipStream_t st) {
     const int jb = std::min(NB, n - j0);
-    const int ncols = (n - j0 - jb) + n;
     const int pj = j0 / NB;
-    pre(1);
-    hipLaunchKernelGGL((bse_pivot_kernel<T, NB>), dim3(1, d.Nq), dim3(pivot_threads<NB>()), 0, s, a, j0);
+    pre(1, st);
+    hipLaunchKernelGGL((bse_pivot_kernel<T, NB>), dim3(1, d.Nq), dim3(pivot_threads<NB>()), 0, st, a, j0);
     if (j0 == 0 || jb < NB) {
       BseCtx<T> am = a;
       am.MT = mtb[pj & 1];
-      hipLaunchKernelGGL((bse_multcopy_kernel<T, NB>), dim3((n + 31) / 32, d.Nq), dim3(kThreads), 0, s, am, j0);
+      hipLaunchKernelGGL((bse_multcopy_kernel<T, NB>), dim3((n + 31) / 32, d.Nq), dim3(kThreads), 0, st, am, j0);
     }
-    post();
-    if (j0 == last) refine_gather(0);
+    post(st);
+    if (j0 == last) refine_gather(0, st);
+  };
+  auto panel_step = [&](int j0, hipStream_t st) {
+    const int jb = std::min(NB, n - j0);
+    const int ncols = (n - j0 - jb) + n;
     constexpr int RW = panel_rows_per_wave<T, NB>();
     const int nwb = ((ncols + 31) / 32 * (NB / RW) + kWaves - 1) / kWaves;
     const int mix = kFuseMix && j0 == last ? 1 : 0;
-    pre(2);
+    pre(2, st);
     if (j0 == 0)
-      hipLaunchKernelGGL((bse_panel_kernel<T, NB, true, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb, mix);
+      hipLaunchKernelGGL((bse_panel_kernel<T, NB, true, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, st, a, j0, nwb, mix);
     else
-      hipLaunchKernelGGL((bse_panel_kernel<T, NB, false, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, s, a, j0, nwb, mix);
-    post();
-    // forward step: the rows below the panel (none below the last one); the
-    // full panels before the last are the only ones with rows below
-    if (j0 + jb < n) {
-      pre(3);
-      const int lo = j0 + jb;
-      C* mt = mtb[pj & 1];
-      C* mtn = mtb[(pj + 1) & 1];
-      const int ntc = std::min(NB, n - lo);      // the next panel's columns
-      if constexpr (sizeof(T) == 4 && !BF3) {
-        if (tile == 1) {
-          if (j0 == 0)
-            launch_update<T, NB, UpdFirst<UpdNarrow<true>>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
-          else
-            launch_update<T, NB, UpdNarrow<true>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
-        } else if (j0 == 0) {
-          launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
-        } else {
-          launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
-        }
+      hipLaunchKernelGGL((bse_panel_kernel<T, NB, false, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, st, a, j0, nwb,
+                         mix);
+    post(st);
+  };
+  // forward step of the panel at j0 for rows [row_lo, row_hi) below it; the
+  // multiplier rows of the next panel start at mult_row
+  auto fwd_update = [&](int j0, int row_lo, int row_hi, int mult_row) {
+    const int jb = std::min(NB, n - j0);
+    const int ncols = (n - j0 - jb) + n;
+    const int pj = j0 / NB;
+    const int lo = j0 + jb;
+    C* mt = mtb[pj & 1];
+    C* mtn = mtb[(pj + 1) & 1];
+    const int ntc = std::min(NB, n - lo);      // the next panel's columns
+    pre(3, s);
+    if constexpr (sizeof(T) == 4 && !BF3) {
+      if (tile == 1) {
+        if (j0 == 0)
+          launch_update<T, NB, UpdFirst<UpdNarrow<true>>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s,
+                                                           -1, mult_row);
+        else
+          launch_update<T, NB, UpdNarrow<true>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1,
+                                                mult_row);
       } else if (j0 == 0) {
-        launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
+        launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc,
+                                                              s, -1, mult_row);
       } else {
-        launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, lo, n, 0, false, mt, mtn, ntc, s);
+        launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1,
+                                                    mult_row);
       }
-      post();
-      if (tm) tm->update_flops += 8.0 * (double)(n - lo) * ncols * jb * d.Nq;
+    } else if (j0 == 0) {
+      launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s,
+                                                            -1, mult_row);
+    } else {
+      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1,
+                                                  mult_row);
+    }
+    post(s);
+    if (tm) tm->update_flops += 8.0 * (double)(row_hi - row_lo) * ncols * jb * d.Nq;
+  };
+  // Look-ahead (a second stream given): once the rows of the next panel are
+  // updated, its diagonal-block inversion runs on the second stream while the
+  // rows below it are updated here. The inversion reads only the next panel's
+  // diagonal block and writes its P (the current panel's P is consumed by
+  // then) and pivot monitor; the rows below read this panel's pivot rows and
+  // multipliers. (The pivot-row step cannot go ahead: it writes the U copy
+  // into the rows below, whose old values this update still reads.) Only for a
+  // full next panel with rows below it (a ragged one has a multiplier copy,
+  // which shares its buffer with the update's multiplier output).
+  bool ahead = false;
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int jb = std::min(NB, n - j0);
+    if (ahead)
+      hipStreamWaitEvent(s, la->done, 0);
+    else
+      pivot_step(j0, s);
+    panel_step(j0, s);
+    ahead = false;
+    // forward step: the rows below the panel (none below the last one)
+    if (j0 + jb < n) {
+      const int lo = j0 + jb;
+      const int mult_row = lo + std::min(NB, n - lo);
+      if (la && lo + NB < n) {
+        fwd_update(j0, lo, lo + NB, mult_row);
+        hipEventRecord(la->ready, s);
+        hipStreamWaitEvent(la->side, la->ready, 0);
+        pivot_step(lo, la->side);
+        hipEventRecord(la->done, la->side);
+        fwd_update(j0, lo + NB, n, mult_row);
+        ahead = true;
+      } else {
+        fwd_update(j0, lo, n, mult_row);
+      }
     }
   }
   // Back substitution: the rows of panel J of B hold F once every later panel
@@ -1766,7 +1819,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   for (int j0 = last; j0 > 0; j0 -= NB) {
     const int jb = std::min(NB, n - j0);
     const int mix_lo = kFuseMix ? j0 - NB : -1;
-    pre(3);
+    pre(3, s);
     if (jb == NB && sizeof(T) == 4 && !BF3 && tile == 1)
       launch_update<T, NB, UpdNarrow<true>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s, mix_lo);
     else if (jb == NB)
@@ -1775,20 +1828,20 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     else
       launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, false, mtb[(j0 / NB) & 1],
                                                    nullptr, 0, s, mix_lo);
-    post();
+    post(s);
     if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
   }
   if (!kFuseMix) {            // every row in a separate pass
-    pre(4);
+    pre(4, s);
     const unsigned ntile = (unsigned)(((n + 63) / 64) * ((n + 31) / 32));
     hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3((ntile + kWaves - 1) / kWaves, d.Nq), dim3(kThreads), 0, s,
                        a);
-    post();
+    post(s);
   }
   if constexpr (sizeof(T) == 4) {
     // error estimate of every block (B holds the complex64 F), then the FP64
     // re-solve of the flagged blocks
-    pre(5);
+    pre(5, s);
     const double sg = kSign[channel];
     const unsigned rows_scr = kWaves * 4, rows_ref = kWaves;
     const unsigned rx_all = (unsigned)((n + rows_scr - 1) / rows_scr);
@@ -1817,7 +1870,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
                        (const double2*)pr, n, sg, cpst, pcq);
     hipLaunchKernelGGL((probe_flag_kernel<kNpRefine>), dim3(d.Nq), dim3(kThreads), 0, s, (const double*)pcq, n,
                        err_tol, a.pst);
-    refine_gather(1);
+    refine_gather(1, s);
     Dims r = d;
     r.Nq = S;
     const BseLayout L64 = bse_layout<double>(r);
@@ -1827,7 +1880,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     hipLaunchKernelGGL(refine_scatter_kernel, dim3(gx, S), dim3(kThreads), 0, s, (const double2*)p64,
                        (const float2*)phis, (const double*)(w + L.ws64 + L64.pst), (const float2*)gamma, fh, n,
                        list, S, alpha, (float2*)phi_io, a.pst);
-    post();
+    post(s);
   }
   if (stats)
     hipLaunchKernelGGL((bse_stats_kernel<T>), dim3((d.Nq + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
@@ -1871,10 +1924,11 @@ hipError_t launch_bse_summary(const pq_bse_block_stats* stats, int nb, double* o
 
 hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precision,
                       const void* gamma, const double2* chi0, void* phi_io, double alpha,
-                      pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm) {
+                      pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm, const BseAsync* la) {
   if (precision == PQ_PREC_FP64) {
     if (p.storage != PQ_STORE_C128) return hipErrorInvalidValue;
-    return run_bse<double>(d, channel, alpha, 1e-10f, 1e12, 0.0, 0, gamma, chi0, phi_io, stats, ws, s, tm);
+    return run_bse<double>(d, channel, alpha, 1e-10f, 1e12, 0.0, 0, gamma, chi0, phi_io, stats, ws, s, tm, nullptr,
+                           0, la);
   }
   if (p.storage != PQ_STORE_C64) return hipErrorInvalidValue;
   // complex64: a block is re-solved in FP64 when its pivot ratio drops below
@@ -1883,9 +1937,9 @@ hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precis
   const double tol = p.bse_tol > 0.0 ? p.bse_tol : kDefaultBseTol;
   if (precision == PQ_PREC_BF16X3)
     return run_bse<float, true>(d, channel, alpha, 1e-3f, 1e3, tol, p.resolve_slots, gamma, chi0, phi_io, stats, ws,
-                                s, tm);
+                                s, tm, nullptr, 0, la);
   return run_bse<float>(d, channel, alpha, 1e-3f, 1e3, tol, p.resolve_slots, gamma, chi0, phi_io, stats, ws, s, tm,
-                        nullptr, p.bse_tile);
+                        nullptr, p.bse_tile, la);
 }
 
 }  // namespace pq

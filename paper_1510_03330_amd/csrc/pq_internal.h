@@ -91,9 +91,18 @@ struct BseTiming {
   int kind[256];
   double update_flops;
 };
+// Look-ahead of the BSE elimination: a second stream and two events (created
+// by the caller, timing disabled); the next panel's diagonal-block inversion
+// runs on the second stream while the rows below it are updated. Not for work
+// captured into a graph.
+struct BseAsync {
+  hipStream_t side;
+  hipEvent_t ready, done;
+};
 hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precision,
                       const void* gamma, const double2* chi0, void* phi_io, double alpha,
-                      pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm = nullptr);
+                      pq_bse_block_stats* stats, void* ws, hipStream_t s, BseTiming* tm = nullptr,
+                      const BseAsync* la = nullptr);
 // summary of nb block stats into out[0..3]: flagged, re-solved and unresolved
 // block counts, largest error estimate (+inf for a non-finite one); with
 // nchunks > 1, over nchunks runs of nb stats, stride apart
