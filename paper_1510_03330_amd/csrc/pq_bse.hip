@@ -400,7 +400,7 @@ struct BseCtx {
   C* phi;                // [Nq][n][n]
   C* A;                  // [Nq][n][n]
   C* B;                  // [Nq][n][n]
-  C* MT;                 // [2][Nq][NB][n] multipliers, k-major (panel J in buffer J % 2; the
+  C* MT;                 // [3][Nq][NB][n] multipliers, k-major (panel J in buffer J % 3; the
                          //                kernels take the buffer of their panel)
   C* PI;                 // [Nq][NB][NB]   inverse P of the current diagonal block, transposed:
                          //                PI[k][r] = P[r][k] (k-major, like MT)
@@ -966,24 +966,26 @@ struct Tile4 : WTile<T, WM, WN> {
   template <class F> __device__ void store_c(F f) { this->store(f); }
 };
 
-template <typename T, int NB, class CF>
+template <typename T, int NB, class CF, int NK = 1>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CF::WPE)))
-void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int col_lo,
-                       const typename cplx_of<T>::type* mt0, size_t mt_bs, typename cplx_of<T>::type* mtn,
-                       int ntc, int mix_lo, int mult_row) {
+void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int col_lo, int col_hi,
+                       const typename cplx_of<T>::type* mt0, const typename cplx_of<T>::type* mt1, size_t mt_bs,
+                       typename cplx_of<T>::type* mtn, int ntc, int mix_lo, int mult_row) {
   using C = typename cplx_of<T>::type;
   static_assert(!CF::BF3 || sizeof(T) == 4, "BF16x3 products take complex64 operands");
   using M = typename std::conditional<CF::BF3, MmaBF3, Mma<T>>::type;
   using UT = typename std::conditional<
       CF::BF3, Tile3BF<CF::UWM, CF::UWN>,
       typename std::conditional<CF::M3, Tile3<T, CF::UWM, CF::UWN>, Tile4<T, CF::UWM, CF::UWN>>::type>::type;
+  static_assert(NK == 1 || CF::FULL, "a paired (rank-2NB) update takes two full panels");
   constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS, PF = CF::PF, KV = M::KV;
+  static_assert(KSTEPS % PF == 0, "the prefetch ring continues across the two panels");
   const unsigned lid = xcd_linear();
   const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
   if (inactive(a, blk)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = a.n;
-  const int jb = CF::FULL ? NB : min(NB, n - j0);
-  const int ncols = (n - j0 - jb) + n;
+  const int jb = CF::FULL ? NK * NB : min(NB, n - j0);
+  const int ncols = min((n - j0 - jb) + n, col_hi);
   const int rb = bx / ncb, cbk = bx - (bx / ncb) * ncb;
   const int wr = wave & 1, wc = wave >> 1;
   const int i0 = row_lo + rb * CF::WGM + wr * CF::UWM;
@@ -992,6 +994,7 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
   C* A = a.A + (size_t)blk * n * n;
   C* B = a.B + (size_t)blk * n * n;
   const C* MT = mt0 + (size_t)blk * mt_bs;      // multipliers, k-major with row stride n
+  const ptrdiff_t mt_delta = mt1 - mt0;         // to the second panel's (paired update; uniform)
   // Every load below is unconditional from a clamped, in-bounds address, so
   // the loads carry no branches and are issued ahead of the matrix-core work.
   // Lanes of rows or columns that are not stored read finite data that never
@@ -1023,40 +1026,49 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
   const C* abase[USR];
 #pragma unroll
   for (int xx = 0; xx < USR; ++xx) abase[xx] = MT + (size_t)ka * n + min(i0 + xx * M::TM + M::a_row(lane), n - 1);
-  // each lane takes KV consecutive k per step (1 for the FP32 / FP64 products)
-  auto fetch = [&](int ks, C (&av)[USR][KV], C (&bv)[USC][KV]) {
+  // each lane takes KV consecutive k per step (1 for the FP32 / FP64 products);
+  // panel h of a paired update: rows NB h .. of the pivot-row operand, the
+  // multipliers from the second buffer
+  auto fetch = [&](int h, int ks, C (&av)[USR][KV], C (&bv)[USC][KV]) {
 #pragma unroll
     for (int i = 0; i < KV; ++i) {
       if (CF::FULL) {
 #pragma unroll
-        for (int y = 0; y < USC; ++y) bv[y][i] = bbase[y][(size_t)(ks * M::KS + i) * n];
+        for (int y = 0; y < USC; ++y) bv[y][i] = bbase[y][(size_t)(h * NB + ks * M::KS + i) * n];
       } else {
         const int kk = min(ks * M::KS + kb + i, jb - 1);
 #pragma unroll
         for (int y = 0; y < USC; ++y) bv[y][i] = bbase[y][(size_t)kk * n];
       }
+      const ptrdiff_t ho = h ? mt_delta : 0;
 #pragma unroll
-      for (int xx = 0; xx < USR; ++xx) av[xx][i] = abase[xx][(size_t)(ks * M::KS + i) * n];
+      for (int xx = 0; xx < USR; ++xx) av[xx][i] = abase[xx][(ptrdiff_t)(ks * M::KS + i) * n + ho];
     }
   };
   C av[PF][USR][KV], bv[PF][USC][KV];
 #pragma unroll
-  for (int s = 0; s < PF; ++s) fetch(s, av[s], bv[s]);
+  for (int s = 0; s < PF; ++s) fetch(0, s, av[s], bv[s]);
 #pragma unroll
-  for (int ks = 0; ks < KSTEPS; ++ks) {
-    const int cur = ks % PF;
-    C ca[USR][KV], cbv[USC][KV];
+  for (int h = 0; h < NK; ++h) {
 #pragma unroll
-    for (int xx = 0; xx < USR; ++xx)
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+      const int cur = ks % PF;
+      C ca[USR][KV], cbv[USC][KV];
 #pragma unroll
-      for (int i = 0; i < KV; ++i) ca[xx][i] = av[cur][xx][i];
+      for (int xx = 0; xx < USR; ++xx)
 #pragma unroll
-    for (int y = 0; y < USC; ++y)
+        for (int i = 0; i < KV; ++i) ca[xx][i] = av[cur][xx][i];
 #pragma unroll
-      for (int i = 0; i < KV; ++i) cbv[y][i] = bv[cur][y][i];
-    if (ks + PF < KSTEPS) fetch(ks + PF, av[cur], bv[cur]);
-    __builtin_amdgcn_sched_barrier(0);     // keep the prefetch ahead of this step's MFMAs
-    acc.mac(ca, cbv);
+      for (int y = 0; y < USC; ++y)
+#pragma unroll
+        for (int i = 0; i < KV; ++i) cbv[y][i] = bv[cur][y][i];
+      if (ks + PF < KSTEPS)
+        fetch(h, ks + PF, av[cur], bv[cur]);
+      else if (h + 1 < NK)
+        fetch(h + 1, ks + PF - KSTEPS, av[cur], bv[cur]);
+      __builtin_amdgcn_sched_barrier(0);     // keep the prefetch ahead of this step's MFMAs
+      acc.mac(ca, cbv);
+    }
   }
   // wave-uniform (mix_lo is a multiple of the workgroup tile height); the
   // BF16x3 form never mixes here (the driver keeps its separate pass)
@@ -1106,19 +1118,21 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
 // from the transposed copy in A's rows J0 .. J0 + NB; the results of the first
 // ntc <= min(NB, n - j0 - jb) combined columns also go transposed into mtn
 // (forward step: the next panel's multipliers)
-template <typename T, int NB, class CF>
+template <typename T, int NB, class CF, int NK = 1>
 void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int row_hi, int col_lo, bool ut,
                    typename cplx_of<T>::type* mt, typename cplx_of<T>::type* mtn, int ntc, hipStream_t s,
-                   int mix_lo = -1, int mult_row = -1) {
+                   int mix_lo = -1, int mult_row = -1, int col_hi = -1,
+                   const typename cplx_of<T>::type* mt1 = nullptr) {
   const auto* mt0 = ut ? a.A + (size_t)j0 * n : mt;
   const size_t mt_bs = ut ? (size_t)n * n : (size_t)NB * n;
-  const int jb = std::min(NB, n - j0);
-  const int ncols = (n - j0 - jb) + n;
+  const int jb = std::min(NK * NB, n - j0);
+  const int ncols_all = (n - j0 - jb) + n;
+  const int ncols = col_hi < 0 ? ncols_all : std::min(col_hi, ncols_all);
   const int nrb = (row_hi - row_lo + CF::WGM - 1) / CF::WGM;
   const int ncb = (ncols - col_lo + CF::WGN - 1) / CF::WGN;
-  hipLaunchKernelGGL((bse_update_kernel<T, NB, CF>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb, row_lo,
-                     row_hi, col_lo, mt0, mt_bs, mtn ? mtn : mt, mtn ? ntc : 0, mix_lo < 0 ? n : mix_lo,
-                     mult_row < 0 ? row_lo + ntc : mult_row);
+  hipLaunchKernelGGL((bse_update_kernel<T, NB, CF, NK>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb,
+                     row_lo, row_hi, col_lo, ncols, mt0, mt1 ? mt1 : mt0, mt_bs, mtn ? mtn : mt, mtn ? ntc : 0,
+                     mix_lo < 0 ? n : mix_lo, mult_row < 0 ? row_lo + ntc : mult_row);
 }
 
 // --------------------------------------------------------------- epilogue
@@ -1599,7 +1613,7 @@ BseLayout bse_layout(const Dims& d, int slots_req) {
   auto take = [&](size_t b) { size_t o = off; off += align256(b); return o; };
   L.A = take(sizeof(C) * nn * d.Nq);
   L.B = take(sizeof(C) * nn * d.Nq);
-  L.MT = take(2 * sizeof(C) * (size_t)NB * d.n * d.Nq);     // panels alternate between two
+  L.MT = take(3 * sizeof(C) * (size_t)NB * d.n * d.Nq);     // panels rotate through three
   L.PI = take(sizeof(C) * (size_t)NB * NB * d.Nq);
   L.pst = take(sizeof(double) * kPst * (size_t)d.Nq);
   if constexpr (sizeof(T) == 4) {
@@ -1674,12 +1688,13 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     }
   };
   if (tm) tm->update_flops = 0.0;
-  // Multipliers: two buffers, panel J in buffer J % 2. The multiplier copy
-  // runs for the first panel (formed from Gamma) and a ragged last panel; every
-  // other panel's multipliers come from the previous forward update (rows
-  // below the panel) and the pivot-row steps of the earlier panels (the U
-  // entries above it, stored in A below the diagonal blocks).
-  C* mtb[2] = {a.MT, a.MT + (size_t)NB * n * d.Nq};
+  // Multipliers: three buffers, panel J in buffer J % 3 (a paired update of
+  // panels J and J + 1 reads both while writing panel J + 2's). The
+  // multiplier copy runs for the first panel (formed from Gamma) and a ragged
+  // last panel; every other panel's multipliers come from the previous forward
+  // update (rows below the panel) and the pivot-row steps of the earlier
+  // panels (the U entries above it, stored in A below the diagonal blocks).
+  C* mtb[3] = {a.MT, a.MT + (size_t)NB * n * d.Nq, a.MT + 2 * (size_t)NB * n * d.Nq};
   const int last = (a.nJ - 1) * NB;
   // The mixing is fused into the kernels that finish rows of F: the
   // back-substitution launch of panel J for the rows of panel J - 1, the last
@@ -1719,7 +1734,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     hipLaunchKernelGGL((bse_pivot_kernel<T, NB>), dim3(1, d.Nq), dim3(pivot_threads<NB>()), 0, st, a, j0);
     if (j0 == 0 || jb < NB) {
       BseCtx<T> am = a;
-      am.MT = mtb[pj & 1];
+      am.MT = mtb[pj % 3];
       hipLaunchKernelGGL((bse_multcopy_kernel<T, NB>), dim3((n + 31) / 32, d.Nq), dim3(kThreads), 0, st, am, j0);
     }
     post(st);
@@ -1739,41 +1754,53 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
                          mix);
     post(st);
   };
-  // forward step of the panel at j0 for rows [row_lo, row_hi) below it; the
-  // multiplier rows of the next panel start at mult_row
-  auto fwd_update = [&](int j0, int row_lo, int row_hi, int mult_row) {
-    const int jb = std::min(NB, n - j0);
-    const int ncols = (n - j0 - jb) + n;
-    const int pj = j0 / NB;
-    const int lo = j0 + jb;
-    C* mt = mtb[pj & 1];
-    C* mtn = mtb[(pj + 1) & 1];
-    const int ntc = std::min(NB, n - lo);      // the next panel's columns
+  // Paired updates on the FP32 and FP64 products; the BF16x3 update holds its
+  // three accumulators at one wave per SIMD and spills with the longer loop.
+  constexpr bool kPair = !BF3;
+  // Forward update of NKP panels from j0 (1, or 2 for a paired rank-2NB
+  // update) for rows [row_lo, row_hi) and the combined columns below col_hi
+  // (the trailing columns right of the panels, then B); the results in the
+  // first ntc columns of the rows from mult_row on are the multipliers of the
+  // panel after them, written transposed into mtn.
+  auto upd = [&](int j0, int nkp, int row_lo, int row_hi, int col_hi, int mult_row, C* mt, C* mt1, C* mtn,
+                 int ntc) {
+    const int jb = std::min(nkp * NB, n - j0);
+    const int ncols = std::min((n - j0 - jb) + n, col_hi < 0 ? n + n : col_hi);
     pre(3, s);
-    if constexpr (sizeof(T) == 4 && !BF3) {
-      if (tile == 1) {
-        if (j0 == 0)
-          launch_update<T, NB, UpdFirst<UpdNarrow<true>>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s,
-                                                           -1, mult_row);
-        else
-          launch_update<T, NB, UpdNarrow<true>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1,
-                                                mult_row);
+    auto go = [&](auto cfg_first, auto cfg) {
+      using CFF = decltype(cfg_first);
+      using CFG = decltype(cfg);
+      if (kPair && nkp == 2) {
+        if constexpr (kPair) {
+          if (j0 == 0)
+            launch_update<T, NB, CFF, 2>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1, mult_row,
+                                         col_hi, mt1);
+          else
+            launch_update<T, NB, CFG, 2>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1, mult_row,
+                                         col_hi, mt1);
+        }
       } else if (j0 == 0) {
-        launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc,
-                                                              s, -1, mult_row);
+        launch_update<T, NB, CFF>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1, mult_row, col_hi);
       } else {
-        launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1,
-                                                    mult_row);
+        launch_update<T, NB, CFG>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1, mult_row, col_hi);
       }
-    } else if (j0 == 0) {
-      launch_update<T, NB, UpdFirst<UpdSel<T, true, BF3>>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s,
-                                                            -1, mult_row);
+    };
+    if constexpr (sizeof(T) == 4 && !BF3) {
+      if (tile == 1)
+        go(UpdFirst<UpdNarrow<true>>{}, UpdNarrow<true>{});
+      else
+        go(UpdFirst<UpdSel<T, true, BF3>>{}, UpdSel<T, true, BF3>{});
     } else {
-      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1,
-                                                  mult_row);
+      go(UpdFirst<UpdSel<T, true, BF3>>{}, UpdSel<T, true, BF3>{});
     }
     post(s);
     if (tm) tm->update_flops += 8.0 * (double)(row_hi - row_lo) * ncols * jb * d.Nq;
+  };
+  auto side_pivot = [&](int j0) {
+    hipEventRecord(la->ready, s);
+    hipStreamWaitEvent(la->side, la->ready, 0);
+    pivot_step(j0, la->side);
+    hipEventRecord(la->done, la->side);
   };
   // Look-ahead (a second stream given): once the rows of the next panel are
   // updated, its diagonal-block inversion runs on the second stream while the
@@ -1784,31 +1811,62 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   // into the rows below, whose old values this update still reads.) Only for a
   // full next panel with rows below it (a ragged one has a multiplier copy,
   // which shares its buffer with the update's multiplier output).
+  //
+  // Paired panels: for two full panels J, J + 1 with rows below them, the
+  // rows of J + 1 (every column) and the columns of J + 1 (the rows below it:
+  // its multipliers) are updated by panel J first; J + 1 is then inverted and
+  // its pivot rows formed; and the rest, the rows below J + 1 right of it, is
+  // updated by both panels at once (depth 2 NB). The flops are those of two
+  // single updates; the C tiles of the rows below are read and written once
+  // instead of twice.
   bool ahead = false;
-  for (int j0 = 0; j0 < n; j0 += NB) {
+  int j0 = 0;
+  while (j0 < n) {
     const int jb = std::min(NB, n - j0);
+    const int pj = j0 / NB;
     if (ahead)
       hipStreamWaitEvent(s, la->done, 0);
     else
       pivot_step(j0, s);
     panel_step(j0, s);
     ahead = false;
-    // forward step: the rows below the panel (none below the last one)
-    if (j0 + jb < n) {
-      const int lo = j0 + jb;
-      const int mult_row = lo + std::min(NB, n - lo);
-      if (la && lo + NB < n) {
-        fwd_update(j0, lo, lo + NB, mult_row);
-        hipEventRecord(la->ready, s);
-        hipStreamWaitEvent(la->side, la->ready, 0);
-        pivot_step(lo, la->side);
-        hipEventRecord(la->done, la->side);
-        fwd_update(j0, lo + NB, n, mult_row);
+    if (j0 + jb >= n) break;                   // the last panel: no rows below
+    const int lo = j0 + jb;                    // the next panel's first row
+    if (kPair && jb == NB && lo + NB < n) {    // pair panels J and J + 1
+      const int hi = lo + NB;                  // the rows below J + 1 start here
+      upd(j0, 1, lo, hi, -1, hi, mtb[pj % 3], nullptr, mtb[(pj + 1) % 3], NB);
+      if (la) side_pivot(lo);
+      upd(j0, 1, hi, n, NB, hi, mtb[pj % 3], nullptr, mtb[(pj + 1) % 3], NB);
+      if (la)
+        hipStreamWaitEvent(s, la->done, 0);
+      else
+        pivot_step(lo, s);
+      panel_step(lo, s);
+      const int ntc = std::min(NB, n - hi);    // panel J + 2's columns
+      const int mrow = hi + ntc;
+      if (la && hi + NB < n) {
+        upd(j0, 2, hi, hi + NB, -1, mrow, mtb[pj % 3], mtb[(pj + 1) % 3], mtb[(pj + 2) % 3], ntc);
+        side_pivot(hi);
+        upd(j0, 2, hi + NB, n, -1, mrow, mtb[pj % 3], mtb[(pj + 1) % 3], mtb[(pj + 2) % 3], ntc);
         ahead = true;
       } else {
-        fwd_update(j0, lo, n, mult_row);
+        upd(j0, 2, hi, n, -1, mrow, mtb[pj % 3], mtb[(pj + 1) % 3], mtb[(pj + 2) % 3], ntc);
       }
+      j0 = hi;
+      continue;
     }
+    // a single panel: the rows below it
+    const int ntc = std::min(NB, n - lo);
+    const int mrow = lo + ntc;
+    if (la && lo + NB < n) {
+      upd(j0, 1, lo, lo + NB, -1, mrow, mtb[pj % 3], nullptr, mtb[(pj + 1) % 3], ntc);
+      side_pivot(lo);
+      upd(j0, 1, lo + NB, n, -1, mrow, mtb[pj % 3], nullptr, mtb[(pj + 1) % 3], ntc);
+      ahead = true;
+    } else {
+      upd(j0, 1, lo, n, -1, mrow, mtb[pj % 3], nullptr, mtb[(pj + 1) % 3], ntc);
+    }
+    j0 = lo;
   }
   // Back substitution: the rows of panel J of B hold F once every later panel
   // has been subtracted from them, so going from the last panel down, the
@@ -1826,7 +1884,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
       launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s,
                                                   mix_lo);
     else
-      launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, false, mtb[(j0 / NB) & 1],
+      launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, false, mtb[(j0 / NB) % 3],
                                                    nullptr, 0, s, mix_lo);
     post(s);
     if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
