@@ -1874,20 +1874,53 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   // below the diagonal blocks (full panels) or from the multiplier copy of a
   // ragged last panel. The rows of panel J - 1 are final after the launch of
   // panel J, which also mixes them into Phi.
-  for (int j0 = last; j0 > 0; j0 -= NB) {
-    const int jb = std::min(NB, n - j0);
-    const int mix_lo = kFuseMix ? j0 - NB : -1;
+  // Paired (two full panels J - 1, J with rows above them): the rows of
+  // J - 1 take panel J alone (and are mixed), then every row above J - 1
+  // takes both panels at depth 2 NB (their U copies are adjacent rows of A,
+  // their F adjacent rows of B) and the rows of J - 2 are mixed.
+  auto back = [&](auto cfg, int nkp, int jp, int row_lo, int row_hi, int mix_lo) {
+    using CFG = decltype(cfg);
+    const int jb = std::min(nkp * NB, n - jp);
     pre(3, s);
-    if (jb == NB && sizeof(T) == 4 && !BF3 && tile == 1)
-      launch_update<T, NB, UpdNarrow<true>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s, mix_lo);
-    else if (jb == NB)
-      launch_update<T, NB, UpdSel<T, true, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, true, a.MT, nullptr, 0, s,
-                                                  mix_lo);
-    else
+    if (nkp == 2) {
+      if constexpr (kPair)
+        launch_update<T, NB, CFG, 2>(a, n, d.Nq, jp, row_lo, row_hi, n - jp - jb, true, a.MT, nullptr, 0, s, mix_lo,
+                                     -1, -1, a.A + (size_t)(jp + NB) * n);
+    } else {
+      launch_update<T, NB, CFG>(a, n, d.Nq, jp, row_lo, row_hi, n - jp - jb, true, a.MT, nullptr, 0, s, mix_lo);
+    }
+    post(s);
+    if (tm) tm->update_flops += 8.0 * (double)(row_hi - row_lo) * n * jb * d.Nq;
+  };
+  auto back_full = [&](int nkp, int jp, int row_lo, int row_hi, int mix_lo) {
+    if constexpr (sizeof(T) == 4 && !BF3) {
+      if (tile == 1) {
+        back(UpdNarrow<true>{}, nkp, jp, row_lo, row_hi, mix_lo);
+        return;
+      }
+    }
+    back(UpdSel<T, true, BF3>{}, nkp, jp, row_lo, row_hi, mix_lo);
+  };
+  for (int j0 = last; j0 > 0;) {
+    const int jb = std::min(NB, n - j0);
+    if (jb == NB && kPair && j0 - NB > 0) {
+      const int j1 = j0 - NB;
+      back_full(1, j0, j1, j0, kFuseMix ? j1 : -1);
+      back_full(2, j1, 0, j1, kFuseMix ? j1 - NB : -1);
+      j0 -= 2 * NB;
+      continue;
+    }
+    const int mix_lo = kFuseMix ? j0 - NB : -1;
+    if (jb == NB) {
+      back_full(1, j0, 0, j0, mix_lo);
+    } else {
+      pre(3, s);
       launch_update<T, NB, UpdSel<T, false, BF3>>(a, n, d.Nq, j0, 0, j0, n - j0 - jb, false, mtb[(j0 / NB) % 3],
                                                    nullptr, 0, s, mix_lo);
-    post(s);
-    if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
+      post(s);
+      if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
+    }
+    j0 -= NB;
   }
   if (!kFuseMix) {            // every row in a separate pass
     pre(4, s);
