@@ -836,9 +836,9 @@ def main():
             "achieved_counts": "algorithmic-equivalent: 8 flops per complex multiply-add; the kernel forms each "
                                "product from three real matrix products (6 flops)",
             "mfma_util": (round(mfma_util / 100.0, 4) if mfma_util is not None else None),
-            "kernel": "bse_update_kernel<float,128> (one launch = one rank-128 update of %d blocks, n=%d: "
-                      "the rows below a panel in the forward sweep or the rows above it in the back "
-                      "substitution)" % (d.Nq, d.n),
+            "kernel": "bse_update_kernel<float,128> (one launch = an update of %d blocks, n=%d, at depth 128 or, "
+                      "for paired panels, 256: rows below the panels in the forward sweep, rows above them in "
+                      "the back substitution)" % (d.Nq, d.n),
             "avg_launch_ms": round(upd_ms, 3), "flops_per_launch": upd_flops,
             "bse_solve_lu_equivalent_tflops": round(bse_alg, 2),
             "bse_solve_ms_per_channel": round(bse_channel_ms, 2),
