@@ -246,6 +246,39 @@ def bse_microbench(reps: int = 5, stress_lam: float = 0.99):
     return out
 
 
+def tail_study():
+    """The self-energy tail: nu Im Sigma(i nu) -> -U^2 n_s (1 - n_s) = -U^2 / 4
+    at half filling, at the local problem's parameters (U = 1, beta = 5,
+    Nv = 32, complex128, to a change below 1e-10), for every kernel level with
+    and without the regulation (regulated: Sigma on the extended box f = 2;
+    plain: the box only)."""
+    import math as _m
+    from paper_1510_03330_amd.ops import Solver
+    from workloads import config
+
+    out = []
+    tail_base = config("c1").replace(tol=1e-10)
+    for level in (0, 1, 2):
+        for reg, f_ext in ((1, 2), (0, 1)):
+            print(f"[study] tail level {level} regulation {reg}", file=sys.stderr, flush=True)
+            p = tail_base.replace(kernel_level=level, regulation=reg, f_ext=f_ext)
+            s = Solver(p, "fp64", device="cuda:0")
+            done, conv, st = s.iterate(400, p.tol)
+            sig = s.get("sigma").cpu().numpy()[:, 0]
+            s.close()
+            ne = sig.shape[0]
+            nus = [(2 * (i - ne // 2) + 1) * _m.pi / p.beta for i in range(ne)]
+            c_exact = -p.U ** 2 / 4.0
+            box_edge = ne // 2 + p.Nv // 2 - 1               # the last box frequency
+            out.append({"kernel_level": level, "regulation": reg, "f_ext": f_ext, "converged": bool(conv),
+                        "iterations": done, "exact": c_exact,
+                        "nu_im_sigma": {round(nus[i], 3): round(float(nus[i] * sig[i].imag), 5)
+                                        for i in range(ne // 2, ne) if (i - ne // 2) % 4 == 3 or i == ne - 1},
+                        "box_edge_rel_error": round(float(nus[box_edge] * sig[box_edge].imag / c_exact - 1.0), 5),
+                        "last_rel_error": round(float(nus[-1] * sig[-1].imag / c_exact - 1.0), 5)})
+    return out
+
+
 def kernel_study(max_iter: int = 600, tol: float = 1e-8, chunk: int = 10):
     """Kernel-level and regulation ablation on synthetic inputs, after the
     paper's convergence claims for its local validation problem: the
@@ -295,29 +328,7 @@ def kernel_study(max_iter: int = 600, tol: float = 1e-8, chunk: int = 10):
     out = {"study": "kernel level / regulation box / U range, local model with a semicircle bath (D=2), "
                     "beta=2, half filling, complex128",
            "max_iter": max_iter, "tol": tol, "u_range": [], "box_convergence": [], "tail": []}
-    # the self-energy tail: nu Im Sigma(i nu) -> -U^2 n_s (1 - n_s) = -U^2 / 4 at half filling, at the
-    # local problem's parameters (U = 1, beta = 5, Nv = 32), for every kernel level with and without
-    # the regulation (regulated: Sigma on the extended box f = 2; plain: the box only)
-    tail_base = config("c1").replace(tol=1e-10)
-    for level in (0, 1, 2):
-        for reg, f_ext in ((1, 2), (0, 1)):
-            print(f"[study] tail level {level} regulation {reg}", file=sys.stderr, flush=True)
-            p = tail_base.replace(kernel_level=level, regulation=reg, f_ext=f_ext)
-            s = Solver(p, "fp64", device="cuda:0")
-            done, conv, st = s.iterate(400, p.tol)
-            sig = s.get("sigma").cpu().numpy()[:, 0]
-            s.close()
-            ne = sig.shape[0]
-            nus = [(2 * (i - ne // 2) + 1) * _m.pi / p.beta for i in range(ne)]
-            c_exact = -p.U ** 2 / 4.0
-            box_edge = ne // 2 + p.Nv // 2 - 1               # the last box frequency
-            rec = {"kernel_level": level, "regulation": reg, "f_ext": f_ext, "converged": bool(conv),
-                   "iterations": done, "exact": c_exact,
-                   "nu_im_sigma": {round(nus[i], 3): round(float(nus[i] * sig[i].imag), 5)
-                                   for i in range(ne // 2, ne) if (i - ne // 2) % 4 == 3 or i == ne - 1},
-                   "box_edge_rel_error": round(float(nus[box_edge] * sig[box_edge].imag / c_exact - 1.0), 5),
-                   "last_rel_error": round(float(nus[-1] * sig[-1].imag / c_exact - 1.0), 5)}
-            out["tail"].append(rec)
+    out["tail"] = tail_study()
     for alpha in (0.3, 0.1):
         for level, f_ext, reg in ((0, 2, 1), (1, 2, 1), (2, 2, 1), (2, 1, 1), (2, 1, 0), (0, 1, 0)):
             for U in (2.0, 2.5, 3.0, 3.5, 4.0):
@@ -333,7 +344,7 @@ def kernel_study(max_iter: int = 600, tol: float = 1e-8, chunk: int = 10):
     return out
 
 
-def batch_study(tol: float = -1e-6, max_iter: int = 150, diverge: float = 1e2, serial: bool = True):
+def batch_study(tol: float = -1e-6, max_iter: int = 150, diverge: float = 1e2, serial: bool = True, nvs=None):
     """Many independent instances on one GPU: 64 seeded draws of the 4x4
     lattice (t = 1, t' = 0; one PCG64(4) stream: U in [0.5, 3], beta in
     [2, 8], filling in [0.8, 1] reached by bisection, Nv in {8, 16, 24, 32},
@@ -344,13 +355,16 @@ def batch_study(tol: float = -1e-6, max_iter: int = 150, diverge: float = 1e2, s
     sequence per channel over every active (instance, q) block, one HIP graph
     per round, update tile chosen by timing at set-up). Serial: the same
     instances one after another in their own contexts, stopped at the same
-    iteration. Also the previous form, concurrent graph replay of contexts."""
+    iteration. nvs: only the draws with these box sizes (the same seeded
+    stream)."""
     import torch
     from paper_1510_03330_amd.native import ParquetError
     from paper_1510_03330_amd.ops import Solver, run_batched
     from workloads import batch_draws
 
     params = batch_draws(64, seed=4)
+    if nvs is not None:
+        params = [p for p in params if p.Nv in nvs]
     print("[batch] batched solver", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -380,7 +394,7 @@ def batch_study(tol: float = -1e-6, max_iter: int = 150, diverge: float = 1e2, s
             torch.cuda.synchronize()
             serial_by_nv[p.Nv] = serial_by_nv.get(p.Nv, 0.0) + time.perf_counter() - ti
             if k % 8 == 7:
-                print(f"[batch] serial {k + 1}/64", file=sys.stderr, flush=True)
+                print(f"[batch] serial {k + 1}/{len(params)}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t_serial = time.perf_counter() - t0
         torch.cuda.empty_cache()
@@ -393,8 +407,9 @@ def batch_study(tol: float = -1e-6, max_iter: int = 150, diverge: float = 1e2, s
         e["failed"] += int(r["state"] in ("nonfinite", "singular"))
         e["iterations"] += r["iterations"]
     out = {"mode": "batch",
-           "workload": "64 seeded instances (PCG64(4)): 4x4 lattice, t'=0, U in [0.5,3], beta in [2,8], "
-                       "n in [0.8,1] by bisection, Nv in {8,16,24,32}; fp32",
+           "workload": "%d seeded instances (PCG64(4), 64 drawn%s): 4x4 lattice, t'=0, U in [0.5,3], beta in "
+                       "[2,8], n in [0.8,1] by bisection, Nv in {8,16,24,32}; fp32"
+                       % (len(params), "" if nvs is None else ", those with Nv in %s kept" % list(nvs)),
            "tol": tol, "max_iter": max_iter, "diverge": diverge,
            "batched_sec": round(t_batch, 3), "batched_instance_iterations": iters,
            "batched_instance_iterations_per_s": round(iters / t_batch, 2), "batches": batches,
@@ -580,6 +595,34 @@ class _VirtualVertex:
             h = (q * 1000003 + a * 7919 + b * 104729 + self.r * 15485863) % 2147483647
             return (np.sin(h * 1e-3) + 1j * np.cos(h * 1.7e-3)) * 0.05
         raise TypeError("unsupported index")
+
+
+def short_studies():
+    """Short forms of the extension studies for the default run (each has a
+    mode of its own for the full form): the learned warm start on the local
+    problem (48 training draws, 8 held out), the batched solver on the Nv = 8
+    instances of the seeded 64-instance workload against the same instances
+    one by one, and the self-energy tail with and without the regulation."""
+    import torch
+    out = {}
+    print("[bench] studies: warm start (local problem)", file=sys.stderr, flush=True)
+    w = warmstart_study("local", n_train=48, n_held=8)
+    out["warmstart_local"] = {k: w[k] for k in ("workload", "network", "inputs", "train_samples", "train_sec",
+                                                "held_out", "iterations_bare_mean", "iterations_warm_mean",
+                                                "iterations_ratio_mean", "iterations_from_exact_kernels_mean",
+                                                "sec_bare_total", "sec_warm_total", "all_converged", "fallbacks")}
+    torch.cuda.empty_cache()
+    print("[bench] studies: batched instances (Nv = 8)", file=sys.stderr, flush=True)
+    b = batch_study(nvs=(8,))
+    out["batch_nv8"] = {k: b[k] for k in ("workload", "batched_sec", "batched_instance_iterations",
+                                          "batched_instance_iterations_per_s", "serial_sec",
+                                          "serial_instance_iterations_per_s", "speedup_vs_serial", "converged")}
+    out["batch_nv8"]["tile"] = b["batches"][0]["tile"] if b["batches"] else None
+    torch.cuda.empty_cache()
+    print("[bench] studies: self-energy tail", file=sys.stderr, flush=True)
+    out["tail"] = [{k: r[k] for k in ("kernel_level", "regulation", "f_ext", "converged", "exact",
+                                      "box_edge_rel_error", "last_rel_error")} for r in tail_study()]
+    return out
 
 
 def cpu_baseline(p):
@@ -772,6 +815,9 @@ def main():
     ap.add_argument("--no-ttc", action="store_true",
                     help="skip the time-to-converged-Sigma (1e-6) runs of both paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the short extension studies of the default run (warm start on the local problem, "
+                         "batched Nv=8 instances, the self-energy tail with and without the regulation)")
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 2 GiB device copy first (reference for HBM counters)")
@@ -936,6 +982,8 @@ def main():
     if not args.no_microbench:
         print("[bench] BSE microbenchmark (4x4, Nv=16)", file=sys.stderr, flush=True)
         out["bse_microbench_4x4_nv16"] = bse_microbench()
+    if not args.no_studies:
+        out["studies"] = short_studies()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)
