@@ -33,10 +33,11 @@
 // triangular solves; full Gauss-Jordan, which also clears U, would take
 // 1.5 n^3. B then holds F. The mixing Phi <- alpha (F - Gamma) + (1 - alpha)
 // Phi is done by each back-substitution launch for the rows it finishes (the
-// panel above), and by the last panel's pivot-row step for its own rows
-// (BF16x3 products: by bse_epilogue for every row). Steps (b) and (c) are complex
-// products on the matrix cores (v_mfma_f32_32x32x2f32 for complex64,
-// v_mfma_f64_16x16x4f64 for complex128).
+// panel above), and by the last panel's pivot-row step for its own rows.
+// Steps (b) and (c) are complex products on the matrix cores
+// (v_mfma_f32_32x32x2f32 for complex64, v_mfma_f64_16x16x4f64 for complex128;
+// with BF16x3 products, (c) runs on v_mfma_f32_32x32x16_bf16 from operands
+// split in LDS, bse_update_bf_kernel).
 //
 // No row exchanges: A is the identity minus the small-norm kernel s Gamma X,
 // and every leading principal block of it stays invertible while the BSE is
@@ -109,14 +110,6 @@ struct MmaBF3 {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
 };
-
-// v = hi + lo + r with hi = bf16(v), lo = bf16(v - hi) (round to nearest) and
-// |r| <= 2^-18 |v|; a product ab is then hi_a hi_b + hi_a lo_b + lo_a hi_b up
-// to ~3 2^-18 |ab| (the lo_a lo_b term and the remainders are dropped)
-__device__ inline void split_bf16(float v, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)v;
-  lo = (__bf16)(v - (float)hi);
-}
 
 // A WM x WN complex output tile owned by one wave (default 32 x 32).
 template <typename T, int WM = 32, int WN = 32>
@@ -250,93 +243,6 @@ struct Tile3 {
           c.y = x1[a][b][v] + x2[a][b][v];
           f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l), c);
         }
-  }
-  template <class F> __device__ void store_c(F f) {    // C - ab = (X3 - X1, -X1 - X2)
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int a = 0; a < SR; ++a)
-#pragma unroll
-      for (int b = 0; b < SC; ++b)
-#pragma unroll
-        for (int v = 0; v < M::NV; ++v) {
-          C c;
-          c.x = x3[a][b][v] - x1[a][b][v];
-          c.y = -x1[a][b][v] - x2[a][b][v];
-          f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l), c);
-        }
-  }
-};
-
-// Three-product complex tile (as Tile3) on BF16x3 split products, complex64
-// operands: X1 += (ar + ai) br, X2 += ar (bi - br), X3 += ai (br + bi), each
-// real product as three bf16 matrix-core products with FP32 accumulation.
-template <int WM, int WN>
-struct Tile3BF {
-  using M = MmaBF3;
-  using C = float2;
-  static constexpr int SR = WM / M::TM, SC = WN / M::TN;
-  M::acc_t x1[SR][SC], x2[SR][SC], x3[SR][SC];
-  template <class F> __device__ void load_c(F f) {     // X1 = 0, X2 = -Im C, X3 = Re C
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int a = 0; a < SR; ++a)
-#pragma unroll
-      for (int b = 0; b < SC; ++b)
-#pragma unroll
-        for (int v = 0; v < M::NV; ++v) {
-          const C c = f(a * M::TM + M::c_row(l, v), b * M::TN + M::c_col(l));
-          x1[a][b][v] = 0.f;
-          x2[a][b][v] = -c.y;
-          x3[a][b][v] = c.x;
-        }
-  }
-  __device__ void mac(const C (&av)[SR][M::KV], const C (&bv)[SC][M::KV]) {
-    bf16x8 sh[SR], sl[SR], rh[SR], rl[SR], ih[SR], il[SR];
-#pragma unroll
-    for (int x = 0; x < SR; ++x)
-#pragma unroll
-      for (int i = 0; i < M::KV; ++i) {
-        __bf16 h, lo;
-        split_bf16(av[x][i].x + av[x][i].y, h, lo);
-        sh[x][i] = h;
-        sl[x][i] = lo;
-        split_bf16(av[x][i].x, h, lo);
-        rh[x][i] = h;
-        rl[x][i] = lo;
-        split_bf16(av[x][i].y, h, lo);
-        ih[x][i] = h;
-        il[x][i] = lo;
-      }
-    bf16x8 bh[SC], bl[SC], dh[SC], dl[SC], eh[SC], el[SC];
-#pragma unroll
-    for (int y = 0; y < SC; ++y)
-#pragma unroll
-      for (int i = 0; i < M::KV; ++i) {
-        __bf16 h, lo;
-        split_bf16(bv[y][i].x, h, lo);
-        bh[y][i] = h;
-        bl[y][i] = lo;
-        split_bf16(bv[y][i].y - bv[y][i].x, h, lo);
-        dh[y][i] = h;
-        dl[y][i] = lo;
-        split_bf16(bv[y][i].x + bv[y][i].y, h, lo);
-        eh[y][i] = h;
-        el[y][i] = lo;
-      }
-#pragma unroll
-    for (int x = 0; x < SR; ++x)
-#pragma unroll
-      for (int y = 0; y < SC; ++y) {
-        x1[x][y] = M::mma(sl[x], bh[y], x1[x][y]);
-        x1[x][y] = M::mma(sh[x], bl[y], x1[x][y]);
-        x1[x][y] = M::mma(sh[x], bh[y], x1[x][y]);
-        x2[x][y] = M::mma(rl[x], dh[y], x2[x][y]);
-        x2[x][y] = M::mma(rh[x], dl[y], x2[x][y]);
-        x2[x][y] = M::mma(rh[x], dh[y], x2[x][y]);
-        x3[x][y] = M::mma(il[x], eh[y], x3[x][y]);
-        x3[x][y] = M::mma(ih[x], el[y], x3[x][y]);
-        x3[x][y] = M::mma(ih[x], eh[y], x3[x][y]);
-      }
   }
   template <class F> __device__ void store_c(F f) {    // C - ab = (X3 - X1, -X1 - X2)
     const int l = threadIdx.x & 63;
@@ -886,8 +792,9 @@ void bse_panel_kernel(BseCtx<T> a, int j0, int nwb, int mix) {
 // multiplier rows start) is stored in A as usual. A forward step may be split
 // by rows (the next panel's rows first), mult_row staying the same.
 // In the back substitution the rows mix_lo .. row_hi (the panel above, whose F
-// is final after this launch) are also mixed into Phi as they are stored (the
-// epilogue's formula; B keeps F, the next launch's operand).
+// is final after this launch) are also mixed into Phi as they are stored
+// (Phi <- alpha (F - Gamma) + (1 - alpha) Phi; B keeps F, the next launch's
+// operand).
 // Tile shape and pipelining of the update: wave tile UWM x UWN, workgroup of
 // 2 x 2 waves, operand prefetch PF k-steps ahead; FULL = the panel is NB wide
 // (every panel but a ragged last one), so the panel rows need no clamping.
@@ -938,13 +845,14 @@ using UpdDefault = typename std::conditional<
                               UpdCfg<T, 64, 32, 2, 3, false, true, false, true>>::type,
     UpdCfg<T, 32, 32, 1, 2, FULL, true, false, true>>::type;
 
-// BF16x3 update (complex64 operands split into bf16 pairs in registers): the
-// 64 x 64 wave tile holds its three accumulators (192 registers) plus the split
-// operands, one wave per SIMD
+// BF16x3 update of full panels: bse_update_bf_kernel (LDS-staged operands,
+// 64 x 64 wave tiles in a 128 x 128 workgroup tile; the UWM / UWN / FIRST /
+// BF3 fields of this configuration select and shape it, the others are
+// unused). A ragged last panel's update takes the complex64 FP32 products.
 template <bool FULL>
-using UpdBF3 = UpdCfg<float, 64, 64, 1, 1, FULL, true, false, true, true>;
+using UpdBF3 = UpdCfg<float, 64, 64, 1, 2, FULL, false, false, true, true>;
 template <typename T, bool FULL, bool BF3>
-using UpdSel = typename std::conditional<BF3, UpdBF3<FULL>, UpdDefault<T, FULL>>::type;
+using UpdSel = typename std::conditional<BF3 && FULL, UpdBF3<FULL>, UpdDefault<T, FULL>>::type;
 // the narrow complex64 tile (bse_tile = 1): 64 x 32 per wave, three waves per
 // SIMD, twice the workgroups of the default for the same update
 template <bool FULL>
@@ -972,11 +880,9 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
                        const typename cplx_of<T>::type* mt0, const typename cplx_of<T>::type* mt1, size_t mt_bs,
                        typename cplx_of<T>::type* mtn, int ntc, int mix_lo, int mult_row) {
   using C = typename cplx_of<T>::type;
-  static_assert(!CF::BF3 || sizeof(T) == 4, "BF16x3 products take complex64 operands");
-  using M = typename std::conditional<CF::BF3, MmaBF3, Mma<T>>::type;
-  using UT = typename std::conditional<
-      CF::BF3, Tile3BF<CF::UWM, CF::UWN>,
-      typename std::conditional<CF::M3, Tile3<T, CF::UWM, CF::UWN>, Tile4<T, CF::UWM, CF::UWN>>::type>::type;
+  static_assert(!CF::BF3, "the BF16x3 products have their own kernel");
+  using M = Mma<T>;
+  using UT = typename std::conditional<CF::M3, Tile3<T, CF::UWM, CF::UWN>, Tile4<T, CF::UWM, CF::UWN>>::type;
   static_assert(NK == 1 || CF::FULL, "a paired (rank-2NB) update takes two full panels");
   constexpr int USR = UT::SR, USC = UT::SC, KSTEPS = NB / M::KS, PF = CF::PF, KV = M::KV;
   static_assert(KSTEPS % PF == 0, "the prefetch ring continues across the two panels");
@@ -1070,9 +976,8 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
       acc.mac(ca, cbv);
     }
   }
-  // wave-uniform (mix_lo is a multiple of the workgroup tile height); the
-  // BF16x3 form never mixes here (the driver keeps its separate pass)
-  if (!CF::BF3 && i0 >= mix_lo) {
+  // wave-uniform (mix_lo is a multiple of the workgroup tile height)
+  if (i0 >= mix_lo) {
     const int ncolA = n - j0 - jb;                 // B column = combined column - ncolA
     const C* G = a.gamma + (size_t)blk * n * n;
     C* P = a.phi + (size_t)blk * n * n;
@@ -1112,6 +1017,230 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
   });
 }
 
+// ------------------------------------------------------ BF16x3 update
+// The update above, C -= sum_k MT[k][i] R[k][col], on the bf16 matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation) for complex64 operands. Each
+// complex product takes four real products,
+//   Re C += (-ar) br + ai bi,   Im C += (-ar) bi + (-ai) br,
+// and each real product x y the bf16 splits x = xh + xl + O(2^-18 |x|)
+// (xh = bf16(x), xl = bf16(x - xh), round to nearest) as xh yh + xh yl + xl yh.
+// A workgroup owns a 128 x 128 tile (2 x 2 waves of 64 x 64, two 32 x 32
+// accumulator pairs per wave row and column). Per 16-deep step its 256 threads
+// load the 128 x 16 slabs of both operands once (thread t: row or column
+// t % 128, the eight k of half t / 128; each load instruction reads 64
+// consecutive elements of one k row), split them and store the bf16 halves in
+// LDS in the operand order of the instruction (lane l: row or column l % 32,
+// k = 8 (l / 32) .. + 7, one 16-byte run per lane), double buffered with one
+// barrier per step; each wave then reads an operand fragment with one 16-byte
+// LDS load. The split is done once per workgroup, not once per wave. The next
+// step's global loads are issued before this step's products. The store phase
+// (mixing of finished rows, the next panel's multipliers) is that of the FP32
+// kernel.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)v[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(v[e] - (float)h);
+  }
+}
+
+__device__ inline bf16x8 neg8(bf16x8 x) {       // exact: sign bits only
+  u32x4 u = __builtin_bit_cast(u32x4, x);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+template <int NB, int NK, bool FIRST>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void bse_update_bf_kernel(BseCtx<float> a, int j0, int ncb, int row_lo, int row_hi, int col_lo, int col_hi,
+                          const float2* mt0, const float2* mt1, size_t mt_bs, float2* mtn, int ntc, int mix_lo,
+                          int mult_row) {
+  using C = float2;
+  using M = MmaBF3;
+  constexpr int WG = 128, SPP = NB / M::KS, KSTEPS = NK * SPP;
+  static_assert(NB % M::KS == 0 && kThreads == 2 * WG, "one staging row per thread and k half");
+  // [buffer][operand: multipliers, pivot rows][component][32-row / column group][lane];
+  // components: multipliers -Re hi, lo, Im hi, lo; pivot rows Re hi, lo, Im hi, lo
+  __shared__ bf16x8 sm[2][2][4][4][64];
+  const unsigned lid = xcd_linear();
+  const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
+  if (inactive(a, blk)) return;                  // uniform over the workgroup
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
+  constexpr int jb = NK * NB;
+  const int ncols = min((n - j0 - jb) + n, col_hi);
+  const int rb = bx / ncb, cbk = bx - (bx / ncb) * ncb;
+  const int R0 = row_lo + rb * WG, C0 = col_lo + cbk * WG;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int i0 = R0 + wr * 64, c0 = C0 + wc * 64;
+  // every wave takes part in the staging and the barriers; a wave whose tile
+  // lies outside the rows or columns skips only its products and stores
+  const bool live = i0 < row_hi && c0 < ncols;
+  C* A = a.A + (size_t)blk * n * n;
+  C* B = a.B + (size_t)blk * n * n;
+  // staging: row / column sr of the workgroup tile, k half kh; clamped,
+  // in-bounds addresses (rows past n and columns past ncols load finite data
+  // that reaches no output)
+  const int sr = t & (WG - 1), kh = t >> 7;
+  const ptrdiff_t mt_delta = mt1 - mt0;          // to the second panel's multipliers (uniform)
+  const C* pa = mt0 + (size_t)blk * mt_bs + (size_t)(8 * kh) * n + min(R0 + sr, n - 1);
+  const C* pb = colptr(A, B, n, j0, jb, C0 + sr < ncols ? C0 + sr : 0) + (size_t)(j0 + 8 * kh) * n;
+  const int grp = sr >> 5, slot = (sr & 31) + 32 * kh;
+  C ra[8], rv[8];
+  auto load = [&](int s) {
+    const int h = s / SPP, ks = s - h * SPP;
+    const C* p = pa + (h ? mt_delta : 0) + (size_t)(ks * M::KS) * n;
+    const C* q = pb + (size_t)(s * M::KS) * n;   // the paired panels' pivot rows are adjacent
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ra[e] = p[(size_t)e * n];
+      rv[e] = q[(size_t)e * n];
+    }
+  };
+  auto commit = [&](int buf) {
+    float v[8];
+    bf16x8 h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = -ra[e].x;
+    split8(v, h, l);
+    sm[buf][0][0][grp][slot] = h;
+    sm[buf][0][1][grp][slot] = l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = ra[e].y;
+    split8(v, h, l);
+    sm[buf][0][2][grp][slot] = h;
+    sm[buf][0][3][grp][slot] = l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = rv[e].x;
+    split8(v, h, l);
+    sm[buf][1][0][grp][slot] = h;
+    sm[buf][1][1][grp][slot] = l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = rv[e].y;
+    split8(v, h, l);
+    sm[buf][1][2][grp][slot] = h;
+    sm[buf][1][3][grp][slot] = l;
+  };
+  load(0);
+  // the C tile (accumulators start at C; Gamma-formed for the first panel)
+  C* cb[2];
+  bool cok[2];
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int col = c0 + y * 32 + (lane & 31);
+    cok[y] = col < ncols;
+    cb[y] = colptr(A, B, n, j0, jb, cok[y] ? col : 0);
+  }
+  floatx16 re[2][2], im[2][2];
+  if (FIRST) {
+    ColSrc<float> src[2];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) src[y] = colsrc<float, true>(a, blk, 0, jb, cok[y] ? c0 + y * 32 + (lane & 31) : 0);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const C c = src[y].at(min(i0 + x * 32 + M::c_row(lane, v), n - 1), n, 0);
+          re[x][y][v] = c.x;
+          im[x][y][v] = c.y;
+        }
+  } else {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const C c = ld_c<true>(&cb[y][(size_t)min(i0 + x * 32 + M::c_row(lane, v), n - 1) * n]);
+          re[x][y][v] = c.x;
+          im[x][y][v] = c.y;
+        }
+  }
+  commit(0);
+  if (KSTEPS > 1) load(1);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < KSTEPS; ++s) {
+    const int buf = s & 1;
+    if (live) {
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const bf16x8 ph = sm[buf][0][0][2 * wr + x][lane], pl = sm[buf][0][1][2 * wr + x][lane];
+        const bf16x8 qh = sm[buf][0][2][2 * wr + x][lane], ql = sm[buf][0][3][2 * wr + x][lane];
+        const bf16x8 nqh = neg8(qh), nql = neg8(ql);
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const bf16x8 bh = sm[buf][1][0][2 * wc + y][lane], bl = sm[buf][1][1][2 * wc + y][lane];
+          const bf16x8 ih = sm[buf][1][2][2 * wc + y][lane], il = sm[buf][1][3][2 * wc + y][lane];
+          re[x][y] = M::mma(pl, bh, re[x][y]);
+          re[x][y] = M::mma(ph, bl, re[x][y]);
+          re[x][y] = M::mma(ql, ih, re[x][y]);
+          re[x][y] = M::mma(qh, il, re[x][y]);
+          re[x][y] = M::mma(ph, bh, re[x][y]);
+          re[x][y] = M::mma(qh, ih, re[x][y]);
+          im[x][y] = M::mma(pl, ih, im[x][y]);
+          im[x][y] = M::mma(ph, il, im[x][y]);
+          im[x][y] = M::mma(nql, bh, im[x][y]);
+          im[x][y] = M::mma(nqh, bl, im[x][y]);
+          im[x][y] = M::mma(ph, ih, im[x][y]);
+          im[x][y] = M::mma(nqh, bh, im[x][y]);
+        }
+      }
+    }
+    if (s + 1 < KSTEPS) {
+      commit(buf ^ 1);            // its readers (step s - 1) passed the last barrier
+      if (s + 2 < KSTEPS) load(s + 2);
+      __syncthreads();
+    }
+  }
+  if (!live) return;
+  auto elem = [&](int x, int y, int v) { return make_float2(re[x][y][v], im[x][y][v]); };
+  if (i0 >= mix_lo) {                            // wave-uniform, as in the FP32 kernel
+    const int ncolA = n - j0 - jb;
+    const C* G = a.gamma + (size_t)blk * n * n;
+    C* P = a.phi + (size_t)blk * n * n;
+    const float al = (float)a.alpha, be = (float)(1.0 - a.alpha);
+    const bool mix = a.alpha != 1.0;
+    float cs[2] = {0.f, 0.f};
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int i = i0 + x * 32 + M::c_row(lane, v);
+          if (cok[y] && i < row_hi) {
+            const C f = elem(x, y, v);
+            st_c<true>(&cb[y][(size_t)i * n], f);
+            const size_t e = (size_t)i * n + (c0 + y * 32 + (lane & 31) - ncolA);
+            P[e] = mix_phi<float>(f, ld_c<true>(&G[e]), mix ? ld_c<true>(&P[e]) : cz<C>(), al, be, mix);
+            cs[y] += f.x * f.x + f.y * f.y;
+          }
+        }
+    if (a.pcs) {
+#pragma unroll
+      for (int y = 0; y < 2; ++y) put_cs(a.pcs, n, blk, i0 / 64, c0 + y * 32 + (lane & 31) - ncolA, cs[y]);
+    }
+    return;
+  }
+  C* MN = mtn + (size_t)blk * NB * n;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = i0 + x * 32 + M::c_row(lane, v), c = c0 + y * 32 + (lane & 31);
+        const bool mult = c < ntc && i >= mult_row;
+        if (cok[y] && i < row_hi && !mult) st_c<true>(&cb[y][(size_t)i * n], elem(x, y, v));
+        if (mult && i < row_hi) MN[(size_t)c * n + i] = elem(x, y, v);
+      }
+}
+
 // rows [row_lo, row_hi) with 0 <= row_lo < row_hi <= n, outside the panel;
 // combined columns [col_lo, ncols) with col_lo <= n - j0 - jb; multipliers from
 // mt (k-major [NB][n] per block) or, ut (back substitution of a full panel),
@@ -1130,44 +1259,15 @@ void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int ro
   const int ncols = col_hi < 0 ? ncols_all : std::min(col_hi, ncols_all);
   const int nrb = (row_hi - row_lo + CF::WGM - 1) / CF::WGM;
   const int ncb = (ncols - col_lo + CF::WGN - 1) / CF::WGN;
-  hipLaunchKernelGGL((bse_update_kernel<T, NB, CF, NK>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb,
-                     row_lo, row_hi, col_lo, ncols, mt0, mt1 ? mt1 : mt0, mt_bs, mtn ? mtn : mt, mtn ? ntc : 0,
-                     mix_lo < 0 ? n : mix_lo, mult_row < 0 ? row_lo + ntc : mult_row);
-}
-
-// --------------------------------------------------------------- epilogue
-// Phi <- alpha (F - Gamma) + (1 - alpha) Phi for every row, where the kernels
-// that finish the rows do not mix them (BF16x3 products). One wave per 64-row
-// x 32-column tile of F (lane l: column l % 32, rows l / 32 + 2 k), which also
-// sums |F_ij|^2 over the tile's columns for the error estimate.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void bse_epilogue_kernel(BseCtx<T> a) {
-  using C = typename cplx_of<T>::type;
-  const int blk = blockIdx.y, n = a.n, lane = threadIdx.x & 63;
-  if (inactive(a, blk)) return;
-  const int nr = (n + 63) / 64, nc = (n + 31) / 32;
-  const int tile = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (tile >= nr * nc) return;
-  const int rowblk = tile / nc, colsub = tile - (tile / nc) * nc;
-  const int col = colsub * 32 + (lane & 31);
-  const size_t nn = (size_t)n * n;
-  const C* F = a.B + (size_t)blk * nn;
-  const C* G = a.gamma + (size_t)blk * nn;
-  C* P = a.phi + (size_t)blk * nn;
-  const T al = (T)a.alpha, be = (T)(1.0 - a.alpha);
-  const bool mix = a.alpha != 1.0;
-  float fs = 0.f;
-  for (int k = 0; k < 32; ++k) {
-    const int row = rowblk * 64 + (lane >> 5) + 2 * k;
-    if (row < n && col < n) {
-      const size_t idx = (size_t)row * n + col;
-      const C f = F[idx];
-      P[idx] = mix_phi<T>(f, G[idx], mix ? P[idx] : cz<C>(), al, be, mix);
-      fs += (float)f.x * f.x + (float)f.y * f.y;
-    }
-  }
-  if constexpr (sizeof(T) == 4) {
-    if (a.pcs) put_cs(a.pcs, n, blk, rowblk, col, fs);
+  if constexpr (CF::BF3) {
+    static_assert(sizeof(T) == 4 && CF::FULL && CF::WGM == 128 && CF::WGN == 128, "BF16x3 tile");
+    hipLaunchKernelGGL((bse_update_bf_kernel<NB, NK, CF::FIRST>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0,
+                       ncb, row_lo, row_hi, col_lo, ncols, mt0, mt1 ? mt1 : mt0, mt_bs, mtn ? mtn : mt,
+                       mtn ? ntc : 0, mix_lo < 0 ? n : mix_lo, mult_row < 0 ? row_lo + ntc : mult_row);
+  } else {
+    hipLaunchKernelGGL((bse_update_kernel<T, NB, CF, NK>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0, ncb,
+                       row_lo, row_hi, col_lo, ncols, mt0, mt1 ? mt1 : mt0, mt_bs, mtn ? mtn : mt, mtn ? ntc : 0,
+                       mix_lo < 0 ? n : mix_lo, mult_row < 0 ? row_lo + ntc : mult_row);
   }
 }
 
@@ -1674,7 +1774,8 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   if constexpr (sizeof(T) == 4) a.pcs = (float*)(w + L.pcs);
   const int n = d.n;
   // event timing around each launch (kind: 0 init, 1 pivot, 2 panel, 3 update,
-  // 4 epilogue, 5 error estimate and FP64 re-solve)
+  // 4 unused (a separate mixing pass, no longer needed), 5 error estimate and
+  // FP64 re-solve)
   auto pre = [&](int kind, hipStream_t st) {
     if (tm && tm->used < tm->cap) {
       tm->kind[tm->used] = kind;
@@ -1698,10 +1799,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   const int last = (a.nJ - 1) * NB;
   // The mixing is fused into the kernels that finish rows of F: the
   // back-substitution launch of panel J for the rows of panel J - 1, the last
-  // panel's pivot-row step for its own rows (not with the BF16x3 products:
-  // that update runs at one wave per SIMD with no registers to spare, and the
-  // loads of the mixing cost it more than a separate pass over every row).
-  constexpr bool kFuseMix = !BF3;
+  // panel's pivot-row step for its own rows.
   // complex64 path: the blocks with weak or non-finite pivots (all known once
   // the last pivot is met) are listed and gathered for the FP64 re-solve
   // before any row is mixed, with their Phi (none flagged: empty launches)
@@ -1745,7 +1843,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     const int ncols = (n - j0 - jb) + n;
     constexpr int RW = panel_rows_per_wave<T, NB>();
     const int nwb = ((ncols + 31) / 32 * (NB / RW) + kWaves - 1) / kWaves;
-    const int mix = kFuseMix && j0 == last ? 1 : 0;
+    const int mix = j0 == last ? 1 : 0;
     pre(2, st);
     if (j0 == 0)
       hipLaunchKernelGGL((bse_panel_kernel<T, NB, true, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, st, a, j0, nwb, mix);
@@ -1754,9 +1852,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
                          mix);
     post(st);
   };
-  // Paired updates on the FP32 and FP64 products; the BF16x3 update holds its
-  // three accumulators at one wave per SIMD and spills with the longer loop.
-  constexpr bool kPair = !BF3;
+  constexpr bool kPair = true;     // paired (rank-2NB) updates of full panels
   // Forward update of NKP panels from j0 (1, or 2 for a paired rank-2NB
   // update) for rows [row_lo, row_hi) and the combined columns below col_hi
   // (the trailing columns right of the panels, then B); the results in the
@@ -1905,12 +2001,12 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     const int jb = std::min(NB, n - j0);
     if (jb == NB && kPair && j0 - NB > 0) {
       const int j1 = j0 - NB;
-      back_full(1, j0, j1, j0, kFuseMix ? j1 : -1);
-      back_full(2, j1, 0, j1, kFuseMix ? j1 - NB : -1);
+      back_full(1, j0, j1, j0, j1);
+      back_full(2, j1, 0, j1, j1 - NB);
       j0 -= 2 * NB;
       continue;
     }
-    const int mix_lo = kFuseMix ? j0 - NB : -1;
+    const int mix_lo = j0 - NB;
     if (jb == NB) {
       back_full(1, j0, 0, j0, mix_lo);
     } else {
@@ -1921,13 +2017,6 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
       if (tm) tm->update_flops += 8.0 * (double)j0 * n * jb * d.Nq;
     }
     j0 -= NB;
-  }
-  if (!kFuseMix) {            // every row in a separate pass
-    pre(4, s);
-    const unsigned ntile = (unsigned)(((n + 63) / 64) * ((n + 31) / 32));
-    hipLaunchKernelGGL((bse_epilogue_kernel<T>), dim3((ntile + kWaves - 1) / kWaves, d.Nq), dim3(kThreads), 0, s,
-                       a);
-    post(s);
   }
   if constexpr (sizeof(T) == 4) {
     // error estimate of every block (B holds the complex64 F), then the FP64
