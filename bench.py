@@ -56,11 +56,11 @@ def measured_counters():
     return rec["hbm_bytes_per_dispatch"], rec.get("mfma_util_pct")
 
 
-def run_gpu(p, precision, steps, warmup):
+def run_gpu(p, precision, steps, warmup, bse_tile=0):
     import torch
     from paper_1510_03330_amd.ops import Solver
 
-    s = Solver(p, precision, device="cuda:0")
+    s = Solver(p, precision, device="cuda:0", bse_tile=bse_tile)
     d = s.dims
     if warmup:
         s.iterate(warmup)
@@ -797,6 +797,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--bf16x3-steps", type=int, default=3)
+    ap.add_argument("--bf16x3-tile", type=int, default=0, choices=(0, 1),
+                    help="BF16x3 update tile (0: 128 x 128 workgroup, 1: 128 x 64 with loads two steps ahead)")
     ap.add_argument("--no-microbench", action="store_true",
                     help="skip the 4x4 Nv=16 BSE microbenchmark")
     ap.add_argument("--study", action="store_true",
@@ -864,7 +866,7 @@ def main():
     r64 = run_gpu(p, "fp64", args.fp64_steps, 1) if args.fp64_steps > 0 else None
     ips64 = (r64["steps"] / r64["sec"]) if r64 else None
     print(f"[bench] bf16x3 path: steps {args.bf16x3_steps}", file=sys.stderr, flush=True)
-    r3 = run_gpu(p, "bf16x3", args.bf16x3_steps, 1) if args.bf16x3_steps > 0 else None
+    r3 = run_gpu(p, "bf16x3", args.bf16x3_steps, 1, args.bf16x3_tile) if args.bf16x3_steps > 0 else None
     ips3 = (r3["steps"] / r3["sec"]) if r3 else None
 
     # dominant kernel: the rank-NB update of the BSE (per launch: one panel step of

@@ -106,11 +106,12 @@ typedef struct {
                               summed over the box with the full F, Sigma on
                               the box only (requires f_ext = 1; the ablation
                               the regulation is measured against)           */
-  int32_t bse_tile;        /* complex64/FP32 BSE update tile: 0 the 128 x 128
-                              workgroup tile (64 x 64 per wave), 1 the
-                              128 x 64 tile (64 x 32 per wave, more
-                              workgroups for small systems); the other
-                              precisions have one tile. Both run the same
+  int32_t bse_tile;        /* complex64 (FP32 and BF16x3) BSE update tile: 0
+                              the 128 x 128 workgroup tile (64 x 64 per
+                              wave), 1 the 128 x 64 tile (64 x 32 per wave:
+                              more workgroups for small systems; with BF16x3
+                              products also operand loads two steps ahead);
+                              complex128 has one tile. Both run the same
                               products in the same order and agree to FP32
                               rounding; the batched solver picks by timing.  */
   double U, beta, t, tp;   /* interaction, inverse temperature, hoppings     */

@@ -604,7 +604,9 @@ struct ColSrc {
   int diag;            // row index whose element gets the unit diagonal (-1: none)
   bool inA;
   __device__ C at(int k, int n, int j0) const {   // row j0 + k
-    const C g = p[(size_t)k * n];
+    return form(p[(size_t)k * n], k, j0);
+  }
+  __device__ C form(C g, int k, int j0) const {    // the element of row j0 + k from its Gamma value
     if (!inA) return g;
     C v;
     v.x = (j0 + k == diag ? (T)1 : (T)0) - (g.x * sx - g.y * sy);
@@ -845,12 +847,16 @@ using UpdDefault = typename std::conditional<
                               UpdCfg<T, 64, 32, 2, 3, false, true, false, true>>::type,
     UpdCfg<T, 32, 32, 1, 2, FULL, true, false, true>>::type;
 
-// BF16x3 update of full panels: bse_update_bf_kernel (LDS-staged operands,
-// 64 x 64 wave tiles in a 128 x 128 workgroup tile; the UWM / UWN / FIRST /
-// BF3 fields of this configuration select and shape it, the others are
-// unused). A ragged last panel's update takes the complex64 FP32 products.
+// BF16x3 update of full panels: bse_update_bf_kernel (LDS-staged operands;
+// the UWN / PF / FIRST / BF3 fields of this configuration select and shape
+// it, the others are unused): a 64 x 64 wave tile (128 x 128 workgroup) with
+// loads one step ahead, or (bse_tile = 1) a 64 x 32 wave tile (128 x 64
+// workgroup) with loads two steps ahead. A ragged last panel's update takes
+// the complex64 FP32 products.
 template <bool FULL>
 using UpdBF3 = UpdCfg<float, 64, 64, 1, 2, FULL, false, false, true, true>;
+template <bool FULL>
+using UpdBF3N = UpdCfg<float, 64, 32, 2, 3, FULL, false, false, true, true>;
 template <typename T, bool FULL, bool BF3>
 using UpdSel = typename std::conditional<BF3 && FULL, UpdBF3<FULL>, UpdDefault<T, FULL>>::type;
 // the narrow complex64 tile (bse_tile = 1): 64 x 32 per wave, three waves per
@@ -1038,13 +1044,23 @@ void bse_update_kernel(BseCtx<T> a, int j0, int ncb, int row_lo, int row_hi, int
 // kernel.
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// two values per conversion; the hi parts are read back from the packed pair
+// (a bf16 is the upper half of the float it rounds to)
 __device__ inline void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
+  u32x4 h, l;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 h = (__bf16)v[e];
-    hi[e] = h;
-    lo[e] = (__bf16)(v[e] - (float)h);
+  for (int e = 0; e < 4; ++e) {
+    const f32x2 x = {v[2 * e], v[2 * e + 1]};
+    const unsigned p = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2));
+    const f32x2 b = {__builtin_bit_cast(float, p << 16), __builtin_bit_cast(float, p & 0xffff0000u)};
+    h[e] = p;
+    l[e] = __builtin_bit_cast(unsigned, __builtin_convertvector(x - b, bf16x2));
   }
+  hi = __builtin_bit_cast(bf16x8, h);
+  lo = __builtin_bit_cast(bf16x8, l);
 }
 
 __device__ inline bf16x8 neg8(bf16x8 x) {       // exact: sign bits only
@@ -1053,18 +1069,44 @@ __device__ inline bf16x8 neg8(bf16x8 x) {       // exact: sign bits only
   return __builtin_bit_cast(bf16x8, u);
 }
 
-template <int NB, int NK, bool FIRST>
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void split4(const float (&v)[4], bf16x4& hi, bf16x4& lo) {
+  unsigned h[2], l[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const f32x2 x = {v[2 * e], v[2 * e + 1]};
+    const unsigned p = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2));
+    const f32x2 b = {__builtin_bit_cast(float, p << 16), __builtin_bit_cast(float, p & 0xffff0000u)};
+    h[e] = p;
+    l[e] = __builtin_bit_cast(unsigned, __builtin_convertvector(x - b, bf16x2));
+  }
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  hi = __builtin_bit_cast(bf16x4, u32x2{h[0], h[1]});
+  lo = __builtin_bit_cast(bf16x4, u32x2{l[0], l[1]});
+}
+
+// WN: 32-column groups per wave (wave tile 64 x 32 WN, workgroup tile
+// 128 x 64 WN); PFD: operand loads in flight, in steps (a register ring).
+// The narrow tile (WN = 1) also spreads the loads of its C tile over the
+// steps: its accumulators start at zero and C is added when they are stored,
+// so a workgroup does not begin with a burst of C loads that every workgroup
+// of the launch makes at the same time (the C stream runs beside the matrix
+// products instead of between them).
+template <int NB, int NK, bool FIRST, int WN, int PFD>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void bse_update_bf_kernel(BseCtx<float> a, int j0, int ncb, int row_lo, int row_hi, int col_lo, int col_hi,
                           const float2* mt0, const float2* mt1, size_t mt_bs, float2* mtn, int ntc, int mix_lo,
                           int mult_row) {
   using C = float2;
   using M = MmaBF3;
-  constexpr int WG = 128, SPP = NB / M::KS, KSTEPS = NK * SPP;
-  static_assert(NB % M::KS == 0 && kThreads == 2 * WG, "one staging row per thread and k half");
-  // [buffer][operand: multipliers, pivot rows][component][32-row / column group][lane];
-  // components: multipliers -Re hi, lo, Im hi, lo; pivot rows Re hi, lo, Im hi, lo
-  __shared__ bf16x8 sm[2][2][4][4][64];
+  constexpr int WR = 128, WC = 64 * WN, SPP = NB / M::KS, KSTEPS = NK * SPP;
+  constexpr int KP = M::KS * WC / kThreads;      // k values of one pivot-row column per thread (8 or 4)
+  static_assert(NB % M::KS == 0 && kThreads == 2 * WR && (WN == 1 || WN == 2), "staging layout");
+  // [buffer][component][32-row / column group][lane]; components: multipliers
+  // -Re hi, lo, Im hi, lo; pivot rows Re hi, lo, Im hi, lo
+  __shared__ bf16x8 sa[2][4][4][64];
+  __shared__ bf16x8 sb[2][4][2 * WN][64];
   const unsigned lid = xcd_linear();
   const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
   if (inactive(a, blk)) return;                  // uniform over the workgroup
@@ -1072,76 +1114,128 @@ void bse_update_bf_kernel(BseCtx<float> a, int j0, int ncb, int row_lo, int row_
   constexpr int jb = NK * NB;
   const int ncols = min((n - j0 - jb) + n, col_hi);
   const int rb = bx / ncb, cbk = bx - (bx / ncb) * ncb;
-  const int R0 = row_lo + rb * WG, C0 = col_lo + cbk * WG;
+  const int R0 = row_lo + rb * WR, C0 = col_lo + cbk * WC;
   const int wr = wave & 1, wc = wave >> 1;
-  const int i0 = R0 + wr * 64, c0 = C0 + wc * 64;
+  const int i0 = R0 + wr * 64, c0 = C0 + wc * 32 * WN;
   // every wave takes part in the staging and the barriers; a wave whose tile
   // lies outside the rows or columns skips only its products and stores
   const bool live = i0 < row_hi && c0 < ncols;
   C* A = a.A + (size_t)blk * n * n;
   C* B = a.B + (size_t)blk * n * n;
-  // staging: row / column sr of the workgroup tile, k half kh; clamped,
-  // in-bounds addresses (rows past n and columns past ncols load finite data
-  // that reaches no output)
-  const int sr = t & (WG - 1), kh = t >> 7;
+  // staging: multiplier row sr (k half kh, 8 k) and pivot-row column sc (k
+  // part kp, KP k) of the workgroup tile; clamped, in-bounds addresses (rows
+  // past n and columns past ncols load finite data that reaches no output)
+  const int sr = t & (WR - 1), kh = t >> 7;
+  const int sc = t % WC, kp = t / WC;
   const ptrdiff_t mt_delta = mt1 - mt0;          // to the second panel's multipliers (uniform)
   const C* pa = mt0 + (size_t)blk * mt_bs + (size_t)(8 * kh) * n + min(R0 + sr, n - 1);
-  const C* pb = colptr(A, B, n, j0, jb, C0 + sr < ncols ? C0 + sr : 0) + (size_t)(j0 + 8 * kh) * n;
-  const int grp = sr >> 5, slot = (sr & 31) + 32 * kh;
-  C ra[8], rv[8];
+  const C* pb = colptr(A, B, n, j0, jb, C0 + sc < ncols ? C0 + sc : 0) + (size_t)(j0 + KP * kp) * n;
+  const int ga = sr >> 5, la = (sr & 31) + 32 * kh;
+  const int gb = sc >> 5, lb = (sc & 31) + 32 * ((KP * kp) >> 3), hb = ((KP * kp) & 7) / 4;
+  C ra[PFD][8], rv[PFD][KP];
   auto load = [&](int s) {
-    const int h = s / SPP, ks = s - h * SPP;
+    const int h = s / SPP, ks = s - h * SPP, r = s % PFD;
     const C* p = pa + (h ? mt_delta : 0) + (size_t)(ks * M::KS) * n;
     const C* q = pb + (size_t)(s * M::KS) * n;   // the paired panels' pivot rows are adjacent
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      ra[e] = p[(size_t)e * n];
-      rv[e] = q[(size_t)e * n];
+    for (int e = 0; e < 8; ++e) ra[r][e] = p[(size_t)e * n];
+#pragma unroll
+    for (int e = 0; e < KP; ++e) rv[r][e] = q[(size_t)e * n];
+  };
+  auto commit = [&](int s, int buf) {
+    const int r = s % PFD;
+    {
+      float v[8];
+      bf16x8 h, l;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = -ra[r][e].x;
+      split8(v, h, l);
+      sa[buf][0][ga][la] = h;
+      sa[buf][1][ga][la] = l;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = ra[r][e].y;
+      split8(v, h, l);
+      sa[buf][2][ga][la] = h;
+      sa[buf][3][ga][la] = l;
+    }
+    if constexpr (KP == 8) {
+      float v[8];
+      bf16x8 h, l;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = rv[r][e].x;
+      split8(v, h, l);
+      sb[buf][0][gb][lb] = h;
+      sb[buf][1][gb][lb] = l;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = rv[r][e].y;
+      split8(v, h, l);
+      sb[buf][2][gb][lb] = h;
+      sb[buf][3][gb][lb] = l;
+    } else {
+      float v[4];
+      bf16x4 h, l;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = rv[r][e].x;
+      split4(v, h, l);
+      reinterpret_cast<bf16x4*>(&sb[buf][0][gb][lb])[hb] = h;
+      reinterpret_cast<bf16x4*>(&sb[buf][1][gb][lb])[hb] = l;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = rv[r][e].y;
+      split4(v, h, l);
+      reinterpret_cast<bf16x4*>(&sb[buf][2][gb][lb])[hb] = h;
+      reinterpret_cast<bf16x4*>(&sb[buf][3][gb][lb])[hb] = l;
     }
   };
-  auto commit = [&](int buf) {
-    float v[8];
-    bf16x8 h, l;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = -ra[e].x;
-    split8(v, h, l);
-    sm[buf][0][0][grp][slot] = h;
-    sm[buf][0][1][grp][slot] = l;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = ra[e].y;
-    split8(v, h, l);
-    sm[buf][0][2][grp][slot] = h;
-    sm[buf][0][3][grp][slot] = l;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = rv[e].x;
-    split8(v, h, l);
-    sm[buf][1][0][grp][slot] = h;
-    sm[buf][1][1][grp][slot] = l;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = rv[e].y;
-    split8(v, h, l);
-    sm[buf][1][2][grp][slot] = h;
-    sm[buf][1][3][grp][slot] = l;
-  };
-  load(0);
+  for (int q = 0; q < PFD && q < KSTEPS; ++q) load(q);
   // the C tile (accumulators start at C; Gamma-formed for the first panel)
-  C* cb[2];
-  bool cok[2];
+  C* cb[WN];
+  bool cok[WN];
 #pragma unroll
-  for (int y = 0; y < 2; ++y) {
+  for (int y = 0; y < WN; ++y) {
     const int col = c0 + y * 32 + (lane & 31);
     cok[y] = col < ncols;
     cb[y] = colptr(A, B, n, j0, jb, cok[y] ? col : 0);
   }
-  floatx16 re[2][2], im[2][2];
+  floatx16 re[2][WN], im[2][WN];
+  constexpr bool CSPREAD = WN == 1;
+  constexpr int NCL = 2 * WN * 16;               // C elements per lane
+  constexpr int CPS = (NCL + KSTEPS - 2) / (KSTEPS - 1);   // spread over all steps but the last
+  static_assert(KSTEPS >= 2, "a spread C tile needs two steps");
+  // first panel: C is formed from Gamma (ColSrc); the spread loads keep only
+  // the Gamma column pointer live, the rest of the formula is rebuilt where
+  // the elements are stored
+  auto first_src = [&](int y) { return colsrc<float, true>(a, blk, 0, jb, cok[y] ? c0 + y * 32 + (lane & 31) : 0); };
+  const C* gp[WN];
   if (FIRST) {
-    ColSrc<float> src[2];
 #pragma unroll
-    for (int y = 0; y < 2; ++y) src[y] = colsrc<float, true>(a, blk, 0, jb, cok[y] ? c0 + y * 32 + (lane & 31) : 0);
+    for (int y = 0; y < WN; ++y) gp[y] = first_src(y).p;
+  }
+  // element e of this lane's part of the C tile: x = e / (16 WN), y = e / 16 % WN, v = e % 16
+  auto c_row_of = [&](int e) { return min(i0 + (e / (16 * WN)) * 32 + M::c_row(lane, e % 16), n - 1); };
+  auto c_ptr = [&](int e) -> const C* {
+    const int y = e / 16 % WN;
+    return FIRST ? gp[y] + (size_t)c_row_of(e) * n : &cb[y][(size_t)c_row_of(e) * n];
+  };
+  C cpre[CSPREAD ? NCL : 1];
+  if constexpr (CSPREAD) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < WN; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          re[x][y][v] = 0.f;
+          im[x][y][v] = 0.f;
+        }
+  } else if (FIRST) {
+    ColSrc<float> src[WN];
+#pragma unroll
+    for (int y = 0; y < WN; ++y) src[y] = first_src(y);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < WN; ++y)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const C c = src[y].at(min(i0 + x * 32 + M::c_row(lane, v), n - 1), n, 0);
@@ -1152,7 +1246,7 @@ void bse_update_bf_kernel(BseCtx<float> a, int j0, int ncb, int row_lo, int row_
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < WN; ++y)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const C c = ld_c<true>(&cb[y][(size_t)min(i0 + x * 32 + M::c_row(lane, v), n - 1) * n]);
@@ -1160,56 +1254,98 @@ void bse_update_bf_kernel(BseCtx<float> a, int j0, int ncb, int row_lo, int row_
           im[x][y][v] = c.y;
         }
   }
-  commit(0);
-  if (KSTEPS > 1) load(1);
+  commit(0, 0);
+  if (PFD < KSTEPS) load(PFD);
   __syncthreads();
+  // One step is one basic block: the products of step s (every wave, also one
+  // outside the rows or columns: clamped data, results never stored), the
+  // split and LDS stores of step s + 1 and the loads of step s + 1 + PFD, so
+  // that the scheduler can interleave the split (VALU) with the matrix-core
+  // products of the same wave instead of running them one after the other.
 #pragma unroll
   for (int s = 0; s < KSTEPS; ++s) {
     const int buf = s & 1;
-    if (live) {
+    if constexpr (CSPREAD) {
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const bf16x8 ph = sm[buf][0][0][2 * wr + x][lane], pl = sm[buf][0][1][2 * wr + x][lane];
-        const bf16x8 qh = sm[buf][0][2][2 * wr + x][lane], ql = sm[buf][0][3][2 * wr + x][lane];
-        const bf16x8 nqh = neg8(qh), nql = neg8(ql);
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          const bf16x8 bh = sm[buf][1][0][2 * wc + y][lane], bl = sm[buf][1][1][2 * wc + y][lane];
-          const bf16x8 ih = sm[buf][1][2][2 * wc + y][lane], il = sm[buf][1][3][2 * wc + y][lane];
-          re[x][y] = M::mma(pl, bh, re[x][y]);
-          re[x][y] = M::mma(ph, bl, re[x][y]);
-          re[x][y] = M::mma(ql, ih, re[x][y]);
-          re[x][y] = M::mma(qh, il, re[x][y]);
-          re[x][y] = M::mma(ph, bh, re[x][y]);
-          re[x][y] = M::mma(qh, ih, re[x][y]);
-          im[x][y] = M::mma(pl, ih, im[x][y]);
-          im[x][y] = M::mma(ph, il, im[x][y]);
-          im[x][y] = M::mma(nql, bh, im[x][y]);
-          im[x][y] = M::mma(nqh, bl, im[x][y]);
-          im[x][y] = M::mma(ph, ih, im[x][y]);
-          im[x][y] = M::mma(nqh, bh, im[x][y]);
-        }
-      }
+      for (int e = s * CPS; e < (s + 1) * CPS && e < NCL; ++e) cpre[e] = ld_c<true>(c_ptr(e));
     }
+    bf16x8 fa[2][6], fb[WN][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fa[x][c] = sa[buf][c][2 * wr + x][lane];
+      fa[x][4] = neg8(fa[x][2]);
+      fa[x][5] = neg8(fa[x][3]);
+    }
+#pragma unroll
+    for (int y = 0; y < WN; ++y)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fb[y][c] = sb[buf][c][WN * wc + y][lane];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < WN; ++y) {
+        const bf16x8 &ph = fa[x][0], &pl = fa[x][1], &qh = fa[x][2], &ql = fa[x][3], &nqh = fa[x][4],
+                     &nql = fa[x][5];
+        const bf16x8 &bh = fb[y][0], &bl = fb[y][1], &ih = fb[y][2], &il = fb[y][3];
+        re[x][y] = M::mma(pl, bh, re[x][y]);
+        re[x][y] = M::mma(ph, bl, re[x][y]);
+        re[x][y] = M::mma(ql, ih, re[x][y]);
+        re[x][y] = M::mma(qh, il, re[x][y]);
+        re[x][y] = M::mma(ph, bh, re[x][y]);
+        re[x][y] = M::mma(qh, ih, re[x][y]);
+        im[x][y] = M::mma(pl, ih, im[x][y]);
+        im[x][y] = M::mma(ph, il, im[x][y]);
+        im[x][y] = M::mma(nql, bh, im[x][y]);
+        im[x][y] = M::mma(nqh, bl, im[x][y]);
+        im[x][y] = M::mma(ph, ih, im[x][y]);
+        im[x][y] = M::mma(nqh, bh, im[x][y]);
+      }
     if (s + 1 < KSTEPS) {
-      commit(buf ^ 1);            // its readers (step s - 1) passed the last barrier
-      if (s + 2 < KSTEPS) load(s + 2);
+      commit(s + 1, buf ^ 1);     // its readers (step s - 1) passed the last barrier
+      if (s + 1 + PFD < KSTEPS) load(s + 1 + PFD);
       __syncthreads();
     }
   }
   if (!live) return;
-  auto elem = [&](int x, int y, int v) { return make_float2(re[x][y][v], im[x][y][v]); };
+  if (FIRST && CSPREAD) {           // the store pointers, not kept through the loop
+#pragma unroll
+    for (int y = 0; y < WN; ++y) {
+      const int col = c0 + y * 32 + (lane & 31);
+      cb[y] = colptr(A, B, n, j0, jb, cok[y] ? col : 0);
+      asm volatile("" : "+v"(cb[y]));
+    }
+  }
+  ColSrc<float> fsrc[WN];
+  int i0e = i0;                     // row origin for the epilogue: the row indices are
+  if (FIRST && CSPREAD) {           // recomputed there, not kept through the loop
+    asm volatile("" : "+v"(i0e));
+#pragma unroll
+    for (int y = 0; y < WN; ++y) fsrc[y] = first_src(y);
+  }
+  auto elem = [&](int x, int y, int v) {
+    C r = make_float2(re[x][y][v], im[x][y][v]);
+    if constexpr (CSPREAD) {                     // C + (-MT^T R)
+      const int e = (x * WN + y) * 16 + v;
+      const C c = FIRST ? fsrc[y].form(cpre[e], min(i0e + x * 32 + M::c_row(lane, v), n - 1), 0) : cpre[e];
+      r.x = c.x + r.x;
+      r.y = c.y + r.y;
+    }
+    return r;
+  };
   if (i0 >= mix_lo) {                            // wave-uniform, as in the FP32 kernel
     const int ncolA = n - j0 - jb;
     const C* G = a.gamma + (size_t)blk * n * n;
     C* P = a.phi + (size_t)blk * n * n;
     const float al = (float)a.alpha, be = (float)(1.0 - a.alpha);
     const bool mix = a.alpha != 1.0;
-    float cs[2] = {0.f, 0.f};
+    float cs[WN];
+#pragma unroll
+    for (int y = 0; y < WN; ++y) cs[y] = 0.f;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < WN; ++y)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int i = i0 + x * 32 + M::c_row(lane, v);
@@ -1223,7 +1359,7 @@ void bse_update_bf_kernel(BseCtx<float> a, int j0, int ncb, int row_lo, int row_
         }
     if (a.pcs) {
 #pragma unroll
-      for (int y = 0; y < 2; ++y) put_cs(a.pcs, n, blk, i0 / 64, c0 + y * 32 + (lane & 31) - ncolA, cs[y]);
+      for (int y = 0; y < WN; ++y) put_cs(a.pcs, n, blk, i0 / 64, c0 + y * 32 + (lane & 31) - ncolA, cs[y]);
     }
     return;
   }
@@ -1231,7 +1367,7 @@ void bse_update_bf_kernel(BseCtx<float> a, int j0, int ncb, int row_lo, int row_
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < WN; ++y)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int i = i0 + x * 32 + M::c_row(lane, v), c = c0 + y * 32 + (lane & 31);
@@ -1260,8 +1396,9 @@ void launch_update(const BseCtx<T>& a, int n, int Nq, int j0, int row_lo, int ro
   const int nrb = (row_hi - row_lo + CF::WGM - 1) / CF::WGM;
   const int ncb = (ncols - col_lo + CF::WGN - 1) / CF::WGN;
   if constexpr (CF::BF3) {
-    static_assert(sizeof(T) == 4 && CF::FULL && CF::WGM == 128 && CF::WGN == 128, "BF16x3 tile");
-    hipLaunchKernelGGL((bse_update_bf_kernel<NB, NK, CF::FIRST>), dim3(nrb * ncb, Nq), dim3(kThreads), 0, s, a, j0,
+    static_assert(sizeof(T) == 4 && CF::FULL && CF::UWM == 64 && (CF::UWN == 64 || CF::UWN == 32), "BF16x3 tile");
+    hipLaunchKernelGGL((bse_update_bf_kernel<NB, NK, CF::FIRST, CF::UWN / 32, CF::PF>), dim3(nrb * ncb, Nq),
+                       dim3(kThreads), 0, s, a, j0,
                        ncb, row_lo, row_hi, col_lo, ncols, mt0, mt1 ? mt1 : mt0, mt_bs, mtn ? mtn : mt,
                        mtn ? ntc : 0, mix_lo < 0 ? n : mix_lo, mult_row < 0 ? row_lo + ntc : mult_row);
   } else {
@@ -1881,7 +2018,12 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
         launch_update<T, NB, CFG>(a, n, d.Nq, j0, row_lo, row_hi, 0, false, mt, mtn, ntc, s, -1, mult_row, col_hi);
       }
     };
-    if constexpr (sizeof(T) == 4 && !BF3) {
+    if constexpr (BF3) {
+      if (tile == 1)
+        go(UpdFirst<UpdBF3N<true>>{}, UpdBF3N<true>{});
+      else
+        go(UpdFirst<UpdBF3<true>>{}, UpdBF3<true>{});
+    } else if constexpr (sizeof(T) == 4) {
       if (tile == 1)
         go(UpdFirst<UpdNarrow<true>>{}, UpdNarrow<true>{});
       else
@@ -1989,9 +2131,12 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     if (tm) tm->update_flops += 8.0 * (double)(row_hi - row_lo) * n * jb * d.Nq;
   };
   auto back_full = [&](int nkp, int jp, int row_lo, int row_hi, int mix_lo) {
-    if constexpr (sizeof(T) == 4 && !BF3) {
+    if constexpr (sizeof(T) == 4) {
       if (tile == 1) {
-        back(UpdNarrow<true>{}, nkp, jp, row_lo, row_hi, mix_lo);
+        if constexpr (BF3)
+          back(UpdBF3N<true>{}, nkp, jp, row_lo, row_hi, mix_lo);
+        else
+          back(UpdNarrow<true>{}, nkp, jp, row_lo, row_hi, mix_lo);
         return;
       }
     }

@@ -154,9 +154,9 @@ class Solver:
     (at least ws_bytes, so that reinit can take parameters of a larger need)."""
 
     def __init__(self, p, precision: str = "fp64", device: str = "cuda:0", stream=None, resolve_slots: int = 0,
-                 bse_tol: float = 0.0, ws_bytes: int = 0):
-        self.stage = Stage(p, precision, resolve_slots, bse_tol)
-        self._stage_args = (precision, resolve_slots, bse_tol)
+                 bse_tol: float = 0.0, ws_bytes: int = 0, bse_tile: int = 0):
+        self.stage = Stage(p, precision, resolve_slots, bse_tol, bse_tile)
+        self._stage_args = (precision, resolve_slots, bse_tol, bse_tile)
         self.device = torch.device(device)
         self.stream = stream
         lib = N.load()

@@ -89,7 +89,8 @@ def test_batch_equals_independent_contexts_with_retirement(prec, tol):
     b.close()
 
 
-def test_fp32_update_tiles_agree():
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_update_tiles_agree(prec):
     """The two complex64 update tiles (bse_tile 0: 64 x 64 per wave, 1: 64 x 32)
     run the same products in the same order; they agree to FP32 rounding (the
     compiler contracts the epilogue arithmetic of the two instantiations
@@ -99,7 +100,7 @@ def test_fp32_update_tiles_agree():
     p = config("c2")
     out = []
     for tile in (0, 1):
-        st = ops.Stage(p, "fp32", bse_tile=tile)
+        st = ops.Stage(p, prec, bse_tile=tile)
         d = st.d
         gam = torch.from_numpy(bse_microbench_gamma(d.n, range(d.Nq)).astype(np.complex64)).to(DEV)
         x = torch.from_numpy(rand_complex((d.Nq, d.n), 77, 0.3)).to(DEV)

@@ -287,16 +287,23 @@ def _bse_config(name):
     return config(base, **over)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def _prec_tile(prec):
+    """"bf16x3:1" -> ("bf16x3", 1): a precision with the second update tile."""
+    name, _, tile = prec.partition(":")
+    return name, int(tile or 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x3:1"])
 @pytest.mark.parametrize("name", ["tiny_2x2", "tiny_2x2_hf", "small_2x4", "small_4x4", "bse_ragged", "bse_odd"])
 def test_bse_solve(prec, name):
     _print_case("bse", prec, name)
+    prec, tile = _prec_tile(prec)
     p = _bse_config(name)
     g, gam, xph, xpp = _bse_inputs(p, 101)
     if prec != "fp64":
         gam = gam.astype(np.complex64).astype(np.complex128)
     ref = P.bse(g, gam, xph, xpp)
-    st = _ops().Stage(p, prec)
+    st = _ops().Stage(p, prec, bse_tile=tile)
     ws = torch.empty(st.bse_workspace_bytes(), dtype=torch.uint8, device=DEV)
     stats = torch.empty((g.Nq, 4), dtype=torch.int32, device=DEV)
     for r in range(4):
@@ -335,7 +342,7 @@ def _deep_inputs(nv):
     return _DEEP[nv]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x3:1"])
 @pytest.mark.parametrize("nv", [52, 64])
 def test_bse_deep_panels_sampled_blocks(prec, nv):
     """Many panels: 2x4 lattice with Nv = 52 (n = 416: three full panels of 128
@@ -349,8 +356,9 @@ def test_bse_deep_panels_sampled_blocks(prec, nv):
     the back substitution gives an error of the size of Phi itself, 10^4 times
     the bound."""
     _print_case("bse deep", prec, nv)
+    prec, tile = _prec_tile(prec)
     p, g, qs, chans = _deep_inputs(nv)
-    st = _ops().Stage(p, prec)
+    st = _ops().Stage(p, prec, bse_tile=tile)
     ws = torch.empty(st.bse_workspace_bytes(), dtype=torch.uint8, device=DEV)
     for r, gam, X in chans:
         if prec != "fp64":
