@@ -39,15 +39,69 @@ def bse_flops_per_launch(d) -> float:
     return d.Nq * (32.0 / 3.0) * float(d.n) ** 3
 
 
-def measured_counters():
-    """HBM bytes per launch of the BSE update kernel (FETCH_SIZE + WRITE_SIZE,
-    each scaled by what it reads for a plain device copy) and its matrix-core
-    utilisation (MfmaUtil) from the committed counter runs, or None when the
-    kernel source has changed since."""
+PEAK_BF16_MFMA = 2500.0  # TFLOP/s, dense bf16 matrix
+
+
+def update_launches(n, NB=128, lookahead=True):
+    """(rows, combined columns, depth, rows mixed into Phi) of each BSE update
+    launch of one channel's solve, in the order the library issues them (full
+    panels, n a multiple of NB; panel pairs, the look-ahead split of the rows
+    below a pair, then the back substitution with its mixing)."""
+    if n % NB:
+        raise ValueError("the launch model covers full panels only")
+    out = []
+    j0 = 0
+    while j0 + NB < n:
+        lo = j0 + NB
+        if lo + NB < n:                                   # panels J, J + 1 paired
+            hi = lo + NB
+            out.append((NB, (n - j0 - NB) + n, NB, 0))    # rows of J + 1, every column
+            out.append((n - hi, NB, NB, 0))               # the columns of J + 1 below it
+            cols = (n - j0 - 2 * NB) + n
+            if lookahead and hi + NB < n:
+                out += [(NB, cols, 2 * NB, 0), (n - hi - NB, cols, 2 * NB, 0)]
+            else:
+                out.append((n - hi, cols, 2 * NB, 0))
+            j0 = hi
+        else:
+            out.append((n - lo, (n - j0 - NB) + n, NB, 0))
+            j0 = lo
+    j0 = n - NB
+    while j0 > 0:                                         # back substitution (B columns only)
+        if j0 - NB > 0:
+            out += [(NB, n, NB, NB), (j0 - NB, n, 2 * NB, NB)]
+            j0 -= 2 * NB
+        else:
+            out.append((j0, n, NB, NB))
+            j0 -= NB
+    return out
+
+
+def update_compulsory(d):
+    """Per update launch, averaged over a solve (complex64): algorithmic flops
+    (8 per complex multiply-add) and compulsory HBM bytes: each C element read
+    and written once (8 + 8 bytes), both operand panels read once, and the
+    mixing of the rows the back substitution finishes (read Gamma and Phi,
+    write Phi)."""
+    L = update_launches(d.n)
+    k = float(d.Nq) / len(L)
+    c_b = sum(r * c * 16.0 for r, c, dp, m in L) * k
+    op_b = sum((dp * r + dp * c) * 8.0 for r, c, dp, m in L) * k
+    mix_b = sum(m * d.n * 24.0 for r, c, dp, m in L) * k
+    flops = sum(8.0 * r * c * dp for r, c, dp, m in L) * k
+    return dict(launches=len(L), flops=flops, c_bytes=c_b, operand_bytes=op_b, mixing_bytes=mix_b,
+                bytes=c_b + op_b + mix_b)
+
+
+def measured_counters(kind):
+    """HBM bytes per launch of a BSE update kernel ("fp32" or "bf16x3";
+    FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a plain device
+    copy) and its matrix-core utilisation (MfmaUtil) from the committed counter
+    runs, or (None, None) when the kernel source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "bse_traffic_8x8_nv16_c64.json")
     try:
-        rec = json.load(open(path))
+        rec = json.load(open(path))[kind]
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     except (OSError, ValueError, KeyError):
         return None, None
@@ -793,10 +847,10 @@ def main():
     faulthandler.enable()               # a Python traceback if the process dies on a signal
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=5, help="timed iterations of the headline (BF16x3) path")
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp32-steps", type=int, default=3, help="timed iterations of the FP32-product path")
     ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--bf16x3-steps", type=int, default=3)
     ap.add_argument("--bf16x3-tile", type=int, default=0, choices=(0, 1),
                     help="BF16x3 update tile (0: 128 x 128 workgroup, 1: 128 x 64 with loads two steps ahead)")
     ap.add_argument("--no-microbench", action="store_true",
@@ -858,47 +912,78 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
 
-    print(f"[bench] fp32 path: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-    r32 = run_gpu(p, "fp32", args.steps, args.warmup)
-    d = r32["dims"]
+    # headline: the BF16x3 path (complex64 operands split into bf16 pairs on the
+    # bf16 matrix cores, FP32 accumulation); the FP32-product and FP64 paths
+    # beside it
+    print(f"[bench] bf16x3 path: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    r3 = run_gpu(p, "bf16x3", args.steps, args.warmup, args.bf16x3_tile)
+    d = r3["dims"]
+    ips3 = r3["steps"] / r3["sec"]
+    print(f"[bench] bf16x3 {ips3:.3f} it/s; fp32 path: steps {args.fp32_steps}", file=sys.stderr, flush=True)
+    r32 = run_gpu(p, "fp32", args.fp32_steps, 1)
     ips = r32["steps"] / r32["sec"]
     print(f"[bench] fp32 {ips:.3f} it/s; fp64 path: steps {args.fp64_steps}", file=sys.stderr, flush=True)
     r64 = run_gpu(p, "fp64", args.fp64_steps, 1) if args.fp64_steps > 0 else None
     ips64 = (r64["steps"] / r64["sec"]) if r64 else None
-    print(f"[bench] bf16x3 path: steps {args.bf16x3_steps}", file=sys.stderr, flush=True)
-    r3 = run_gpu(p, "bf16x3", args.bf16x3_steps, 1, args.bf16x3_tile) if args.bf16x3_steps > 0 else None
-    ips3 = (r3["steps"] / r3["sec"]) if r3 else None
 
-    # dominant kernel: the rank-NB update of the BSE (per launch: one panel step of
-    # all 960 blocks of a channel, forward or back substitution); flops = 8 per
-    # complex multiply-add it performs, averaged over its launches
+    comp = update_compulsory(d)
+    kernel_ms = lambda r: {k: round(r["kern_ms"][i] / r["steps"], 2) for k, i in
+                           (("pivot", 1), ("pivot_rows", 2), ("update", 3), ("epilogue", 4),
+                            ("error_estimate_and_fp64_resolve", 5))}
+    # dominant kernel of the headline path: the BF16x3 update (per launch: one
+    # panel step of all 960 blocks of a channel, forward or back substitution).
+    # Below the bf16 ridge point (~190 bf16 matrix flops per compulsory byte
+    # against 2500 / 8 = 312): bound by HBM; achieved = compulsory bytes per
+    # launch over its average launch time, timed with HIP events on the
+    # library's stream
+    n3 = r3["kern_n"][3]
+    upd3_ms = r3["kern_ms"][3] / n3
+    upd3_gbs = comp["bytes"] / (upd3_ms * 1e-3) / 1e9
+    bse3_channel_ms = sum(r3["bse_ms"]) / len(r3["bse_ms"]) / 4.0
+    rates = hbm_rates()
+    traffic3, util3 = measured_counters("bf16x3")
+    roof = {"bound": "hbm", "achieved": round(upd3_gbs, 1), "peak": PEAK_HBM, "unit": "GB/s",
+            "frac": round(upd3_gbs / PEAK_HBM, 4), "traffic": traffic3,
+            "kernel": "bse_update_bf_kernel (BF16x3 products; one launch = an update of %d blocks, n=%d, at depth "
+                      "128 or 256 (paired panels), forward sweep or back substitution)" % (d.Nq, d.n),
+            "avg_launch_ms": round(upd3_ms, 3), "launches_per_solve": comp["launches"],
+            "compulsory_bytes_per_launch": comp["bytes"],
+            "compulsory_bytes_split": {"c_tiles": comp["c_bytes"], "operand_panels": comp["operand_bytes"],
+                                       "mixing": comp["mixing_bytes"]},
+            "copy_ceiling": round(rates["copy"], 1), "frac_of_copy_ceiling": round(upd3_gbs / rates["copy"], 4),
+            "bf16_matrix": {"flops_per_launch": 3.0 * comp["flops"],
+                            "flops_note": "four real products per complex multiply-add, each as three bf16 "
+                                          "products (hi hi + hi lo + lo hi): 24 flops, 3x the 8-flop count",
+                            "achieved_tflops": round(3.0 * comp["flops"] / (upd3_ms * 1e-3) / 1e12, 1),
+                            "peak_tflops": PEAK_BF16_MFMA,
+                            "mfma_util": (round(util3 / 100.0, 4) if util3 is not None else None)},
+            "algorithmic_fp32_equivalent_tflops": round(comp["flops"] / (upd3_ms * 1e-3) / 1e12, 1),
+            "bse_solve_lu_equivalent_tflops": round(bse_flops_per_launch(d) / (bse3_channel_ms * 1e-3) / 1e12, 2),
+            "bse_solve_ms_per_channel": round(bse3_channel_ms, 2),
+            "bse_kernel_ms_per_channel": kernel_ms(r3)}
+    # the FP32-product path's update: bound by the FP32 matrix cores
     n_upd = r32["kern_n"][3]
     upd_ms = r32["kern_ms"][3] / n_upd
     upd_flops = r32["upd_flops"] / n_upd
     achieved = upd_flops / (upd_ms * 1e-3) / 1e12
     bse_channel_ms = sum(r32["bse_ms"]) / len(r32["bse_ms"]) / 4.0
     bse_alg = bse_flops_per_launch(d) / (bse_channel_ms * 1e-3) / 1e12
-    traffic, mfma_util = measured_counters()
-    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": traffic,
-            "achieved_counts": "algorithmic-equivalent: 8 flops per complex multiply-add; the kernel forms each "
-                               "product from three real matrix products (6 flops)",
-            "mfma_util": (round(mfma_util / 100.0, 4) if mfma_util is not None else None),
-            "kernel": "bse_update_kernel<float,128> (one launch = an update of %d blocks, n=%d, at depth 128 or, "
-                      "for paired panels, 256: rows below the panels in the forward sweep, rows above them in "
-                      "the back substitution)" % (d.Nq, d.n),
-            "avg_launch_ms": round(upd_ms, 3), "flops_per_launch": upd_flops,
-            "bse_solve_lu_equivalent_tflops": round(bse_alg, 2),
-            "bse_solve_ms_per_channel": round(bse_channel_ms, 2),
-            "bse_kernel_ms_per_channel": {k: round(r32["kern_ms"][i] / args.steps, 2) for k, i in
-                                          (("pivot", 1), ("pivot_rows", 2), ("update", 3), ("epilogue", 4),
-                                           ("error_estimate_and_fp64_resolve", 5))}}
+    traffic, mfma_util = measured_counters("fp32")
+    roof32 = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
+              "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": traffic,
+              "achieved_counts": "algorithmic-equivalent: 8 flops per complex multiply-add; the kernel forms each "
+                                 "product from three real matrix products (6 flops)",
+              "mfma_util": (round(mfma_util / 100.0, 4) if mfma_util is not None else None),
+              "kernel": "bse_update_kernel<float,128> (FP32 products, same launches as above)",
+              "avg_launch_ms": round(upd_ms, 3), "flops_per_launch": upd_flops,
+              "bse_solve_lu_equivalent_tflops": round(bse_alg, 2),
+              "bse_solve_ms_per_channel": round(bse_channel_ms, 2),
+              "bse_kernel_ms_per_channel": kernel_ms(r32)}
 
     # remap: algorithmic bytes (read the 4 Phi arrays, write the 4 Gamma arrays
     # once) over its stage time, against the HBM peak and against a plain copy
-    rates = hbm_rates()
     copy_gbs = rates["copy"]
-    remap_ms = r32["stage_ms"][3]
+    remap_ms = r3["stage_ms"][3]
     remap_bytes = 8.0 * d.Nq * float(d.n) ** 2 * 8
     remap_gbs = remap_bytes / (remap_ms * 1e-3) / 1e9
     remap_roof = {"bound": "hbm", "ms": round(remap_ms, 3), "algorithmic_bytes": remap_bytes,
@@ -906,42 +991,39 @@ def main():
                   "frac": round(remap_gbs / PEAK_HBM, 4), "copy_ceiling": round(copy_gbs, 1),
                   "frac_of_copy_ceiling": round(remap_gbs / copy_gbs, 4), "hbm_streams_gbs": rates}
     # the Schwinger-Dyson stage: its box part reads the 4 Phi arrays once
-    sde_ms = r32["stage_ms"][4]
+    sde_ms = r3["stage_ms"][4]
     sde_bytes = 4.0 * d.Nq * float(d.n) ** 2 * 8
     sde_roof = {"bound": "hbm", "ms": round(sde_ms, 3), "algorithmic_bytes": sde_bytes,
                 "achieved": round(sde_bytes / (sde_ms * 1e-3) / 1e9, 1), "read_ceiling": rates["read"],
                 "frac_of_read_ceiling": round(sde_bytes / (sde_ms * 1e-3) / 1e9 / rates["read"], 4)}
 
+    stage_keys = (("dyson", 0), ("bubbles_kernels", 1), ("remap", 3), ("sigma", 4), ("bse", 5), ("mix", 6))
     out = {
         "metric": "parquet iterations/s + time-to-converged Σ (1e-6) vs FP64 GPU, 8x8 Nv=16",
-        "value": round(ips, 4),
+        "value": round(ips3, 4),
         "unit": "iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1000.0 / ips, 2),
+        "ms_per_step": round(1000.0 / ips3, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (fp32 MFMA BSE, fp64 Sigma/filling accumulation)",
+        "dtype": "c64 (BSE on BF16x3-split bf16 MFMA with FP32 accumulation; fp64 Sigma/filling accumulation)",
         "data": "synthetic (bare-vertex start of the 8x8 Hubbard parquet approximation)",
         "config": {"workload": "8x8 lattice, t=1, t'=-0.2, U=2, beta=5, n=0.9, Nv=16, kernel level 2",
-                   "bse_dim": d.n, "transfer_blocks": d.Nq, "channels": 4},
-        "fp64_iterations_per_s": round(ips64, 4) if ips64 else None,
-        "speedup_vs_fp64_gpu": round(ips / ips64, 3) if ips64 else None,
-        "stage_ms_fp32": {k: round(r32["stage_ms"][i], 3) for k, i in
-                          (("dyson", 0), ("bubbles_kernels", 1), ("remap", 3), ("sigma", 4), ("bse", 5),
-                           ("mix", 6))},
-        "stage_ms_fp64": ({k: round(r64["stage_ms"][i], 3) for k, i in
-                           (("dyson", 0), ("bubbles_kernels", 1), ("remap", 3), ("sigma", 4), ("bse", 5),
-                            ("mix", 6))} if r64 else None),
+                   "bse_dim": d.n, "transfer_blocks": d.Nq, "channels": 4, "bse_products": "bf16x3",
+                   "bse_tile": args.bf16x3_tile},
+        "stage_ms_bf16x3": {k: round(r3["stage_ms"][i], 3) for k, i in stage_keys},
         "roofline": roof,
+        "fp32_iterations_per_s": round(ips, 4),
+        "stage_ms_fp32": {k: round(r32["stage_ms"][i], 3) for k, i in stage_keys},
+        "roofline_fp32": roof32,
+        "fp64_iterations_per_s": round(ips64, 4) if ips64 else None,
+        "speedup_vs_fp64_gpu": round(ips3 / ips64, 3) if ips64 else None,
+        "stage_ms_fp64": ({k: round(r64["stage_ms"][i], 3) for k, i in stage_keys} if r64 else None),
         "remap": remap_roof,
         "sde": sde_roof,
-        "bf16x3_iterations_per_s": round(ips3, 4) if ips3 else None,
-        "bf16x3_update_avg_launch_ms": (round(r3["kern_ms"][3] / r3["kern_n"][3], 3) if r3 else None),
-        "stage_ms_bf16x3": ({k: round(r3["stage_ms"][i], 3) for k, i in
-                             (("remap", 3), ("sigma", 4), ("bse", 5))} if r3 else None),
     }
     if not args.no_ttc:
         # time from the bare-vertex start to Sigma within 1e-6 (relative) of the

@@ -23,3 +23,26 @@ def test_study_draws_are_seeded():
     x = parameter_draws(config("c2"), box, range(5))
     assert x == parameter_draws(config("c2"), box, range(5))
     assert all(1.0 <= p.U <= 2.0 and -0.2 <= p.tp <= 0.0 for p in x)
+
+
+def test_update_launch_model():
+    """The launch model behind the update kernel's roofline: pairing panels
+    changes the launches, not the work, so the multiply-adds of the modelled
+    launches equal the sum over single panels (forward: rows below x columns
+    right of the panel, A and B; back substitution: rows above x the n columns
+    of B); with n = 1024 a solve makes 20 launches."""
+    import bench
+
+    for n in (256, 384, 512, 1024):
+        L = bench.update_launches(n)
+        macs = sum(r * c * k for r, c, k, m in L)
+        fwd = sum((n - 128 * (j + 1)) * ((n - 128 * (j + 1)) + n) * 128 for j in range(n // 128))
+        back = sum(128 * j * n * 128 for j in range(n // 128))
+        assert macs == fwd + back, n
+        assert sum(m for r, c, k, m in L) == n - 128          # every row but the last panel's is mixed here
+    assert len(bench.update_launches(1024)) == 20
+
+    class D:
+        n, Nq = 1024, 960
+    c = bench.update_compulsory(D)
+    assert c["launches"] == 20 and c["flops"] == 8.0 * (fwd + back) * 960 / 20     # fwd, back of n = 1024
