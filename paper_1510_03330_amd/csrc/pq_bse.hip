@@ -1377,6 +1377,169 @@ void bse_update_bf_kernel(BseCtx<float> a, int j0, int ncb, int row_lo, int row_
       }
 }
 
+// ------------------------------------------------- BF16x3 pivot-row step
+// The pivot rows R_JK = P A_JK of a full panel (every column right of it in A
+// and every column of B) with the products of bse_update_bf_kernel: the
+// multiplier operand is P (transposed, k-major with row stride NB), the other
+// the panel rows of the column tile (for the first panel A = 1 - s Gamma
+// diag(X) formed from Gamma as it is staged), the accumulators start at zero.
+// A workgroup owns the 128 panel rows x 128 combined columns (2 x 2 waves of
+// 64 x 64). The rows are overwritten in place (every wave has passed the last
+// step's barrier, after the staging of the last panel rows, before any
+// store); the A part also goes transposed below the diagonal block (the U copy
+// the back substitution reads), and the last panel's rows are mixed into Phi
+// with their column sums, as in bse_panel_kernel.
+template <int NB, bool FIRST>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void bse_panel_bf_kernel(BseCtx<float> a, int j0, int mix) {
+  using C = float2;
+  using M = MmaBF3;
+  constexpr int W = 128, KSTEPS = NB / M::KS;
+  static_assert(NB == W && kThreads == 2 * W, "one workgroup covers the panel rows");
+  __shared__ bf16x8 sa[2][4][4][64];
+  __shared__ bf16x8 sb[2][4][4][64];
+  const unsigned lid = xcd_linear();
+  const int blk = lid / gridDim.x, bx = lid - (lid / gridDim.x) * gridDim.x;
+  if (inactive(a, blk)) return;                  // uniform over the workgroup
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, n = a.n;
+  constexpr int jb = NB;
+  const int ncolA = n - j0 - jb, ncols = ncolA + n;
+  const int C0 = bx * W;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int i0 = wr * 64, c0 = C0 + wc * 64;     // panel row, combined column of the wave tile
+  const bool live = c0 < ncols;
+  C* A = a.A + (size_t)blk * n * n;
+  C* B = a.B + (size_t)blk * n * n;
+  // staging: row sr of P^T's k slab (k half kh) and combined column sr of the
+  // panel rows (clamped: columns past ncols stage finite data no output uses)
+  const int sr = t & (W - 1), kh = t >> 7;
+  const C* pa = a.PI + (size_t)blk * NB * NB + (size_t)(8 * kh) * NB + sr;
+  const int scol = C0 + sr < ncols ? C0 + sr : 0;
+  const ColSrc<float> src = colsrc<float, FIRST>(a, blk, j0, jb, scol);
+  const C* pb = src.p + (size_t)(8 * kh) * n;
+  const int grp = sr >> 5, slot = (sr & 31) + 32 * kh;
+  C ra[8], rv[8];
+  auto load = [&](int s) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ra[e] = pa[(size_t)(s * M::KS + e) * NB];
+      rv[e] = pb[(size_t)(s * M::KS + e) * n];
+    }
+  };
+  auto commit = [&](int s, int buf) {
+    float v[8];
+    bf16x8 h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = -ra[e].x;
+    split8(v, h, l);
+    sa[buf][0][grp][slot] = h;
+    sa[buf][1][grp][slot] = l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = ra[e].y;
+    split8(v, h, l);
+    sa[buf][2][grp][slot] = h;
+    sa[buf][3][grp][slot] = l;
+    C b[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b[e] = FIRST ? src.form(rv[e], s * M::KS + 8 * kh + e, j0) : rv[e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = b[e].x;
+    split8(v, h, l);
+    sb[buf][0][grp][slot] = h;
+    sb[buf][1][grp][slot] = l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = b[e].y;
+    split8(v, h, l);
+    sb[buf][2][grp][slot] = h;
+    sb[buf][3][grp][slot] = l;
+  };
+  floatx16 re[2][2], im[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        re[x][y][v] = 0.f;
+        im[x][y][v] = 0.f;
+      }
+  load(0);
+  commit(0, 0);
+  load(1);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < KSTEPS; ++s) {
+    const int buf = s & 1;
+    bf16x8 fa[2][6], fb[2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fa[x][c] = sa[buf][c][2 * wr + x][lane];
+      fa[x][4] = neg8(fa[x][2]);
+      fa[x][5] = neg8(fa[x][3]);
+    }
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fb[y][c] = sb[buf][c][2 * wc + y][lane];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const bf16x8 &ph = fa[x][0], &pl = fa[x][1], &qh = fa[x][2], &ql = fa[x][3], &nqh = fa[x][4],
+                     &nql = fa[x][5];
+        const bf16x8 &bh = fb[y][0], &bl = fb[y][1], &ih = fb[y][2], &il = fb[y][3];
+        re[x][y] = M::mma(pl, bh, re[x][y]);
+        re[x][y] = M::mma(ph, bl, re[x][y]);
+        re[x][y] = M::mma(ql, ih, re[x][y]);
+        re[x][y] = M::mma(qh, il, re[x][y]);
+        re[x][y] = M::mma(ph, bh, re[x][y]);
+        re[x][y] = M::mma(qh, ih, re[x][y]);
+        im[x][y] = M::mma(pl, ih, im[x][y]);
+        im[x][y] = M::mma(ph, il, im[x][y]);
+        im[x][y] = M::mma(nql, bh, im[x][y]);
+        im[x][y] = M::mma(nqh, bl, im[x][y]);
+        im[x][y] = M::mma(ph, ih, im[x][y]);
+        im[x][y] = M::mma(nqh, bh, im[x][y]);
+      }
+    if (s + 1 < KSTEPS) {
+      commit(s + 1, buf ^ 1);
+      if (s + 2 < KSTEPS) load(s + 2);
+      __syncthreads();
+    }
+  }
+  if (!live) return;
+  // the products accumulated -(P A): R is their negative
+  const bool mixes = mix && c0 >= ncolA;         // wave-uniform: the last panel has no A columns
+  const float al = (float)a.alpha, be = (float)(1.0 - a.alpha);
+  const bool m = a.alpha != 1.0;
+  float cs[2] = {0.f, 0.f};
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int col = c0 + y * 32 + (lane & 31);
+    if (col >= ncols) continue;
+    C* cp = colptr(A, B, n, j0, jb, col);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = i0 + x * 32 + M::c_row(lane, v);
+        const C val = make_float2(-re[x][y][v], -im[x][y][v]);
+        cp[(size_t)(j0 + r) * n] = val;
+        if (col < ncolA) A[(size_t)(j0 + jb + col) * n + j0 + r] = val;
+        if (mixes) {
+          const size_t e = (size_t)blk * n * n + (size_t)(j0 + r) * n + (col - ncolA);
+          a.phi[e] = mix_phi<float>(val, a.gamma[e], m ? a.phi[e] : cz<C>(), al, be, m);
+          cs[y] += val.x * val.x + val.y * val.y;
+        }
+      }
+  }
+  if (mixes && a.pcs) {
+#pragma unroll
+    for (int y = 0; y < 2; ++y) put_cs(a.pcs, n, blk, (j0 + i0) / 64, c0 + y * 32 + (lane & 31) - ncolA, cs[y]);
+  }
+}
+
 // rows [row_lo, row_hi) with 0 <= row_lo < row_hi <= n, outside the panel;
 // combined columns [col_lo, ncols) with col_lo <= n - j0 - jb; multipliers from
 // mt (k-major [NB][n] per block) or, ut (back substitution of a full panel),
@@ -1982,6 +2145,17 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     const int nwb = ((ncols + 31) / 32 * (NB / RW) + kWaves - 1) / kWaves;
     const int mix = j0 == last ? 1 : 0;
     pre(2, st);
+    if constexpr (BF3) {
+      if (jb == NB) {                            // full panel: the BF16x3 products
+        const unsigned ncb = (unsigned)((ncols + NB - 1) / NB);
+        if (j0 == 0)
+          hipLaunchKernelGGL((bse_panel_bf_kernel<NB, true>), dim3(ncb, d.Nq), dim3(kThreads), 0, st, a, j0, mix);
+        else
+          hipLaunchKernelGGL((bse_panel_bf_kernel<NB, false>), dim3(ncb, d.Nq), dim3(kThreads), 0, st, a, j0, mix);
+        post(st);
+        return;
+      }
+    }
     if (j0 == 0)
       hipLaunchKernelGGL((bse_panel_kernel<T, NB, true, RW>), dim3(nwb, d.Nq), dim3(kThreads), 0, st, a, j0, nwb, mix);
     else
