@@ -485,7 +485,7 @@ pq_status parquet_destroy(pq_ctx* ctx);
  * K1 and K2 stay readable).
  *
  * parquet_batch_init starts every instance from the bare vertex; with
- * autotune != 0 and FP32 precision it first times both update tiles
+ * autotune != 0 and complex64 products (FP32 or BF16x3) it first times both update tiles
  * (pq_params.bse_tile) of the batch's BSE on its own block count and keeps the
  * faster (parquet_batch_tile reports the choice and the times, ms per launch
  * sequence of one channel). ws: parquet_batch_query_workspace bytes, owned by

@@ -15,8 +15,9 @@
 // the active blocks stay a contiguous prefix; the retired instance keeps its
 // Sigma, G, mu and kernel functions.
 //
-// The complex64/FP32 BSE update has two tile shapes (bse_tile); at set-up the
-// batch times both on its own block count and keeps the faster one.
+// The complex64 BSE update (FP32 and BF16x3 products) has two tile shapes
+// (bse_tile); at set-up the batch times both on its own block count and keeps
+// the faster one.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -263,7 +264,7 @@ hipError_t batch_setup(pq_batch* b, bool autotune) {
   if ((e = hipMemsetAsync(b->ws + L.phi, 0, vb, b->s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(b->ws + L.xph, 0, xb, b->s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(b->ws + L.xpp, 0, xb, b->s)) != hipSuccess) return e;
-  if (autotune && b->p0.precision == PQ_PREC_FP32) {
+  if (autotune && (b->p0.precision == PQ_PREC_FP32 || b->p0.precision == PQ_PREC_BF16X3)) {
     // Both update tiles on the batch's own block count: Gamma a fixed pattern,
     // X = 0, so every block is the identity system, F = Gamma and the mixing
     // leaves Phi = 0 (the start state).

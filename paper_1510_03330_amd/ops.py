@@ -311,7 +311,7 @@ def iterate_batch(solvers, n_iter: int, tol: float = 0.0):
 class Batch:
     """Instances of one box iterated together (parquet_batch_*): one vertex
     arena, one BSE launch sequence per channel over every active (instance, q)
-    block, one HIP graph per round; autotune times the two FP32 update tiles
+    block, one HIP graph per round; autotune times the two complex64 update tiles
     on the batch's own block count at set-up."""
 
     def __init__(self, params, precision: str = "fp32", device: str = "cuda:0", autotune: bool = True):

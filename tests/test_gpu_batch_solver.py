@@ -60,7 +60,7 @@ def test_batch_instances_match_oracle():
     b.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", -1e-7), ("fp32", -1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", -1e-7), ("fp32", -1e-5), ("bf16x3", -1e-5)])
 def test_batch_equals_independent_contexts_with_retirement(prec, tol):
     """Six seeded 2x4, Nv = 6 instances run to the relative stopping rule in
     one batch and each in its own context: every instance stops at the same
