@@ -928,7 +928,7 @@ def main():
 
     comp = update_compulsory(d)
     kernel_ms = lambda r: {k: round(r["kern_ms"][i] / r["steps"], 2) for k, i in
-                           (("pivot", 1), ("pivot_rows", 2), ("update", 3), ("epilogue", 4),
+                           (("pivot", 1), ("pivot_rows", 2), ("update", 3),
                             ("error_estimate_and_fp64_resolve", 5))}
     # dominant kernel of the headline path: the BF16x3 update (per launch: one
     # panel step of all 960 blocks of a channel, forward or back substitution).

@@ -76,12 +76,13 @@ typedef enum { PQ_STORE_C128 = 0, PQ_STORE_C64 = 1 } pq_storage;
 typedef enum {
   PQ_PREC_FP64 = 0,        /* complex128 elimination, FP64 MFMA              */
   PQ_PREC_FP32 = 1,        /* complex64 elimination, FP32 MFMA               */
-  PQ_PREC_BF16X3 = 2       /* complex64 elimination whose rank-NB updates
-                              split each FP32 operand into two bf16 parts and
-                              keep three of the four cross products on the
-                              bf16 matrix cores, FP32 accumulation (per-product
-                              relative error ~1e-5); every other step as
-                              PQ_PREC_FP32                                    */
+  PQ_PREC_BF16X3 = 2       /* complex64 elimination whose rank-NB updates and
+                              pivot-row steps (full panels) split each FP32
+                              operand into two bf16 parts and keep three of
+                              the four cross products on the bf16 matrix
+                              cores, FP32 accumulation (per-product relative
+                              error ~1e-5); the diagonal-block inversion and
+                              ragged panels as PQ_PREC_FP32                   */
 } pq_precision;
 
 typedef enum { PQ_CH_D = 0, PQ_CH_M = 1, PQ_CH_S = 2, PQ_CH_T = 3 } pq_channel;
@@ -373,11 +374,11 @@ typedef struct {
   double ms_total;         /* wall time of the last iteration (device events)   */
   double ms_stage[8];      /* dyson, bubbles+kernels, -, remap, sigma, bse (4 channels), mix, - */
   /* BSE of the density channel, per kernel kind (init, pivot and multiplier
-   * copy, pivot rows, update, separate mixing pass, error estimate and FP64
-   * re-solve): summed device time of its launches and the number of
-   * launches. The update includes the back substitution and the mixing fused
-   * into it; the separate mixing pass runs only with BF16x3 products
-   * (otherwise 0 launches); the last kind runs on the complex64 paths. */
+   * copy, pivot rows, update, a separate mixing pass (no longer used: 0
+   * launches), error estimate and FP64 re-solve): summed device time of its
+   * launches and the number of launches. The update includes the back
+   * substitution and the mixing fused into it; the last kind runs on the
+   * complex64 paths. */
   double ms_bse_kernel[6];
   int32_t n_bse_launch[6];
   int32_t resolved_blocks;   /* blocks re-solved in FP64 (stats bit 2), last iteration */
