@@ -371,6 +371,7 @@ typedef struct {
   int32_t flagged_blocks;  /* BSE blocks flagged (stats bit 0) in the last iteration */
   double dsigma;           /* max |Sigma_new - Sigma_old| of the last iteration */
   double mu;               /* mu~ used by the last iteration                    */
+  /* Timings from device events: NaN where an event pair cannot be read. */
   double ms_total;         /* wall time of the last iteration (device events)   */
   double ms_stage[8];      /* dyson, bubbles+kernels, -, remap, sigma, bse (4 channels), mix, - */
   /* BSE of the density channel, per kernel kind (init, pivot and multiplier

@@ -434,6 +434,12 @@ void* field_ptr(pq_ctx* c, int f) {
   }
 }
 
+// Milliseconds between two recorded events; NaN where they cannot be read.
+float elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  return hipEventElapsedTime(&ms, a, b) == hipSuccess ? ms : __builtin_nanf("");
+}
+
 // The launches of one iteration on the context stream: Dyson -> bubbles ->
 // kernels -> remap -> Schwinger-Dyson -> BSE (4 channels) -> mixing (writes
 // dnorm). Nothing here waits on the host, allocates or clears memory, so the
@@ -444,8 +450,10 @@ hipError_t enqueue_iteration(pq_ctx* c, bool record, BseTiming* tm, const char**
   const double lam[4] = {p.U, -p.U, 2.0 * p.U, 0.0};
   const size_t vstride = elem_bytes(p) * (size_t)d.Nq * d.n * d.n;
   const double2* lam_box = c->has_lam ? c->lam : nullptr;
-  hipError_t e;
-  auto rec = [&](int i) { if (record) hipEventRecord(c->ev[i], c->s); };
+  hipError_t e, er = hipSuccess;  // er: the first failed stage-event record
+  auto rec = [&](int i) {
+    if (record && er == hipSuccess) er = hipEventRecord(c->ev[i], c->s);
+  };
   rec(0);
   if ((e = launch_dyson(p, d, c->sigma, c->g, c->mu, c->s)) != hipSuccess) { *where = "dyson"; return e; }
   rec(1);
@@ -477,7 +485,8 @@ hipError_t enqueue_iteration(pq_ctx* c, bool record, BseTiming* tm, const char**
     return e;
   }
   rec(6);
-  return hipSuccess;
+  if (er != hipSuccess) *where = "stage events";
+  return er;
 }
 
 // Convergence test of one iteration. tol > 0: the change of Sigma below tol.
@@ -554,12 +563,12 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
   // look-ahead stream (default priority) and its two events
   c->have_la = hipStreamCreateWithFlags(&c->la.side, hipStreamNonBlocking) == hipSuccess;
   if (c->have_la && hipEventCreateWithFlags(&c->la.ready, hipEventDisableTiming) != hipSuccess) {
-    hipStreamDestroy(c->la.side);
+    (void)hipStreamDestroy(c->la.side);
     c->have_la = false;
   }
   if (c->have_la && hipEventCreateWithFlags(&c->la.done, hipEventDisableTiming) != hipSuccess) {
-    hipEventDestroy(c->la.ready);
-    hipStreamDestroy(c->la.side);
+    (void)hipEventDestroy(c->la.ready);
+    (void)hipStreamDestroy(c->la.side);
     c->have_la = false;
   }
   hipError_t e;
@@ -574,13 +583,13 @@ pq_status parquet_init(const pq_params* p, void* ws, size_t ws_bytes, pq_stream 
   return PQ_OK;
 fail:
   for (int i = 0; i < 8; ++i)
-    if (c->have_events) hipEventDestroy(c->ev[i]);
+    if (c->have_events) (void)hipEventDestroy(c->ev[i]);
   for (int i = 0; i < 512; ++i)
-    if (c->have_bev) hipEventDestroy(c->bev[i]);
+    if (c->have_bev) (void)hipEventDestroy(c->bev[i]);
   if (c->have_la) {
-    hipEventDestroy(c->la.ready);
-    hipEventDestroy(c->la.done);
-    hipStreamDestroy(c->la.side);
+    (void)hipEventDestroy(c->la.ready);
+    (void)hipEventDestroy(c->la.done);
+    (void)hipStreamDestroy(c->la.side);
   }
   delete c;
   return hip_fail(e, "parquet_init");
@@ -621,20 +630,17 @@ pq_status parquet_iterate(pq_ctx* c, int32_t n_iter, double tol, pq_iter_stats* 
       stats->unresolved_blocks = (int32_t)res[3];
       stats->max_err_est = res[4];
       if (c->have_events) {
-        float ms;
-        hipEventElapsedTime(&ms, c->ev[0], c->ev[6]); stats->ms_total = ms;
-        hipEventElapsedTime(&ms, c->ev[0], c->ev[1]); stats->ms_stage[0] = ms;
-        hipEventElapsedTime(&ms, c->ev[1], c->ev[2]); stats->ms_stage[1] = ms;
-        hipEventElapsedTime(&ms, c->ev[2], c->ev[3]); stats->ms_stage[3] = ms;
-        hipEventElapsedTime(&ms, c->ev[3], c->ev[4]); stats->ms_stage[4] = ms;
-        hipEventElapsedTime(&ms, c->ev[4], c->ev[5]); stats->ms_stage[5] = ms;
-        hipEventElapsedTime(&ms, c->ev[5], c->ev[6]); stats->ms_stage[6] = ms;
+        stats->ms_total = elapsed_ms(c->ev[0], c->ev[6]);
+        stats->ms_stage[0] = elapsed_ms(c->ev[0], c->ev[1]);
+        stats->ms_stage[1] = elapsed_ms(c->ev[1], c->ev[2]);
+        stats->ms_stage[3] = elapsed_ms(c->ev[2], c->ev[3]);
+        stats->ms_stage[4] = elapsed_ms(c->ev[3], c->ev[4]);
+        stats->ms_stage[5] = elapsed_ms(c->ev[4], c->ev[5]);
+        stats->ms_stage[6] = elapsed_ms(c->ev[5], c->ev[6]);
       }
       if (timing) {
         for (int i = 0; i < tm.used; ++i) {
-          float ms = 0.f;
-          hipEventElapsedTime(&ms, c->bev[2 * i], c->bev[2 * i + 1]);
-          stats->ms_bse_kernel[tm.kind[i]] += ms;
+          stats->ms_bse_kernel[tm.kind[i]] += elapsed_ms(c->bev[2 * i], c->bev[2 * i + 1]);
           stats->n_bse_launch[tm.kind[i]] += 1;
         }
         stats->update_flops = tm.update_flops;
@@ -677,7 +683,7 @@ pq_status parquet_iterate_batch(pq_ctx* const* ctxs, int32_t count, int32_t n_it
   for (int i = 0; i < count; ++i) {
     pq_ctx* c = ctxs[i];
     if (c->have_graph && c->graph_has_lam != c->has_lam) {
-      hipGraphExecDestroy(c->graph);
+      (void)hipGraphExecDestroy(c->graph);
       c->have_graph = false;
     }
     if (!c->have_graph) {
@@ -688,12 +694,12 @@ pq_status parquet_iterate_batch(pq_ctx* const* ctxs, int32_t count, int32_t n_it
       hipError_t ei = enqueue_iteration(c, false, nullptr, &where);
       e = hipStreamEndCapture(c->s, &g);
       if (ei != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return hip_fail(ei, where);
       }
       if (e != hipSuccess) return hip_fail(e, "graph capture (end)");
       e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if (e != hipSuccess) return hip_fail(e, "graph instantiate");
       c->have_graph = true;
       c->graph_has_lam = c->has_lam;
@@ -837,16 +843,16 @@ pq_status parquet_copy_state(pq_ctx* dst, pq_ctx* src) {
 pq_status parquet_destroy(pq_ctx* c) {
   if (!c) return PQ_OK;
   if (c->have_la) {
-    hipStreamSynchronize(c->la.side);
-    hipEventDestroy(c->la.ready);
-    hipEventDestroy(c->la.done);
-    hipStreamDestroy(c->la.side);
+    (void)hipStreamSynchronize(c->la.side);
+    (void)hipEventDestroy(c->la.ready);
+    (void)hipEventDestroy(c->la.done);
+    (void)hipStreamDestroy(c->la.side);
   }
-  if (c->have_graph) hipGraphExecDestroy(c->graph);
+  if (c->have_graph) (void)hipGraphExecDestroy(c->graph);
   if (c->have_events)
-    for (int i = 0; i < 8; ++i) hipEventDestroy(c->ev[i]);
+    for (int i = 0; i < 8; ++i) (void)hipEventDestroy(c->ev[i]);
   if (c->have_bev)
-    for (int i = 0; i < 512; ++i) hipEventDestroy(c->bev[i]);
+    for (int i = 0; i < 512; ++i) (void)hipEventDestroy(c->bev[i]);
   delete c;
   return PQ_OK;
 }

@@ -206,7 +206,7 @@ hipError_t enqueue_post(pq_batch* b, int slot, const char** where) {
 // one round of the active instances, captured into b->graph
 hipError_t capture_round(pq_batch* b, const char** where) {
   if (b->have_graph) {
-    hipGraphExecDestroy(b->graph);
+    (void)hipGraphExecDestroy(b->graph);
     b->have_graph = false;
   }
   const int A = b->active;
@@ -219,12 +219,12 @@ hipError_t capture_round(pq_batch* b, const char** where) {
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(b->s, &g);
   if (err != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return err;
   }
   if (e != hipSuccess) { *where = "capture end"; return e; }
   e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) { *where = "graph instantiate"; return e; }
   b->have_graph = true;
   return hipSuccess;
@@ -273,7 +273,7 @@ hipError_t batch_setup(pq_batch* b, bool autotune) {
     hipEvent_t t0, t1;
     if ((e = hipEventCreate(&t0)) != hipSuccess) return e;
     if ((e = hipEventCreate(&t1)) != hipSuccess) {
-      hipEventDestroy(t0);
+      (void)hipEventDestroy(t0);
       return e;
     }
     const char* where = nullptr;
@@ -288,8 +288,8 @@ hipError_t batch_setup(pq_batch* b, bool autotune) {
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
       b->tile_ms[tile] = ms / 2.f;
     }
-    hipEventDestroy(t0);
-    hipEventDestroy(t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
     if (e != hipSuccess) return e;
     b->tile = b->tile_ms[1] < b->tile_ms[0] ? 1 : 0;
     if ((e = hipMemsetAsync(b->ws + L.phi, 0, vb, b->s)) != hipSuccess) return e;
@@ -375,7 +375,7 @@ pq_status parquet_batch_init(const pq_params* ps, int32_t count, void* ws, size_
   }
   e = batch_setup(b, autotune != 0);
   if (e != hipSuccess) {
-    hipHostFree(b->dn_host);
+    (void)hipHostFree(b->dn_host);
     delete b;
     return hip_fail(e, "parquet_batch_init");
   }
@@ -414,7 +414,7 @@ pq_status parquet_batch_iterate(pq_batch* b, int32_t n_iter, double tol, double 
     if (!done.empty()) {
       if ((e = retire(b, done)) != hipSuccess) return hip_fail(e, "batch retire");
       if (b->have_graph) {
-        hipGraphExecDestroy(b->graph);
+        (void)hipGraphExecDestroy(b->graph);
         b->have_graph = false;
       }
     }
@@ -482,9 +482,9 @@ pq_status parquet_batch_tile(pq_batch* b, int32_t* tile, float* ms) {
 
 pq_status parquet_batch_destroy(pq_batch* b) {
   if (!b) return PQ_OK;
-  hipStreamSynchronize(b->s);
-  if (b->have_graph) hipGraphExecDestroy(b->graph);
-  if (b->dn_host) hipHostFree(b->dn_host);
+  (void)hipStreamSynchronize(b->s);
+  if (b->have_graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->dn_host) (void)hipHostFree(b->dn_host);
   delete b;
   return PQ_OK;
 }

@@ -2076,15 +2076,20 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   // event timing around each launch (kind: 0 init, 1 pivot, 2 panel, 3 update,
   // 4 unused (a separate mixing pass, no longer needed), 5 error estimate and
   // FP64 re-solve)
+  // the first failed event call (timing or the look-ahead's stream order)
+  hipError_t ev_err = hipSuccess;
+  auto note = [&](hipError_t e) {
+    if (ev_err == hipSuccess) ev_err = e;
+  };
   auto pre = [&](int kind, hipStream_t st) {
     if (tm && tm->used < tm->cap) {
       tm->kind[tm->used] = kind;
-      hipEventRecord(tm->ev[2 * tm->used], st);
+      note(hipEventRecord(tm->ev[2 * tm->used], st));
     }
   };
   auto post = [&](hipStream_t st) {
     if (tm && tm->used < tm->cap) {
-      hipEventRecord(tm->ev[2 * tm->used + 1], st);
+      note(hipEventRecord(tm->ev[2 * tm->used + 1], st));
       tm->used++;
     }
   };
@@ -2209,10 +2214,10 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     if (tm) tm->update_flops += 8.0 * (double)(row_hi - row_lo) * ncols * jb * d.Nq;
   };
   auto side_pivot = [&](int j0) {
-    hipEventRecord(la->ready, s);
-    hipStreamWaitEvent(la->side, la->ready, 0);
+    note(hipEventRecord(la->ready, s));
+    note(hipStreamWaitEvent(la->side, la->ready, 0));
     pivot_step(j0, la->side);
-    hipEventRecord(la->done, la->side);
+    note(hipEventRecord(la->done, la->side));
   };
   // Look-ahead (a second stream given): once the rows of the next panel are
   // updated, its diagonal-block inversion runs on the second stream while the
@@ -2237,7 +2242,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
     const int jb = std::min(NB, n - j0);
     const int pj = j0 / NB;
     if (ahead)
-      hipStreamWaitEvent(s, la->done, 0);
+      note(hipStreamWaitEvent(s, la->done, 0));
     else
       pivot_step(j0, s);
     panel_step(j0, s);
@@ -2250,7 +2255,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
       if (la) side_pivot(lo);
       upd(j0, 1, hi, n, NB, hi, mtb[pj % 3], nullptr, mtb[(pj + 1) % 3], NB);
       if (la)
-        hipStreamWaitEvent(s, la->done, 0);
+        note(hipStreamWaitEvent(s, la->done, 0));
       else
         pivot_step(lo, s);
       panel_step(lo, s);
@@ -2383,6 +2388,7 @@ static hipError_t run_bse(const Dims& d, int channel, double alpha, float weak, 
   }
   if (stats)
     hipLaunchKernelGGL((bse_stats_kernel<T>), dim3((d.Nq + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
+  if (ev_err != hipSuccess) return ev_err;
   return hipGetLastError();
 }
 
