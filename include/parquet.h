@@ -113,8 +113,10 @@ typedef struct {
                               more workgroups for small systems; with BF16x3
                               products also operand loads two steps ahead);
                               complex128 has one tile. Both run the same
-                              products in the same order and agree to FP32
-                              rounding; the batched solver picks by timing.  */
+                              products in the same order; they agree to FP32
+                              rounding (the BF16x3 narrow tile adds C after
+                              the products, a different FP32 summation
+                              order); the batched solver picks by timing.   */
   double U, beta, t, tp;   /* interaction, inverse temperature, hoppings     */
   double filling;          /* total density n for mu_mode = 1                */
   double D;                /* semicircle half-bandwidth (local mode)         */

@@ -2442,7 +2442,7 @@ hipError_t launch_bse(const pq_params& p, const Dims& d, int channel, int precis
   const double tol = p.bse_tol > 0.0 ? p.bse_tol : kDefaultBseTol;
   if (precision == PQ_PREC_BF16X3)
     return run_bse<float, true>(d, channel, alpha, 1e-3f, 1e3, tol, p.resolve_slots, gamma, chi0, phi_io, stats, ws,
-                                s, tm, nullptr, 0, la);
+                                s, tm, nullptr, p.bse_tile, la);
   return run_bse<float>(d, channel, alpha, 1e-3f, 1e3, tol, p.resolve_slots, gamma, chi0, phi_io, stats, ws, s, tm,
                         nullptr, p.bse_tile, la);
 }

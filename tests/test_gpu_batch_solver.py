@@ -89,18 +89,22 @@ def test_batch_equals_independent_contexts_with_retirement(prec, tol):
     b.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_update_tiles_agree(prec):
-    """The two complex64 update tiles (bse_tile 0: 64 x 64 per wave, 1: 64 x 32)
-    run the same products in the same order; they agree to FP32 rounding (the
-    compiler contracts the epilogue arithmetic of the two instantiations
-    differently) on the 4x4, Nv = 16 box (n = 256: two panels, the forward
-    and the back-substitution update both take the tile)."""
+@pytest.mark.parametrize("prec,tile,rel", [("fp32", 1, 1e-6), ("bf16x3", 1, 5e-5)])
+def test_update_tiles_agree(prec, tile, rel):
+    """The complex64 update tiles (bse_tile 0: 64 x 64 per wave, 1: 64 x 32)
+    run the same products in the same order. The FP32 tiles both start their
+    accumulators from C and agree to FP32 rounding (the compiler contracts the
+    epilogue arithmetic of the two instantiations differently); the BF16x3
+    narrow tile loads its C tile across the steps and adds it after the
+    products, a different FP32 summation order whose rounding the solve
+    carries (about 1e-5 of max|F| here). On the 4x4, Nv = 16 box (n = 256: two
+    panels, the forward and the back-substitution update both take the
+    tile)."""
     ops = _ops()
     p = config("c2")
     out = []
-    for tile in (0, 1):
-        st = ops.Stage(p, prec, bse_tile=tile)
+    for t in (0, tile):
+        st = ops.Stage(p, prec, bse_tile=t)
         d = st.d
         gam = torch.from_numpy(bse_microbench_gamma(d.n, range(d.Nq)).astype(np.complex64)).to(DEV)
         x = torch.from_numpy(rand_complex((d.Nq, d.n), 77, 0.3)).to(DEV)
@@ -108,7 +112,8 @@ def test_update_tiles_agree(prec):
         st.bse_solve(1, gam, x, phi, alpha=0.5)
         out.append(phi)
     assert not torch.equal(out[0], torch.zeros_like(out[0]))
-    assert (out[0] - out[1]).abs().max().item() <= 1e-6 * out[0].abs().max().item()
+    diff = (out[0] - out[1]).abs().max().item()
+    assert diff <= rel * out[0].abs().max().item(), (tile, diff)
 
 
 @pytest.mark.parametrize("prec,nv", [("fp32", 64), ("bf16x3", 64), ("fp64", 48)])
